@@ -1,0 +1,174 @@
+/*
+ * pdc.h -- C ABI of libpdc: pixel-detector correction and photon finding on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * The operations follow Blaj, Chang and Kenney, "Ultrafast Processing of Pixel
+ * Detector Data with Machine Learning Frameworks" (AIP Conf. Proc. 2054,
+ * 060077, 2019; arXiv:1903.06838):
+ *   - a minibatch of N raw frames is an N x H x W tensor of 14-bit ADC values
+ *     (Novel Tensorflow Models, Dark and Gain; Fig. b "Raw");
+ *   - Frames1 = (Raw - Dark) / Gain per pixel (Fig. b);
+ *   - common mode: a per-bank offset is estimated and subtracted, giving
+ *     Frames2 (Common Mode section, Fig. c; the section allows row, column or
+ *     block common modes; here a bank is one row of bank_cols contiguous
+ *     columns of a tile and the estimate is the bank's lower median);
+ *   - photon finding: a photon's charge is summed from its cloud and placed on
+ *     the cloud's highest pixel (Photon Charge Summing section, Fig. e), with
+ *     pixels within noise zeroed (Photon Subpixel Resolution section);
+ *   - photon counting: charge / single-photon signal, rounded to the nearest
+ *     integer (Photon Charge Summing section);
+ *   - summarization into sparse photon lists (Summarization section).
+ *
+ * Exact contract, per frame f, tile t, row r, column c, pixel
+ * p = (t*rows + r)*cols + c, all arithmetic IEEE binary32 round-to-nearest-even
+ * with every operation rounded on its own:
+ *   adc = raw & 0x3FFF;  u = ((float)adc - pedestal[p]) * k[p],  k[p] = 1.0f / gain[p]
+ *   m   = element of rank (B-1)/2 (0-based, ascending) of the bank's B values u
+ *   v   = u - m                                                  (Frames2)
+ *   hit at p iff v[p] > T_seed and, for every neighbour q of the 3x3 window
+ *   inside the same tile, v[p] > v[q] or (v[p] == v[q] and p < q)
+ *   charge = sum over the in-tile 3x3 window, rows top to bottom, columns left
+ *            to right, from +0.0f, of (v[j] > T_nb ? v[j] : 0.0f)
+ *   nphot  = rint(charge / photon_adu) (ties to even), saturating at 2^32-1
+ *   T_seed = n_seed * sigma,  T_nb = n_nb * sigma  (formed in binary32)
+ *
+ * Threading: a context is used by one host thread at a time.  All functions
+ * return a pdc_status; no C++ exception crosses this boundary; on a negative
+ * status the output parameters are left untouched.
+ */
+#ifndef PDC_H
+#define PDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pdc_status;
+
+#define PDC_OK 0
+#define PDC_WARN_TRUNCATED 1 /* soft: more hits than the destination holds */
+#define PDC_EINVAL (-1)      /* invalid argument, geometry, plane value or parameter */
+#define PDC_ENOMEM (-2)      /* device or host memory exhausted */
+#define PDC_EDEVICE (-3)     /* HIP runtime error, no device, or a kernel-reported fault */
+#define PDC_ESTATE (-4)      /* unknown or released detector / batch, wrong call order */
+
+/* Keep Frames2 (float32 [N][T][H][W]) of a batch for pdc_get_corrected. */
+#define PDC_KEEP_CORRECTED 1u
+
+typedef struct pdc_ctx pdc_ctx;
+
+/* Detector geometry.  A frame is n_tiles tiles of rows x cols pixels (tiles are
+ * separate sensors: 3x3 windows stop at tile edges).  Common-mode banks are
+ * one row of bank_cols contiguous columns; cols % bank_cols == 0.
+ * Limits: 1 <= n_tiles, rows; 1 <= bank_cols <= cols <= 2048; bank_cols <= 1024;
+ * n_tiles*rows*cols < 2^31.  gain_mode must be 0 (single gain range). */
+typedef struct {
+    int32_t n_tiles;
+    int32_t rows;
+    int32_t cols;
+    int32_t bank_cols;
+    int32_t gain_mode;
+} pdc_geometry;
+
+/* Thresholds and photon scale (Results, Accuracy: the two noise thresholds,
+ * typically 3 to 5 sigma).  sigma > 0, n_seed >= 0, n_nb >= 0 finite, with
+ * T_nb <= T_seed; photon_adu in [2^-24, 2^24]; flags is 0 or PDC_KEEP_CORRECTED. */
+typedef struct {
+    float sigma;
+    float n_seed;
+    float n_nb;
+    float photon_adu;
+    uint32_t flags;
+} pdc_params;
+
+/* One photon hit (16 bytes).  frame is relative to the batch. */
+typedef struct {
+    uint32_t frame;
+    uint32_t pixel;  /* (tile*rows + row)*cols + col */
+    float charge;    /* masked 3x3 charge sum, ADU after gain correction */
+    uint32_t nphot;  /* rint(charge / photon_adu) */
+} pdc_hit;
+
+/* Static text for a status code. */
+const char *pdc_strerror(pdc_status status);
+
+/* Message of the last failing call on ctx (empty string if none). */
+const char *pdc_last_error(const pdc_ctx *ctx);
+
+/* Open a context on HIP device `device`.  The library owns every device buffer
+ * it allocates; they are freed by pdc_destroy.  EDEVICE if the device does not
+ * exist or is not gfx950. */
+pdc_status pdc_create(int32_t device, pdc_ctx **out);
+
+/* Wait for outstanding work, free everything.  NULL is accepted. */
+pdc_status pdc_destroy(pdc_ctx *ctx);
+
+/* Host-only validation of what pdc_calibrate would accept (no device use).
+ * pedestal and gain are host arrays float32 [n_tiles][rows][cols].  Each
+ * pedestal must be finite with |x| <= 2^24 and (x == 0 or |x| >= 2^-64); each
+ * gain finite in [2^-24, 2^24].  These bounds keep every intermediate finite,
+ * normal or +0 (no -0, no subnormal, no NaN).  EINVAL names the first
+ * offending value in the status text of the context-free check. */
+pdc_status pdc_check_calibration(const pdc_geometry *geom, const float *pedestal,
+                                 const float *gain, const pdc_params *params);
+
+/* Dark and gain calibration (Fig. b weights "Dark" and "Gain", 1 x H x W).
+ * Copies the host planes into resident device memory (the caller keeps its
+ * arrays), forms k = 1.0f / gain on the host, T_seed and T_nb, and returns a
+ * detector id in *det_out.  EINVAL on invalid geometry, planes or params. */
+pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pedestal,
+                         const float *gain, const pdc_params *params, int32_t *det_out);
+
+/* Free a detector's planes after its pending batches complete. */
+pdc_status pdc_release_detector(pdc_ctx *ctx, int32_t det);
+
+/* Enqueue the whole pipeline on a batch of frames.
+ * frames_dev: DEVICE pointer to uint16 [n_frames][n_tiles][rows][cols], raw
+ *   ADC words (bits 14-15 ignored); borrowed, it must stay valid and unchanged
+ *   until pdc_get_hits or pdc_release_batch of this batch returns.
+ * hit_capacity: expected upper bound on hits in the batch; buffers are sized
+ *   from it.  If the batch holds more, pdc_get_hits recomputes it with exact
+ *   sizes, so the result is always complete.
+ * hip_stream: a hipStream_t of the context's device, or NULL for the
+ *   context's own stream.  The call returns once the work is enqueued.
+ * *batch_out: id for pdc_get_hits / pdc_get_corrected / pdc_release_batch.
+ * n_frames may be 0.  Results of a frame do not depend on the other frames of
+ * the batch.  EINVAL on a bad pointer or size, ESTATE on an unknown detector,
+ * ENOMEM if device buffers cannot be allocated. */
+pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev,
+                              uint64_t n_frames, uint64_t hit_capacity, void *hip_stream,
+                              uint64_t *batch_out);
+
+/* Wait for the batch and copy its results, hits in (frame, pixel) order.
+ * dst: room for dst_capacity records, in host memory (dst_is_device = 0) or
+ *   device memory of the context's device (dst_is_device = 1); may be NULL
+ *   when dst_capacity is 0.  The first min(total, dst_capacity) hits are
+ *   written; *n_hits_total (may be NULL) receives the true total.
+ * per_frame_hits (uint32 [n_frames]) and per_frame_photons (uint64
+ *   [n_frames]): host arrays or NULL.
+ * Returns PDC_WARN_TRUNCATED when total > dst_capacity, else PDC_OK.  The batch
+ * stays alive until pdc_release_batch.  ESTATE for an unknown batch. */
+pdc_status pdc_get_hits(pdc_ctx *ctx, uint64_t batch, pdc_hit *dst, uint64_t dst_capacity,
+                        int32_t dst_is_device, uint64_t *n_hits_total, uint32_t *per_frame_hits,
+                        uint64_t *per_frame_photons);
+
+/* Frames2 of a batch processed with PDC_KEEP_CORRECTED: float32
+ * [n_frames][n_tiles][rows][cols] into host or device memory.  ESTATE if the
+ * flag was not set. */
+pdc_status pdc_get_corrected(pdc_ctx *ctx, uint64_t batch, float *dst, int32_t dst_is_device);
+
+/* Wait for the batch and return its buffers to the context for reuse. */
+pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
+
+/* Timing of a finished batch from HIP events recorded on its stream:
+ * *main_ms = the fused frame kernel alone, *total_ms = every kernel of the
+ * batch (frame kernel, scans, hit scatter).  Either pointer may be NULL. */
+pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PDC_H */

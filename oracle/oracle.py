@@ -114,17 +114,23 @@ class Oracle:
         dark = np.ascontiguousarray(dark, dtype=np.float32)
         gain = np.ascontiguousarray(gain, dtype=np.float32)
         assert dark.shape == gain.shape == (T, H, W)
-        if hit_cap is None:
+        auto_cap = hit_cap is None
+        if auto_cap:
             hit_cap = max(1, N * T * ((H + 1) // 2) * ((W + 1) // 2) // 8 + 1024)
-        hits = np.empty(hit_cap, dtype=HIT_DTYPE)
-        n = ctypes.c_int64(0)
-        fh = np.empty(N, dtype=np.uint32)
-        fp = np.empty(N, dtype=np.uint64)
-        corr = np.empty(raw.shape, dtype=np.float32) if keep_corrected else None
-        total = self.lib.oracle_process(
-            raw.ctypes.data, N, T, H, W, bank_cols, dark.ctypes.data, gain.ctypes.data,
-            sigma, n_seed, n_nb, photon_adu, hits.ctypes.data, hit_cap, ctypes.byref(n),
-            fh.ctypes.data, fp.ctypes.data, corr.ctypes.data if corr is not None else None)
+        while True:
+            hits = np.empty(hit_cap, dtype=HIT_DTYPE)
+            n = ctypes.c_int64(0)
+            fh = np.empty(N, dtype=np.uint32)
+            fp = np.empty(N, dtype=np.uint64)
+            corr = np.empty(raw.shape, dtype=np.float32) if keep_corrected else None
+            total = self.lib.oracle_process(
+                raw.ctypes.data, N, T, H, W, bank_cols, dark.ctypes.data, gain.ctypes.data,
+                sigma, n_seed, n_nb, photon_adu, hits.ctypes.data, hit_cap, ctypes.byref(n),
+                fh.ctypes.data, fp.ctypes.data, corr.ctypes.data if corr is not None else None)
+            if auto_cap and total > n.value:
+                hit_cap = int(total)     # the first capacity was a guess: run again
+                continue
+            break
         out = dict(hits=hits[:n.value].copy(), frame_hits=fh, frame_photons=fp, total=int(total))
         if corr is not None:
             out["corrected"] = corr

@@ -1,0 +1,80 @@
+// Internal interfaces between the host runtime (pdc_runtime.cpp) and the HIP
+// kernels (pdc_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdc {
+
+// Sentinel for "this unit's hits could not be staged" (staging pool full).
+constexpr uint64_t kNoBase = ~0ull;
+// Staging chunk claimed by one workgroup from the batch-wide pool cursor.
+constexpr uint64_t kChunkHits = 8192;
+
+// Device-side batch state, cleared by init_state before each run.
+struct BatchState {
+    unsigned long long cursor;    // next free staging slot
+    unsigned int overflow;        // 1 if some unit could not be staged
+    unsigned int pad;
+    unsigned long long total;     // total hits of the batch (set by the frame scan)
+};
+
+// A work unit is (frame, strip): rows [r0, r0 + strip_rows) of one tile.
+// Units are numbered frame-major, then tile, then strip, which is raster order
+// of their pixels.
+struct FrameKernelArgs {
+    const uint16_t *frames;       // [n_frames][T][H][W]
+    const float *ped;             // [T][H][W]
+    const float *k;               // [T][H][W], k = 1/gain
+    uint64_t n_frames;
+    uint64_t n_units;
+    int32_t T, H, W, B, nb;       // geometry; nb = W / B
+    int32_t strip_rows;           // rows per strip
+    int32_t strips_per_tile;
+    int32_t units_per_frame;      // T * strips_per_tile
+    int32_t sort_width;           // power of two >= B
+    int32_t sort_rows;            // rows sorted together (v1)
+    uint32_t max_unit_hits;       // upper bound on hits of one unit
+    float t_seed, t_nb, photon_adu;
+    uint2 *pool;                  // staging: {pixel, charge bits}
+    uint64_t pool_cap;
+    uint32_t *unit_count;         // [n_units]
+    unsigned long long *unit_photons;  // [n_units]
+    uint64_t *unit_base;          // [n_units] staging start or kNoBase
+    BatchState *state;
+    float *corrected;             // Frames2 or nullptr
+};
+
+size_t frame_kernel_v1_lds_bytes(int strip_rows, int W, int nb, int sort_width, int sort_rows,
+                                 uint32_t max_unit_hits);
+
+hipError_t launch_init_state(BatchState *state, hipStream_t s);
+hipError_t launch_frame_kernel_v1(const FrameKernelArgs &a, uint32_t grid, size_t lds_bytes,
+                                  bool keep_corrected, hipStream_t s);
+// Per frame: in-frame exclusive offsets of units, hit counts and photon totals.
+hipError_t launch_frame_sums(const uint32_t *unit_count, const unsigned long long *unit_photons,
+                             uint64_t n_frames, int32_t units_per_frame, uint32_t *unit_local,
+                             uint32_t *frame_hits, unsigned long long *frame_photons,
+                             hipStream_t s);
+// Exclusive scan of frame hit counts: frame_offset[0..n_frames], total into state.
+hipError_t launch_frame_scan(const uint32_t *frame_hits, uint64_t n_frames,
+                             unsigned long long *frame_offset, BatchState *state, hipStream_t s);
+// Copy each unit's staged hits to its place in the raster-order list.
+hipError_t launch_scatter(const uint32_t *unit_count, const uint64_t *unit_base,
+                          const uint32_t *unit_local, const unsigned long long *frame_offset,
+                          const uint2 *pool, uint64_t n_units, int32_t units_per_frame,
+                          uint2 *hits, uint64_t hits_cap, hipStream_t s);
+
+// The 16-byte hit record of the public ABI.
+struct HitRecord {
+    uint32_t frame, pixel;
+    float charge;
+    uint32_t nphot;
+};
+// Expand hits [first, first + n) of the raster-order list into records.
+hipError_t launch_format_hits(const uint2 *hits, const unsigned long long *frame_offset,
+                              uint64_t n_frames, uint64_t first, uint64_t n, float photon_adu,
+                              HitRecord *out, hipStream_t s);
+
+}  // namespace pdc

@@ -1,0 +1,631 @@
+// Host runtime of libpdc: contexts, resident calibration, batches, buffers and
+// the C ABI declared in include/pdc.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pdc.h"
+#include "pdc_internal.h"
+
+using namespace pdc;
+
+namespace {
+
+thread_local char g_thread_error[512] = "";
+
+// LDS budget of the v1 frame kernel (bytes per workgroup).
+constexpr size_t kV1LdsBudget = 64 * 1024;
+constexpr int kMaxOutstandingBatches = 256;
+
+struct Detector {
+    bool live = false;
+    pdc_geometry g{};
+    pdc_params p{};
+    float t_seed = 0, t_nb = 0;
+    float *d_ped = nullptr;
+    float *d_k = nullptr;
+    // derived launch shape
+    int strip_rows = 0, strips_per_tile = 0, units_per_frame = 0, sort_width = 0, sort_rows = 0;
+    uint32_t max_unit_hits = 0;
+    size_t lds_bytes = 0;
+    int pending = 0;
+    bool release_requested = false;
+};
+
+// Device buffers of one batch; kept by the context and reused.
+struct Buffers {
+    uint64_t cap_units = 0, cap_frames = 0, cap_pool = 0, cap_corr = 0;
+    uint32_t *unit_count = nullptr;
+    unsigned long long *unit_photons = nullptr;
+    uint64_t *unit_base = nullptr;
+    uint32_t *unit_local = nullptr;
+    uint32_t *frame_hits = nullptr;
+    unsigned long long *frame_photons = nullptr;
+    unsigned long long *frame_offset = nullptr;
+    uint2 *pool = nullptr;
+    uint2 *hits = nullptr;
+    float *corrected = nullptr;
+    BatchState *state = nullptr;
+    BatchState *host_state = nullptr;  // pinned mirror
+    hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr;
+};
+
+struct Batch {
+    uint64_t id = 0;
+    int32_t det = -1;
+    const uint16_t *frames = nullptr;
+    uint64_t n_frames = 0;
+    uint64_t n_units = 0;
+    uint64_t pool_cap = 0;
+    hipStream_t stream = nullptr;
+    bool keep = false;
+    bool checked = false;  // overflow handled, totals final
+    Buffers *buf = nullptr;
+};
+
+void free_buffers(Buffers *b)
+{
+    if (!b) return;
+    hipFree(b->unit_count);
+    hipFree(b->unit_photons);
+    hipFree(b->unit_base);
+    hipFree(b->unit_local);
+    hipFree(b->frame_hits);
+    hipFree(b->frame_photons);
+    hipFree(b->frame_offset);
+    hipFree(b->pool);
+    hipFree(b->hits);
+    hipFree(b->corrected);
+    hipFree(b->state);
+    if (b->host_state) hipHostFree(b->host_state);
+    if (b->ev_start) hipEventDestroy(b->ev_start);
+    if (b->ev_main) hipEventDestroy(b->ev_main);
+    if (b->ev_end) hipEventDestroy(b->ev_end);
+    delete b;
+}
+
+}  // namespace
+
+struct pdc_ctx {
+    int device = -1;
+    hipStream_t stream = nullptr;
+    std::vector<Detector> dets;
+    std::map<uint64_t, Batch> batches;
+    std::vector<Buffers *> spare;
+    uint64_t next_batch = 1;
+    std::string err;
+    HitRecord *fmt_buf = nullptr;  // staging for host-destination get_hits
+    uint64_t fmt_cap = 0;
+};
+
+namespace {
+
+pdc_status fail(pdc_ctx *ctx, pdc_status st, const char *fmt, ...)
+{
+    char msg[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(msg, sizeof msg, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = msg;
+    snprintf(g_thread_error, sizeof g_thread_error, "%s", msg);
+    return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (expr);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail((ctx), e_ == hipErrorOutOfMemory ? PDC_ENOMEM : PDC_EDEVICE,         \
+                        "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), __FILE__, __LINE__); \
+    } while (0)
+
+bool finite_in(float x, float lo, float hi) { return std::isfinite(x) && x >= lo && x <= hi; }
+
+pdc_status check_geometry(const pdc_geometry *g)
+{
+    if (!g) return fail(nullptr, PDC_EINVAL, "geometry is NULL");
+    if (g->n_tiles < 1 || g->rows < 1 || g->cols < 1 || g->bank_cols < 1)
+        return fail(nullptr, PDC_EINVAL, "geometry sizes must be >= 1");
+    if (g->cols > 2048 || g->bank_cols > 1024 || g->bank_cols > g->cols)
+        return fail(nullptr, PDC_EINVAL, "cols <= 2048 and bank_cols <= min(cols, 1024) required");
+    if (g->cols % g->bank_cols != 0)
+        return fail(nullptr, PDC_EINVAL, "cols (%d) must be a multiple of bank_cols (%d)", g->cols,
+                    g->bank_cols);
+    if ((int64_t)g->n_tiles * g->rows * g->cols >= (int64_t)1 << 31)
+        return fail(nullptr, PDC_EINVAL, "n_tiles*rows*cols must be < 2^31");
+    if (g->gain_mode != 0) return fail(nullptr, PDC_EINVAL, "gain_mode must be 0");
+    return PDC_OK;
+}
+
+pdc_status check_params(const pdc_params *p, float *t_seed, float *t_nb)
+{
+    if (!p) return fail(nullptr, PDC_EINVAL, "params is NULL");
+    if (!(std::isfinite(p->sigma) && p->sigma > 0.0f)) return fail(nullptr, PDC_EINVAL, "sigma must be finite and > 0");
+    if (!(std::isfinite(p->n_seed) && p->n_seed >= 0.0f && std::isfinite(p->n_nb) && p->n_nb >= 0.0f))
+        return fail(nullptr, PDC_EINVAL, "n_seed and n_nb must be finite and >= 0");
+    volatile float ts = p->n_seed * p->sigma;  // binary32 products
+    volatile float tn = p->n_nb * p->sigma;
+    if (!std::isfinite(ts) || !std::isfinite(tn)) return fail(nullptr, PDC_EINVAL, "thresholds overflow");
+    if (!(tn <= ts)) return fail(nullptr, PDC_EINVAL, "n_nb*sigma must be <= n_seed*sigma");
+    if (!finite_in(p->photon_adu, 0x1p-24f, 0x1p24f))
+        return fail(nullptr, PDC_EINVAL, "photon_adu must be in [2^-24, 2^24]");
+    if (p->flags & ~PDC_KEEP_CORRECTED) return fail(nullptr, PDC_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (t_seed) *t_seed = ts;
+    if (t_nb) *t_nb = tn;
+    return PDC_OK;
+}
+
+pdc_status check_planes(const pdc_geometry *g, const float *ped, const float *gain)
+{
+    if (!ped || !gain) return fail(nullptr, PDC_EINVAL, "pedestal and gain must be non-NULL");
+    const int64_t n = (int64_t)g->n_tiles * g->rows * g->cols;
+    for (int64_t i = 0; i < n; ++i) {
+        float d = ped[i];
+        if (!(std::isfinite(d) && std::fabs(d) <= 0x1p24f && (d == 0.0f || std::fabs(d) >= 0x1p-64f)))
+            return fail(nullptr, PDC_EINVAL, "pedestal[%lld] = %g outside the valid range", (long long)i, (double)d);
+        float k = gain[i];
+        if (!finite_in(k, 0x1p-24f, 0x1p24f))
+            return fail(nullptr, PDC_EINVAL, "gain[%lld] = %g outside [2^-24, 2^24]", (long long)i, (double)k);
+    }
+    return PDC_OK;
+}
+
+int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Launch shape of the v1 kernel for a geometry; false if it does not fit.
+bool plan_v1(Detector &d)
+{
+    const pdc_geometry &g = d.g;
+    int nb = g.cols / g.bank_cols;
+    d.sort_width = next_pow2(g.bank_cols);
+    for (int s = 16; s >= 1; --s) {
+        int sr = std::min(s, g.rows);
+        uint32_t mh = (uint32_t)((sr + 1) / 2) * (uint32_t)((g.cols + 1) / 2);
+        for (int srt = sr + 2; srt >= 1; --srt) {
+            size_t lds = frame_kernel_v1_lds_bytes(sr, g.cols, nb, d.sort_width, srt, mh);
+            if (lds <= kV1LdsBudget) {
+                d.strip_rows = sr;
+                d.sort_rows = srt;
+                d.max_unit_hits = mh;
+                d.lds_bytes = lds;
+                d.strips_per_tile = (g.rows + sr - 1) / sr;
+                d.units_per_frame = g.n_tiles * d.strips_per_tile;
+                // prefer more rows per strip only while the sort still holds a few rows
+                if (srt >= std::min(sr + 2, 4)) return true;
+                break;
+            }
+        }
+    }
+    return d.strip_rows > 0;
+}
+
+template <typename T>
+hipError_t grow(T **ptr, uint64_t &cap, uint64_t need)
+{
+    if (need <= cap && *ptr) return hipSuccess;
+    hipFree(*ptr);
+    *ptr = nullptr;
+    cap = 0;
+    uint64_t n = std::max<uint64_t>(need, 1);
+    hipError_t e = hipMalloc((void **)ptr, n * sizeof(T));
+    if (e == hipSuccess) cap = n;
+    return e;
+}
+
+pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n_frames,
+                          uint64_t pool_cap, uint64_t corr_floats)
+{
+    if (!b->state) {
+        HIP_TRY(ctx, hipMalloc((void **)&b->state, sizeof(BatchState)));
+        HIP_TRY(ctx, hipHostMalloc((void **)&b->host_state, sizeof(BatchState), hipHostMallocDefault));
+        HIP_TRY(ctx, hipEventCreate(&b->ev_start));
+        HIP_TRY(ctx, hipEventCreate(&b->ev_main));
+        HIP_TRY(ctx, hipEventCreate(&b->ev_end));
+    }
+    if (n_units > b->cap_units || !b->unit_count) {
+        uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        HIP_TRY(ctx, grow(&b->unit_count, c0, n_units));
+        HIP_TRY(ctx, grow(&b->unit_photons, c1, n_units));
+        HIP_TRY(ctx, grow(&b->unit_base, c2, n_units));
+        HIP_TRY(ctx, grow(&b->unit_local, c3, n_units));
+        b->cap_units = std::max<uint64_t>(n_units, 1);
+    }
+    if (n_frames > b->cap_frames || !b->frame_hits) {
+        uint64_t c0 = 0, c1 = 0, c2 = 0;
+        HIP_TRY(ctx, grow(&b->frame_hits, c0, n_frames));
+        HIP_TRY(ctx, grow(&b->frame_photons, c1, n_frames));
+        HIP_TRY(ctx, grow(&b->frame_offset, c2, n_frames + 1));
+        b->cap_frames = std::max<uint64_t>(n_frames, 1);
+    }
+    if (pool_cap > b->cap_pool || !b->pool) {
+        uint64_t c0 = 0, c1 = 0;
+        HIP_TRY(ctx, grow(&b->pool, c0, pool_cap));
+        HIP_TRY(ctx, grow(&b->hits, c1, pool_cap));
+        b->cap_pool = std::max<uint64_t>(pool_cap, 1);
+    }
+    if (corr_floats > b->cap_corr) {
+        HIP_TRY(ctx, grow(&b->corrected, b->cap_corr, corr_floats));
+    }
+    return PDC_OK;
+}
+
+uint32_t v1_grid(uint64_t n_units)
+{
+    return (uint32_t)std::min<uint64_t>(n_units, 256 * 8);
+}
+
+uint64_t pool_capacity(const Detector &d, uint64_t hit_capacity, uint32_t grid)
+{
+    // Each workgroup may hold a partly used chunk, and each chunk may leave a
+    // tail smaller than one unit's hits.
+    uint64_t per_chunk_waste = d.max_unit_hits;
+    uint64_t slack = (uint64_t)grid * (kChunkHits + per_chunk_waste) +
+                     (hit_capacity / kChunkHits + 1) * per_chunk_waste;
+    return hit_capacity + slack;
+}
+
+pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
+{
+    Detector &d = ctx->dets[bt.det];
+    Buffers *b = bt.buf;
+    hipStream_t s = bt.stream;
+    const uint32_t grid = v1_grid(bt.n_units);
+    FrameKernelArgs a{};
+    a.frames = bt.frames;
+    a.ped = d.d_ped;
+    a.k = d.d_k;
+    a.n_frames = bt.n_frames;
+    a.n_units = bt.n_units;
+    a.T = d.g.n_tiles;
+    a.H = d.g.rows;
+    a.W = d.g.cols;
+    a.B = d.g.bank_cols;
+    a.nb = d.g.cols / d.g.bank_cols;
+    a.strip_rows = d.strip_rows;
+    a.strips_per_tile = d.strips_per_tile;
+    a.units_per_frame = d.units_per_frame;
+    a.sort_width = d.sort_width;
+    a.sort_rows = d.sort_rows;
+    a.max_unit_hits = d.max_unit_hits;
+    a.t_seed = d.t_seed;
+    a.t_nb = d.t_nb;
+    a.photon_adu = d.p.photon_adu;
+    a.pool = b->pool;
+    a.pool_cap = bt.pool_cap;
+    a.unit_count = b->unit_count;
+    a.unit_photons = b->unit_photons;
+    a.unit_base = b->unit_base;
+    a.state = b->state;
+    a.corrected = bt.keep ? b->corrected : nullptr;
+
+    HIP_TRY(ctx, launch_init_state(b->state, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
+    if (bt.n_units > 0) HIP_TRY(ctx, launch_frame_kernel_v1(a, grid, d.lds_bytes, bt.keep, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
+    HIP_TRY(ctx, launch_frame_sums(b->unit_count, b->unit_photons, bt.n_frames, d.units_per_frame,
+                                   b->unit_local, b->frame_hits, b->frame_photons, s));
+    HIP_TRY(ctx, launch_frame_scan(b->frame_hits, bt.n_frames, b->frame_offset, b->state, s));
+    HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
+                                bt.n_units, d.units_per_frame, b->hits, b->cap_pool, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
+    HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    return PDC_OK;
+}
+
+Batch *find_batch(pdc_ctx *ctx, uint64_t id)
+{
+    auto it = ctx->batches.find(id);
+    return it == ctx->batches.end() ? nullptr : &it->second;
+}
+
+// Wait for a batch; if its staging pool overflowed, run it again with exact
+// capacity so that its hit list is complete.
+pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
+{
+    HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+    if (bt.checked) return PDC_OK;
+    BatchState st = *bt.buf->host_state;
+    if (st.overflow) {
+        Detector &d = ctx->dets[bt.det];
+        uint64_t cap = pool_capacity(d, st.total, v1_grid(bt.n_units));
+        pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
+        if (rc != PDC_OK) return rc;
+        bt.pool_cap = cap;
+        rc = enqueue(ctx, bt);
+        if (rc != PDC_OK) return rc;
+        HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+        if (bt.buf->host_state->overflow)
+            return fail(ctx, PDC_EDEVICE, "staging overflow persisted after resizing");
+    }
+    bt.checked = true;
+    return PDC_OK;
+}
+
+void maybe_free_detector(pdc_ctx *ctx, int32_t det)
+{
+    Detector &d = ctx->dets[det];
+    if (d.live && d.release_requested && d.pending == 0) {
+        hipFree(d.d_ped);
+        hipFree(d.d_k);
+        d = Detector{};
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pdc_strerror(pdc_status s)
+{
+    switch (s) {
+    case PDC_OK: return "ok";
+    case PDC_WARN_TRUNCATED: return "hit list truncated to the destination capacity";
+    case PDC_EINVAL: return "invalid argument";
+    case PDC_ENOMEM: return "out of memory";
+    case PDC_EDEVICE: return "device or HIP runtime error";
+    case PDC_ESTATE: return "invalid state (unknown or released object)";
+    default: return "unknown status";
+    }
+}
+
+const char *pdc_last_error(const pdc_ctx *ctx)
+{
+    if (!ctx) return g_thread_error;
+    return ctx->err.c_str();
+}
+
+pdc_status pdc_create(int32_t device, pdc_ctx **out)
+{
+    if (!out) return fail(nullptr, PDC_EINVAL, "out is NULL");
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(nullptr, PDC_EDEVICE, "no HIP device");
+    if (device < 0 || device >= n) return fail(nullptr, PDC_EDEVICE, "device %d out of range (%d devices)", device, n);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+        return fail(nullptr, PDC_EDEVICE, "hipGetDeviceProperties failed");
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(nullptr, PDC_EDEVICE, "device %d is %s, this library is built for gfx950", device, prop.gcnArchName);
+    pdc_ctx *ctx = new (std::nothrow) pdc_ctx;
+    if (!ctx) return fail(nullptr, PDC_ENOMEM, "host allocation failed");
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return fail(nullptr, PDC_EDEVICE, "stream creation failed");
+    }
+    *out = ctx;
+    return PDC_OK;
+}
+
+pdc_status pdc_destroy(pdc_ctx *ctx)
+{
+    if (!ctx) return PDC_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    for (auto &kv : ctx->batches) free_buffers(kv.second.buf);
+    for (Buffers *b : ctx->spare) free_buffers(b);
+    for (Detector &d : ctx->dets)
+        if (d.live) {
+            hipFree(d.d_ped);
+            hipFree(d.d_k);
+        }
+    hipFree(ctx->fmt_buf);
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return PDC_OK;
+}
+
+pdc_status pdc_check_calibration(const pdc_geometry *geom, const float *pedestal, const float *gain,
+                                 const pdc_params *params)
+{
+    pdc_status rc = check_geometry(geom);
+    if (rc != PDC_OK) return rc;
+    rc = check_params(params, nullptr, nullptr);
+    if (rc != PDC_OK) return rc;
+    rc = check_planes(geom, pedestal, gain);
+    if (rc != PDC_OK) return rc;
+    g_thread_error[0] = 0;
+    return PDC_OK;
+}
+
+pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pedestal,
+                         const float *gain, const pdc_params *params, int32_t *det_out)
+{
+    if (!ctx || !det_out) return fail(ctx, PDC_EINVAL, "ctx and det_out must be non-NULL");
+    pdc_status rc = pdc_check_calibration(geom, pedestal, gain, params);
+    if (rc != PDC_OK) return fail(ctx, rc, "%s", g_thread_error);
+    Detector d;
+    d.g = *geom;
+    d.p = *params;
+    check_params(params, &d.t_seed, &d.t_nb);
+    if (!plan_v1(d)) return fail(ctx, PDC_EINVAL, "geometry does not fit the kernel's on-chip budget");
+    const size_t n = (size_t)geom->n_tiles * geom->rows * geom->cols;
+    std::vector<float> k(n);
+    for (size_t i = 0; i < n; ++i) {
+        volatile float r = 1.0f / gain[i];  // binary32 division
+        k[i] = r;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMalloc((void **)&d.d_ped, n * sizeof(float)));
+    HIP_TRY(ctx, hipMalloc((void **)&d.d_k, n * sizeof(float)));
+    HIP_TRY(ctx, hipMemcpy(d.d_ped, pedestal, n * sizeof(float), hipMemcpyHostToDevice));
+    HIP_TRY(ctx, hipMemcpy(d.d_k, k.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    d.live = true;
+    for (size_t i = 0; i < ctx->dets.size(); ++i)
+        if (!ctx->dets[i].live) {
+            ctx->dets[i] = d;
+            *det_out = (int32_t)i;
+            return PDC_OK;
+        }
+    ctx->dets.push_back(d);
+    *det_out = (int32_t)ctx->dets.size() - 1;
+    return PDC_OK;
+}
+
+pdc_status pdc_release_detector(pdc_ctx *ctx, int32_t det)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    ctx->dets[det].release_requested = true;
+    maybe_free_detector(ctx, det);
+    return PDC_OK;
+}
+
+pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                              uint64_t hit_capacity, void *hip_stream, uint64_t *batch_out)
+{
+    if (!ctx || !batch_out) return fail(ctx, PDC_EINVAL, "ctx and batch_out must be non-NULL");
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    if (n_frames > 0 && !frames_dev) return fail(ctx, PDC_EINVAL, "frames_dev is NULL");
+    if (n_frames > ((uint64_t)1 << 31)) return fail(ctx, PDC_EINVAL, "n_frames must be <= 2^31");
+    if ((int)ctx->batches.size() >= kMaxOutstandingBatches)
+        return fail(ctx, PDC_ESTATE, "too many outstanding batches (release some)");
+    Detector &d = ctx->dets[det];
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Batch bt;
+    bt.id = ctx->next_batch;
+    bt.det = det;
+    bt.frames = frames_dev;
+    bt.n_frames = n_frames;
+    bt.n_units = n_frames * (uint64_t)d.units_per_frame;
+    bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+    bt.pool_cap = pool_capacity(d, hit_capacity, v1_grid(bt.n_units));
+    Buffers *b = nullptr;
+    if (!ctx->spare.empty()) {
+        b = ctx->spare.back();
+        ctx->spare.pop_back();
+    } else {
+        b = new (std::nothrow) Buffers;
+        if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    }
+    const uint64_t corr = bt.keep ? n_frames * (uint64_t)d.g.n_tiles * d.g.rows * d.g.cols : 0;
+    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr);
+    if (rc != PDC_OK) {
+        ctx->spare.push_back(b);
+        return rc;
+    }
+    bt.buf = b;
+    rc = enqueue(ctx, bt);
+    if (rc != PDC_OK) {
+        ctx->spare.push_back(b);
+        return rc;
+    }
+    ++ctx->next_batch;
+    d.pending += 1;
+    ctx->batches[bt.id] = bt;
+    *batch_out = bt.id;
+    return PDC_OK;
+}
+
+pdc_status pdc_get_hits(pdc_ctx *ctx, uint64_t batch, pdc_hit *dst, uint64_t dst_capacity, int32_t dst_is_device,
+                        uint64_t *n_hits_total, uint32_t *per_frame_hits, uint64_t *per_frame_photons)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (dst_capacity > 0 && !dst) return fail(ctx, PDC_EINVAL, "dst is NULL with dst_capacity > 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    Buffers *b = bt->buf;
+    const uint64_t total = b->host_state->total;
+    const float E = ctx->dets[bt->det].p.photon_adu;
+    const uint64_t n_out = std::min<uint64_t>(total, dst_capacity);
+    if (n_out > 0) {
+        if (dst_is_device) {
+            HIP_TRY(ctx, launch_format_hits(b->hits, b->frame_offset, bt->n_frames, 0, n_out, E,
+                                            reinterpret_cast<HitRecord *>(dst), bt->stream));
+        } else {
+            const uint64_t chunk = (uint64_t)1 << 24;
+            if (!ctx->fmt_buf) HIP_TRY(ctx, grow(&ctx->fmt_buf, ctx->fmt_cap, std::min(chunk, n_out)));
+            if (ctx->fmt_cap < std::min(chunk, n_out))
+                HIP_TRY(ctx, grow(&ctx->fmt_buf, ctx->fmt_cap, std::min(chunk, n_out)));
+            for (uint64_t first = 0; first < n_out; first += ctx->fmt_cap) {
+                uint64_t n = std::min(ctx->fmt_cap, n_out - first);
+                HIP_TRY(ctx, launch_format_hits(b->hits, b->frame_offset, bt->n_frames, first, n, E,
+                                                ctx->fmt_buf, bt->stream));
+                HIP_TRY(ctx, hipMemcpyAsync(dst + first, ctx->fmt_buf, n * sizeof(pdc_hit),
+                                            hipMemcpyDeviceToHost, bt->stream));
+                HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+            }
+        }
+    }
+    if (per_frame_hits && bt->n_frames)
+        HIP_TRY(ctx, hipMemcpyAsync(per_frame_hits, b->frame_hits, bt->n_frames * sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, bt->stream));
+    if (per_frame_photons && bt->n_frames)
+        HIP_TRY(ctx, hipMemcpyAsync(per_frame_photons, b->frame_photons, bt->n_frames * sizeof(uint64_t),
+                                    hipMemcpyDeviceToHost, bt->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+    if (n_hits_total) *n_hits_total = total;
+    return total > dst_capacity ? PDC_WARN_TRUNCATED : PDC_OK;
+}
+
+pdc_status pdc_get_corrected(pdc_ctx *ctx, uint64_t batch, float *dst, int32_t dst_is_device)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (!bt->keep) return fail(ctx, PDC_ESTATE, "batch was not processed with PDC_KEEP_CORRECTED");
+    const Detector &d = ctx->dets[bt->det];
+    const uint64_t n = bt->n_frames * (uint64_t)d.g.n_tiles * d.g.rows * d.g.cols;
+    if (n > 0 && !dst) return fail(ctx, PDC_EINVAL, "dst is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    if (n > 0)
+        HIP_TRY(ctx, hipMemcpyAsync(dst, bt->buf->corrected, n * sizeof(float),
+                                    dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                    bt->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+    return PDC_OK;
+}
+
+pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+    int32_t det = bt->det;
+    ctx->spare.push_back(bt->buf);
+    ctx->batches.erase(batch);
+    ctx->dets[det].pending -= 1;
+    maybe_free_detector(ctx, det);
+    return PDC_OK;
+}
+
+pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipEventSynchronize(bt->buf->ev_end));
+    float a = 0, t = 0;
+    HIP_TRY(ctx, hipEventElapsedTime(&a, bt->buf->ev_start, bt->buf->ev_main));
+    HIP_TRY(ctx, hipEventElapsedTime(&t, bt->buf->ev_start, bt->buf->ev_end));
+    if (main_ms) *main_ms = a;
+    if (total_ms) *total_ms = t;
+    return PDC_OK;
+}
+
+}  // extern "C"

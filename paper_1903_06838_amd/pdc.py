@@ -1,0 +1,195 @@
+"""Thin Python binding of libpdc (include/pdc.h): argument marshalling only.
+
+Every function has the C name without the ``pdc_`` prefix and raises
+``PdcError`` on a negative status.  Device memory and streams come from
+PyTorch (``tensor.data_ptr()``, ``stream.cuda_stream``); all computation runs
+in the library's HIP kernels.  There is no fallback: if libpdc.so is missing
+or cannot be loaded, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpdc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libpdc.so is not built (run `python -m paper_1903_06838_amd.build` or "
+                      "__graft_entry__.build()); there is no non-HIP fallback")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK = 0
+WARN_TRUNCATED = 1
+EINVAL = -1
+ENOMEM = -2
+EDEVICE = -3
+ESTATE = -4
+KEEP_CORRECTED = 1
+
+HIT_DTYPE = np.dtype([("frame", "<u4"), ("pixel", "<u4"), ("charge", "<f4"), ("nphot", "<u4")])
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("n_tiles", ctypes.c_int32), ("rows", ctypes.c_int32), ("cols", ctypes.c_int32),
+                ("bank_cols", ctypes.c_int32), ("gain_mode", ctypes.c_int32)]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("sigma", ctypes.c_float), ("n_seed", ctypes.c_float), ("n_nb", ctypes.c_float),
+                ("photon_adu", ctypes.c_float), ("flags", ctypes.c_uint32)]
+
+
+class PdcError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("pdc status %d (%s): %s" % (status, strerror(status), message))
+        self.status = status
+
+
+_P = ctypes.c_void_p
+_st = ctypes.c_int32
+_sig = {
+    "pdc_strerror": (ctypes.c_char_p, [_st]),
+    "pdc_last_error": (ctypes.c_char_p, [_P]),
+    "pdc_create": (_st, [ctypes.c_int32, ctypes.POINTER(_P)]),
+    "pdc_destroy": (_st, [_P]),
+    "pdc_check_calibration": (_st, [ctypes.POINTER(Geometry), _P, _P, ctypes.POINTER(Params)]),
+    "pdc_calibrate": (_st, [_P, ctypes.POINTER(Geometry), _P, _P, ctypes.POINTER(Params),
+                            ctypes.POINTER(ctypes.c_int32)]),
+    "pdc_release_detector": (_st, [_P, ctypes.c_int32]),
+    "pdc_process_frames": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64, _P,
+                                 ctypes.POINTER(ctypes.c_uint64)]),
+    "pdc_get_hits": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.c_int32,
+                           ctypes.POINTER(ctypes.c_uint64), _P, _P]),
+    "pdc_get_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_int32]),
+    "pdc_release_batch": (_st, [_P, ctypes.c_uint64]),
+    "pdc_batch_timing": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
+                               ctypes.POINTER(ctypes.c_float)]),
+}
+for _name, (_res, _args) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+EXPORTED = tuple(_sig)
+
+
+def strerror(status: int) -> str:
+    return _lib.pdc_strerror(status).decode()
+
+
+def last_error(ctx=None) -> str:
+    return (_lib.pdc_last_error(ctx) or b"").decode()
+
+
+def _check(status, ctx=None):
+    if status < 0:
+        raise PdcError(status, last_error(ctx))
+    return status
+
+
+def _ptr(x):
+    """Address of a numpy array, a torch tensor, or an int."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return x.data_ptr()
+
+
+def geometry(n_tiles, rows, cols, bank_cols, gain_mode=0) -> Geometry:
+    return Geometry(n_tiles, rows, cols, bank_cols, gain_mode)
+
+
+def params(sigma=3.0, n_seed=5.0, n_nb=3.0, photon_adu=150.0, flags=0) -> Params:
+    return Params(sigma, n_seed, n_nb, photon_adu, flags)
+
+
+def create(device: int = 0):
+    h = _P()
+    _check(_lib.pdc_create(device, ctypes.byref(h)))
+    return h.value
+
+
+def destroy(ctx) -> None:
+    _check(_lib.pdc_destroy(ctx))
+
+
+def check_calibration(geom: Geometry, pedestal: np.ndarray, gain: np.ndarray, prm: Params) -> int:
+    """Host-only validation; returns the status (0 = accepted) without raising."""
+    ped = np.ascontiguousarray(pedestal, dtype=np.float32)
+    g = np.ascontiguousarray(gain, dtype=np.float32)
+    return _lib.pdc_check_calibration(ctypes.byref(geom), ped.ctypes.data, g.ctypes.data,
+                                      ctypes.byref(prm))
+
+
+def calibrate(ctx, geom: Geometry, pedestal: np.ndarray, gain: np.ndarray, prm: Params) -> int:
+    ped = np.ascontiguousarray(pedestal, dtype=np.float32)
+    g = np.ascontiguousarray(gain, dtype=np.float32)
+    n = geom.n_tiles * geom.rows * geom.cols
+    if ped.size != n or g.size != n:
+        raise ValueError("pedestal/gain must hold n_tiles*rows*cols values")
+    det = ctypes.c_int32(-1)
+    _check(_lib.pdc_calibrate(ctx, ctypes.byref(geom), ped.ctypes.data, g.ctypes.data,
+                              ctypes.byref(prm), ctypes.byref(det)), ctx)
+    return det.value
+
+
+def release_detector(ctx, det: int) -> None:
+    _check(_lib.pdc_release_detector(ctx, det), ctx)
+
+
+def process_frames(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int, stream=None) -> int:
+    """frames_dev: device uint16 tensor (or address); stream: torch stream, raw handle or None."""
+    if stream is not None and not isinstance(stream, int):
+        stream = stream.cuda_stream
+    b = ctypes.c_uint64(0)
+    _check(_lib.pdc_process_frames(ctx, det, _ptr(frames_dev), n_frames, hit_capacity, stream,
+                                   ctypes.byref(b)), ctx)
+    return b.value
+
+
+def get_hits(ctx, batch: int, n_frames: int, capacity: int | None = None, dst_dev=None):
+    """Returns (hits, total, per_frame_hits, per_frame_photons, status).
+
+    Without dst_dev, hits is a host numpy array of HIT_DTYPE; with dst_dev (a
+    device tensor of >= capacity*16 bytes) the records are written there and
+    hits is None."""
+    fh = np.zeros(n_frames, dtype=np.uint32)
+    fp = np.zeros(n_frames, dtype=np.uint64)
+    total = ctypes.c_uint64(0)
+    if capacity is None:
+        # first call: learn the total
+        _check(_lib.pdc_get_hits(ctx, batch, None, 0, 0, ctypes.byref(total), fh.ctypes.data,
+                                 fp.ctypes.data), ctx)
+        capacity = total.value
+    if dst_dev is not None:
+        st = _check(_lib.pdc_get_hits(ctx, batch, _ptr(dst_dev), capacity, 1, ctypes.byref(total),
+                                      fh.ctypes.data, fp.ctypes.data), ctx)
+        return None, total.value, fh, fp, st
+    hits = np.zeros(capacity, dtype=HIT_DTYPE)
+    st = _check(_lib.pdc_get_hits(ctx, batch, hits.ctypes.data if capacity else None, capacity, 0,
+                                  ctypes.byref(total), fh.ctypes.data, fp.ctypes.data), ctx)
+    return hits[:min(capacity, total.value)], total.value, fh, fp, st
+
+
+def get_corrected(ctx, batch: int, dst) -> None:
+    """dst: host float32 numpy array or device float32 tensor of n_frames*T*H*W."""
+    is_dev = 0 if isinstance(dst, np.ndarray) else 1
+    _check(_lib.pdc_get_corrected(ctx, batch, _ptr(dst), is_dev), ctx)
+
+
+def release_batch(ctx, batch: int) -> None:
+    _check(_lib.pdc_release_batch(ctx, batch), ctx)
+
+
+def batch_timing(ctx, batch: int):
+    a = ctypes.c_float(0)
+    t = ctypes.c_float(0)
+    _check(_lib.pdc_batch_timing(ctx, batch, ctypes.byref(a), ctypes.byref(t)), ctx)
+    return a.value, t.value

@@ -1,0 +1,229 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle, bit for bit:
+hit lists (frame, pixel, charge bits, count), per-frame hit counts and photon
+totals, and Frames2 where requested."""
+import numpy as np
+import pytest
+
+from paper_1903_06838_amd import synth
+from tests.helpers import assert_same, hits_u32, oracle_threads, run_pdc
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1903_06838_amd import pdc
+
+    c = pdc.create(0)
+    yield c
+    pdc.destroy(c)
+
+
+def _case(geom, occ, n_frames, cfg_id):
+    ped, gain = synth.make_calibration(geom, cfg_id)
+    raw = synth.make_frames(geom, ped, gain, n_frames, occ, cfg_id)
+    return raw, ped, gain
+
+
+def test_epix100_full_batch(ctx):
+    """ePix100 704x768, 96-pixel banks, 100 frames at 0.01 photons/pixel: every
+    hit, every count and every corrected pixel."""
+    geom = synth.EPIX100
+    raw, ped, gain = _case(geom, 0.01, 100, 0)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    got = run_pdc(ctx, raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    assert want["total"] > 400000
+    assert_same(got, want, corrected=True)
+
+
+RAGGED = [
+    # (T, H, W, B, occupancy, frames)
+    (1, 1, 1, 1, 0.5, 3),
+    (1, 3, 5, 5, 0.3, 2),
+    (3, 17, 40, 8, 0.05, 3),
+    (2, 13, 388, 194, 0.05, 2),
+    (1, 7, 96, 96, 0.1, 4),
+    (4, 30, 64, 32, 0.05, 2),
+    (1, 50, 100, 25, 0.05, 2),
+    (1, 2, 1024, 1024, 0.02, 2),
+    (2, 185, 388, 194, 0.05, 2),
+    (1, 33, 2048, 128, 0.01, 1),
+    (1, 9, 2048, 1, 0.05, 1),
+]
+
+
+@pytest.mark.parametrize("T,H,W,B,occ,n", RAGGED, ids=lambda x: str(x))
+def test_ragged_geometries(ctx, T, H, W, B, occ, n):
+    geom = synth.Geometry(T, H, W, B)
+    raw, ped, gain = _case(geom, occ, n, 100 + T * 7 + H)
+    want = oracle_threads(raw, ped, gain, B, keep_corrected=True)
+    got = run_pdc(ctx, raw, ped, gain, B, keep_corrected=True)
+    assert_same(got, want, corrected=True)
+
+
+def test_adversarial_ties(ctx):
+    """Integer frames with unit gain and integer dark: dense plateaus and exact
+    ties in the median and the local maximum, thresholds hit exactly."""
+    rng = np.random.default_rng(5)
+    T, H, W, B = 2, 24, 60, 12
+    ped = rng.integers(1000, 1010, size=(T, H, W)).astype(np.float32)
+    gain = np.ones((T, H, W), np.float32)
+    raw = (ped[None] + rng.choice([0, 0, 0, 9, 15, 16, 30, 30, 45], size=(5, T, H, W))).astype(np.uint16)
+    for n_nb in (3.0, 0.0, 5.0):
+        want = oracle_threads(raw, ped, gain, B, n_nb=n_nb, keep_corrected=True)
+        got = run_pdc(ctx, raw, ped, gain, B, n_nb=n_nb, keep_corrected=True)
+        assert want["total"] > 100
+        assert_same(got, want, corrected=True)
+
+
+def test_power_of_two_gains_and_gain_bits(ctx):
+    """Gain bits 14-15 set in the raw words are ignored; gains of 2^j."""
+    rng = np.random.default_rng(6)
+    geom = synth.Geometry(1, 20, 96, 48)
+    ped, _ = synth.make_calibration(geom, 3)
+    gain = (2.0 ** rng.integers(-2, 3, size=geom.shape)).astype(np.float32)
+    raw = synth.make_frames(geom, ped, gain, 3, 0.05, 3)
+    raw |= (rng.integers(0, 4, size=raw.shape).astype(np.uint16) << 14)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    got = run_pdc(ctx, raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    assert_same(got, want, corrected=True)
+
+
+def test_empty_batch(ctx):
+    geom = synth.Geometry(1, 8, 16, 8)
+    ped, gain = synth.make_calibration(geom, 1)
+    raw = np.zeros((0, *geom.shape), np.uint16)
+    import torch
+
+    got = run_pdc(ctx, raw, ped, gain, 8, frames_dev=torch.zeros(1, dtype=torch.int16, device="cuda"))
+    assert got["total"] == 0 and len(got["hits"]) == 0
+
+
+def test_dark_frames_no_hits(ctx):
+    """Noise truncated below 2.5 sigma: no pixel exceeds a 5 sigma seed."""
+    rng = np.random.default_rng(8)
+    T, H, W, B = 2, 40, 96, 48
+    ped = rng.normal(1500, 50, size=(T, H, W)).round().astype(np.float32)
+    gain = np.ones((T, H, W), np.float32)
+    noise = np.clip(rng.normal(0, 3, size=(6, T, H, W)), -7.4, 7.4)
+    cm = rng.normal(0, 10, size=(6, T, H, W // B)).repeat(B, axis=3)
+    raw = np.rint(ped[None] + cm + noise).astype(np.uint16)
+    got = run_pdc(ctx, raw, ped, gain, B)
+    assert got["total"] == 0
+
+
+def test_overflow_recompute_and_truncation(ctx):
+    """A hit capacity of 0 forces the staging pool to overflow; the batch is
+    recomputed with exact sizes and still matches.  A small destination gets
+    the first hits in raster order and a truncation status."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(2, 60, 194, 97)
+    raw, ped, gain = _case(geom, 0.08, 6, 9)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols)
+    got = run_pdc(ctx, raw, ped, gain, geom.bank_cols, hit_capacity=0)
+    assert_same(got, want)
+
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
+    frames = torch.from_numpy(raw).cuda()
+    b = pdc.process_frames(ctx, det, frames, raw.shape[0], 0, None)
+    cap = want["total"] // 3
+    hits, total, fh, fp, st = pdc.get_hits(ctx, b, raw.shape[0], capacity=cap)
+    assert st == pdc.WARN_TRUNCATED and total == want["total"] and len(hits) == cap
+    assert np.array_equal(hits_u32(hits), hits_u32(want["hits"][:cap]))
+    # device destination
+    dst = torch.zeros(want["total"] * 4, dtype=torch.int32, device="cuda")
+    _, total2, _, _, st2 = pdc.get_hits(ctx, b, raw.shape[0], capacity=want["total"], dst_dev=dst)
+    assert st2 == pdc.OK and total2 == want["total"]
+    assert np.array_equal(dst.cpu().numpy().view(np.uint32).reshape(-1, 4), hits_u32(want["hits"]))
+    pdc.release_batch(ctx, b)
+    pdc.release_detector(ctx, det)
+
+
+def test_streams_and_determinism(ctx):
+    """Same batch on a side stream, twice: identical; each frame alone gives the
+    same result as inside the batch."""
+    import torch
+
+    geom = synth.Geometry(4, 37, 388, 194)
+    raw, ped, gain = _case(geom, 0.03, 5, 11)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols)
+    s = torch.cuda.Stream()
+    a = run_pdc(ctx, raw, ped, gain, geom.bank_cols, stream=s)
+    b = run_pdc(ctx, raw, ped, gain, geom.bank_cols, stream=s)
+    assert_same(a, want)
+    assert_same(b, want)
+    for i in (0, 3):
+        one = run_pdc(ctx, raw[i:i + 1], ped, gain, geom.bank_cols)
+        mine = want["hits"][want["hits"]["frame"] == i].copy()
+        mine["frame"] = 0
+        assert np.array_equal(hits_u32(one["hits"]), hits_u32(mine))
+
+
+def test_two_detectors_one_context(ctx):
+    from paper_1903_06838_amd import pdc
+    import torch
+
+    g1, g2 = synth.Geometry(1, 64, 192, 96), synth.Geometry(3, 30, 194, 97)
+    r1, p1, k1 = _case(g1, 0.02, 2, 21)
+    r2, p2, k2 = _case(g2, 0.02, 3, 22)
+    d1 = pdc.calibrate(ctx, pdc.geometry(*g1.shape, 96), p1, k1, pdc.params())
+    d2 = pdc.calibrate(ctx, pdc.geometry(*g2.shape, 97), p2, k2, pdc.params(n_seed=4.0))
+    f1, f2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+    b1 = pdc.process_frames(ctx, d1, f1, 2, 10000, None)
+    b2 = pdc.process_frames(ctx, d2, f2, 3, 10000, None)
+    h2 = pdc.get_hits(ctx, b2, 3)
+    h1 = pdc.get_hits(ctx, b1, 2)
+    w1 = oracle_threads(r1, p1, k1, 96)
+    w2 = oracle_threads(r2, p2, k2, 97, n_seed=4.0)
+    assert np.array_equal(hits_u32(h1[0]), hits_u32(w1["hits"]))
+    assert np.array_equal(hits_u32(h2[0]), hits_u32(w2["hits"]))
+    for b in (b1, b2):
+        pdc.release_batch(ctx, b)
+    pdc.release_detector(ctx, d1)
+    pdc.release_detector(ctx, d2)
+
+
+@pytest.mark.parametrize("occ_id", [1])
+def test_cspad_full_batch(ctx, occ_id):
+    """CSPAD-like 32 x 185 x 388, 194-pixel banks, 10,000 frames in one batch
+    (64 distinct frames replicated on the device).  Every frame's counts and
+    photon totals, and every hit, against the oracle's result for its pool
+    frame."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.CSPAD
+    occ = synth.CSPAD_OCCUPANCIES[occ_id]
+    P, N = 64, 10000
+    ped, gain = synth.make_calibration(geom, 1)
+    pool = synth.make_frames(geom, ped, gain, P, occ, 1, occ_id)
+    want = oracle_threads(pool, ped, gain, geom.bank_cols)
+    dpool = torch.from_numpy(pool).cuda()
+    frames = torch.empty((N, *geom.shape), dtype=torch.int16, device="cuda")
+    for i in range(0, N, P):
+        n = min(P, N - i)
+        frames[i:i + n].copy_(dpool[:n])
+    del dpool
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
+    b = pdc.process_frames(ctx, det, frames, N, int(want["total"] * (N / P) * 1.1) + 1, None)
+    hits, total, fh, fp, st = pdc.get_hits(ctx, b, N)
+    pdc.release_batch(ctx, b)
+    pdc.release_detector(ctx, det)
+    del frames
+    idx = np.arange(N) % P
+    assert np.array_equal(fh, want["frame_hits"][idx])
+    assert np.array_equal(fp, want["frame_photons"][idx])
+    assert total == int(want["frame_hits"][idx].sum())
+    # expected list: pool frame hits repeated with their batch frame index
+    starts = np.concatenate([[0], np.cumsum(want["frame_hits"])]).astype(np.int64)
+    sel = np.concatenate([np.arange(starts[j], starts[j + 1]) for j in idx])
+    exp = want["hits"][sel].copy()
+    exp["frame"] = np.repeat(np.arange(N, dtype=np.uint32), want["frame_hits"][idx])
+    assert np.array_equal(hits_u32(hits), hits_u32(exp))
