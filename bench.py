@@ -1,0 +1,335 @@
+"""Throughput benchmark of the detector-correction and photon-finding path.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+One step = one pdc_process_frames call over a device-resident batch of
+10,000 CSPAD-like frames (32 tiles of 185 x 388 uint16, 194-pixel common-mode
+banks, 0.01 photons/pixel): 14-bit decode, dark, gain, bank median, common-mode
+subtraction, seeds, 3x3 local maximum, masked charge sum, photon count and the
+compacted raster-order hit list with per-frame counts and photon totals, all in
+HBM.  pdc_release_batch waits for it.  The batch is 64 distinct synthetic
+frames replicated on the device (45.9 GB, far larger than the on-chip caches).
+
+Printed: ONE JSON line with the throughput (Mpixel/s), the roofline of the
+dominant kernel (algorithmic HBM bytes / its event-timed duration against the
+8 TB/s peak), the CPU oracle's rate on the 64-frame pool (which also checks the
+GPU hits of that pool), single-frame latency percentiles, and an occupancy
+sweep.
+
+Other modes:
+  --profile            short run for rocprofv3 (1 warm-up + --steps batches,
+                       then a plain 2 GiB device copy used to scale counters)
+  --ingest-pmc F W     turn two rocprofv3 --pmc counter CSVs (FETCH_SIZE, then
+                       WRITE_SIZE) of a --profile run into
+                       profiles/frame_kernel_cspad_traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import concurrent.futures as cf
+import csv
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Mpixel/s processed (% of HBM roofline), bit-exact hits; p99 frame latency"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frame_kernel_cspad_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_06838_amd", "csrc", f)
+                  for f in ("pdc_kernels.hip", "pdc_runtime.cpp", "pdc_internal.h")]
+MAIN_KERNEL_PREFIX = "frame_kernel"
+COPY_BYTES = 2 << 30
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# ---------------------------------------------------------------------------
+def make_batch(torch, synth, geom, ped, gain, occ_id, pool_frames, n_frames, dev):
+    occ = synth.CSPAD_OCCUPANCIES[occ_id]
+    t0 = time.time()
+    pool = synth.make_frames(geom, ped, gain, pool_frames, occ, 1, occ_id)
+    dpool = torch.from_numpy(pool).to(dev)
+    frames = torch.empty((n_frames, *geom.shape), dtype=torch.int16, device=dev)
+    for i in range(0, n_frames, pool_frames):
+        n = min(pool_frames, n_frames - i)
+        frames[i:i + n].copy_(dpool[:n])
+    del dpool
+    torch.cuda.synchronize()
+    log("batch occ=%g: %d frames (%d distinct) ready in %.1f s" % (occ, n_frames, pool_frames, time.time() - t0))
+    return pool, frames
+
+
+def run_steps(torch, pdc, ctx, det, frames, n_frames, hit_cap, steps, warmup):
+    """Returns (ms_per_step, main_ms list, total_ms list, hits per batch, per-frame hits)."""
+    stream = torch.cuda.current_stream()
+    b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
+    _, total, fh, fp, _ = pdc.get_hits(ctx, b, n_frames, capacity=0)
+    pdc.release_batch(ctx, b)
+    hit_cap = int(total * 1.02) + 1024
+    for _ in range(warmup):
+        b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
+        pdc.release_batch(ctx, b)
+    mains, totals = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
+        m, t = pdc.batch_timing(ctx, b)
+        mains.append(m)
+        totals.append(t)
+        pdc.release_batch(ctx, b)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) * 1e3 / steps, mains, totals, total, (fh, fp), hit_cap
+
+
+def roofline(n_frames, npix, hits, main_ms):
+    # algorithmic bytes of one launch: 2 B per raw pixel, 8 B per hit
+    # (pixel index + charge), and the two float32 calibration planes once.
+    alg = 2.0 * n_frames * npix + 8.0 * hits + 8.0 * npix
+    avg_s = sum(main_ms) / len(main_ms) / 1e3
+    achieved = alg / avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("n_frames") == n_frames:
+            traffic = tr.get("bytes_per_launch")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+            "kernel": "frame_kernel", "algorithmic_bytes_per_launch": alg,
+            "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+
+def cpu_baseline(pool, ped, gain, bank_cols, gpu_fh, gpu_fp, gpu_hits_fn):
+    """The oracle (test infrastructure) on the 64-frame pool with frame-parallel
+    threads; also checks the GPU's per-frame counts and hit list for the pool."""
+    import numpy as np
+
+    from oracle import oracle
+
+    o = oracle.load()
+    P = pool.shape[0]
+    threads = min(16, os.cpu_count() or 1, P)
+    bounds = np.linspace(0, P, threads + 1).astype(int)
+    parts = [(bounds[i], bounds[i + 1]) for i in range(threads) if bounds[i + 1] > bounds[i]]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(len(parts)) as ex:
+        outs = list(ex.map(lambda ab: o.process(pool[ab[0]:ab[1]], ped, gain, bank_cols), parts))
+    wall = time.perf_counter() - t0
+    fh = np.concatenate([r["frame_hits"] for r in outs])
+    fp = np.concatenate([r["frame_photons"] for r in outs])
+    hits = []
+    for (a, _), r in zip(parts, outs):
+        h = r["hits"].copy()
+        h["frame"] += np.uint32(a)
+        hits.append(h)
+    hits = np.concatenate(hits)
+    idx = np.arange(len(gpu_fh)) % P
+    exact = bool(np.array_equal(gpu_fh, fh[idx]) and np.array_equal(gpu_fp, fp[idx]))
+    g = gpu_hits_fn(int(fh.sum()))
+    exact = exact and g is not None and np.array_equal(
+        np.ascontiguousarray(g).view(np.uint32), np.ascontiguousarray(hits).view(np.uint32))
+    rate = pool.size / wall / 1e6
+    return {"value": round(rate, 2), "unit": "Mpixel/s", "cores": len(parts), "kind": "oracle",
+            "sample": "%d CSPAD-like frames (32x185x388, occupancy 0.01), the distinct frames the "
+                      "10,000-frame GPU batch replicates; %.1f s wall" % (P, wall)}, exact
+
+
+def latency(torch, pdc, ctx, det, frame, calls=300):
+    """Single-frame process_frames + get_hits, host-observed and kernel-only."""
+    import numpy as np
+
+    stream = torch.cuda.current_stream()
+    host, kern = [], []
+    for i in range(calls + 20):
+        t0 = time.perf_counter()
+        b = pdc.process_frames(ctx, det, frame, 1, 1 << 20, stream)
+        pdc.get_hits(ctx, b, 1)
+        t1 = time.perf_counter()
+        _, tk = pdc.batch_timing(ctx, b)
+        pdc.release_batch(ctx, b)
+        if i >= 20:
+            host.append((t1 - t0) * 1e3)
+            kern.append(tk)
+    q = lambda a, p: round(float(np.percentile(a, p)), 4)
+    return {"host_ms_p50": q(host, 50), "host_ms_p99": q(host, 99),
+            "kernel_ms_p50": q(kern, 50), "kernel_ms_p99": q(kern, 99), "calls": calls}
+
+
+# ---------------------------------------------------------------------------
+def ingest_pmc(fetch_csv, write_csv):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the frame kernel, scaled by
+    what the same counters read for the plain 2 GiB copy of a --profile run."""
+    def rows(path, counter):
+        out = []
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = r.get("Kernel_Name") or r.get("Kernel-Name") or ""
+                if r.get("Counter_Name", counter) != counter:
+                    continue
+                out.append((name, float(r["Counter_Value"])))
+        return out
+
+    res = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        rs = rows(path, counter)
+        main = [v for n, v in rs if MAIN_KERNEL_PREFIX in n and "pdc" in n]
+        copy = [v for n, v in rs if "copy" in n.lower() or "elementwise" in n.lower()]
+        copy = [v for v in copy if v > 0.5 * COPY_BYTES / 1024]
+        if not main or not copy:
+            raise SystemExit("no %s rows for the frame kernel or the copy kernel in %s" % (counter, path))
+        kib_main = sorted(main)[len(main) // 2]
+        kib_copy = sorted(copy)[len(copy) // 2]
+        scale = COPY_BYTES / (kib_copy * 1024.0)
+        res[key] = {"kib_per_dispatch": kib_main, "copy_kib": kib_copy, "scale": scale,
+                    "bytes": kib_main * 1024.0 * scale}
+    out = {"kernel_hash": kernel_hash(), "n_frames": 10000,
+           "bytes_per_launch": res["fetch"]["bytes"] + res["write"]["bytes"],
+           "fetch": res["fetch"], "write": res["write"],
+           "note": "FETCH_SIZE and WRITE_SIZE from two rocprofv3 --pmc runs of "
+                   "`python bench.py --profile --steps 2`, each scaled by the counter's "
+                   "reading for a plain 2 GiB device copy in the same run"}
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
+# ---------------------------------------------------------------------------
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--frames", type=int, default=10000)
+    ap.add_argument("--pool", type=int, default=64)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--profile", action="store_true")
+    ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
+    args = ap.parse_args()
+
+    if args.ingest_pmc:
+        ingest_pmc(*args.ingest_pmc)
+        return
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (--gpus 1); frames shard across GPUs "
+              "with no exchange, but multi-GPU runs are not part of it", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1903_06838_amd import pdc, synth
+
+    dev = torch.device("cuda:0")
+    geom = synth.CSPAD
+    npix = geom.pixels
+    ped, gain = synth.make_calibration(geom, 1)
+    ctx = pdc.create(0)
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
+    N = args.frames
+
+    pool, frames = make_batch(torch, synth, geom, ped, gain, 1, args.pool, N, dev)
+    est = int(0.01 * 1.2 * npix * N) + 4096
+    ms, mains, totals, hits, (fh, fp), hit_cap = run_steps(
+        torch, pdc, ctx, det, frames, N, est, args.steps, args.warmup)
+    log("headline: %.3f ms/step, frame kernel %.3f ms, all kernels %.3f ms, %d hits"
+        % (ms, sum(mains) / len(mains), sum(totals) / len(totals), hits))
+
+    if args.profile:
+        src = torch.empty(COPY_BYTES // 2, dtype=torch.int16, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "ms_per_step": ms,
+                          "frame_kernel_ms": sum(mains) / len(mains), "hits": hits}))
+        pdc.destroy(ctx)
+        return
+
+    value = N * npix / (ms / 1e3) / 1e6
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "Mpixel/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "CSPAD-like 32x185x388 uint16, 194-pixel banks, %d frames per "
+                                  "batch (64 distinct, replicated in HBM), occupancy 0.01" % N,
+                      "frames": N, "tiles": 32, "rows": 185, "cols": 388, "bank_cols": 194,
+                      "occupancy": 0.01, "thresholds": "5 sigma seed, 3 sigma neighbours, sigma 3 ADU"},
+           "roofline": roofline(N, npix, hits, mains),
+           "hits_per_step": hits,
+           "all_kernels_ms": round(sum(totals) / len(totals), 4)}
+
+    # stream-copy context: achievable HBM bandwidth of a plain device copy
+    src = torch.empty(COPY_BYTES // 2, dtype=torch.int16, device=dev)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    out["copy_GBps"] = round(5 * 2 * COPY_BYTES / (time.perf_counter() - t0) / 1e9, 1)
+    del src, dst
+
+    if not args.no_cpu:
+        def gpu_pool_hits(n):
+            b = pdc.process_frames(ctx, det, frames, args.pool, n + 1024, torch.cuda.current_stream())
+            h, total, _, _, _ = pdc.get_hits(ctx, b, args.pool)
+            pdc.release_batch(ctx, b)
+            return h if total == n else None
+        cb, exact = cpu_baseline(pool, ped, gain, geom.bank_cols, fh, fp, gpu_pool_hits)
+        out["cpu_baseline"] = cb
+        out["bit_exact_vs_oracle"] = exact
+        log("cpu baseline: %s; GPU bit-exact on the pool: %s" % (cb, exact))
+
+    if not args.no_latency:
+        lat = {"cspad_frame": latency(torch, pdc, ctx, det, frames[:1])}
+        eg = synth.EPIX100
+        eped, egain = synth.make_calibration(eg, 0)
+        edet = pdc.calibrate(ctx, pdc.geometry(*eg.shape, eg.bank_cols), eped, egain, pdc.params())
+        ef = torch.from_numpy(synth.make_frames(eg, eped, egain, 1, 0.01, 0)).to(dev)
+        lat["epix100_frame"] = latency(torch, pdc, ctx, edet, ef)
+        pdc.release_detector(ctx, edet)
+        out["latency"] = lat
+        log("latency: %s" % lat)
+
+    if not args.no_sweep:
+        sweep = [{"occupancy": 0.01, "Mpixel_s": out["value"], "frac": out["roofline"]["frac"],
+                  "hits": hits}]
+        del frames
+        for occ_id in (0, 2):
+            _, fr = make_batch(torch, synth, geom, ped, gain, occ_id, args.pool, N, dev)
+            occ = synth.CSPAD_OCCUPANCIES[occ_id]
+            ms2, m2, _, h2, _, _ = run_steps(torch, pdc, ctx, det, fr, N,
+                                             int(occ * 1.3 * npix * N) + 4096, max(2, args.steps // 3), 1)
+            rf = roofline(N, npix, h2, m2)
+            sweep.append({"occupancy": occ, "Mpixel_s": round(N * npix / (ms2 / 1e3) / 1e6, 1),
+                          "frac": rf["frac"], "hits": h2, "ms_per_step": round(ms2, 4)})
+            del fr
+        out["sweep"] = sorted(sweep, key=lambda s: s["occupancy"])
+    pdc.destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

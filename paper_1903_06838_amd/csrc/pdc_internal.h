@@ -16,7 +16,7 @@ constexpr uint64_t kChunkHits = 8192;
 struct BatchState {
     unsigned long long cursor;    // next free staging slot
     unsigned int overflow;        // 1 if some unit could not be staged
-    unsigned int pad;
+    unsigned int fallback;        // 1 if the fast kernel left some unit to the general kernel
     unsigned long long total;     // total hits of the batch (set by the frame scan)
 };
 
@@ -45,6 +45,38 @@ struct FrameKernelArgs {
     BatchState *state;
     float *corrected;             // Frames2 or nullptr
 };
+
+// Persistent kernel (v2): strips of own rows [r0, r1) of a tile.
+struct V2Strip {
+    int32_t tile, r0, r1, pad;
+};
+
+struct V2Args {
+    const uint16_t *frames;
+    const float *ped;
+    const float *k;
+    uint64_t n_frames;
+    int32_t T, H, W, B, nb;
+    int32_t n_strips;             // strips per frame
+    int32_t n_fgroups;            // frame groups (frames split into contiguous ranges)
+    int32_t rmax;                 // max loaded rows of a strip (own rows + halos)
+    int32_t seed_cap;             // seeds per strip-frame held in LDS
+    const int32_t *wg_item;       // [grid] item = fgroup * n_strips + strip
+    const V2Strip *strips;        // [n_strips], raster order
+    float t_seed, t_nb, photon_adu;
+    float rank_width;             // expected value spacing near a bank median (ADU per rank)
+    uint2 *pool;
+    uint64_t pool_cap;
+    uint32_t *unit_count;
+    unsigned long long *unit_photons;
+    uint64_t *unit_base;
+    BatchState *state;
+    float *corrected;
+};
+
+size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);
+hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
+                                  hipStream_t s);
 
 size_t frame_kernel_v1_lds_bytes(int strip_rows, int W, int nb, int sort_width, int sort_rows,
                                  uint32_t max_unit_hits);

@@ -7,36 +7,19 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include "pdc_device.h"
 #include "pdc_internal.h"
 
 #pragma clang fp contract(off)
 
 namespace pdc {
 
-// Photon counting: division by the single-photon signal, rounded to the
-// nearest integer, ties to even (Photon Charge Summing section).  The quotient
-// is the correctly rounded binary32 division; counts saturate at 2^32 - 1.
-__device__ __forceinline__ uint32_t photon_count(float q, float photon_adu)
-{
-    float x = __fdiv_rn(q, photon_adu);
-    if (x >= 4294967296.0f) return 0xFFFFFFFFu;
-    return (uint32_t)__builtin_rintf(x);
-}
-
-// Frames1 for one pixel (Fig. b): (adc - dark) * (1 / gain), two roundings.
-__device__ __forceinline__ float dark_gain(uint32_t raw, float ped, float k)
-{
-    float a = (float)(raw & 0x3FFFu);
-    float t = __fsub_rn(a, ped);
-    return __fmul_rn(t, k);
-}
-
 __global__ void init_state_kernel(BatchState *st)
 {
     if (threadIdx.x == 0) {
         st->cursor = 0;
         st->overflow = 0;
-        st->pad = 0;
+        st->fallback = 0;
         st->total = 0;
     }
 }

@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -33,10 +34,19 @@ struct Detector {
     float t_seed = 0, t_nb = 0;
     float *d_ped = nullptr;
     float *d_k = nullptr;
-    // derived launch shape
+    // derived launch shape of the general kernel (v1)
     int strip_rows = 0, strips_per_tile = 0, units_per_frame = 0, sort_width = 0, sort_rows = 0;
     uint32_t max_unit_hits = 0;
     size_t lds_bytes = 0;
+    // persistent kernel (v2): resident calibration per strip
+    bool v2_ok = false;
+    int nq = 0, gmax = 0, n_strips = 0, rmax = 0, seed_cap = 0, fg_max = 0;
+    uint32_t v2_max_unit_hits = 0;
+    size_t v2_lds = 0;
+    float rank_width = 0;
+    V2Strip *d_strips = nullptr;
+    int32_t *d_items = nullptr;           // block -> item tables for 1..fg_max frame groups
+    std::vector<uint32_t> item_off;       // offset of the table for g frame groups (index g)
     int pending = 0;
     bool release_requested = false;
 };
@@ -62,6 +72,9 @@ struct Buffers {
 struct Batch {
     uint64_t id = 0;
     int32_t det = -1;
+    int path = 1;            // 1: general kernel, 2: persistent kernel
+    int n_fg = 1;            // frame groups (path 2)
+    int32_t upf = 0;         // units per frame
     const uint16_t *frames = nullptr;
     uint64_t n_frames = 0;
     uint64_t n_units = 0;
@@ -97,6 +110,8 @@ void free_buffers(Buffers *b)
 
 struct pdc_ctx {
     int device = -1;
+    int n_cu = 0;
+    int max_lds = 0;
     hipStream_t stream = nullptr;
     std::vector<Detector> dets;
     std::map<uint64_t, Batch> batches;
@@ -105,6 +120,7 @@ struct pdc_ctx {
     std::string err;
     HitRecord *fmt_buf = nullptr;  // staging for host-destination get_hits
     uint64_t fmt_cap = 0;
+    bool force_v1 = false;         // PDC_FORCE_GENERAL=1 in the environment
 };
 
 namespace {
@@ -214,6 +230,75 @@ bool plan_v1(Detector &d)
     return d.strip_rows > 0;
 }
 
+// Plan of the persistent kernel: strips of at most rmax loaded rows, as many
+// strips x frame groups as there are compute units; false if the geometry is
+// outside its fast path (odd widths, banks wider than 256, or too little LDS).
+bool plan_v2(pdc_ctx *ctx, Detector &d)
+{
+    const pdc_geometry &g = d.g;
+    d.v2_ok = false;
+    if (g.gain_mode != 0 || (g.cols & 1) || (g.bank_cols & 1) || g.bank_cols > 256 || g.bank_cols < 2)
+        return false;
+    const int nb = g.cols / g.bank_cols;
+    d.nq = g.bank_cols > 128 ? 2 : 1;
+    d.gmax = d.nq == 2 ? 7 : 16;
+    const int max_bank_rows = 8 * d.gmax;
+    const int rmax_lim = max_bank_rows / nb;
+    if (rmax_lim < 3) return false;
+    const int own_max = rmax_lim - 2;
+    int n_st = (g.rows + own_max - 1) / own_max;
+    // more strips per tile only while all strips still fit on the chip at once
+    while ((int64_t)g.n_tiles * (n_st + 1) <= ctx->n_cu && (g.rows + n_st) / (n_st + 1) >= 8 &&
+           (int64_t)g.n_tiles * n_st * 2 <= ctx->n_cu && false)
+        ++n_st;
+    if (n_st > g.rows) n_st = g.rows;
+    std::vector<V2Strip> strips;
+    int rmax = 0, own_rows_max = 0;
+    for (int t = 0; t < g.n_tiles; ++t)
+        for (int j = 0; j < n_st; ++j) {
+            int r0 = (int)((int64_t)g.rows * j / n_st), r1 = (int)((int64_t)g.rows * (j + 1) / n_st);
+            if (r1 <= r0) continue;
+            strips.push_back(V2Strip{t, r0, r1, 0});
+            int lr0 = std::max(r0 - 1, 0), lr1 = std::min(r1 + 1, g.rows);
+            rmax = std::max(rmax, lr1 - lr0);
+            own_rows_max = std::max(own_rows_max, r1 - r0);
+        }
+    if (rmax * nb > max_bank_rows) return false;
+    d.n_strips = (int)strips.size();
+    d.rmax = rmax;
+    d.v2_max_unit_hits = (uint32_t)((own_rows_max + 1) / 2) * (uint32_t)((g.cols + 1) / 2);
+    // seed list: as large as the LDS allows up to 96 KB per workgroup (which also
+    // keeps one workgroup per compute unit), at least 1024 entries
+    const size_t lds_cap = std::min<size_t>((size_t)ctx->max_lds, 96 * 1024);
+    size_t base = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, 0);
+    if (base + 4 * 4 * 1024 > lds_cap) return false;
+    d.seed_cap = (int)std::min<size_t>((lds_cap - base) / 16, 16384);
+    d.v2_lds = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, d.seed_cap);
+    d.fg_max = std::max(1, ctx->n_cu / d.n_strips);
+    d.rank_width = d.p.sigma / (0.4f * (float)g.bank_cols);
+    // block -> item tables: items (fg, strip) in raster order are split into
+    // contiguous runs per XCD (blocks are dealt to the 8 XCDs round-robin), so
+    // neighbouring strips, which share halo rows, share an L2.
+    std::vector<int32_t> items;
+    d.item_off.assign(d.fg_max + 1, 0);
+    for (int nfg = 1; nfg <= d.fg_max; ++nfg) {
+        d.item_off[nfg] = (uint32_t)items.size();
+        const int n = nfg * d.n_strips;
+        std::vector<int32_t> tab(n);
+        int next = 0;
+        for (int x = 0; x < 8; ++x)
+            for (int b = x; b < n; b += 8) tab[b] = next++;
+        items.insert(items.end(), tab.begin(), tab.end());
+    }
+    if (hipMalloc((void **)&d.d_strips, strips.size() * sizeof(V2Strip)) != hipSuccess) return false;
+    if (hipMalloc((void **)&d.d_items, items.size() * sizeof(int32_t)) != hipSuccess) return false;
+    if (hipMemcpy(d.d_strips, strips.data(), strips.size() * sizeof(V2Strip), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(d.d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+        return false;
+    d.v2_ok = true;
+    return true;
+}
+
 template <typename T>
 hipError_t grow(T **ptr, uint64_t &cap, uint64_t need)
 {
@@ -269,14 +354,19 @@ uint32_t v1_grid(uint64_t n_units)
     return (uint32_t)std::min<uint64_t>(n_units, 256 * 8);
 }
 
-uint64_t pool_capacity(const Detector &d, uint64_t hit_capacity, uint32_t grid)
+uint64_t pool_capacity(const Detector &d, int path, uint64_t hit_capacity, uint32_t grid)
 {
     // Each workgroup may hold a partly used chunk, and each chunk may leave a
     // tail smaller than one unit's hits.
-    uint64_t per_chunk_waste = d.max_unit_hits;
+    uint64_t per_chunk_waste = path == 2 ? d.v2_max_unit_hits : d.max_unit_hits;
     uint64_t slack = (uint64_t)grid * (kChunkHits + per_chunk_waste) +
                      (hit_capacity / kChunkHits + 1) * per_chunk_waste;
     return hit_capacity + slack;
+}
+
+uint32_t batch_grid(const Detector &d, const Batch &bt)
+{
+    return bt.path == 2 ? (uint32_t)(bt.n_fg * d.n_strips) : v1_grid(bt.n_units);
 }
 
 pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
@@ -284,47 +374,90 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     Detector &d = ctx->dets[bt.det];
     Buffers *b = bt.buf;
     hipStream_t s = bt.stream;
-    const uint32_t grid = v1_grid(bt.n_units);
-    FrameKernelArgs a{};
-    a.frames = bt.frames;
-    a.ped = d.d_ped;
-    a.k = d.d_k;
-    a.n_frames = bt.n_frames;
-    a.n_units = bt.n_units;
-    a.T = d.g.n_tiles;
-    a.H = d.g.rows;
-    a.W = d.g.cols;
-    a.B = d.g.bank_cols;
-    a.nb = d.g.cols / d.g.bank_cols;
-    a.strip_rows = d.strip_rows;
-    a.strips_per_tile = d.strips_per_tile;
-    a.units_per_frame = d.units_per_frame;
-    a.sort_width = d.sort_width;
-    a.sort_rows = d.sort_rows;
-    a.max_unit_hits = d.max_unit_hits;
-    a.t_seed = d.t_seed;
-    a.t_nb = d.t_nb;
-    a.photon_adu = d.p.photon_adu;
-    a.pool = b->pool;
-    a.pool_cap = bt.pool_cap;
-    a.unit_count = b->unit_count;
-    a.unit_photons = b->unit_photons;
-    a.unit_base = b->unit_base;
-    a.state = b->state;
-    a.corrected = bt.keep ? b->corrected : nullptr;
-
     HIP_TRY(ctx, launch_init_state(b->state, s));
     HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
-    if (bt.n_units > 0) HIP_TRY(ctx, launch_frame_kernel_v1(a, grid, d.lds_bytes, bt.keep, s));
+    if (bt.n_units > 0 && bt.path == 2) {
+        V2Args a{};
+        a.frames = bt.frames;
+        a.ped = d.d_ped;
+        a.k = d.d_k;
+        a.n_frames = bt.n_frames;
+        a.T = d.g.n_tiles;
+        a.H = d.g.rows;
+        a.W = d.g.cols;
+        a.B = d.g.bank_cols;
+        a.nb = d.g.cols / d.g.bank_cols;
+        a.n_strips = d.n_strips;
+        a.n_fgroups = bt.n_fg;
+        a.rmax = d.rmax;
+        a.seed_cap = d.seed_cap;
+        a.wg_item = d.d_items + d.item_off[bt.n_fg];
+        a.strips = d.d_strips;
+        a.t_seed = d.t_seed;
+        a.t_nb = d.t_nb;
+        a.photon_adu = d.p.photon_adu;
+        a.rank_width = d.rank_width;
+        a.pool = b->pool;
+        a.pool_cap = bt.pool_cap;
+        a.unit_count = b->unit_count;
+        a.unit_photons = b->unit_photons;
+        a.unit_base = b->unit_base;
+        a.state = b->state;
+        a.corrected = bt.keep ? b->corrected : nullptr;
+        HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
+    } else if (bt.n_units > 0) {
+        FrameKernelArgs a{};
+        a.frames = bt.frames;
+        a.ped = d.d_ped;
+        a.k = d.d_k;
+        a.n_frames = bt.n_frames;
+        a.n_units = bt.n_units;
+        a.T = d.g.n_tiles;
+        a.H = d.g.rows;
+        a.W = d.g.cols;
+        a.B = d.g.bank_cols;
+        a.nb = d.g.cols / d.g.bank_cols;
+        a.strip_rows = d.strip_rows;
+        a.strips_per_tile = d.strips_per_tile;
+        a.units_per_frame = d.units_per_frame;
+        a.sort_width = d.sort_width;
+        a.sort_rows = d.sort_rows;
+        a.max_unit_hits = d.max_unit_hits;
+        a.t_seed = d.t_seed;
+        a.t_nb = d.t_nb;
+        a.photon_adu = d.p.photon_adu;
+        a.pool = b->pool;
+        a.pool_cap = bt.pool_cap;
+        a.unit_count = b->unit_count;
+        a.unit_photons = b->unit_photons;
+        a.unit_base = b->unit_base;
+        a.state = b->state;
+        a.corrected = bt.keep ? b->corrected : nullptr;
+        HIP_TRY(ctx, launch_frame_kernel_v1(a, batch_grid(d, bt), d.lds_bytes, bt.keep, s));
+    }
     HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
-    HIP_TRY(ctx, launch_frame_sums(b->unit_count, b->unit_photons, bt.n_frames, d.units_per_frame,
+    HIP_TRY(ctx, launch_frame_sums(b->unit_count, b->unit_photons, bt.n_frames, bt.upf,
                                    b->unit_local, b->frame_hits, b->frame_photons, s));
     HIP_TRY(ctx, launch_frame_scan(b->frame_hits, bt.n_frames, b->frame_offset, b->state, s));
     HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
-                                bt.n_units, d.units_per_frame, b->hits, b->cap_pool, s));
+                                bt.n_units, bt.upf, b->hits, b->cap_pool, s));
     HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
     HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
     return PDC_OK;
+}
+
+// Choose the kernel for a batch and size its unit arrays.
+void set_path(const Detector &d, Batch &bt, int path)
+{
+    bt.path = path;
+    if (path == 2) {
+        bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)d.fg_max, bt.n_frames));
+        bt.upf = d.n_strips;
+    } else {
+        bt.n_fg = 1;
+        bt.upf = d.units_per_frame;
+    }
+    bt.n_units = bt.n_frames * (uint64_t)bt.upf;
 }
 
 Batch *find_batch(pdc_ctx *ctx, uint64_t id)
@@ -340,9 +473,23 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
     HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
     if (bt.checked) return PDC_OK;
     BatchState st = *bt.buf->host_state;
+    if (st.fallback) {
+        // some strip-frame had more seed pixels than the fast kernel holds on
+        // chip: recompute the whole batch with the general kernel
+        Detector &d = ctx->dets[bt.det];
+        set_path(d, bt, 1);
+        uint64_t cap = pool_capacity(d, 1, st.total, batch_grid(d, bt));
+        pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
+        if (rc != PDC_OK) return rc;
+        bt.pool_cap = cap;
+        rc = enqueue(ctx, bt);
+        if (rc != PDC_OK) return rc;
+        HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+        st = *bt.buf->host_state;
+    }
     if (st.overflow) {
         Detector &d = ctx->dets[bt.det];
-        uint64_t cap = pool_capacity(d, st.total, v1_grid(bt.n_units));
+        uint64_t cap = pool_capacity(d, bt.path, st.total, batch_grid(d, bt));
         pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
         if (rc != PDC_OK) return rc;
         bt.pool_cap = cap;
@@ -362,6 +509,8 @@ void maybe_free_detector(pdc_ctx *ctx, int32_t det)
     if (d.live && d.release_requested && d.pending == 0) {
         hipFree(d.d_ped);
         hipFree(d.d_k);
+        hipFree(d.d_strips);
+        hipFree(d.d_items);
         d = Detector{};
     }
 }
@@ -403,6 +552,16 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
     pdc_ctx *ctx = new (std::nothrow) pdc_ctx;
     if (!ctx) return fail(nullptr, PDC_ENOMEM, "host allocation failed");
     ctx->device = device;
+    ctx->n_cu = prop.multiProcessorCount;
+    {
+        const char *fv = std::getenv("PDC_FORCE_GENERAL");
+        ctx->force_v1 = fv && fv[0] == '1';
+    }
+    {
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
+        ctx->max_lds = lds;
+    }
     if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
         delete ctx;
         return fail(nullptr, PDC_EDEVICE, "stream creation failed");
@@ -422,6 +581,8 @@ pdc_status pdc_destroy(pdc_ctx *ctx)
         if (d.live) {
             hipFree(d.d_ped);
             hipFree(d.d_k);
+            hipFree(d.d_strips);
+            hipFree(d.d_items);
         }
     hipFree(ctx->fmt_buf);
     hipStreamDestroy(ctx->stream);
@@ -464,6 +625,7 @@ pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pe
     HIP_TRY(ctx, hipMalloc((void **)&d.d_k, n * sizeof(float)));
     HIP_TRY(ctx, hipMemcpy(d.d_ped, pedestal, n * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(d.d_k, k.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    if (!ctx->force_v1) plan_v2(ctx, d);
     d.live = true;
     for (size_t i = 0; i < ctx->dets.size(); ++i)
         if (!ctx->dets[i].live) {
@@ -503,10 +665,10 @@ pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_
     bt.det = det;
     bt.frames = frames_dev;
     bt.n_frames = n_frames;
-    bt.n_units = n_frames * (uint64_t)d.units_per_frame;
+    set_path(d, bt, d.v2_ok ? 2 : 1);
     bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
-    bt.pool_cap = pool_capacity(d, hit_capacity, v1_grid(bt.n_units));
+    bt.pool_cap = pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
     Buffers *b = nullptr;
     if (!ctx->spare.empty()) {
         b = ctx->spare.back();

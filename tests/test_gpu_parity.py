@@ -227,3 +227,61 @@ def test_cspad_full_batch(ctx, occ_id):
     exp = want["hits"][sel].copy()
     exp["frame"] = np.repeat(np.arange(N, dtype=np.uint32), want["frame_hits"][idx])
     assert np.array_equal(hits_u32(hits), hits_u32(exp))
+
+
+@pytest.fixture(scope="module")
+def ctx_general():
+    """A context whose batches all take the general kernel (PDC_FORCE_GENERAL=1)."""
+    import os
+
+    from paper_1903_06838_amd import pdc
+
+    os.environ["PDC_FORCE_GENERAL"] = "1"
+    try:
+        c = pdc.create(0)
+    finally:
+        del os.environ["PDC_FORCE_GENERAL"]
+    yield c
+    pdc.destroy(c)
+
+
+@pytest.mark.parametrize("geom", [synth.Geometry(2, 50, 388, 194), synth.Geometry(1, 64, 768, 96),
+                                  synth.Geometry(3, 21, 256, 128), synth.Geometry(1, 40, 512, 256)],
+                         ids=lambda g: "%dx%dx%d_B%d" % (g.n_tiles, g.rows, g.cols, g.bank_cols))
+def test_general_and_persistent_kernels_agree(ctx, ctx_general, geom):
+    """The same batch through the persistent kernel and the general kernel:
+    both equal the oracle, corrected frames included."""
+    raw, ped, gain = _case(geom, 0.03, 4, 31)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    assert_same(run_pdc(ctx, raw, ped, gain, geom.bank_cols, keep_corrected=True), want, corrected=True)
+    assert_same(run_pdc(ctx_general, raw, ped, gain, geom.bank_cols, keep_corrected=True), want, corrected=True)
+
+
+def test_flood_frame_falls_back_exactly(ctx):
+    """A frame where a third of the pixels carry photons has more seed pixels per
+    strip than the persistent kernel holds on chip; the batch is recomputed by
+    the general kernel and still matches."""
+    geom = synth.Geometry(2, 60, 388, 194)
+    ped, gain = synth.make_calibration(geom, 41)
+    raw = synth.make_frames(geom, ped, gain, 2, 0.4, 41)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols)
+    assert want["total"] > 1000
+    assert_same(run_pdc(ctx, raw, ped, gain, geom.bank_cols), want)
+
+
+def test_median_with_outliers_and_plateaus(ctx):
+    """Banks whose median sits on a long run of equal values, banks with far
+    outliers on one side, and banks of identical values."""
+    rng = np.random.default_rng(12)
+    T, H, W, B = 1, 24, 388, 194
+    ped = np.full((T, H, W), 1000.0, np.float32)
+    gain = np.ones((T, H, W), np.float32)
+    raw = np.full((3, T, H, W), 1000, np.int64)
+    raw[0, 0, :8] += rng.integers(0, 3, size=(8, W))            # plateaus of 0/1/2
+    raw[0, 0, 8:16] += rng.integers(0, 2, size=(8, W)) * 9000   # two far clusters
+    raw[1, 0, :, :97] += 15000 - 1000                            # one side saturates
+    raw[2] += rng.integers(-3, 4, size=(T, H, W))
+    raw[2, 0, 5, 10:20] += 300
+    raw = np.clip(raw, 0, 16383).astype(np.uint16)
+    want = oracle_threads(raw, ped, gain, B, keep_corrected=True)
+    assert_same(run_pdc(ctx, raw, ped, gain, B, keep_corrected=True), want, corrected=True)
