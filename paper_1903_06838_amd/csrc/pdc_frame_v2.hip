@@ -29,123 +29,167 @@
 
 namespace pdc {
 
-constexpr int kV2Waves = 8;
+constexpr int kV2Waves = 16;
 constexpr int kV2Threads = kV2Waves * 64;
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
-// Sum over the 64 lanes of a wave (every lane gets the total).
+__device__ __forceinline__ float uniform_f(float x)
+{
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
+}
+
+// Sum over the 64 lanes of a wave, wave-uniform result (DPP reduction; the
+// summation order is fixed but it only feeds a search heuristic).
 __device__ __forceinline__ float wave_sum(float x)
 {
-    for (int d = 32; d >= 1; d >>= 1) x += __shfl_xor(x, d, 64);
-    return x;
+    int v = __float_as_int(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
+    v = __float_as_int(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
+    v = __float_as_int(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false)); // row_half_mirror
+    v = __float_as_int(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false)); // row_mirror
+    v = __float_as_int(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false)); // row_bcast15
+    v = __float_as_int(x);
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false)); // row_bcast31
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
 }
 
 // Smallest binary32 value th such that fl(th - m) > t (fl(x - m) is
-// monotone in x, so fl(u - m) > t  <=>  u >= th).
+// monotone in x, so fl(u - m) > t  <=>  u >= th).  Wave-uniform.
 __device__ __forceinline__ float seed_threshold(float m, float t)
 {
-    float th = __fadd_rn(m, t);
-    for (int i = 0; i < 64 && !(__fsub_rn(th, m) > t); ++i) th = key2f(f2key(th) + 1);
+    float th = uniform_f(__fadd_rn(m, t));
+    for (int i = 0; i < 64 && !(__fsub_rn(th, m) > t); ++i) th = uniform_f(key2f(f2key(th) + 1));
     for (int i = 0; i < 64; ++i) {
-        float d = key2f(f2key(th) - 1);
+        float d = uniform_f(key2f(f2key(th) - 1));
         if (__fsub_rn(d, m) > t) th = d;
         else break;
     }
     return th;
 }
 
-// Exact element of rank k (0-based, ascending) of the NV*64 lane values x
-// (absent values are +inf; n_valid finite values).  Wave-uniform result.
-// Invariant of the search: count(x < lo) <= k < count(x < hi).
 template <int NV>
-__device__ float bank_select(const float (&x)[NV], int n_valid, int k, float est, float rank_width)
+__device__ __forceinline__ int count_below(const float (&x)[NV], float p)
 {
-    float lo = -INFINITY, hi = INFINITY;
-    int clo = 0, chi = n_valid;
-    uint64_t mlo[NV], mhi[NV];
+    int c = 0;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        mlo[v] = 0;
-        mhi[v] = ballot(x[v] < INFINITY);
+    for (int v = 0; v < NV; ++v) c += popc64(ballot(x[v] < p));
+    return c;
+}
+
+// Wave-uniform minimum (max_mode false) or maximum of the lanes' values.
+__device__ __forceinline__ float wave_minmax(float x, bool max_mode)
+{
+    int v = __float_as_int(x);
+#define PDC_MM(ctrl, rm)                                                                          \
+    {                                                                                             \
+        float o = __int_as_float(__builtin_amdgcn_update_dpp(v, v, ctrl, rm, 0xF, false));        \
+        x = max_mode ? fmaxf(x, o) : fminf(x, o);                                                 \
+        v = __float_as_int(x);                                                                    \
     }
-    float p = est;
+    PDC_MM(0xB1, 0xF)
+    PDC_MM(0x4E, 0xF)
+    PDC_MM(0x141, 0xF)
+    PDC_MM(0x140, 0xF)
+    PDC_MM(0x142, 0xA)
+    PDC_MM(0x143, 0xC)
+#undef PDC_MM
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+}
+
+// Exact element of rank k (0-based, ascending) among the n_valid finite lane
+// values of x (absent values are +inf).  Bracketing search on counts:
+// count(x < lo) <= k < count(x < hi) holds throughout.  The first pass tests
+// est - w and est + w together; later passes interpolate a pivot from the
+// bracket counts (bisecting in key space when interpolation stalls).  Once at
+// most two values remain in [lo, hi), the answer is the smallest value >= lo
+// (if it has rank k) or the largest value < hi.
+template <int NV>
+__device__ float bank_median(const float (&x)[NV], int n_valid, int k, float est, float w)
+{
+    float lo = uniform_f(est - w), hi = uniform_f(est + w);
+    int clo = count_below<NV>(x, lo), chi = count_below<NV>(x, hi);
+    // widen until bracketed (rare): each widening doubles the step
+    for (int i = 0; i < 40 && !(clo <= k && k < chi); ++i) {
+        w = w + w;
+        if (clo > k) {
+            hi = lo;
+            chi = clo;
+            lo = uniform_f(i < 38 ? est - w : -INFINITY);
+            clo = i < 38 ? count_below<NV>(x, lo) : 0;
+        } else {
+            lo = hi;
+            clo = chi;
+            hi = uniform_f(i < 38 ? est + w : INFINITY);
+            chi = i < 38 ? count_below<NV>(x, hi) : n_valid;
+        }
+    }
     int last_n = n_valid;
     bool bisect = false;
-    int expand = 0;
-    for (int it = 0; it < 256; ++it) {
-        uint64_t mp[NV];
-        int c = 0;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            mp[v] = ballot(x[v] < p);
-            c += popc64(mp[v]);
-        }
-        if (c <= k) {
-            lo = p;
-            clo = c;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) mlo[v] = mp[v];
-        } else {
-            hi = p;
-            chi = c;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) mhi[v] = mp[v];
-        }
+    for (int it = 0; it < 200; ++it) {
         const int n = chi - clo;
-        if (n == 1) {
-            // the single element in [lo, hi) has rank k
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                uint64_t m = mhi[v] & ~mlo[v];
-                if (m) return __shfl(x[v], (int)(__ffsll((unsigned long long)m) - 1), 64);
-            }
-        }
-        const bool lo_f = lo > -INFINITY, hi_f = hi < INFINITY;
-        if (lo_f && hi_f && f2key(hi) - f2key(lo) == 1) return lo;  // [lo, hi) holds only lo
-        if (!(lo_f && hi_f)) {
-            // one side open: step by the expected rank distance, growing
-            ++expand;
-            float d = (float)(k - c) + 0.5f;
-            float step = d * rank_width * (float)(1 << min(2 * (expand - 1), 24));
-            float q = __fadd_rn(p, step);
-            if (expand > 3) {
-                // far outliers: take the extreme element as the open bound
-                if (!lo_f) {
-                    float mn = INFINITY;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) mn = fminf(mn, x[v]);
-                    for (int d2 = 32; d2 >= 1; d2 >>= 1) mn = fminf(mn, __shfl_xor(mn, d2, 64));
-                    q = mn;  // count(x < min) = 0 <= k
-                } else {
-                    float mx = -INFINITY;
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) mx = x[v] < INFINITY ? fmaxf(mx, x[v]) : mx;
-                    for (int d2 = 32; d2 >= 1; d2 >>= 1) mx = fmaxf(mx, __shfl_xor(mx, d2, 64));
-                    q = key2f(f2key(mx) + 1);  // count(x < next(max)) = n_valid > k
-                }
-            }
-            if (lo_f && !(q > lo)) q = key2f(f2key(lo) + 1);
-            if (hi_f && !(q < hi)) q = key2f(f2key(hi) - 1);
-            p = q;
-            continue;
-        }
+        if (n <= 2) break;
+        const int32_t klo = f2key(lo), khi = f2key(hi);
+        if ((int64_t)khi - (int64_t)klo <= 1) return lo;  // [lo, hi) holds only the value lo
         float q;
-        if (bisect) {
-            q = key2f((int32_t)(((int64_t)f2key(lo) + (int64_t)f2key(hi)) >> 1));
+        if (bisect || !(lo > -INFINITY && hi < INFINITY)) {
+            q = key2f((int32_t)(((int64_t)klo + (int64_t)khi) >> 1));
             bisect = false;
         } else {
-            float frac = ((float)(k - clo) + 0.5f) / (float)n;
+            const float frac = ((float)(k - clo) + 0.5f) * __builtin_amdgcn_rcpf((float)n);
             q = lo + (hi - lo) * frac;
-            if (n * 2 > last_n) bisect = true;
+            bisect = n * 2 > last_n;
+            if (!(q > lo && q < hi)) q = key2f((int32_t)(((int64_t)klo + (int64_t)khi) >> 1));
         }
-        if (!(q > lo && q < hi)) q = key2f((int32_t)(((int64_t)f2key(lo) + (int64_t)f2key(hi)) >> 1));
+        q = uniform_f(q);
         last_n = n;
-        p = q;
+        const int c = count_below<NV>(x, q);
+        if (c <= k) {
+            lo = q;
+            clo = c;
+        } else {
+            hi = q;
+            chi = c;
+        }
     }
-    return lo;  // not reached for finite inputs
+    float r;
+    if (k == clo) {
+        r = INFINITY;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r = fminf(r, x[v] >= lo ? x[v] : INFINITY);
+        r = wave_minmax(r, false);
+    } else {
+        r = -INFINITY;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) r = fmaxf(r, x[v] < hi ? x[v] : -INFINITY);
+        r = wave_minmax(r, true);
+    }
+    return r;
+}
+
+// Mean over lanes of the median of three of the lane's values: a start point
+// for the search.
+template <int NV>
+__device__ __forceinline__ float median_estimate(const float (&x)[NV])
+{
+    float m3;
+    if (NV >= 3) {
+        const float c = x[2] < INFINITY ? x[2] : x[0];
+        m3 = __builtin_amdgcn_fmed3f(x[0], x[1], c);
+    } else {
+        const float c = __shfl_xor(x[0], 1, 64);
+        m3 = __builtin_amdgcn_fmed3f(x[0], x[1], c < INFINITY ? c : x[0]);
+    }
+    const bool lv = x[0] < INFINITY;
+    const float sum = wave_sum(lv ? m3 : 0.0f);
+    const int nl = popc64(ballot(lv));
+    return uniform_f(sum * __builtin_amdgcn_rcpf((float)nl));
 }
 
 struct V2Layout {
@@ -221,28 +265,34 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const int kmed = (B - 1) / 2;
     const uint32_t row_base = ((uint32_t)t * H + lr0) * (uint32_t)W;  // pixel index of loaded row 0
 
-    // pixel offset (from row_base) of bank-row g's first column, wave-uniform
-    auto gbase = [&](int g) -> uint32_t {
-        const int i = wave + kV2Waves * g;
-        return (uint32_t)(i / nb) * W + (uint32_t)(i - (i / nb) * nb) * B;
-    };
     // lane l of pair-slot q holds bank columns 128q + 2l and 128q + 2l + 1
     bool lane_ok[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) lane_ok[q] = 128 * q + 2 * lane < B;
     const uint32_t lane_off = 2u * lane;
+    // this wave's bank-rows g < ng: bank-row index i = wave + 8g, its local row
+    // and its first pixel (offset from row_base), all wave-uniform
+    const int ng = BR > wave ? min(GMAX, (BR - wave + kV2Waves - 1) / kV2Waves) : 0;
+    int row_[GMAX];
+    uint32_t gb_[GMAX];
+#pragma unroll
+    for (int g = 0; g < GMAX; ++g) {
+        const int i = wave + kV2Waves * g;
+        row_[g] = i / nb;
+        gb_[g] = (uint32_t)row_[g] * W + (uint32_t)(i - row_[g] * nb) * B;
+    }
 
     // resident calibration of this wave's bank-rows
     float pd[GMAX][NQ][2], kk[GMAX][NQ][2];
 #pragma unroll
     for (int g = 0; g < GMAX; ++g) {
-        const bool gv = wave + kV2Waves * g < BR;
+        const bool gv = g < ng;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             pd[g][q][0] = pd[g][q][1] = 0.0f;
             kk[g][q][0] = kk[g][q][1] = 0.0f;
             if (gv && lane_ok[q]) {
-                const uint32_t o = row_base + gbase(g) + 128 * q + lane_off;
+                const uint32_t o = row_base + gb_[g] + 128 * q + lane_off;
                 const float2 pp = *reinterpret_cast<const float2 *>(A.ped + o);
                 const float2 kp = *reinterpret_cast<const float2 *>(A.k + o);
                 pd[g][q][0] = pp.x;
@@ -264,10 +314,10 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         const uint32_t *fr = reinterpret_cast<const uint32_t *>(A.frames + f * npix + row_base);
 #pragma unroll
         for (int g = 0; g < GMAX; ++g) {
-            const bool gv = wave + kV2Waves * g < BR;
+            const bool gv = g < ng;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                raw[g][q] = (gv && lane_ok[q]) ? __builtin_nontemporal_load(fr + ((gbase(g) + 128 * q + lane_off) >> 1)) : 0u;
+                raw[g][q] = (gv && lane_ok[q]) ? __builtin_nontemporal_load(fr + ((gb_[g] + 128 * q + lane_off) >> 1)) : 0u;
         }
     };
     if (f_begin < f_end) load_raw(f_begin);
@@ -284,51 +334,44 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 
         // ---------------- phase 1: correction, bank medians, seeds --------
         uint32_t seedbits = 0;  // bit (g*NV + v) set: seed at this lane's value-slot v of bank-row g
+        float xs[GMAX][NV];
 #pragma unroll
         for (int g = 0; g < GMAX; ++g) {
-            const int i = wave + kV2Waves * g;
-            if (i >= BR) break;
-            const int row = i / nb;
-            float x[NV];
-            const uint32_t gb = gbase(g);
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
-                if (lane_ok[q]) {
-                    x[2 * q] = dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]);
-                    x[2 * q + 1] = dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]);
-                    *reinterpret_cast<float2 *>(s_u + gb + 128 * q + lane_off) = make_float2(x[2 * q], x[2 * q + 1]);
+                if (g < ng && lane_ok[q]) {
+                    xs[g][2 * q] = dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]);
+                    xs[g][2 * q + 1] = dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]);
+                    *reinterpret_cast<float2 *>(s_u + gb_[g] + 128 * q + lane_off) =
+                        make_float2(xs[g][2 * q], xs[g][2 * q + 1]);
                 } else {
-                    x[2 * q] = INFINITY;
-                    x[2 * q + 1] = INFINITY;
+                    xs[g][2 * q] = INFINITY;
+                    xs[g][2 * q + 1] = INFINITY;
                 }
             }
-            // estimate: mean over lanes of the median of three of the lane's values
-            float m3 = x[0];
-            if (NV >= 3) {
-                const float a = x[0], b = x[1], c = x[2] < INFINITY ? x[2] : x[0];
-                m3 = __builtin_amdgcn_fmed3f(a, b, c);
-            } else {
-                m3 = x[1] < INFINITY ? fminf(x[0], x[1]) : x[0];
-            }
-            const bool lv = x[0] < INFINITY;
-            float sum = wave_sum(lv ? m3 : 0.0f);
-            const int nl = popc64(ballot(lv));
-            const float est = sum / (float)nl;
-            const float m = bank_select<NV>(x, B, kmed, est, A.rank_width);
+        }
+#pragma unroll
+        for (int g = 0; g < GMAX; ++g) {
+            if (g >= ng) break;
+            const float est = median_estimate<NV>(xs[g]);
+            const float m = bank_median<NV>(xs[g], B, kmed, est, A.rank_width * 24.0f);
+            const int i = wave + kV2Waves * g;
+            const int row = row_[g];
             if (lane == 0) s_med[i] = m;
             if (row >= own_lo && row < own_hi) {
                 if (KEEP) {
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
                         if (lane_ok[q]) {
-                            float2 v2 = make_float2(__fsub_rn(x[2 * q], m), __fsub_rn(x[2 * q + 1], m));
-                            *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb + 128 * q + lane_off) = v2;
+                            float2 v2 = make_float2(__fsub_rn(xs[g][2 * q], m), __fsub_rn(xs[g][2 * q + 1], m));
+                            *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q +
+                                                        lane_off) = v2;
                         }
                 }
                 const float th = seed_threshold(m, A.t_seed);
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    if (x[v] >= th && x[v] < INFINITY) seedbits |= 1u << (g * NV + v);
+                    if (xs[g][v] >= th && xs[g][v] < INFINITY) seedbits |= 1u << (g * NV + v);
             }
         }
         // append this wave's seeds to the pooled list
@@ -496,8 +539,8 @@ static hipError_t launch_v2_t(const V2Args &a, uint32_t grid, size_t lds, bool k
 hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
                                   hipStream_t s)
 {
-    if (nq == 2 && gmax == 7) return launch_v2_t<2, 7>(a, grid, lds, keep, s);
-    if (nq == 1 && gmax == 16) return launch_v2_t<1, 16>(a, grid, lds, keep, s);
+    if (nq == 2 && gmax == 4) return launch_v2_t<2, 4>(a, grid, lds, keep, s);
+    if (nq == 1 && gmax == 8) return launch_v2_t<1, 8>(a, grid, lds, keep, s);
     return hipErrorInvalidValue;
 }
 

@@ -241,8 +241,8 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
         return false;
     const int nb = g.cols / g.bank_cols;
     d.nq = g.bank_cols > 128 ? 2 : 1;
-    d.gmax = d.nq == 2 ? 7 : 16;
-    const int max_bank_rows = 8 * d.gmax;
+    d.gmax = d.nq == 2 ? 4 : 8;
+    const int max_bank_rows = 16 * d.gmax;  // 16 waves per workgroup
     const int rmax_lim = max_bank_rows / nb;
     if (rmax_lim < 3) return false;
     const int own_max = rmax_lim - 2;

@@ -285,3 +285,26 @@ def test_median_with_outliers_and_plateaus(ctx):
     raw = np.clip(raw, 0, 16383).astype(np.uint16)
     want = oracle_threads(raw, ped, gain, B, keep_corrected=True)
     assert_same(run_pdc(ctx, raw, ped, gain, B, keep_corrected=True), want, corrected=True)
+
+
+def test_median_brackets_straddling_zero(ctx):
+    """Banks whose values spread widely on both sides of zero (and whose lane
+    estimate is pulled away by bright pixels), so the median search widens its
+    bracket across zero before converging."""
+    rng = np.random.default_rng(21)
+    T, H, W, B = 2, 30, 388, 194
+    ped = np.full((T, H, W), 2000.0, np.float32)
+    gain = rng.uniform(0.95, 1.05, size=(T, H, W)).astype(np.float32)
+    raw = 2000 + rng.normal(0, 40, size=(4, T, H, W))
+    hot = rng.random(size=raw.shape) < 0.15
+    raw[hot] += 400
+    raw = np.clip(np.rint(raw), 0, 16383).astype(np.uint16)
+    want = oracle_threads(raw, ped, gain, B, keep_corrected=True)
+    assert_same(run_pdc(ctx, raw, ped, gain, B, keep_corrected=True), want, corrected=True)
+    eg = synth.Geometry(1, 40, 768, 96)
+    rawe = np.clip(np.rint(2000 + rng.normal(0, 40, size=(4, *eg.shape))
+                           + (rng.random(size=(4, *eg.shape)) < 0.15) * 400), 0, 16383).astype(np.uint16)
+    pe = np.full(eg.shape, 2000.0, np.float32)
+    ge = rng.uniform(0.95, 1.05, size=eg.shape).astype(np.float32)
+    want = oracle_threads(rawe, pe, ge, 96, keep_corrected=True)
+    assert_same(run_pdc(ctx, rawe, pe, ge, 96, keep_corrected=True), want, corrected=True)
