@@ -106,16 +106,17 @@ __device__ __forceinline__ float wave_minmax(float x, bool max_mode)
 // Exact element of rank k (0-based, ascending) among the n_valid finite lane
 // values of x (absent values are +inf).  Bracketing search on counts:
 // count(x < lo) <= k < count(x < hi) holds throughout.  The first pass tests
-// est - w and est + w together; later passes interpolate a pivot from the
-// bracket counts (bisecting in key space when interpolation stalls).  Once at
-// most two values remain in [lo, hi), the answer is the smallest value >= lo
-// (if it has rank k) or the largest value < hi.
+// est - w and est + w together (widening until they bracket); later passes
+// interpolate the pivot from the bracket counts, bisecting in key space when
+// the interpolated pivot coincides with a bound or the bracket stops halving.
+// Once at most two values remain in [lo, hi), the answer is the smallest value
+// >= lo (if it has rank k) or the largest value < hi.  All state is
+// wave-uniform.
 template <int NV>
 __device__ float bank_median(const float (&x)[NV], int n_valid, int k, float est, float w)
 {
     float lo = uniform_f(est - w), hi = uniform_f(est + w);
     int clo = count_below<NV>(x, lo), chi = count_below<NV>(x, hi);
-    // widen until bracketed (rare): each widening doubles the step
     for (int i = 0; i < 40 && !(clo <= k && k < chi); ++i) {
         w = w + w;
         if (clo > k) {
@@ -130,25 +131,22 @@ __device__ float bank_median(const float (&x)[NV], int n_valid, int k, float est
             chi = i < 38 ? count_below<NV>(x, hi) : n_valid;
         }
     }
-    int last_n = n_valid;
-    bool bisect = false;
-    for (int it = 0; it < 200; ++it) {
-        const int n = chi - clo;
-        if (n <= 2) break;
-        const int32_t klo = f2key(lo), khi = f2key(hi);
-        if ((int64_t)khi - (int64_t)klo <= 1) return lo;  // [lo, hi) holds only the value lo
-        float q;
-        if (bisect || !(lo > -INFINITY && hi < INFINITY)) {
-            q = key2f((int32_t)(((int64_t)klo + (int64_t)khi) >> 1));
-            bisect = false;
-        } else {
-            const float frac = ((float)(k - clo) + 0.5f) * __builtin_amdgcn_rcpf((float)n);
-            q = lo + (hi - lo) * frac;
-            bisect = n * 2 > last_n;
-            if (!(q > lo && q < hi)) q = key2f((int32_t)(((int64_t)klo + (int64_t)khi) >> 1));
-        }
+    int n = chi - clo;
+    int last_n = 4 * n_valid;
+    for (int it = 0; it < 200 && n > 2; ++it) {
+        // interpolated pivot: lo + (hi - lo) * (k - clo + 1/2) / n lies in [lo, hi]
+        float q = lo + (hi - lo) * (((float)(k - clo) + 0.5f) * __builtin_amdgcn_rcpf((float)n));
         q = uniform_f(q);
-        last_n = n;
+        const int32_t qb = __float_as_int(q);
+        if (2 * n > last_n || qb == __float_as_int(lo) || qb == __float_as_int(hi) ||
+            !(lo > -INFINITY && hi < INFINITY)) {
+            const int32_t klo = f2key(lo), khi = f2key(hi);
+            if ((int64_t)khi - (int64_t)klo <= 1) return lo;  // [lo, hi) holds only the value lo
+            q = key2f((int32_t)(((int64_t)klo + (int64_t)khi) >> 1));
+            last_n = 4 * n_valid;  // the next step interpolates again
+        } else {
+            last_n = n;
+        }
         const int c = count_below<NV>(x, q);
         if (c <= k) {
             lo = q;
@@ -157,37 +155,47 @@ __device__ float bank_median(const float (&x)[NV], int n_valid, int k, float est
             hi = q;
             chi = c;
         }
+        n = chi - clo;
     }
     float r;
     if (k == clo) {
         r = INFINITY;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) r = fminf(r, x[v] >= lo ? x[v] : INFINITY);
+        for (int v = 0; v < NV; ++v) r = __builtin_fminf(r, x[v] >= lo ? x[v] : INFINITY);
         r = wave_minmax(r, false);
     } else {
         r = -INFINITY;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) r = fmaxf(r, x[v] < hi ? x[v] : -INFINITY);
+        for (int v = 0; v < NV; ++v) r = __builtin_fmaxf(r, x[v] < hi ? x[v] : -INFINITY);
         r = wave_minmax(r, true);
     }
     return r;
 }
 
-// Mean over lanes of the median of three of the lane's values: a start point
-// for the search.
+// Start point for the search: each lane takes the median of three of its
+// values (lanes short of a third value borrow the neighbour lane's), then the
+// median of three across lane pairs of its quad, and the wave averages those.
+// Photon pixels rarely survive two median-of-three stages.
 template <int NV>
 __device__ __forceinline__ float median_estimate(const float (&x)[NV])
 {
     float m3;
     if (NV >= 3) {
-        const float c = x[2] < INFINITY ? x[2] : x[0];
+        const float nb1 = __shfl_xor(x[1], 1, 64);
+        const float c = x[2] < INFINITY ? x[2] : (nb1 < INFINITY ? nb1 : x[0]);
         m3 = __builtin_amdgcn_fmed3f(x[0], x[1], c);
     } else {
         const float c = __shfl_xor(x[0], 1, 64);
         m3 = __builtin_amdgcn_fmed3f(x[0], x[1], c < INFINITY ? c : x[0]);
     }
     const bool lv = x[0] < INFINITY;
-    const float sum = wave_sum(lv ? m3 : 0.0f);
+    m3 = lv ? m3 : INFINITY;
+    const int v = __float_as_int(m3);
+    const float a = __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
+    const float b = __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
+    float n9 = __builtin_amdgcn_fmed3f(m3, a, b);
+    n9 = lv ? (n9 < INFINITY ? n9 : m3) : 0.0f;
+    const float sum = wave_sum(n9);
     const int nl = popc64(ballot(lv));
     return uniform_f(sum * __builtin_amdgcn_rcpf((float)nl));
 }
@@ -354,7 +362,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         for (int g = 0; g < GMAX; ++g) {
             if (g >= ng) break;
             const float est = median_estimate<NV>(xs[g]);
-            const float m = bank_median<NV>(xs[g], B, kmed, est, A.rank_width * 24.0f);
+            const float m = bank_median<NV>(xs[g], B, kmed, est, A.rank_width * 12.0f);
             const int i = wave + kV2Waves * g;
             const int row = row_[g];
             if (lane == 0) s_med[i] = m;
