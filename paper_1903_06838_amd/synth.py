@@ -154,3 +154,39 @@ CSPAD_OCCUPANCIES = (0.001, 0.01, 0.05)
 # Default thresholds: sigma = 3 ADU, seed at 5 sigma, neighbour mask at 3 sigma,
 # 150 ADU per photon.
 DEFAULT_PARAMS = dict(sigma=3.0, n_seed=5.0, n_nb=3.0, photon_adu=150.0)
+
+
+# ---------------------------------------------------------------------------
+# Charge-sharing patches for the subpixel stage
+# ---------------------------------------------------------------------------
+def make_patches(n: int, seed: int, sigma_lo: float = 0.1, sigma_hi: float = 0.4,
+                 noise_sigma: float = 3.0, photon_adu: float = 150.0, size: int = 5):
+    """Simulated corrected 5x5 patches around single-photon hits.
+
+    Each photon lands at a uniform position inside the central pixel; its
+    charge (photon_adu) spreads as a 2-D Gaussian cloud of width
+    sigma ~ U(sigma_lo, sigma_hi) px, integrated over the pixel areas of the
+    patch, plus N(0, noise_sigma) noise per pixel.
+
+    Returns (patches float32 [n, size, size], truth float32 [n, 2]) where truth
+    is (dy, dx) of the impact point relative to the central pixel's centre, in
+    pixel pitches, each in [-0.5, 0.5).
+    """
+    rng = _rng(7, 1, seed)
+    h = size // 2
+    truth = rng.uniform(-0.5, 0.5, size=(n, 2))
+    sig = rng.uniform(sigma_lo, sigma_hi, size=n)
+    edges = np.arange(-h, h + 2, dtype=np.float64) - 0.5          # pixel edges around the centre pixel
+    out = np.empty((n, size, size), dtype=np.float32)
+    chunk = 1 << 18
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        s = sig[a:b, None]
+        cy = ndtr((edges[None, :] - truth[a:b, 0:1]) / s)
+        cx = ndtr((edges[None, :] - truth[a:b, 1:2]) / s)
+        fy = np.diff(cy, axis=1)
+        fx = np.diff(cx, axis=1)
+        pat = photon_adu * fy[:, :, None] * fx[:, None, :]
+        pat += rng.normal(0.0, noise_sigma, size=pat.shape)
+        out[a:b] = pat.astype(np.float32)
+    return out, truth.astype(np.float32)
