@@ -167,6 +167,92 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
  * batch (frame kernel, scans, hit scatter).  Either pointer may be NULL. */
 pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms);
 
+/* ------------------------------------------------------------------------
+ * Subpixel position of hits (Photon Subpixel Resolution section and its
+ * figure comparing centroid and learned positions).
+ *
+ * A patch is the 5x5 block of Frames2 values centred on a hit, float32
+ * [5][5] row-major (rows top to bottom), zero outside the hit's tile.  A
+ * position is (dy, dx) in pixel pitches relative to the centre of the hit
+ * pixel.  Patch, position and table arguments named *_dev are DEVICE pointers
+ * of the context's device; hip_stream is a hipStream_t of that device or NULL
+ * for the context's stream; the calls return once the work is enqueued unless
+ * stated otherwise.  EINVAL for a NULL pointer with n > 0 or an out-of-range
+ * scalar.
+ * ------------------------------------------------------------------------ */
+
+/* Patches of the first min(total, capacity) hits of a batch processed with
+ * PDC_KEEP_CORRECTED, in hit-list order, into patches_dev float32
+ * [capacity][25]; *n_out (may be NULL) receives the number written.
+ * Synchronous.  ESTATE for an unknown batch or one without the flag. */
+pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev, uint64_t capacity,
+                               uint64_t *n_out);
+
+/* Masked 3x3 centroid of each patch: s = (v > t_nb ? v : 0) over the central
+ * 3x3 pixels; dy = sum(s*dr) / sum(s), dx = sum(s*dc) / sum(s), the sums in
+ * row-major order from +0.0f, IEEE binary32, (0, 0) when sum(s) == 0.
+ * If eta_dev is not NULL (float32 [2][nbins + 1] from pdc_eta_table) each
+ * coordinate c is then mapped to CDF(c) - 1/2, linear between the table's
+ * edges (eta correction: the linearization of centroids into positions).
+ * out_dev: float32 [n][2].  t_nb finite; 1 <= nbins <= 65536 when eta_dev is
+ * used. */
+pdc_status pdc_centroid(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float t_nb,
+                        const float *eta_dev, int32_t nbins, float *out_dev, void *hip_stream);
+
+/* Eta table from n patches of hits with impact points uniform over the pixel:
+ * per axis, the empirical CDF of the centroid coordinate at the nbins + 1
+ * edges of nbins equal bins over [-1, 1] (coordinates are clamped to the
+ * range).  table_dev: float32 [2][nbins + 1]; workspace_dev: uint32
+ * [2 * nbins], scratch of this call.  1 <= nbins <= 65536. */
+pdc_status pdc_eta_table(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float t_nb, int32_t nbins,
+                         uint32_t *workspace_dev, float *table_dev, void *hip_stream);
+
+/* Learned estimator: a 25-64-64-2 ReLU network on the patch divided by
+ * photon_adu, y = W3^T relu(W2^T relu(W1^T x + b1) + b2) + b3.  Its products
+ * take bfloat16 operands (round to nearest even: inputs, activations,
+ * back-propagated gradients and a bf16 copy of the weights) with float32
+ * accumulation (MFMA); parameters, biases and Adam state are float32.
+ * theta layout, float32 [PDC_MLP_PARAMS]: W1[25][64], b1[64], W2[64][64],
+ * b2[64], W3[64][2], b3[2] (row-major, W[in][out]).
+ * Calls on one network are ordered: use one stream, or synchronize. */
+#define PDC_MLP_PARAMS 5954
+typedef struct pdc_mlp pdc_mlp;
+
+/* Create a network on ctx's device with parameters theta_host (host, finite)
+ * and zero Adam state.  It holds about 25 MB of device memory. */
+pdc_status pdc_mlp_create(pdc_ctx *ctx, const float *theta_host, pdc_mlp **out);
+pdc_status pdc_mlp_destroy(pdc_mlp *net);
+/* Replace the parameters and reset the Adam state (synchronous). */
+pdc_status pdc_mlp_set_params(pdc_mlp *net, const float *theta_host);
+/* Copy the parameters to theta_host (synchronous). */
+pdc_status pdc_mlp_get_params(pdc_mlp *net, float *theta_host);
+
+/* Positions of n hits: out_dev float32 [n][2].  photon_adu in [2^-24, 2^24]. */
+pdc_status pdc_mlp_infer(pdc_mlp *net, const float *patches_dev, uint64_t n, float photon_adu,
+                         float *out_dev, void *hip_stream);
+
+/* Gradient of L = sum((y - target)^2) / (2 n) over n >= 1 hits (target_dev
+ * float32 [n][2]) into grad_host float32 [PDC_MLP_PARAMS] and L into
+ * *loss_host (either may be NULL).  Deterministic.  Synchronous. */
+pdc_status pdc_mlp_gradient(pdc_mlp *net, const float *patches_dev, const float *target_dev, uint64_t n,
+                            float photon_adu, float *grad_host, double *loss_host, void *hip_stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected, step count
+ * kept by the network) on the gradient of L over the n >= 1 hits given.
+ * lr finite and >= 0. */
+pdc_status pdc_mlp_train_step(pdc_mlp *net, const float *patches_dev, const float *target_dev, uint64_t n,
+                              float photon_adu, float lr, void *hip_stream);
+
+/* L of the last pdc_mlp_train_step, at the parameters before its update
+ * (synchronous).  ESTATE before the first step. */
+pdc_status pdc_mlp_last_loss(pdc_mlp *net, double *loss);
+
+/* Test hook: D = A B for one 16x32 by 32x16 bfloat16 tile through the MFMA
+ * operand loads the network kernels use.  A (uint16 bf16 bits [16][32]),
+ * B ([32][16]) and D (float32 [16][16]) are host arrays, row-major.
+ * Synchronous. */
+pdc_status pdc_debug_mfma_probe(pdc_ctx *ctx, const uint16_t *A, const uint16_t *B, float *D);
+
 #ifdef __cplusplus
 }
 #endif

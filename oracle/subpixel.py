@@ -141,23 +141,41 @@ def centroid(patches, t_nb):
     return np.stack([cy, cx], axis=1)
 
 
-def eta_table(centroids, nbins=1024, lo=-1.0, hi=1.0):
-    """Per axis, the empirical CDF of centroids on [lo, hi] at nbins+1 edges."""
-    out = np.empty((2, nbins + 1), np.float64)
-    edges = np.linspace(lo, hi, nbins + 1)
+def eta_bin_pos(c, nbins):
+    """Position of centroid coordinates on [-1, 1] in units of bins, in
+    float32: (clamp(c, -1, 1) + 1) * 0.5 * nbins.  The bin of c is
+    min(floor(pos), nbins - 1); float32 takes this integer decision on both
+    sides."""
+    c = np.clip(np.asarray(c, F32), F32(-1), F32(1))
+    return ((c + F32(1)) * F32(0.5) * F32(nbins)).astype(F32)
+
+
+def eta_table(centroids, nbins=1023):
+    """Per axis, the empirical CDF of the centroid coordinate at the nbins + 1
+    bin edges: table[a][b] = (number of centroids in bins < b) / n, float32
+    (quotient formed in float64).  An odd nbins puts 0 inside a bin."""
+    c = np.asarray(centroids)
+    out = np.empty((2, nbins + 1), F32)
     for a in range(2):
-        c = np.asarray(centroids[:, a], np.float64)
-        out[a] = np.searchsorted(np.sort(c), edges, side="right") / len(c)
+        b = np.minimum(np.floor(eta_bin_pos(c[:, a], nbins)).astype(np.int64), nbins - 1)
+        h = np.bincount(b, minlength=nbins)
+        out[a, 0] = 0.0
+        out[a, 1:] = (np.cumsum(h) / float(len(b))).astype(F32)
     return out
 
 
-def eta_apply(centroids, table, lo=-1.0, hi=1.0):
-    """Position = CDF(centroid) - 1/2, linear between table edges."""
+def eta_apply(centroids, table):
+    """Position = CDF(c) - 1/2 with the CDF linear between table edges, in
+    float32: t = bin position, i = min(floor(t), nbins - 1), f = t - i,
+    table[i] (1 - f) + table[i + 1] f - 0.5 evaluated left to right."""
     nb = table.shape[1] - 1
-    out = np.empty_like(np.asarray(centroids, np.float64))
+    c = np.asarray(centroids)
+    out = np.empty((len(c), 2), F32)
     for a in range(2):
-        t = (np.clip(np.asarray(centroids[:, a], np.float64), lo, hi) - lo) / (hi - lo) * nb
-        i = np.minimum(np.floor(t).astype(int), nb - 1)
-        f = t - i
-        out[:, a] = table[a, i] * (1 - f) + table[a, i + 1] * f - 0.5
+        t = eta_bin_pos(c[:, a], nb)
+        i = np.minimum(np.floor(t).astype(np.int64), nb - 1)
+        f = (t - i.astype(F32)).astype(F32)
+        lo = (table[a, i] * (F32(1) - f)).astype(F32)
+        hi = (table[a, i + 1] * f).astype(F32)
+        out[:, a] = ((lo + hi).astype(F32) - F32(0.5)).astype(F32)
     return out

@@ -16,6 +16,7 @@
 
 #include "pdc.h"
 #include "pdc_internal.h"
+#include "pdc_subpixel.h"
 
 using namespace pdc;
 
@@ -787,6 +788,269 @@ pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float 
     HIP_TRY(ctx, hipEventElapsedTime(&t, bt->buf->ev_start, bt->buf->ev_end));
     if (main_ms) *main_ms = a;
     if (total_ms) *total_ms = t;
+    return PDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// subpixel stage
+// ---------------------------------------------------------------------------
+
+pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev, uint64_t capacity, uint64_t *n_out)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (!bt->keep) return fail(ctx, PDC_ESTATE, "batch was not processed with PDC_KEEP_CORRECTED");
+    if (capacity > 0 && !patches_dev) return fail(ctx, PDC_EINVAL, "patches_dev is NULL with capacity > 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    const Detector &d = ctx->dets[bt->det];
+    Buffers *b = bt->buf;
+    const uint64_t n = std::min<uint64_t>(b->host_state->total, capacity);
+    HIP_TRY(ctx, launch_capture_patches(b->corrected, b->hits, b->frame_offset, bt->n_frames, n, d.g.n_tiles,
+                                        d.g.rows, d.g.cols, patches_dev, bt->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+    if (n_out) *n_out = n;
+    return PDC_OK;
+}
+
+pdc_status pdc_centroid(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float t_nb, const float *eta_dev,
+                        int32_t nbins, float *out_dev, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (n > 0 && (!patches_dev || !out_dev)) return fail(ctx, PDC_EINVAL, "patches_dev and out_dev must be non-NULL");
+    if (!std::isfinite(t_nb)) return fail(ctx, PDC_EINVAL, "t_nb must be finite");
+    if (eta_dev && (nbins < 1 || nbins > 65536)) return fail(ctx, PDC_EINVAL, "nbins must be in [1, 65536]");
+    if (n > ((uint64_t)1 << 36)) return fail(ctx, PDC_EINVAL, "n too large");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_centroid_eta(patches_dev, n, t_nb, eta_dev, nbins, out_dev, s));
+    return PDC_OK;
+}
+
+pdc_status pdc_eta_table(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float t_nb, int32_t nbins,
+                         uint32_t *workspace_dev, float *table_dev, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if ((n > 0 && !patches_dev) || !workspace_dev || !table_dev)
+        return fail(ctx, PDC_EINVAL, "patches_dev, workspace_dev and table_dev must be non-NULL");
+    if (!std::isfinite(t_nb)) return fail(ctx, PDC_EINVAL, "t_nb must be finite");
+    if (nbins < 1 || nbins > 65536) return fail(ctx, PDC_EINVAL, "nbins must be in [1, 65536]");
+    if (n > ((uint64_t)1 << 36)) return fail(ctx, PDC_EINVAL, "n too large");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_eta_table(patches_dev, n, t_nb, nbins, workspace_dev, table_dev, s));
+    return PDC_OK;
+}
+
+}  // extern "C"
+
+struct pdc_mlp {
+    pdc_ctx *ctx = nullptr;
+    float *theta = nullptr, *m = nullptr, *v = nullptr;
+    float *grad = nullptr;    // kMlpParams gradient + 1 loss sum
+    float *slots = nullptr;   // per-wave partial gradients
+    uint16_t *packed = nullptr;
+    uint32_t max_grid = 0;
+    int64_t step = 0;
+    uint64_t last_n = 0;
+};
+
+namespace {
+
+bool mlp_theta_ok(const float *theta)
+{
+    for (int i = 0; i < kMlpParams; ++i)
+        if (!std::isfinite(theta[i])) return false;
+    return true;
+}
+
+void mlp_free(pdc_mlp *net)
+{
+    hipFree(net->theta);
+    hipFree(net->m);
+    hipFree(net->v);
+    hipFree(net->grad);
+    hipFree(net->slots);
+    hipFree(net->packed);
+    delete net;
+}
+
+pdc_status mlp_check_run(pdc_mlp *net, const float *patches_dev, const float *target_dev, bool need_target,
+                         uint64_t n, float photon_adu)
+{
+    pdc_ctx *ctx = net->ctx;
+    if (n > 0 && (!patches_dev || (need_target && !target_dev)))
+        return fail(ctx, PDC_EINVAL, "device pointers must be non-NULL");
+    if (!finite_in(photon_adu, 0x1p-24f, 0x1p24f)) return fail(ctx, PDC_EINVAL, "photon_adu must be in [2^-24, 2^24]");
+    if (n > ((uint64_t)1 << 36)) return fail(ctx, PDC_EINVAL, "n too large");
+    return PDC_OK;
+}
+
+float inv_adu_of(float photon_adu) { return (float)(1.0 / (double)photon_adu); }
+
+}  // namespace
+
+extern "C" {
+
+pdc_status pdc_mlp_create(pdc_ctx *ctx, const float *theta_host, pdc_mlp **out)
+{
+    if (!ctx || !theta_host || !out) return fail(ctx, PDC_EINVAL, "ctx, theta_host and out must be non-NULL");
+    if (!mlp_theta_ok(theta_host)) return fail(ctx, PDC_EINVAL, "theta has a non-finite value");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_mlp *net = new (std::nothrow) pdc_mlp;
+    if (!net) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    net->ctx = ctx;
+    net->max_grid = (uint32_t)std::max(1, ctx->n_cu);
+    const size_t pbytes = sizeof(float) * kMlpParams;
+    hipError_t e = hipMalloc((void **)&net->theta, pbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->m, pbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->v, pbytes);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->grad, pbytes + sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&net->slots, sizeof(float) * kMlpSlotStride * 4 * (size_t)net->max_grid);
+    if (e == hipSuccess) e = hipMalloc((void **)&net->packed, sizeof(uint16_t) * kPackElems);
+    if (e != hipSuccess) {
+        mlp_free(net);
+        return fail(ctx, e == hipErrorOutOfMemory ? PDC_ENOMEM : PDC_EDEVICE, "device allocation failed: %s",
+                    hipGetErrorString(e));
+    }
+    pdc_status rc = pdc_mlp_set_params(net, theta_host);
+    if (rc != PDC_OK) {
+        mlp_free(net);
+        return rc;
+    }
+    *out = net;
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_destroy(pdc_mlp *net)
+{
+    if (!net) return PDC_OK;
+    hipSetDevice(net->ctx->device);
+    hipDeviceSynchronize();
+    mlp_free(net);
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_set_params(pdc_mlp *net, const float *theta_host)
+{
+    if (!net || !theta_host) return fail(net ? net->ctx : nullptr, PDC_EINVAL, "net and theta_host must be non-NULL");
+    pdc_ctx *ctx = net->ctx;
+    if (!mlp_theta_ok(theta_host)) return fail(ctx, PDC_EINVAL, "theta has a non-finite value");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = ctx->stream;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipMemcpyAsync(net->theta, theta_host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, launch_fill_zero(net->m, kMlpParams, s));
+    HIP_TRY(ctx, launch_fill_zero(net->v, kMlpParams, s));
+    HIP_TRY(ctx, launch_mlp_pack(net->theta, net->packed, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    net->step = 0;
+    net->last_n = 0;
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_get_params(pdc_mlp *net, float *theta_host)
+{
+    if (!net || !theta_host) return fail(net ? net->ctx : nullptr, PDC_EINVAL, "net and theta_host must be non-NULL");
+    pdc_ctx *ctx = net->ctx;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipMemcpy(theta_host, net->theta, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_infer(pdc_mlp *net, const float *patches_dev, uint64_t n, float photon_adu, float *out_dev,
+                         void *hip_stream)
+{
+    if (!net) return fail(nullptr, PDC_EINVAL, "net is NULL");
+    pdc_ctx *ctx = net->ctx;
+    pdc_status rc = mlp_check_run(net, patches_dev, nullptr, false, n, photon_adu);
+    if (rc != PDC_OK) return rc;
+    if (n > 0 && !out_dev) return fail(ctx, PDC_EINVAL, "out_dev is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_mlp_infer(patches_dev, n, inv_adu_of(photon_adu), net->theta, net->packed, out_dev,
+                                  8u * (uint32_t)ctx->n_cu, s));
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_gradient(pdc_mlp *net, const float *patches_dev, const float *target_dev, uint64_t n,
+                            float photon_adu, float *grad_host, double *loss_host, void *hip_stream)
+{
+    if (!net) return fail(nullptr, PDC_EINVAL, "net is NULL");
+    pdc_ctx *ctx = net->ctx;
+    pdc_status rc = mlp_check_run(net, patches_dev, target_dev, true, n, photon_adu);
+    if (rc != PDC_OK) return rc;
+    if (n == 0) return fail(ctx, PDC_EINVAL, "n must be >= 1");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_mlp_grad(patches_dev, target_dev, n, inv_adu_of(photon_adu), net->theta, net->packed,
+                                 net->grad, net->slots, net->max_grid, s));
+    std::vector<float> h(kMlpParams + 1);
+    HIP_TRY(ctx, hipMemcpyAsync(h.data(), net->grad, sizeof(float) * h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    if (grad_host) std::memcpy(grad_host, h.data(), sizeof(float) * kMlpParams);
+    if (loss_host) *loss_host = (double)h[kMlpParams] / (2.0 * (double)n);
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_train_step(pdc_mlp *net, const float *patches_dev, const float *target_dev, uint64_t n,
+                              float photon_adu, float lr, void *hip_stream)
+{
+    if (!net) return fail(nullptr, PDC_EINVAL, "net is NULL");
+    pdc_ctx *ctx = net->ctx;
+    pdc_status rc = mlp_check_run(net, patches_dev, target_dev, true, n, photon_adu);
+    if (rc != PDC_OK) return rc;
+    if (n == 0) return fail(ctx, PDC_EINVAL, "n must be >= 1");
+    if (!(std::isfinite(lr) && lr >= 0.0f)) return fail(ctx, PDC_EINVAL, "lr must be finite and >= 0");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_mlp_grad(patches_dev, target_dev, n, inv_adu_of(photon_adu), net->theta, net->packed,
+                                 net->grad, net->slots, net->max_grid, s));
+    HIP_TRY(ctx, launch_adam(net->theta, net->m, net->v, net->grad, lr, net->step + 1, s));
+    HIP_TRY(ctx, launch_mlp_pack(net->theta, net->packed, s));
+    net->step += 1;
+    net->last_n = n;
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_last_loss(pdc_mlp *net, double *loss)
+{
+    if (!net || !loss) return fail(net ? net->ctx : nullptr, PDC_EINVAL, "net and loss must be non-NULL");
+    pdc_ctx *ctx = net->ctx;
+    if (net->last_n == 0) return fail(ctx, PDC_ESTATE, "no training step yet");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    float l = 0.0f;
+    HIP_TRY(ctx, hipMemcpy(&l, net->grad + kMlpParams, sizeof(float), hipMemcpyDeviceToHost));
+    *loss = (double)l / (2.0 * (double)net->last_n);
+    return PDC_OK;
+}
+
+// Test hook (not in pdc.h): one 16x32 by 32x16 bf16 MFMA product through the
+// kernels' operand loads.  A, B (uint16 bf16 bits, row-major) and D (float32
+// [16][16]) are host arrays.
+pdc_status pdc_debug_mfma_probe(pdc_ctx *ctx, const uint16_t *A, const uint16_t *B, float *D)
+{
+    if (!ctx || !A || !B || !D) return fail(ctx, PDC_EINVAL, "NULL argument");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    uint16_t *dA = nullptr, *dB = nullptr;
+    float *dD = nullptr;
+    HIP_TRY(ctx, hipMalloc((void **)&dA, 2 * 16 * 32));
+    HIP_TRY(ctx, hipMalloc((void **)&dB, 2 * 32 * 16));
+    HIP_TRY(ctx, hipMalloc((void **)&dD, 4 * 16 * 16));
+    hipStream_t s = ctx->stream;
+    hipError_t e = hipMemcpyAsync(dA, A, 2 * 16 * 32, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(dB, B, 2 * 32 * 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_mfma_probe(dA, dB, dD, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(D, dD, 4 * 16 * 16, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(dA);
+    hipFree(dB);
+    hipFree(dD);
+    if (e != hipSuccess) return fail(ctx, PDC_EDEVICE, "mfma probe: %s", hipGetErrorString(e));
     return PDC_OK;
 }
 

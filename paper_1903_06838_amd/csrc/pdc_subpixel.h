@@ -1,0 +1,47 @@
+// Internal launchers of the subpixel stage (pdc_subpixel.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pdc {
+
+// Parameter vector of the 25-64-64-2 network, float32, in this order:
+// W1[25][64], b1[64], W2[64][64], b2[64], W3[64][2], b3[2].
+constexpr int kMlpIn = 25, kMlpHidden = 64, kMlpOut = 2;
+constexpr int kMlpParams = 25 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2;  // 5954
+constexpr int kOffW1 = 0, kOffB1 = 1600, kOffW2 = 1664, kOffB2 = 5760, kOffW3 = 5824, kOffB3 = 5952;
+
+// bfloat16 copies of the weights in the layouts the MFMA operand loads want
+// (each row holds the contraction index contiguously):
+//   w1t[64][32]  = W1^T, columns 25..31 zero        (forward, layer 1)
+//   w2t[64][64]  = W2^T                               (forward, layer 2)
+//   w2 [64][64]  = W2                                 (backward, dH1 = dH2 W2^T)
+//   w3t[16][64]  = W3^T, rows 2..15 zero             (forward, layer 3)
+//   w3p[64][32]  = W3, columns 2..31 zero             (backward, dH2 = dY W3^T)
+constexpr int kPackW1t = 0, kPackW2t = 2048, kPackW2 = 6144, kPackW3t = 10240, kPackW3p = 11264;
+constexpr int kPackElems = 13312;  // bf16 elements (26 KiB)
+
+hipError_t launch_fill_zero(float *p, uint64_t n, hipStream_t s);
+hipError_t launch_centroid_eta(const float *patches, uint64_t n, float t_nb, const float *eta, int nbins,
+                               float *out, hipStream_t s);
+hipError_t launch_eta_table(const float *patches, uint64_t n, float t_nb, int nbins, uint32_t *hist,
+                            float *table, hipStream_t s);
+hipError_t launch_mlp_pack(const float *theta, uint16_t *packed, hipStream_t s);
+hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, const float *theta,
+                            const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s);
+// Gradient of sum((y - t)^2) / (2 n) over n hits: out[0..kMlpParams) gets the
+// gradient, out[kMlpParams] gets sum((y - t)^2).  Each wave writes its partial
+// sums to a slot of kMlpSlotStride floats; slots must hold
+// mlp_grad_grid(n, max_grid) * 4 slots.  The result is deterministic.
+constexpr int kMlpSlotStride = 5960;
+uint32_t mlp_grad_grid(uint64_t n, uint32_t max_grid);
+hipError_t launch_mlp_grad(const float *patches, const float *target, uint64_t n, float inv_adu,
+                           const float *theta, const uint16_t *packed, float *out, float *slots, uint32_t max_grid,
+                           hipStream_t s);
+hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, float lr, int64_t step, hipStream_t s);
+hipError_t launch_capture_patches(const float *corrected, const uint2 *hits,
+                                  const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, int T,
+                                  int H, int W, float *patches, hipStream_t s);
+hipError_t launch_mfma_probe(const uint16_t *A, const uint16_t *B, float *D, hipStream_t s);
+
+}  // namespace pdc

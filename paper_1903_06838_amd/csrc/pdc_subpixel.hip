@@ -1,0 +1,647 @@
+// Subpixel position of photon hits (Photon Subpixel Resolution section and
+// its figure of centroid versus learned positions): the classical masked 3x3
+// centroid with eta linearization, and a small learned estimator (a
+// 25-64-64-2 ReLU network on the 5x5 patch of corrected values around a hit)
+// trained and evaluated with bfloat16 MFMA (v_mfma_f32_16x16x32_bf16) and
+// float32 accumulation.
+//
+// MFMA 16x16x32 bf16 operand layout (wave64): lane l holds
+//   A[l % 16][8 (l / 16) + j]  and  B[8 (l / 16) + j][l % 16],  j = 0..7,
+// and receives C[4 (l / 16) + i][l % 16], i = 0..3.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "pdc_subpixel.h"
+
+#pragma clang fp contract(off)
+
+namespace pdc {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+
+namespace {
+
+// float32 -> bfloat16 bits, round to nearest even (finite inputs).
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+
+// Operand fragment: 8 bf16 values base[o * SO + (k + j) * SK], j = 0..7.
+// With SK == 1 one 16-byte load (o * SO + k is a multiple of 8 at every call).
+template <int SO, int SK>
+__device__ __forceinline__ bf16x8 frag(const uint16_t *base, int o, int k)
+{
+    if constexpr (SK == 1) {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4 *>(base + o * SO + k));
+    } else {
+        bf16x8 r;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = __builtin_bit_cast(__bf16, base[o * SO + (k + j) * SK]);
+        return r;
+    }
+}
+
+__device__ __forceinline__ f32x4 mfma(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ f32x4 zero4() { return f32x4{0.f, 0.f, 0.f, 0.f}; }
+
+// Orders this wave's LDS accesses (all lanes) before the ones that follow.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+}  // namespace
+
+__global__ void fill_zero_kernel(float *p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0f;
+}
+
+hipError_t launch_fill_zero(float *p, uint64_t n, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_zero_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// classical estimator
+// ---------------------------------------------------------------------------
+// Masked 3x3 centroid of a 5x5 patch: pixels not above t_nb count as 0; the
+// sums run over rows top to bottom and columns left to right;
+// (dy, dx) = (sum s*dr, sum s*dc) / sum s, and (0, 0) when sum s is 0.
+__device__ __forceinline__ void centroid3(const float *p, float t_nb, float &cy, float &cx)
+{
+    float s = 0.0f, sy = 0.0f, sx = 0.0f;
+#pragma unroll
+    for (int dr = -1; dr <= 1; ++dr)
+#pragma unroll
+        for (int dc = -1; dc <= 1; ++dc) {
+            const float v = p[(2 + dr) * 5 + 2 + dc];
+            const float m = v > t_nb ? v : 0.0f;
+            s = __fadd_rn(s, m);
+            sy = __fadd_rn(sy, __fmul_rn(m, (float)dr));
+            sx = __fadd_rn(sx, __fmul_rn(m, (float)dc));
+        }
+    cy = s > 0.0f ? __fdiv_rn(sy, s) : 0.0f;
+    cx = s > 0.0f ? __fdiv_rn(sx, s) : 0.0f;
+}
+
+// Position of a centroid coordinate on [-1, 1] in units of bins (nbins bins).
+__device__ __forceinline__ float eta_pos(float c, int nbins)
+{
+    return (fminf(fmaxf(c, -1.0f), 1.0f) + 1.0f) * 0.5f * (float)nbins;
+}
+
+// Eta linearization: position = CDF(c) - 1/2, linear between table edges
+// (tab holds the CDF at the nbins + 1 bin edges).
+__device__ __forceinline__ float eta_map(const float *tab, int nbins, float c)
+{
+    const float t = eta_pos(c, nbins);
+    const int i = min((int)floorf(t), nbins - 1);
+    const float f = t - (float)i;
+    return tab[i] * (1.0f - f) + tab[i + 1] * f - 0.5f;
+}
+
+__global__ void centroid_eta_kernel(const float *patches, uint64_t n, float t_nb, const float *eta, int nbins,
+                                    float *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float cy, cx;
+    centroid3(patches + i * 25, t_nb, cy, cx);
+    if (eta) {
+        cy = eta_map(eta, nbins, cy);
+        cx = eta_map(eta + nbins + 1, nbins, cx);
+    }
+    out[2 * i] = cy;
+    out[2 * i + 1] = cx;
+}
+
+hipError_t launch_centroid_eta(const float *patches, uint64_t n, float t_nb, const float *eta, int nbins,
+                               float *out, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(centroid_eta_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, patches, n, t_nb,
+                       eta, nbins, out);
+    return hipGetLastError();
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+// Per-axis histogram of centroids over [-1, 1] in nbins bins.
+__global__ void eta_hist_kernel(const float *patches, uint64_t n, float t_nb, int nbins, uint32_t *hist)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float c[2];
+    centroid3(patches + i * 25, t_nb, c[0], c[1]);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        const int b = min((int)floorf(eta_pos(c[a], nbins)), nbins - 1);
+        atomicAdd(&hist[a * nbins + b], 1u);
+    }
+}
+
+// Empirical CDF at the bin edges, one thread per axis (nbins is small).
+__global__ void eta_cdf_kernel(const uint32_t *hist, int nbins, uint64_t n, float *table)
+{
+    const int a = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    const uint32_t *h = hist + (uint64_t)a * nbins;
+    float *t = table + (uint64_t)a * (nbins + 1);
+    uint64_t acc = 0;
+    t[0] = 0.0f;
+    for (int b = 0; b < nbins; ++b) {
+        acc += h[b];
+        t[b + 1] = (float)((double)acc / (double)n);
+    }
+}
+
+hipError_t launch_eta_table(const float *patches, uint64_t n, float t_nb, int nbins, uint32_t *hist,
+                            float *table, hipStream_t s)
+{
+    const uint64_t nh = 2 * (uint64_t)nbins;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3((uint32_t)((nh + 255) / 256)), dim3(256), 0, s, hist, nh);
+    if (n)
+        hipLaunchKernelGGL(eta_hist_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, patches, n, t_nb,
+                           nbins, hist);
+    hipLaunchKernelGGL(eta_cdf_kernel, dim3(2), dim3(64), 0, s, hist, nbins, n ? n : (uint64_t)1, table);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// learned estimator
+// ---------------------------------------------------------------------------
+constexpr int kTile = 32;          // hits per wave tile
+constexpr int kWaves = 4;          // waves per workgroup
+
+__global__ void mlp_pack_kernel(const float *theta, uint16_t *pk)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 64 * 32) {  // w1t[c][k] = W1[k][c]
+        const int c = t / 32, k = t % 32;
+        pk[kPackW1t + t] = k < 25 ? f2bf(theta[kOffW1 + k * 64 + c]) : (uint16_t)0;
+    }
+    if (t < 64 * 64) {
+        const int c = t / 64, k = t % 64;
+        pk[kPackW2t + t] = f2bf(theta[kOffW2 + k * 64 + c]);  // w2t[c][k] = W2[k][c]
+        pk[kPackW2 + t] = f2bf(theta[kOffW2 + t]);            // w2 = W2
+    }
+    if (t < 16 * 64) {  // w3t[c][k] = W3[k][c]
+        const int c = t / 64, k = t % 64;
+        pk[kPackW3t + t] = c < 2 ? f2bf(theta[kOffW3 + k * 2 + c]) : (uint16_t)0;
+    }
+    if (t < 64 * 32) {  // w3p[r][k] = W3[r][k]
+        const int r = t / 32, k = t % 32;
+        pk[kPackW3p + t] = k < 2 ? f2bf(theta[kOffW3 + r * 2 + k]) : (uint16_t)0;
+    }
+}
+
+hipError_t launch_mlp_pack(const float *theta, uint16_t *packed, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_pack_kernel, dim3(16), dim3(256), 0, s, theta, packed);
+    return hipGetLastError();
+}
+
+struct alignas(16) WeightLds {
+    uint16_t w[kPackElems];
+    float b1[64], b2[64], b3[4];
+};
+
+struct alignas(16) FwdLds {
+    uint16_t X[kTile * 32];   // [hit][input], inputs 25..31 zero
+    uint16_t H1[kTile * 64];  // [hit][unit]
+    uint16_t H2[kTile * 64];
+};
+
+struct alignas(16) BwdLds {
+    uint16_t D[kTile * 64];   // dH2 (bf16)
+    uint16_t DY[kTile * 32];  // dY, columns 2..31 zero
+};
+
+// Copy the packed weights and biases into the workgroup's LDS.
+__device__ __forceinline__ void stage_weights(WeightLds &W, const float *theta, const uint16_t *packed)
+{
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(packed);
+    u32x4 *dst = reinterpret_cast<u32x4 *>(W.w);
+    for (int i = threadIdx.x; i < kPackElems / 8; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        W.b1[i] = theta[kOffB1 + i];
+        W.b2[i] = theta[kOffB2 + i];
+    }
+    if (threadIdx.x < 4) W.b3[threadIdx.x] = threadIdx.x < 2 ? theta[kOffB3 + threadIdx.x] : 0.0f;
+}
+
+// Forward pass of the tile of hits [h0, h0 + 32): X, H1, H2 in LDS (bf16),
+// ReLU activity bits pos1/pos2 (bit i of [rt][nt] for C-layout row i), and
+// the outputs y[rt] in C layout (columns 0 and 1 valid).  Rows past n hold
+// zero inputs.
+__device__ __forceinline__ void tile_forward(const float *patches, uint64_t n, uint64_t h0, float inv_adu,
+                                             const WeightLds &W, FwdLds &F, int lane, f32x4 (&y)[2],
+                                             uint32_t (&pos1)[2][4], uint32_t (&pos2)[2][4])
+{
+    const uint64_t nv = n - h0 < (uint64_t)kTile ? n - h0 : (uint64_t)kTile;
+    const int nflat = (int)nv * 25;
+    const float *src = patches + h0 * 25;
+    for (int e = lane; e < kTile * 25; e += 64) {
+        const int r = e / 25, k = e - 25 * r;
+        const float v = e < nflat ? src[e] * inv_adu : 0.0f;
+        F.X[r * 32 + k] = f2bf(v);
+    }
+    wave_lds_sync();
+    const int lo = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
+    // layer 1: X[32 x 32] W1[32 x 64]
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const bf16x8 a = frag<32, 1>(F.X, 16 * rt + lo, kq);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 acc = mfma(a, frag<32, 1>(W.w + kPackW1t, 16 * nt + lo, kq), zero4());
+            const int col = 16 * nt + lo;
+            const float bias = W.b1[col];
+            uint32_t pm = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[i] + bias;
+                F.H1[(16 * rt + rq + i) * 64 + col] = f2bf(z > 0.0f ? z : 0.0f);
+                pm |= (uint32_t)(z > 0.0f) << i;
+            }
+            pos1[rt][nt] = pm;
+        }
+    }
+    wave_lds_sync();
+    // layer 2: H1[32 x 64] W2[64 x 64]
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const bf16x8 a0 = frag<64, 1>(F.H1, 16 * rt + lo, kq);
+        const bf16x8 a1 = frag<64, 1>(F.H1, 16 * rt + lo, 32 + kq);
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 acc = mfma(a0, frag<64, 1>(W.w + kPackW2t, 16 * nt + lo, kq), zero4());
+            acc = mfma(a1, frag<64, 1>(W.w + kPackW2t, 16 * nt + lo, 32 + kq), acc);
+            const int col = 16 * nt + lo;
+            const float bias = W.b2[col];
+            uint32_t pm = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[i] + bias;
+                F.H2[(16 * rt + rq + i) * 64 + col] = f2bf(z > 0.0f ? z : 0.0f);
+                pm |= (uint32_t)(z > 0.0f) << i;
+            }
+            pos2[rt][nt] = pm;
+        }
+    }
+    wave_lds_sync();
+    // layer 3: H2[32 x 64] W3[64 x 16] (output columns 2..15 zero)
+    const float b3 = W.b3[lo < 2 ? lo : 3];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        f32x4 acc = mfma(frag<64, 1>(F.H2, 16 * rt + lo, kq), frag<64, 1>(W.w + kPackW3t, lo, kq), zero4());
+        acc = mfma(frag<64, 1>(F.H2, 16 * rt + lo, 32 + kq), frag<64, 1>(W.w + kPackW3t, lo, 32 + kq), acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = acc[i] + b3;
+        y[rt] = acc;
+    }
+}
+
+// Inference: out[2h], out[2h + 1] = (dy, dx) of hit h.  Waves take 32-hit
+// tiles in a grid-stride loop.
+__global__ void __launch_bounds__(256) mlp_infer_kernel(const float *patches, uint64_t n, float inv_adu,
+                                                        const float *theta, const uint16_t *packed, float *out)
+{
+    __shared__ WeightLds W;
+    __shared__ FwdLds F[kWaves];
+    stage_weights(W, theta, packed);
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint64_t tiles = (n + kTile - 1) / kTile;
+    const int lo = lane & 15, rq = 4 * (lane >> 4);
+    for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wv; t < tiles; t += (uint64_t)gridDim.x * kWaves) {
+        const uint64_t h0 = t * kTile;
+        f32x4 y[2];
+        uint32_t p1[2][4], p2[2][4];
+        tile_forward(patches, n, h0, inv_adu, W, F[wv], lane, y, p1, p2);
+        if (lo < 2)
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint64_t h = h0 + 16 * rt + rq + i;
+                    if (h < n) out[2 * h + lo] = y[rt][i];
+                }
+        wave_lds_sync();
+    }
+}
+
+hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, const float *theta,
+                            const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t tiles = (n + kTile - 1) / kTile;
+    uint64_t grid = (tiles + kWaves - 1) / kWaves;
+    if (grid > max_grid) grid = max_grid;
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3((uint32_t)grid), dim3(64 * kWaves), 0, s, patches, n, inv_adu, theta,
+                       packed, out);
+    return hipGetLastError();
+}
+
+// Sum over the 4 lane groups that share l % 16 (the rows of a C tile).
+__device__ __forceinline__ float col_sum(float v)
+{
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Per-wave gradient of L = sum((y - t)^2) / (2 n) over its tiles, written to
+// the wave's slot (kMlpSlotStride floats: parameters in packed order, then
+// sum((y - t)^2)).  Products take bf16 operands (X, H1, H2, dY, dH2, dH1 and
+// the weights) with float32 accumulation; bias gradients sum float32 values.
+__global__ void __launch_bounds__(256) mlp_grad_kernel(const float *patches, const float *target, uint64_t n,
+                                                       float inv_adu, float inv_n, const float *theta,
+                                                       const uint16_t *packed, float *slots)
+{
+    __shared__ WeightLds W;
+    __shared__ FwdLds Fs[kWaves];
+    __shared__ BwdLds Bs[kWaves];
+    stage_weights(W, theta, packed);
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    FwdLds &F = Fs[wv];
+    BwdLds &Bk = Bs[wv];
+    for (int i = lane; i < kTile * 32; i += 64) Bk.DY[i] = 0;
+    __syncthreads();
+    const int lo = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
+
+    f32x4 gW1[2][4], gW2[4][4], gW3[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW3[a] = zero4();
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW2[a][b] = zero4();
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW1[a][b] = zero4();
+    float gb1[4] = {0.f, 0.f, 0.f, 0.f}, gb2[4] = {0.f, 0.f, 0.f, 0.f}, gb3 = 0.f, lsum = 0.f;
+
+    const uint64_t tiles = (n + kTile - 1) / kTile;
+    for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wv; t < tiles; t += (uint64_t)gridDim.x * kWaves) {
+        const uint64_t h0 = t * kTile;
+        f32x4 y[2];
+        uint32_t p1[2][4], p2[2][4];
+        tile_forward(patches, n, h0, inv_adu, W, F, lane, y, p1, p2);
+        // dY = (y - t) / n, zero for columns >= 2 and rows past n
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * rt + rq + i;
+                const uint64_t h = h0 + row;
+                float d = 0.0f;
+                if (lo < 2 && h < n) {
+                    const float e = y[rt][i] - target[2 * h + lo];
+                    lsum += e * e;
+                    d = e * inv_n;
+                }
+                gb3 += d;
+                Bk.DY[row * 32 + lo] = f2bf(d);
+            }
+        wave_lds_sync();
+        // dW3[64 x 16] += H2^T[64 x 32] dY[32 x 16]
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            gW3[mt] = mfma(frag<1, 64>(F.H2, 16 * mt + lo, kq), frag<1, 32>(Bk.DY, lo, kq), gW3[mt]);
+        // dH2[32 x 64] = (dY[32 x 32] W3^T[32 x 64]) * relu'(z2)
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const bf16x8 a = frag<32, 1>(Bk.DY, 16 * rt + lo, kq);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                const f32x4 acc = mfma(a, frag<32, 1>(W.w + kPackW3p, 16 * nt + lo, kq), zero4());
+                const int col = 16 * nt + lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float g = ((p2[rt][nt] >> i) & 1u) ? acc[i] : 0.0f;
+                    gb2[nt] += g;
+                    Bk.D[(16 * rt + rq + i) * 64 + col] = f2bf(g);
+                }
+            }
+        }
+        wave_lds_sync();
+        // dW2[64 x 64] += H1^T[64 x 32] dH2[32 x 64]
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const bf16x8 a = frag<1, 64>(F.H1, 16 * mt + lo, kq);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) gW2[mt][nt] = mfma(a, frag<1, 64>(Bk.D, 16 * nt + lo, kq), gW2[mt][nt]);
+        }
+        // dH1[32 x 64] = (dH2[32 x 64] W2^T[64 x 64]) * relu'(z1), into H2's space
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const bf16x8 a0 = frag<64, 1>(Bk.D, 16 * rt + lo, kq);
+            const bf16x8 a1 = frag<64, 1>(Bk.D, 16 * rt + lo, 32 + kq);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) {
+                f32x4 acc = mfma(a0, frag<64, 1>(W.w + kPackW2, 16 * nt + lo, kq), zero4());
+                acc = mfma(a1, frag<64, 1>(W.w + kPackW2, 16 * nt + lo, 32 + kq), acc);
+                const int col = 16 * nt + lo;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float g = ((p1[rt][nt] >> i) & 1u) ? acc[i] : 0.0f;
+                    gb1[nt] += g;
+                    F.H2[(16 * rt + rq + i) * 64 + col] = f2bf(g);
+                }
+            }
+        }
+        wave_lds_sync();
+        // dW1[32 x 64] += X^T[32 x 32] dH1[32 x 64]
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            const bf16x8 a = frag<1, 32>(F.X, 16 * mt + lo, kq);
+#pragma unroll
+            for (int nt = 0; nt < 4; ++nt) gW1[mt][nt] = mfma(a, frag<1, 64>(F.H2, 16 * nt + lo, kq), gW1[mt][nt]);
+        }
+        wave_lds_sync();
+    }
+
+    float *slot = slots + ((uint64_t)blockIdx.x * kWaves + wv) * kMlpSlotStride;
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int k = 16 * mt + rq + i;
+                if (k < 25) slot[kOffW1 + k * 64 + 16 * nt + lo] = gW1[mt][nt][i];
+            }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) slot[kOffW2 + (16 * mt + rq + i) * 64 + 16 * nt + lo] = gW2[mt][nt][i];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (lo < 2) slot[kOffW3 + (16 * mt + rq + i) * 2 + lo] = gW3[mt][i];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const float s1 = col_sum(gb1[nt]);
+        const float s2 = col_sum(gb2[nt]);
+        if (lane < 16) {
+            slot[kOffB1 + 16 * nt + lane] = s1;
+            slot[kOffB2 + 16 * nt + lane] = s2;
+        }
+    }
+    const float s3 = col_sum(gb3);
+    if (lane < 2) slot[kOffB3 + lane] = s3;
+    for (int d = 32; d >= 1; d >>= 1) lsum += __shfl_xor(lsum, d, 64);
+    if (lane == 0) slot[kMlpParams] = lsum;
+}
+
+// out[p] = sum over the slots in index order (deterministic), p <= kMlpParams.
+__global__ void slot_reduce_kernel(const float *slots, uint32_t n_slots, float *out)
+{
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > kMlpParams) return;
+    float s = 0.0f;
+    for (uint32_t i = 0; i < n_slots; ++i) s += slots[(uint64_t)i * kMlpSlotStride + p];
+    out[p] = s;
+}
+
+uint32_t mlp_grad_grid(uint64_t n, uint32_t max_grid)
+{
+    const uint64_t tiles = (n + kTile - 1) / kTile;
+    uint64_t grid = (tiles + kWaves - 1) / kWaves;
+    if (grid > max_grid) grid = max_grid;
+    return grid ? (uint32_t)grid : 1u;
+}
+
+hipError_t launch_mlp_grad(const float *patches, const float *target, uint64_t n, float inv_adu,
+                           const float *theta, const uint16_t *packed, float *out, float *slots, uint32_t max_grid,
+                           hipStream_t s)
+{
+    if (n == 0) return launch_fill_zero(out, kMlpParams + 1, s);
+    const uint32_t grid = mlp_grad_grid(n, max_grid);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grid), dim3(64 * kWaves), 0, s, patches, target, n, inv_adu,
+                       (float)(1.0 / (double)n), theta, packed, slots);
+    hipLaunchKernelGGL(slot_reduce_kernel, dim3((kMlpParams + 256) / 256), dim3(256), 0, s, slots,
+                       grid * (uint32_t)kWaves, out);
+    return hipGetLastError();
+}
+
+// Adam in float32, every operation rounded to nearest even:
+//   m = b1 m + (1 - b1) g;  v = b2 v + ((1 - b2) g) g;
+//   theta -= (lr (m / c1)) / (sqrt(v / c2) + eps),  c1 = 1 - b1^t, c2 = 1 - b2^t.
+// sqrtf is correctly rounded under -fhip-fp32-correctly-rounded-divide-sqrt;
+// __fsqrt_rn is not used: it maps to the native approximation.
+__global__ void adam_kernel(float *theta, float *m, float *v, const float *grad, int n, float lr, float b1,
+                            float omb1, float b2, float omb2, float eps, float c1, float c2)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float g = grad[i];
+    const float mi = __fadd_rn(__fmul_rn(b1, m[i]), __fmul_rn(omb1, g));
+    const float vi = __fadd_rn(__fmul_rn(b2, v[i]), __fmul_rn(__fmul_rn(omb2, g), g));
+    m[i] = mi;
+    v[i] = vi;
+    const float step = __fdiv_rn(__fmul_rn(lr, __fdiv_rn(mi, c1)), __fadd_rn(sqrtf(__fdiv_rn(vi, c2)), eps));
+    theta[i] = __fsub_rn(theta[i], step);
+}
+
+hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, float lr, int64_t step, hipStream_t s)
+{
+    const double b1 = 0.9, b2 = 0.999;
+    const float c1 = (float)(1.0 - pow(b1, (double)step)), c2 = (float)(1.0 - pow(b2, (double)step));
+    hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, theta, m, v, grad, kMlpParams,
+                       lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), 1e-8f, c1, c2);
+    return hipGetLastError();
+}
+
+// 5x5 neighbourhood of each hit in the corrected frames (zero outside the
+// tile).  hits[i] = {pixel, charge bits} of the raster-order list; its frame
+// is the largest f with frame_offset[f] <= i.
+__global__ void capture_patches_kernel(const float *corrected, const uint2 *hits,
+                                       const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, int T,
+                                       int H, int W, float *patches)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t lo = 0, hi = n_frames;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (frame_offset[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const uint32_t p = hits[i].x;
+    const int c = (int)(p % (uint32_t)W);
+    const int rt = (int)(p / (uint32_t)W);
+    const int t = rt / H, r = rt - t * H;
+    const float *fr = corrected + (lo * (uint64_t)T + (uint64_t)t) * (uint64_t)H * W;
+    float *dst = patches + i * 25;
+#pragma unroll
+    for (int dr = -2; dr <= 2; ++dr)
+#pragma unroll
+        for (int dc = -2; dc <= 2; ++dc) {
+            const int rr = r + dr, cc = c + dc;
+            dst[(dr + 2) * 5 + dc + 2] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? fr[(uint64_t)rr * W + cc] : 0.0f;
+        }
+}
+
+hipError_t launch_capture_patches(const float *corrected, const uint2 *hits, const unsigned long long *frame_offset,
+                                  uint64_t n_frames, uint64_t n, int T, int H, int W, float *patches, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(capture_patches_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, corrected, hits,
+                       frame_offset, n_frames, n, T, H, W, patches);
+    return hipGetLastError();
+}
+
+// One 16x32 by 32x16 bf16 product D = A B (A, B, D row-major) through the
+// same fragment loads as the network kernels: checks the operand layout.
+__global__ void mfma_probe_kernel(const uint16_t *A, const uint16_t *B, float *D)
+{
+    __shared__ alignas(16) uint16_t a[16 * 32];
+    __shared__ alignas(16) uint16_t bt[16 * 32];  // B^T: [col][k]
+    const int lane = threadIdx.x;
+    for (int e = lane; e < 16 * 32; e += 64) {
+        a[e] = A[e];
+        const int k = e / 16, c = e % 16;
+        bt[c * 32 + k] = B[e];
+    }
+    __syncthreads();
+    const int lo = lane & 15, kq = 8 * (lane >> 4);
+    const f32x4 acc = mfma(frag<32, 1>(a, lo, kq), frag<32, 1>(bt, lo, kq), zero4());
+#pragma unroll
+    for (int i = 0; i < 4; ++i) D[(4 * (lane >> 4) + i) * 16 + lo] = acc[i];
+}
+
+hipError_t launch_mfma_probe(const uint16_t *A, const uint16_t *B, float *D, hipStream_t s)
+{
+    hipLaunchKernelGGL(mfma_probe_kernel, dim3(1), dim3(64), 0, s, A, B, D);
+    return hipGetLastError();
+}
+
+}  // namespace pdc

@@ -68,6 +68,19 @@ _sig = {
     "pdc_release_batch": (_st, [_P, ctypes.c_uint64]),
     "pdc_batch_timing": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
                                ctypes.POINTER(ctypes.c_float)]),
+    "pdc_capture_patches": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "pdc_centroid": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, _P, ctypes.c_int32, _P, _P]),
+    "pdc_eta_table": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.c_int32, _P, _P, _P]),
+    "pdc_mlp_create": (_st, [_P, _P, ctypes.POINTER(_P)]),
+    "pdc_mlp_destroy": (_st, [_P]),
+    "pdc_mlp_set_params": (_st, [_P, _P]),
+    "pdc_mlp_get_params": (_st, [_P, _P]),
+    "pdc_mlp_infer": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, _P, _P]),
+    "pdc_mlp_gradient": (_st, [_P, _P, _P, ctypes.c_uint64, ctypes.c_float, _P,
+                               ctypes.POINTER(ctypes.c_double), _P]),
+    "pdc_mlp_train_step": (_st, [_P, _P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, _P]),
+    "pdc_mlp_last_loss": (_st, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "pdc_debug_mfma_probe": (_st, [_P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -193,3 +206,91 @@ def batch_timing(ctx, batch: int):
     t = ctypes.c_float(0)
     _check(_lib.pdc_batch_timing(ctx, batch, ctypes.byref(a), ctypes.byref(t)), ctx)
     return a.value, t.value
+
+
+# ---------------------------------------------------------------------------
+# subpixel stage
+# ---------------------------------------------------------------------------
+MLP_PARAMS = 5954
+
+
+def _stream(stream):
+    if stream is not None and not isinstance(stream, int):
+        return stream.cuda_stream
+    return stream
+
+
+def capture_patches(ctx, batch: int, patches_dev, capacity: int) -> int:
+    """5x5 Frames2 patches of the batch's first min(total, capacity) hits; returns the count."""
+    n = ctypes.c_uint64(0)
+    _check(_lib.pdc_capture_patches(ctx, batch, _ptr(patches_dev), capacity, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def centroid(ctx, patches_dev, n: int, t_nb: float, out_dev, eta_dev=None, nbins: int = 0, stream=None) -> None:
+    _check(_lib.pdc_centroid(ctx, _ptr(patches_dev), n, t_nb, _ptr(eta_dev), nbins, _ptr(out_dev),
+                             _stream(stream)), ctx)
+
+
+def eta_table(ctx, patches_dev, n: int, t_nb: float, nbins: int, workspace_dev, table_dev, stream=None) -> None:
+    _check(_lib.pdc_eta_table(ctx, _ptr(patches_dev), n, t_nb, nbins, _ptr(workspace_dev), _ptr(table_dev),
+                              _stream(stream)), ctx)
+
+
+def mlp_create(ctx, theta: np.ndarray):
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    if t.size != MLP_PARAMS:
+        raise ValueError("theta must hold %d values" % MLP_PARAMS)
+    h = _P()
+    _check(_lib.pdc_mlp_create(ctx, t.ctypes.data, ctypes.byref(h)), ctx)
+    return h.value
+
+
+def mlp_destroy(net) -> None:
+    _check(_lib.pdc_mlp_destroy(net))
+
+
+def mlp_set_params(net, theta: np.ndarray) -> None:
+    t = np.ascontiguousarray(theta, dtype=np.float32)
+    if t.size != MLP_PARAMS:
+        raise ValueError("theta must hold %d values" % MLP_PARAMS)
+    _check(_lib.pdc_mlp_set_params(net, t.ctypes.data))
+
+
+def mlp_get_params(net) -> np.ndarray:
+    t = np.zeros(MLP_PARAMS, np.float32)
+    _check(_lib.pdc_mlp_get_params(net, t.ctypes.data))
+    return t
+
+
+def mlp_infer(net, patches_dev, n: int, photon_adu: float, out_dev, stream=None) -> None:
+    _check(_lib.pdc_mlp_infer(net, _ptr(patches_dev), n, photon_adu, _ptr(out_dev), _stream(stream)))
+
+
+def mlp_gradient(net, patches_dev, target_dev, n: int, photon_adu: float, stream=None):
+    """Returns (grad float32 [MLP_PARAMS], loss)."""
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = ctypes.c_double(0)
+    _check(_lib.pdc_mlp_gradient(net, _ptr(patches_dev), _ptr(target_dev), n, photon_adu, g.ctypes.data,
+                                 ctypes.byref(loss), _stream(stream)))
+    return g, loss.value
+
+
+def mlp_train_step(net, patches_dev, target_dev, n: int, photon_adu: float, lr: float, stream=None) -> None:
+    _check(_lib.pdc_mlp_train_step(net, _ptr(patches_dev), _ptr(target_dev), n, photon_adu, lr, _stream(stream)))
+
+
+def mlp_last_loss(net) -> float:
+    loss = ctypes.c_double(0)
+    _check(_lib.pdc_mlp_last_loss(net, ctypes.byref(loss)))
+    return loss.value
+
+
+def debug_mfma_probe(ctx, a_bits: np.ndarray, b_bits: np.ndarray) -> np.ndarray:
+    """D = A B for bf16 bit patterns A uint16 [16][32], B uint16 [32][16]."""
+    a = np.ascontiguousarray(a_bits, dtype=np.uint16)
+    b = np.ascontiguousarray(b_bits, dtype=np.uint16)
+    assert a.shape == (16, 32) and b.shape == (32, 16)
+    d = np.zeros((16, 16), np.float32)
+    _check(_lib.pdc_debug_mfma_probe(ctx, a.ctypes.data, b.ctypes.data, d.ctypes.data), ctx)
+    return d

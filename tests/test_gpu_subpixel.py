@@ -1,0 +1,284 @@
+"""Subpixel stage on the GPU (through the C ABI) against the oracle in
+oracle/subpixel.py: centroid and eta correction bit for bit, the network's
+forward pass and gradient within bfloat16 tolerance, Adam bit for bit, patch
+capture from Frames2 bit for bit, and a training run showing the learned
+estimator beats centroid + eta on held-out hits."""
+import numpy as np
+import pytest
+
+from oracle import subpixel as S
+from paper_1903_06838_amd import synth
+from tests.helpers import oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+F32 = np.float32
+T_NB = 9.0          # 3 sigma at sigma = 3 ADU
+ADU = 150.0
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1903_06838_amd import pdc
+
+    c = pdc.create(0)
+    yield c
+    pdc.destroy(c)
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _bits(a):
+    return np.ascontiguousarray(a, dtype=F32).view(np.uint32)
+
+
+def _edge_patches():
+    """Patches that probe the mask: all zero, all at the threshold, negative
+    values, one pixel above it, signal outside the 3x3 only."""
+    P = np.zeros((6, 5, 5), F32)
+    P[1, 1:4, 1:4] = T_NB                       # not above t_nb: sum 0 -> (0, 0)
+    P[2, 1:4, 1:4] = -50.0
+    P[3, 2, 2], P[3, 1, 3] = 100.0, np.nextafter(F32(T_NB), F32(100))
+    P[4, 0, :], P[4, :, 4] = 400.0, 400.0
+    P[5, 3, 1], P[5, 1, 3], P[5, 2, 2] = 77.0, 23.0, 12.5
+    return P
+
+
+def test_mfma_operand_layout(ctx):
+    from paper_1903_06838_amd import pdc
+
+    rng = np.random.default_rng(0)
+    A = rng.integers(-4, 5, size=(16, 32)).astype(F32)
+    B = rng.integers(-4, 5, size=(32, 16)).astype(F32)
+    D = pdc.debug_mfma_probe(ctx, S.bf16(A).view(np.uint32) >> 16, S.bf16(B).view(np.uint32) >> 16)
+    assert np.array_equal(D, A @ B)                 # small integers: exact
+    A = S.bf16(rng.normal(size=(16, 32)).astype(F32))
+    B = S.bf16(rng.normal(size=(32, 16)).astype(F32))
+    D = pdc.debug_mfma_probe(ctx, A.view(np.uint32) >> 16, B.view(np.uint32) >> 16)
+    want = A.astype(np.float64) @ B.astype(np.float64)
+    assert np.max(np.abs(D - want)) <= 32 * 2 ** -23 * np.max(np.abs(A).astype(np.float64) @ np.abs(B))
+
+
+@pytest.mark.parametrize("t_nb", [T_NB, 0.0])
+def test_centroid_bit_exact(ctx, t_nb):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    P, _ = synth.make_patches(100003, seed=11)
+    P = np.concatenate([_edge_patches(), P])
+    n = len(P)
+    out = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    pdc.centroid(ctx, _dev(P), n, t_nb, out)
+    torch.cuda.synchronize()
+    want = S.centroid(P, t_nb)
+    assert np.array_equal(_bits(out.cpu().numpy()), _bits(want))
+
+
+@pytest.mark.parametrize("nbins", [1023, 4, 1])
+def test_eta_table_and_correction_bit_exact(ctx, nbins):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    P, _ = synth.make_patches(50001, seed=12)
+    P = np.concatenate([_edge_patches(), P])
+    n = len(P)
+    dP = _dev(P)
+    table = torch.zeros((2, nbins + 1), dtype=torch.float32, device="cuda")
+    ws = torch.zeros(2 * nbins, dtype=torch.int32, device="cuda")
+    pdc.eta_table(ctx, dP, n, T_NB, nbins, ws, table)
+    out = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    pdc.centroid(ctx, dP, n, T_NB, out, eta_dev=table, nbins=nbins)
+    torch.cuda.synchronize()
+    c = S.centroid(P, T_NB)
+    want_tab = S.eta_table(c, nbins=nbins)
+    assert np.array_equal(_bits(table.cpu().numpy()), _bits(want_tab))
+    assert np.array_equal(_bits(out.cpu().numpy()), _bits(S.eta_apply(c, want_tab)))
+
+
+def test_eta_table_empty_is_zero(ctx):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    table = torch.full((2, 9), 7.0, dtype=torch.float32, device="cuda")
+    ws = torch.zeros(16, dtype=torch.int32, device="cuda")
+    pdc.eta_table(ctx, None, 0, T_NB, 8, ws, table)
+    torch.cuda.synchronize()
+    assert not table.cpu().numpy().any()
+
+
+def _theta(seed):
+    rng = np.random.default_rng(seed)
+    th = S.init_params(seed)
+    th = th + rng.normal(0, 0.05, th.size).astype(F32)   # non-zero biases too
+    return th.astype(F32)
+
+
+def test_mlp_forward_matches_oracle(ctx):
+    """Same bf16-rounded operands on both sides; they differ by float32
+    summation order, which can move a bf16 rounding by one unit (2^-8
+    relative) in rare activations."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    th = _theta(3)
+    P, _ = synth.make_patches(4133, seed=13)
+    net = pdc.mlp_create(ctx, th)
+    try:
+        out = torch.zeros((len(P), 2), dtype=torch.float32, device="cuda")
+        pdc.mlp_infer(net, _dev(P), len(P), ADU, out)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+    finally:
+        pdc.mlp_destroy(net)
+    want, _ = S.mlp_forward(th, P, ADU, bf16_ops=True)
+    d = np.abs(got - want)
+    assert np.quantile(d, 0.99) <= 1e-5, np.quantile(d, 0.99)
+    assert d.max() <= 2e-2, d.max()
+    ref64, _ = S.mlp_forward(th.astype(np.float64), P, ADU, bf16_ops=False)
+    assert np.sqrt(np.mean((got - ref64) ** 2)) <= 0.02
+
+
+@pytest.mark.parametrize("n", [1, 37, 2005, 150001])
+def test_mlp_gradient_matches_oracle(ctx, n):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    th = _theta(4)
+    P, T = synth.make_patches(n, seed=14)
+    net = pdc.mlp_create(ctx, th)
+    try:
+        dP, dT = _dev(P), _dev(T)
+        g, loss = pdc.mlp_gradient(net, dP, dT, n, ADU)
+        g2, loss2 = pdc.mlp_gradient(net, dP, dT, n, ADU)
+        torch.cuda.synchronize()
+    finally:
+        pdc.mlp_destroy(net)
+    assert np.array_equal(g, g2) and loss == loss2          # deterministic
+    want, wloss = S.mlp_backward(th, P, T, ADU, bf16_ops=True)
+    rel = np.linalg.norm(g - want) / np.linalg.norm(want)
+    assert rel <= 1e-2, rel
+    assert abs(loss - wloss) <= 1e-4 * wloss
+    # every parameter block carries its gradient
+    for name, sl in [("W1", slice(0, 1600)), ("b1", slice(1600, 1664)), ("W2", slice(1664, 5760)),
+                     ("b2", slice(5760, 5824)), ("W3", slice(5824, 5952)), ("b3", slice(5952, 5954))]:
+        r = np.linalg.norm(g[sl] - want[sl]) / max(np.linalg.norm(want[sl]), 1e-30)
+        assert r <= 3e-2, (name, r)
+    # and the float64 definition agrees to bf16 accuracy
+    g64, _ = S.mlp_backward(th.astype(np.float64), P, T, ADU, bf16_ops=False)
+    assert np.linalg.norm(g - g64) / np.linalg.norm(g64) <= 5e-2
+
+
+def test_adam_step_bit_exact(ctx):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    th = _theta(5)
+    P, T = synth.make_patches(3000, seed=15)
+    net = pdc.mlp_create(ctx, th)
+    try:
+        dP, dT = _dev(P), _dev(T)
+        m = np.zeros_like(th)
+        v = np.zeros_like(th)
+        cur = th
+        for step, lr in [(1, 1e-3), (2, 3e-3), (3, 5e-4)]:
+            g, loss = pdc.mlp_gradient(net, dP, dT, len(P), ADU)
+            pdc.mlp_train_step(net, dP, dT, len(P), ADU, lr)
+            torch.cuda.synchronize()
+            assert pdc.mlp_last_loss(net) == loss
+            cur, m, v = S.adam(cur, m, v, g, step, F32(lr))
+            got = pdc.mlp_get_params(net)
+            assert np.array_equal(got.view(np.uint32), cur.view(np.uint32)), step
+    finally:
+        pdc.mlp_destroy(net)
+
+
+def test_training_beats_centroid_eta(ctx):
+    """Held-out RMS position error of the trained network is well below that
+    of centroid + eta correction on the same hits (cloud widths 0.1 to 0.4
+    px, 3 ADU noise, 150 ADU photons)."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    n_tr, n_te, bs, steps = 262144, 65536, 1024, 3000
+    P, T = synth.make_patches(n_tr, seed=1)
+    Pt, Tt = synth.make_patches(n_te, seed=2)
+    perm = np.random.default_rng(0).permutation(n_tr)
+    dP, dT = _dev(P[perm]), _dev(T[perm])
+    dPt = _dev(Pt)
+    # classical: eta table from the training hits
+    nb = 1023
+    table = torch.zeros((2, nb + 1), dtype=torch.float32, device="cuda")
+    ws = torch.zeros(2 * nb, dtype=torch.int32, device="cuda")
+    pdc.eta_table(ctx, dP, n_tr, T_NB, nb, ws, table)
+    ce = torch.zeros((n_te, 2), dtype=torch.float32, device="cuda")
+    pdc.centroid(ctx, dPt, n_te, T_NB, ce, eta_dev=table, nbins=nb)
+    net = pdc.mlp_create(ctx, S.init_params(0))
+    try:
+        per_epoch = n_tr // bs
+        first = None
+        for s in range(steps):
+            o = (s % per_epoch) * bs
+            pdc.mlp_train_step(net, dP[o:o + bs], dT[o:o + bs], bs, ADU, 2e-3)
+            if s == 0:
+                first = pdc.mlp_last_loss(net)
+        last = pdc.mlp_last_loss(net)
+        y = torch.zeros((n_te, 2), dtype=torch.float32, device="cuda")
+        pdc.mlp_infer(net, dPt, n_te, ADU, y)
+        torch.cuda.synchronize()
+    finally:
+        pdc.mlp_destroy(net)
+    rms_eta = float(np.sqrt(np.mean((ce.cpu().numpy() - Tt) ** 2)))
+    rms_mlp = float(np.sqrt(np.mean((y.cpu().numpy() - Tt) ** 2)))
+    print("rms centroid+eta %.4f  mlp %.4f  loss %.4f -> %.4f" % (rms_eta, rms_mlp, first, last))
+    assert last < 0.2 * first
+    assert rms_mlp < 0.9 * rms_eta, (rms_mlp, rms_eta)
+
+
+def test_capture_patches_from_frames2(ctx):
+    """Patches around every hit of a batch, cut from Frames2 (zero outside the
+    tile), equal the oracle's Frames2 cut at the oracle's hits."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(3, 37, 96, 48)
+    ped, gain = synth.make_calibration(geom, 21)
+    raw = synth.make_frames(geom, ped, gain, 4, 0.02, 21)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    N, Tn, H, W = raw.shape
+    det = pdc.calibrate(ctx, pdc.geometry(Tn, H, W, geom.bank_cols), ped, gain,
+                        pdc.params(3.0, 5.0, 3.0, ADU, pdc.KEEP_CORRECTED))
+    try:
+        b = pdc.process_frames(ctx, det, _dev(raw), N, 100000)
+        cap = want["total"] + 5
+        out = torch.full((cap, 25), -1.0, dtype=torch.float32, device="cuda")
+        n = pdc.capture_patches(ctx, b, out, cap)
+        small = torch.full((7, 25), -1.0, dtype=torch.float32, device="cuda")
+        n7 = pdc.capture_patches(ctx, b, small, 7)
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
+    assert n == want["total"] > 50 and n7 == 7
+    corr = np.pad(want["corrected"], ((0, 0), (0, 0), (2, 2), (2, 2)))
+    h = want["hits"]
+    t, rc = np.divmod(h["pixel"].astype(np.int64), H * W)
+    r, c = np.divmod(rc, W)
+    exp = np.stack([corr[h["frame"][i], t[i], r[i]:r[i] + 5, c[i]:c[i] + 5].reshape(25) for i in range(n)])
+    got = out.cpu().numpy()
+    assert np.array_equal(_bits(got[:n]), _bits(exp))
+    assert np.all(got[n:] == -1.0)
+    assert np.array_equal(_bits(small.cpu().numpy()), _bits(exp[:7]))

@@ -96,7 +96,7 @@ def test_centroid_closed_forms(t_nb):
 def test_eta_maps_uniform_to_identity():
     rng = np.random.default_rng(4)
     c = rng.uniform(-0.5, 0.5, size=(200000, 2))
-    tab = S.eta_table(c, nbins=512)
+    tab = S.eta_table(c, nbins=511)
     q = np.linspace(-0.45, 0.45, 19)
     out = S.eta_apply(np.stack([q, q], axis=1), tab)
     assert np.allclose(out, np.stack([q, q], axis=1), atol=0.01)
@@ -106,3 +106,17 @@ def test_eta_maps_uniform_to_identity():
     u = S.eta_apply(s, tab2)
     hist = np.histogram(u[:, 0], bins=10, range=(-0.5, 0.5))[0]
     assert hist.min() > 0.9 * len(s) / 10
+
+
+def test_eta_table_hand_count():
+    """4 centroids, 4 bins of width 0.5 on [-1, 1]: x-coordinates -0.5, 0, 0,
+    0.5 fall in bins 1, 2, 2, 3 (a coordinate on an edge belongs to the bin
+    above it); y-coordinates -1, 1, 1, 0.99 in bins 0, 3, 3, 3 (1 is in the
+    last bin)."""
+    c = np.array([[-1.0, -0.5], [1.0, 0.0], [1.0, 0.0], [0.99, 0.5]], F32)
+    tab = S.eta_table(c, nbins=4)
+    assert np.array_equal(tab[1], np.array([0, 0, 0.25, 0.75, 1.0], F32))
+    assert np.array_equal(tab[0], np.array([0, 0.25, 0.25, 0.25, 1.0], F32))
+    # CDF at the x edges -0.5 and 0 -> positions -0.25 and 0.25 - 0.5
+    out = S.eta_apply(np.array([[0.0, -0.5], [0.0, 0.0], [0.0, 0.25]], F32), tab)
+    assert np.allclose(out[:, 1], [0.0 - 0.5, 0.25 - 0.5, 0.5 * (0.25 + 0.75) - 0.5])
