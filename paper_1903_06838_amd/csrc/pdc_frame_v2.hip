@@ -1,14 +1,16 @@
 // Persistent frame kernel for gfx950.
 //
-// One workgroup (8 waves) owns a strip of rows of one tile for a range of
+// One workgroup (16 waves) owns a strip of rows of one tile for a range of
 // frames.  The strip's dark and 1/gain planes are loaded once into registers
 // and stay there for every frame; only the 2-byte raw words stream from HBM.
 // Per frame:
-//   phase 1 (each wave, its own bank-rows): load raw words (prefetched one
-//     frame ahead), correct them (Fig. b), write u to LDS, find each bank's
-//     lower median exactly by ballot-counted pivot passes (common mode,
-//     Fig. c), derive the seed threshold, and append seed pixels to a
-//     workgroup list;
+//   phase 1a (each wave, its own bank-rows): load raw words (prefetched one
+//     frame ahead), correct them (Fig. b) and write u to LDS;
+//   phase 1b (all waves): every bank-row's lower median, exactly, by a
+//     bracketing count search with L lanes per bank-row (common mode, Fig. c),
+//     and the seed threshold it implies;
+//   phase 1c (each wave, its own bank-rows): Frames2 if kept, seed pixels
+//     appended to a workgroup list;
 //   phase 2 (all waves, over the pooled seeds): 3x3 local maximum with the
 //     raster tie-break, masked 3x3 charge sum, photon count (Fig. e and the
 //     charge summing section); hits mark a per-bank-row column bitmap;
@@ -16,9 +18,11 @@
 //   phase 4 (all waves): each hit's raster position = bank-row prefix +
 //     number of hits left of it in its bank-row (bitmap popcount).
 //
-// Lane layout: a bank-row (B pixels of one row) is held by one wave as NQ
-// pair-slots; lane l of pair-slot q holds columns 128q + 2l and 128q + 2l + 1
-// of the bank (value-slots 2q and 2q+1).  Absent pixels hold +inf.
+// Lane layouts.  Phases 1a and 1c: a bank-row (B pixels of one row) is held
+// by one wave as NQ pair-slots; lane l of pair-slot q holds columns 128q + 2l
+// and 128q + 2l + 1 of the bank (value-slots 2q and 2q+1); absent pixels hold
+// +inf.  Phase 1b: bank-row i belongs to lane group i % (64 / L) of wave
+// i / (64 / L); lane j of the group holds columns L v + j, v < V.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -41,167 +45,158 @@ __device__ __forceinline__ float uniform_f(float x)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
-// Sum over the 64 lanes of a wave, wave-uniform result (DPP reduction; the
-// summation order is fixed but it only feeds a search heuristic).
-__device__ __forceinline__ float wave_sum(float x)
+// Group reductions over aligned groups of L lanes (L = 2, 4, 8 or 16; the
+// groups lie inside 16-lane DPP rows).  Every lane of a group receives the
+// group's result.  All lanes of the wave must be active.
+template <int L>
+__device__ __forceinline__ int gsum_i(int v)
 {
-    int v = __float_as_int(x);
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
-    v = __float_as_int(x);
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
-    v = __float_as_int(x);
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false)); // row_half_mirror
-    v = __float_as_int(x);
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false)); // row_mirror
-    v = __float_as_int(x);
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false)); // row_bcast15
-    v = __float_as_int(x);
-    x += __int_as_float(__builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false)); // row_bcast31
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);                // quad_perm 1,0,3,2
+    if (L >= 4) v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);    // quad_perm 2,3,0,1
+    if (L >= 8) v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    if (L >= 16) v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    return v;
+}
+
+template <int L>
+__device__ __forceinline__ float gsum_f(float x)
+{
+#define PDC_GS(ctrl) x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false))
+    PDC_GS(0xB1);
+    if (L >= 4) PDC_GS(0x4E);
+    if (L >= 8) PDC_GS(0x141);
+    if (L >= 16) PDC_GS(0x140);
+#undef PDC_GS
+    return x;
+}
+
+template <int L>
+__device__ __forceinline__ float gmin_f(float x)
+{
+#define PDC_GM(ctrl) x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false)))
+    PDC_GM(0xB1);
+    if (L >= 4) PDC_GM(0x4E);
+    if (L >= 8) PDC_GM(0x141);
+    if (L >= 16) PDC_GM(0x140);
+#undef PDC_GM
+    return x;
+}
+
+template <int V>
+__device__ __forceinline__ int lane_count(const float (&x)[V], float p)
+{
+    int c = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) c += x[v] < p ? 1 : 0;
+    return c;
+}
+
+// Exact element of rank k (0-based, ascending) among the nval finite values
+// held by an L-lane group (V values per lane, absent values +inf); every
+// group of the wave searches its own bank at once.  Bracketing search on
+// counts, count(x < lo) <= k < count(x < hi) throughout: the first step tests
+// est - w0 and est + w0 together (widening until they bracket), later steps
+// interpolate the pivot from the bracket counts and bisect in key space when
+// the interpolated pivot is not strictly inside or the bracket stopped
+// halving.  Once at most two values remain in [lo, hi) (or [lo, hi) holds a
+// single float), the answer is min{x >= lo} when k == count(x < lo), else
+// max{x < hi}.  Groups with act false return an unspecified value.
+template <int V, int L>
+__device__ float group_median(const float (&x)[V], int nval, int k, float w0, bool act)
+{
+    static_assert(V >= 3, "the start estimate takes three values per lane");
+    // start: each lane's median of three, averaged over the group's lanes
+    const float a = x[0];
+    const float b = x[1] < INFINITY ? x[1] : a;
+    const float c3 = x[2] < INFINITY ? x[2] : b;
+    const bool has = a < INFINITY;
+    const float ssum = gsum_f<L>(has ? __builtin_amdgcn_fmed3f(a, b, c3) : 0.0f);
+    const int nl = gsum_i<L>(has ? 1 : 0);
+    const float est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
+
+    float lo = est - w0, hi = est + w0;
+    int clo, chi;
+    {
+        const int pk = gsum_i<L>(lane_count<V>(x, lo) | (lane_count<V>(x, hi) << 16));
+        clo = pk & 0xFFFF;
+        chi = pk >> 16;
+    }
+    bool ok = !act || (clo <= k && k < chi);
+    float w = w0;
+    for (int it = 0; it < 40; ++it) {
+        if (__ballot(!ok) == 0) break;
+        w = w + w;
+        const bool down = clo > k;
+        const float p = it < 38 ? (down ? est - w : est + w) : (down ? -INFINITY : INFINITY);
+        const int cp = gsum_i<L>(lane_count<V>(x, p));
+        if (!ok) {
+            if (down) {
+                hi = lo;
+                chi = clo;
+                lo = p;
+                clo = cp;
+            } else {
+                lo = hi;
+                clo = chi;
+                hi = p;
+                chi = cp;
+            }
+            ok = clo <= k && k < chi;
+        }
+    }
+
+    int last_n = 4 * nval;
+    bool done = !act;
+    for (int it = 0; it < 200; ++it) {
+        const int n = chi - clo;
+        const int32_t klo = f2key(lo), khi = f2key(hi);
+        done = done || n <= 2 || (uint32_t)(khi - klo) <= 1u;
+        if (__ballot(!done) == 0) break;
+        float q = lo + (hi - lo) * (((float)(k - clo) + 0.5f) * __builtin_amdgcn_rcpf((float)n));
+        const bool interp = 2 * n <= last_n && q > lo && q < hi && lo > -INFINITY && hi < INFINITY;
+        if (!interp) q = key2f((klo >> 1) + (khi >> 1) + (klo & khi & 1));
+        last_n = interp ? n : 4 * nval;
+        const int cq = gsum_i<L>(lane_count<V>(x, q));
+        if (!done) {
+            if (cq <= k) {
+                lo = q;
+                clo = cq;
+            } else {
+                hi = q;
+                chi = cq;
+            }
+        }
+    }
+    // min{x >= lo} = min{s x >= lo} with s = 1, or max{x < hi} = -min{s x >= b}
+    // with s = -1 and b the float just above -hi
+    const bool lowm = k == clo;
+    const float sg = lowm ? 1.0f : -1.0f;
+    const float bnd = lowm ? lo : key2f(f2key(-hi) + 1);
+    float r = INFINITY;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const float t = sg * x[v];
+        r = fminf(r, t >= bnd ? t : INFINITY);
+    }
+    return sg * gmin_f<L>(r);
 }
 
 // Smallest binary32 value th such that fl(th - m) > t (fl(x - m) is
-// monotone in x, so fl(u - m) > t  <=>  u >= th).  Wave-uniform.
+// monotone in x, so fl(u - m) > t  <=>  u >= th).  Per lane.
 __device__ __forceinline__ float seed_threshold(float m, float t)
 {
-    float th = uniform_f(__fadd_rn(m, t));
-    for (int i = 0; i < 64 && !(__fsub_rn(th, m) > t); ++i) th = uniform_f(key2f(f2key(th) + 1));
+    float th = __fadd_rn(m, t);
+    for (int i = 0; i < 64 && !(__fsub_rn(th, m) > t); ++i) th = key2f(f2key(th) + 1);
     for (int i = 0; i < 64; ++i) {
-        float d = uniform_f(key2f(f2key(th) - 1));
+        const float d = key2f(f2key(th) - 1);
         if (__fsub_rn(d, m) > t) th = d;
         else break;
     }
     return th;
 }
 
-template <int NV>
-__device__ __forceinline__ int count_below(const float (&x)[NV], float p)
-{
-    int c = 0;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) c += popc64(ballot(x[v] < p));
-    return c;
-}
-
-// Wave-uniform minimum (max_mode false) or maximum of the lanes' values.
-__device__ __forceinline__ float wave_minmax(float x, bool max_mode)
-{
-    int v = __float_as_int(x);
-#define PDC_MM(ctrl, rm)                                                                          \
-    {                                                                                             \
-        float o = __int_as_float(__builtin_amdgcn_update_dpp(v, v, ctrl, rm, 0xF, false));        \
-        x = max_mode ? fmaxf(x, o) : fminf(x, o);                                                 \
-        v = __float_as_int(x);                                                                    \
-    }
-    PDC_MM(0xB1, 0xF)
-    PDC_MM(0x4E, 0xF)
-    PDC_MM(0x141, 0xF)
-    PDC_MM(0x140, 0xF)
-    PDC_MM(0x142, 0xA)
-    PDC_MM(0x143, 0xC)
-#undef PDC_MM
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
-}
-
-// Exact element of rank k (0-based, ascending) among the n_valid finite lane
-// values of x (absent values are +inf).  Bracketing search on counts:
-// count(x < lo) <= k < count(x < hi) holds throughout.  The first pass tests
-// est - w and est + w together (widening until they bracket); later passes
-// interpolate the pivot from the bracket counts, bisecting in key space when
-// the interpolated pivot coincides with a bound or the bracket stops halving.
-// Once at most two values remain in [lo, hi), the answer is the smallest value
-// >= lo (if it has rank k) or the largest value < hi.  All state is
-// wave-uniform.
-template <int NV>
-__device__ float bank_median(const float (&x)[NV], int n_valid, int k, float est, float w)
-{
-    float lo = uniform_f(est - w), hi = uniform_f(est + w);
-    int clo = count_below<NV>(x, lo), chi = count_below<NV>(x, hi);
-    for (int i = 0; i < 40 && !(clo <= k && k < chi); ++i) {
-        w = w + w;
-        if (clo > k) {
-            hi = lo;
-            chi = clo;
-            lo = uniform_f(i < 38 ? est - w : -INFINITY);
-            clo = i < 38 ? count_below<NV>(x, lo) : 0;
-        } else {
-            lo = hi;
-            clo = chi;
-            hi = uniform_f(i < 38 ? est + w : INFINITY);
-            chi = i < 38 ? count_below<NV>(x, hi) : n_valid;
-        }
-    }
-    int n = chi - clo;
-    int last_n = 4 * n_valid;
-    for (int it = 0; it < 200 && n > 2; ++it) {
-        // interpolated pivot: lo + (hi - lo) * (k - clo + 1/2) / n lies in [lo, hi]
-        float q = lo + (hi - lo) * (((float)(k - clo) + 0.5f) * __builtin_amdgcn_rcpf((float)n));
-        q = uniform_f(q);
-        const int32_t qb = __float_as_int(q);
-        if (2 * n > last_n || qb == __float_as_int(lo) || qb == __float_as_int(hi) ||
-            !(lo > -INFINITY && hi < INFINITY)) {
-            const int32_t klo = f2key(lo), khi = f2key(hi);
-            if ((int64_t)khi - (int64_t)klo <= 1) return lo;  // [lo, hi) holds only the value lo
-            q = key2f((int32_t)(((int64_t)klo + (int64_t)khi) >> 1));
-            last_n = 4 * n_valid;  // the next step interpolates again
-        } else {
-            last_n = n;
-        }
-        const int c = count_below<NV>(x, q);
-        if (c <= k) {
-            lo = q;
-            clo = c;
-        } else {
-            hi = q;
-            chi = c;
-        }
-        n = chi - clo;
-    }
-    float r;
-    if (k == clo) {
-        r = INFINITY;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) r = __builtin_fminf(r, x[v] >= lo ? x[v] : INFINITY);
-        r = wave_minmax(r, false);
-    } else {
-        r = -INFINITY;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) r = __builtin_fmaxf(r, x[v] < hi ? x[v] : -INFINITY);
-        r = wave_minmax(r, true);
-    }
-    return r;
-}
-
-// Start point for the search: each lane takes the median of three of its
-// values (lanes short of a third value borrow the neighbour lane's), then the
-// median of three across lane pairs of its quad, and the wave averages those.
-// Photon pixels rarely survive two median-of-three stages.
-template <int NV>
-__device__ __forceinline__ float median_estimate(const float (&x)[NV])
-{
-    float m3;
-    if (NV >= 3) {
-        const float nb1 = __shfl_xor(x[1], 1, 64);
-        const float c = x[2] < INFINITY ? x[2] : (nb1 < INFINITY ? nb1 : x[0]);
-        m3 = __builtin_amdgcn_fmed3f(x[0], x[1], c);
-    } else {
-        const float c = __shfl_xor(x[0], 1, 64);
-        m3 = __builtin_amdgcn_fmed3f(x[0], x[1], c < INFINITY ? c : x[0]);
-    }
-    const bool lv = x[0] < INFINITY;
-    m3 = lv ? m3 : INFINITY;
-    const int v = __float_as_int(m3);
-    const float a = __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
-    const float b = __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
-    float n9 = __builtin_amdgcn_fmed3f(m3, a, b);
-    n9 = lv ? (n9 < INFINITY ? n9 : m3) : 0.0f;
-    const float sum = wave_sum(n9);
-    const int nl = popc64(ballot(lv));
-    return uniform_f(sum * __builtin_amdgcn_rcpf((float)nl));
-}
-
 struct V2Layout {
-    uint32_t u, med, bits, cnt, seed, q, nseed, pref, total;  // float offsets
+    uint32_t u, med, th, bits, cnt, seed, q, nseed, pref, total;  // float offsets
 };
 
 __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
@@ -211,6 +206,8 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
     L.u = o;
     o += (uint32_t)rmax * W;
     L.med = o;
+    o += (uint32_t)rmax * nb;
+    L.th = o;
     o += (uint32_t)rmax * nb;
     L.bits = o;
     o += 2u * rmax * nb * 8;
@@ -230,12 +227,12 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
-    size_t o = (size_t)rmax * W + (size_t)rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
+    size_t o = (size_t)rmax * W + 2ull * rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
                4ull * seed_cap + 2 + (size_t)rmax * nb + 1;
     return o * 4;
 }
 
-template <int NQ, int GMAX, bool KEEP>
+template <int NQ, int GMAX, int L, int V, bool KEEP>
 __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 {
     extern __shared__ float lds[];
@@ -247,15 +244,16 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = A.W, B = A.B, nb = A.nb, H = A.H;
-    const V2Layout L = v2_layout(A.rmax, W, nb, A.seed_cap);
-    float *s_u = lds + L.u;
-    float *s_med = lds + L.med;
-    uint32_t *s_bits = reinterpret_cast<uint32_t *>(lds + L.bits);
-    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(lds + L.cnt);
-    uint32_t *s_seed = reinterpret_cast<uint32_t *>(lds + L.seed);
-    float *s_q = lds + L.q;
-    uint32_t *s_nseed = reinterpret_cast<uint32_t *>(lds + L.nseed);
-    uint32_t *s_pref = reinterpret_cast<uint32_t *>(lds + L.pref);
+    const V2Layout Ly = v2_layout(A.rmax, W, nb, A.seed_cap);
+    float *s_u = lds + Ly.u;
+    float *s_med = lds + Ly.med;
+    float *s_th = lds + Ly.th;
+    uint32_t *s_bits = reinterpret_cast<uint32_t *>(lds + Ly.bits);
+    uint32_t *s_cnt = reinterpret_cast<uint32_t *>(lds + Ly.cnt);
+    uint32_t *s_seed = reinterpret_cast<uint32_t *>(lds + Ly.seed);
+    float *s_q = lds + Ly.q;
+    uint32_t *s_nseed = reinterpret_cast<uint32_t *>(lds + Ly.nseed);
+    uint32_t *s_pref = reinterpret_cast<uint32_t *>(lds + Ly.pref);
 
     const int item = A.wg_item[blockIdx.x];
     const int strip = item % A.n_strips;
@@ -340,46 +338,77 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             for (int q = 0; q < NQ; ++q) cur[g][q] = raw[g][q];
         if (f + 1 < f_end) load_raw(f + 1);
 
-        // ---------------- phase 1: correction, bank medians, seeds --------
+        // ---------------- phase 1a: correction into LDS ----------------------
         uint32_t seedbits = 0;  // bit (g*NV + v) set: seed at this lane's value-slot v of bank-row g
-        float xs[GMAX][NV];
 #pragma unroll
         for (int g = 0; g < GMAX; ++g) {
 #pragma unroll
             for (int q = 0; q < NQ; ++q) {
                 if (g < ng && lane_ok[q]) {
-                    xs[g][2 * q] = dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]);
-                    xs[g][2 * q + 1] = dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]);
                     *reinterpret_cast<float2 *>(s_u + gb_[g] + 128 * q + lane_off) =
-                        make_float2(xs[g][2 * q], xs[g][2 * q + 1]);
-                } else {
-                    xs[g][2 * q] = INFINITY;
-                    xs[g][2 * q + 1] = INFINITY;
+                        make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
+                                    dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
                 }
             }
         }
+        __syncthreads();  // B0: u of every bank-row of the strip is in LDS
+
+        // ---------------- phase 1b: bank medians, L lanes per bank-row -----
+        {
+            constexpr int G = 64 / L;
+            const int grp = lane / L, gl = lane - grp * L;
+            const int i = wave * G + grp;
+            const bool act = i < BR;
+            const int row = act ? i / nb : 0;
+            const int bank = act ? i - row * nb : 0;
+            const float *src = s_u + row * W + bank * B;
+            float x[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int c = L * v + gl;
+                x[v] = (act && c < B) ? src[c] : INFINITY;
+            }
+            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 12.0f, act);
+            if (act && gl == 0) {
+                s_med[i] = m;
+                s_th[i] = seed_threshold(m, A.t_seed);
+            }
+        }
+        __syncthreads();  // B0': medians and seed thresholds of every bank-row
+
+        // ---------------- phase 1c: Frames2 and seeds of own bank-rows -----
 #pragma unroll
         for (int g = 0; g < GMAX; ++g) {
             if (g >= ng) break;
-            const float est = median_estimate<NV>(xs[g]);
-            const float m = bank_median<NV>(xs[g], B, kmed, est, A.rank_width * 12.0f);
             const int i = wave + kV2Waves * g;
             const int row = row_[g];
-            if (lane == 0) s_med[i] = m;
             if (row >= own_lo && row < own_hi) {
+                float xs[NV];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    if (lane_ok[q]) {
+                        const float2 u2 = *reinterpret_cast<const float2 *>(s_u + gb_[g] + 128 * q + lane_off);
+                        xs[2 * q] = u2.x;
+                        xs[2 * q + 1] = u2.y;
+                    } else {
+                        xs[2 * q] = INFINITY;
+                        xs[2 * q + 1] = INFINITY;
+                    }
+                }
                 if (KEEP) {
+                    const float m = uniform_f(s_med[i]);
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
                         if (lane_ok[q]) {
-                            float2 v2 = make_float2(__fsub_rn(xs[g][2 * q], m), __fsub_rn(xs[g][2 * q + 1], m));
+                            float2 v2 = make_float2(__fsub_rn(xs[2 * q], m), __fsub_rn(xs[2 * q + 1], m));
                             *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q +
                                                         lane_off) = v2;
                         }
                 }
-                const float th = seed_threshold(m, A.t_seed);
+                const float th = uniform_f(s_th[i]);
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    if (xs[g][v] >= th && xs[g][v] < INFINITY) seedbits |= 1u << (g * NV + v);
+                    if (xs[v] >= th && xs[v] < INFINITY) seedbits |= 1u << (g * NV + v);
             }
         }
         // append this wave's seeds to the pooled list
@@ -527,16 +556,16 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     }
 }
 
-template <int NQ, int GMAX>
+template <int NQ, int GMAX, int L, int V>
 static hipError_t launch_v2_t(const V2Args &a, uint32_t grid, size_t lds, bool keep, hipStream_t s)
 {
     if (keep) {
-        auto k = frame_kernel_v2<NQ, GMAX, true>;
+        auto k = frame_kernel_v2<NQ, GMAX, L, V, true>;
         hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(grid), dim3(kV2Threads), lds, s, a);
     } else {
-        auto k = frame_kernel_v2<NQ, GMAX, false>;
+        auto k = frame_kernel_v2<NQ, GMAX, L, V, false>;
         hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(grid), dim3(kV2Threads), lds, s, a);
@@ -544,11 +573,22 @@ static hipError_t launch_v2_t(const V2Args &a, uint32_t grid, size_t lds, bool k
     return hipGetLastError();
 }
 
+// Lanes per bank-row in the median phase: L * (bank-rows of a strip) must not
+// exceed the workgroup's 1024 lanes (16 * GMAX bank-rows at most), and
+// V = ceil(B / L) values per lane.
 hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
                                   hipStream_t s)
 {
-    if (nq == 2 && gmax == 4) return launch_v2_t<2, 4>(a, grid, lds, keep, s);
-    if (nq == 1 && gmax == 8) return launch_v2_t<1, 8>(a, grid, lds, keep, s);
+    if (a.B < 1 || a.rmax * a.nb > 16 * gmax) return hipErrorInvalidValue;
+    if (nq == 2 && gmax == 4 && a.B <= 256) {
+        if (a.B <= 16 * 13) return launch_v2_t<2, 4, 16, 13>(a, grid, lds, keep, s);
+        return launch_v2_t<2, 4, 16, 16>(a, grid, lds, keep, s);
+    }
+    if (nq == 1 && gmax == 8 && a.B <= 128) {
+        if (a.B <= 8 * 8) return launch_v2_t<1, 8, 8, 8>(a, grid, lds, keep, s);
+        if (a.B <= 8 * 12) return launch_v2_t<1, 8, 8, 12>(a, grid, lds, keep, s);
+        return launch_v2_t<1, 8, 8, 16>(a, grid, lds, keep, s);
+    }
     return hipErrorInvalidValue;
 }
 
