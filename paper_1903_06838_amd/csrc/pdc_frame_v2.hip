@@ -45,6 +45,20 @@ __device__ __forceinline__ float uniform_f(float x)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
+// Inclusive prefix sum over the 64 lanes (DPP row shifts, then row
+// broadcasts); all lanes must be active.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    int v = (int)x;
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false); // row_bcast:31
+    return (uint32_t)v;
+}
+
 // Group reductions over aligned groups of L lanes (L = 2, 4, 8 or 16; the
 // groups lie inside 16-lane DPP rows).  Every lane of a group receives the
 // group's result.  All lanes of the wave must be active.
@@ -82,13 +96,23 @@ __device__ __forceinline__ float gmin_f(float x)
     return x;
 }
 
+// Number of the lane's values below p.  For finite p, x < p exactly when
+// fl(x - p) has its sign bit set (a nonzero difference never rounds to +0,
+// x == p gives +0, x = +inf gives +inf); p is clamped to the finite range,
+// which changes no count because the values are bounded far below FLT_MAX.
+// The sign bits are summed in a tree, so the count is no serial chain.
 template <int V>
 __device__ __forceinline__ int lane_count(const float (&x)[V], float p)
 {
-    int c = 0;
+    const float pc = __builtin_amdgcn_fmed3f(p, -3.40282347e38f, 3.40282347e38f);
+    uint32_t t[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) c += x[v] < p ? 1 : 0;
-    return c;
+    for (int v = 0; v < V; ++v) t[v] = __float_as_uint(__fsub_rn(x[v], pc)) >> 31;
+#pragma unroll
+    for (int w = 1; w < V; w *= 2)
+#pragma unroll
+        for (int v = 0; v + w < V; v += 2 * w) t[v] += t[v + w];
+    return (int)t[0];
 }
 
 // Exact element of rank k (0-based, ascending) among the nval finite values
@@ -96,22 +120,31 @@ __device__ __forceinline__ int lane_count(const float (&x)[V], float p)
 // group of the wave searches its own bank at once.  Bracketing search on
 // counts, count(x < lo) <= k < count(x < hi) throughout: the first step tests
 // est - w0 and est + w0 together (widening until they bracket), later steps
-// interpolate the pivot from the bracket counts and bisect in key space when
-// the interpolated pivot is not strictly inside or the bracket stopped
-// halving.  Once at most two values remain in [lo, hi) (or [lo, hi) holds a
+// interpolate the pivot from the bracket counts and bisect when the
+// interpolated pivot is not strictly inside or the bracket stopped halving.  Once at most two values remain in [lo, hi) (or [lo, hi) holds a
 // single float), the answer is min{x >= lo} when k == count(x < lo), else
 // max{x < hi}.  Groups with act false return an unspecified value.
 template <int V, int L>
 __device__ float group_median(const float (&x)[V], int nval, int k, float w0, bool act)
 {
-    static_assert(V >= 3, "the start estimate takes three values per lane");
-    // start: each lane's median of three, averaged over the group's lanes
-    const float a = x[0];
-    const float b = x[1] < INFINITY ? x[1] : a;
-    const float c3 = x[2] < INFINITY ? x[2] : b;
-    const bool has = a < INFINITY;
-    const float ssum = gsum_f<L>(has ? __builtin_amdgcn_fmed3f(a, b, c3) : 0.0f);
-    const int nl = gsum_i<L>(has ? 1 : 0);
+    static_assert(V >= 3, "the start estimate takes triples of values per lane");
+    // start: medians of three of each lane's values (up to eight triples),
+    // averaged over the group
+    constexpr int NT = V / 3 < 8 ? V / 3 : 8;
+    float s3 = 0.0f;
+    int n3 = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const float a = x[3 * t];
+        const float b = x[3 * t + 1] < INFINITY ? x[3 * t + 1] : a;
+        const float c = x[3 * t + 2] < INFINITY ? x[3 * t + 2] : b;
+        if (a < INFINITY) {
+            s3 += __builtin_amdgcn_fmed3f(a, b, c);
+            ++n3;
+        }
+    }
+    const float ssum = gsum_f<L>(s3);
+    const int nl = gsum_i<L>(n3);
     const float est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
 
     float lo = est - w0, hi = est + w0;
@@ -149,12 +182,23 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float w0, bo
     bool done = !act;
     for (int it = 0; it < 200; ++it) {
         const int n = chi - clo;
-        const int32_t klo = f2key(lo), khi = f2key(hi);
-        done = done || n <= 2 || (uint32_t)(khi - klo) <= 1u;
-        if (__ballot(!done) == 0) break;
         float q = lo + (hi - lo) * (((float)(k - clo) + 0.5f) * __builtin_amdgcn_rcpf((float)n));
-        const bool interp = 2 * n <= last_n && q > lo && q < hi && lo > -INFINITY && hi < INFINITY;
-        if (!interp) q = key2f((klo >> 1) + (khi >> 1) + (klo & khi & 1));
+        // q is NaN or not strictly inside when a bound is infinite
+        const bool interp = 2 * n <= last_n && q > lo && q < hi;
+        bool single = false;  // [lo, hi) holds one float only (never when interp holds)
+        if (!interp) {
+            // bisect in value space; in key space only when no float lies
+            // strictly between the value midpoint and the bounds (adjacent
+            // floats) or a bound is infinite
+            q = lo + (hi - lo) * 0.5f;
+            if (!(q > lo && q < hi)) {
+                const int32_t klo = f2key(lo), khi = f2key(hi);
+                single = (uint32_t)(khi - klo) <= 1u;
+                q = key2f((klo >> 1) + (khi >> 1) + (klo & khi & 1));
+            }
+        }
+        done = done || n <= 2 || single;
+        if (__ballot(!done) == 0) break;
         last_n = interp ? n : 4 * nval;
         const int cq = gsum_i<L>(lane_count<V>(x, q));
         if (!done) {
@@ -368,7 +412,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const int c = L * v + gl;
                 x[v] = (act && c < B) ? src[c] : INFINITY;
             }
-            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 12.0f, act);
+            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 8.0f, act);
             if (act && gl == 0) {
                 s_med[i] = m;
                 s_th[i] = seed_threshold(m, A.t_seed);
@@ -383,7 +427,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             const int i = wave + kV2Waves * g;
             const int row = row_[g];
             if (row >= own_lo && row < own_hi) {
-                float xs[NV];
+                float xs[NV];  // absent pixels: -inf (never a seed)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
                     if (lane_ok[q]) {
@@ -391,10 +435,11 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                         xs[2 * q] = u2.x;
                         xs[2 * q + 1] = u2.y;
                     } else {
-                        xs[2 * q] = INFINITY;
-                        xs[2 * q + 1] = INFINITY;
+                        xs[2 * q] = -INFINITY;
+                        xs[2 * q + 1] = -INFINITY;
                     }
                 }
+                const float th = uniform_f(s_th[i]);
                 if (KEEP) {
                     const float m = uniform_f(s_med[i]);
 #pragma unroll
@@ -405,34 +450,36 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                                                         lane_off) = v2;
                         }
                 }
-                const float th = uniform_f(s_th[i]);
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
-                    if (xs[v] >= th && xs[v] < INFINITY) seedbits |= 1u << (g * NV + v);
+                    if (xs[v] >= th) seedbits |= 1u << (g * NV + v);
             }
         }
-        // append this wave's seeds to the pooled list
+        // append this wave's seeds to the pooled list (list order is free;
+        // phase 4 restores raster order): DPP prefix of the lanes' counts,
+        // one LDS atomic per wave
         {
             const uint32_t ns = (uint32_t)__popc(seedbits);
-            uint32_t incl = ns;
-            for (int d = 1; d < 64; d <<= 1) {
-                uint32_t y = __shfl_up(incl, d, 64);
-                if (lane >= d) incl += y;
-            }
-            const uint32_t wtot = __shfl(incl, 63, 64);
-            uint32_t base = 0;
-            if (lane == 0 && wtot) base = atomicAdd(&s_nseed[par], wtot);
-            base = __shfl(base, 0, 64);
-            uint32_t pos = base + incl - ns;
-            uint32_t bits = seedbits;
-            while (bits) {
-                const int b = __ffs(bits) - 1;
-                bits &= bits - 1;
-                const int g = b / NV, v = b - (b / NV) * NV;
-                const int i = wave + kV2Waves * g;
-                const int col = (i - (i / nb) * nb) * B + 128 * (v >> 1) + 2 * lane + (v & 1);
-                if (pos < (uint32_t)A.seed_cap) s_seed[par * A.seed_cap + pos] = ((uint32_t)i << 16) | (uint32_t)col;
-                ++pos;
+            const uint32_t incl = wave_incl_scan(ns);
+            const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            if (wtot) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_nseed[par], wtot);
+                uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
+#pragma unroll
+                for (int g = 0; g < GMAX; ++g) {
+                    if (g >= ng) break;
+                    uint32_t bits = (seedbits >> (g * NV)) & ((1u << NV) - 1u);
+                    const int colbase = (int)(gb_[g] - (uint32_t)row_[g] * W) + 2 * lane;
+                    const uint32_t keyhi = (uint32_t)(wave + kV2Waves * g) << 16;
+                    while (bits) {
+                        const int v = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        if (pos < (uint32_t)A.seed_cap)
+                            s_seed[par * A.seed_cap + pos] = keyhi | (uint32_t)(colbase + 128 * (v >> 1) + (v & 1));
+                        ++pos;
+                    }
+                }
             }
         }
         __syncthreads();  // B1
@@ -573,9 +620,11 @@ static hipError_t launch_v2_t(const V2Args &a, uint32_t grid, size_t lds, bool k
     return hipGetLastError();
 }
 
-// Lanes per bank-row in the median phase: L * (bank-rows of a strip) must not
-// exceed the workgroup's 1024 lanes (16 * GMAX bank-rows at most), and
-// V = ceil(B / L) values per lane.
+// Lanes per bank-row in the median phase and values per lane (L, V): 16 lanes
+// for banks of more than 128 pixels, else 8 (strips hold at most 64 and 128
+// bank-rows, so L * bank-rows <= 1024), V = ceil(B / L) rounded up to a
+// compiled size.  Four to eight searches per wave and four waves per SIMD
+// hide the latency of the reductions.
 hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
                                   hipStream_t s)
 {
