@@ -243,14 +243,16 @@ struct V2Layout {
     uint32_t u, med, th, bits, cnt, seed, q, nseed, pref, total;  // float offsets
 };
 
+// LDS of one workgroup (floats): u and med are double-buffered by frame
+// parity, bits/cnt/seed/q/nseed likewise; th and pref are single.
 __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
 {
     V2Layout L;
     uint32_t o = 0;
     L.u = o;
-    o += (uint32_t)rmax * W;
+    o += 2u * rmax * W;
     L.med = o;
-    o += (uint32_t)rmax * nb;
+    o += 2u * rmax * nb;
     L.th = o;
     o += (uint32_t)rmax * nb;
     L.bits = o;
@@ -271,9 +273,15 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
-    size_t o = (size_t)rmax * W + 2ull * rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
+    size_t o = 2ull * rmax * W + 2ull * rmax * nb + (size_t)rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
                4ull * seed_cap + 2 + (size_t)rmax * nb + 1;
     return o * 4;
+}
+
+// Seed key: loaded row (7 bits), bank (7 bits), column (11 bits).
+__device__ __forceinline__ uint32_t seed_key(int row, int bank, int col)
+{
+    return ((uint32_t)row << 18) | ((uint32_t)bank << 11) | (uint32_t)col;
 }
 
 template <int NQ, int GMAX, int L, int V, bool KEEP>
@@ -289,6 +297,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = A.W, B = A.B, nb = A.nb, H = A.H;
     const V2Layout Ly = v2_layout(A.rmax, W, nb, A.seed_cap);
+    const int RW = A.rmax * W, RN = A.rmax * nb, cap = A.seed_cap;
     float *s_u = lds + Ly.u;
     float *s_med = lds + Ly.med;
     float *s_th = lds + Ly.th;
@@ -314,22 +323,24 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const uint64_t f_end = (A.n_frames * (uint64_t)(fg + 1)) / A.n_fgroups;
     const int kmed = (B - 1) / 2;
     const uint32_t row_base = ((uint32_t)t * H + lr0) * (uint32_t)W;  // pixel index of loaded row 0
+    constexpr int kP3Wave = kV2Waves - 1;  // wave that runs phase 3
 
     // lane l of pair-slot q holds bank columns 128q + 2l and 128q + 2l + 1
     bool lane_ok[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) lane_ok[q] = 128 * q + 2 * lane < B;
     const uint32_t lane_off = 2u * lane;
-    // this wave's bank-rows g < ng: bank-row index i = wave + 8g, its local row
-    // and its first pixel (offset from row_base), all wave-uniform
+    // this wave's bank-rows g < ng: bank-row index i = wave + 16g, its local
+    // row and its first pixel (offset from row_base), all wave-uniform
     const int ng = BR > wave ? min(GMAX, (BR - wave + kV2Waves - 1) / kV2Waves) : 0;
-    int row_[GMAX];
+    int row_[GMAX], bank_[GMAX];
     uint32_t gb_[GMAX];
 #pragma unroll
     for (int g = 0; g < GMAX; ++g) {
         const int i = wave + kV2Waves * g;
         row_[g] = i / nb;
-        gb_[g] = (uint32_t)row_[g] * W + (uint32_t)(i - row_[g] * nb) * B;
+        bank_[g] = i - row_[g] * nb;
+        gb_[g] = (uint32_t)row_[g] * W + (uint32_t)bank_[g] * B;
     }
 
     // resident calibration of this wave's bank-rows
@@ -352,13 +363,12 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             }
         }
     }
-    // clear both parities of the per-frame LDS lists
-    for (int x = tid; x < 2 * A.rmax * nb * 8; x += kV2Threads) s_bits[x] = 0;
-    for (int x = tid; x < 2 * A.rmax * nb; x += kV2Threads) s_cnt[x] = 0;
+    for (int x = tid; x < 2 * RN * 8; x += kV2Threads) s_bits[x] = 0;
+    for (int x = tid; x < 2 * RN; x += kV2Threads) s_cnt[x] = 0;
     if (tid < 2) s_nseed[tid] = 0;
     if (tid == 0) s_photons = 0;
 
-    uint64_t chunk_cur = 0, chunk_end = 0;  // staging chunk of thread 0
+    uint64_t chunk_cur = 0, chunk_end = 0;  // staging chunk, held by the phase-3 wave's lane 0
     uint32_t raw[GMAX][NQ];
     auto load_raw = [&](uint64_t f) {
         const uint32_t *fr = reinterpret_cast<const uint32_t *>(A.frames + f * npix + row_base);
@@ -373,146 +383,88 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     if (f_begin < f_end) load_raw(f_begin);
     __syncthreads();
 
-    for (uint64_t f = f_begin; f < f_end; ++f) {
-        const int par = (int)(f & 1);
-        uint32_t cur[GMAX][NQ];
-#pragma unroll
-        for (int g = 0; g < GMAX; ++g)
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) cur[g][q] = raw[g][q];
-        if (f + 1 < f_end) load_raw(f + 1);
+    // Software pipeline: iteration f runs frame f's phases 1a, 1b, 1c and
+    // frame f-1's phases 2, 3, 4 beside them (one iteration more drains it).
+    for (uint64_t f = f_begin; f <= f_end; ++f) {
+        const bool cur_ok = f < f_end, prev_ok = f > f_begin;
+        const int par = (int)(f & 1), pp = par ^ 1;
+        const uint32_t nseed_p = prev_ok ? s_nseed[pp] : 0u;
+        const bool ovf_p = nseed_p > (uint32_t)cap;
+        float *u_c = s_u + par * RW;
+        const float *u_p = s_u + pp * RW;
+        float *med_c = s_med + par * RN;
+        const float *med_p = s_med + pp * RN;
 
-        // ---------------- phase 1a: correction into LDS ----------------------
-        uint32_t seedbits = 0;  // bit (g*NV + v) set: seed at this lane's value-slot v of bank-row g
+        // ================= A: 1a(f) | 2(f-1) ======================================
+        if (cur_ok) {
+            uint32_t cur[GMAX][NQ];
 #pragma unroll
-        for (int g = 0; g < GMAX; ++g) {
+            for (int g = 0; g < GMAX; ++g)
 #pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (g < ng && lane_ok[q]) {
-                    *reinterpret_cast<float2 *>(s_u + gb_[g] + 128 * q + lane_off) =
-                        make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
-                                    dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
-                }
-            }
+                for (int q = 0; q < NQ; ++q) cur[g][q] = raw[g][q];
+            if (f + 1 < f_end) load_raw(f + 1);
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g)
+#pragma unroll
+                for (int q = 0; q < NQ; ++q)
+                    if (g < ng && lane_ok[q])
+                        *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) =
+                            make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
+                                        dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
+            // lists of parity par were last used by frame f-2 (finished)
+            for (int x = tid; x < RN * 8; x += kV2Threads) s_bits[par * RN * 8 + x] = 0;
+            for (int x = tid; x < RN; x += kV2Threads) s_cnt[par * RN + x] = 0;
+            if (tid == 0) s_nseed[par] = 0;
         }
-        __syncthreads();  // B0: u of every bank-row of the strip is in LDS
-
-        // ---------------- phase 1b: bank medians, L lanes per bank-row -----
-        {
-            constexpr int G = 64 / L;
-            const int grp = lane / L, gl = lane - grp * L;
-            const int i = wave * G + grp;
-            const bool act = i < BR;
-            const int row = act ? i / nb : 0;
-            const int bank = act ? i - row * nb : 0;
-            const float *src = s_u + row * W + bank * B;
-            float x[V];
-#pragma unroll
-            for (int v = 0; v < V; ++v) {
-                const int c = L * v + gl;
-                x[v] = (act && c < B) ? src[c] : INFINITY;
-            }
-            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 8.0f, act);
-            if (act && gl == 0) {
-                s_med[i] = m;
-                s_th[i] = seed_threshold(m, A.t_seed);
-            }
-        }
-        __syncthreads();  // B0': medians and seed thresholds of every bank-row
-
-        // ---------------- phase 1c: Frames2 and seeds of own bank-rows -----
-#pragma unroll
-        for (int g = 0; g < GMAX; ++g) {
-            if (g >= ng) break;
-            const int i = wave + kV2Waves * g;
-            const int row = row_[g];
-            if (row >= own_lo && row < own_hi) {
-                float xs[NV];  // absent pixels: -inf (never a seed)
-#pragma unroll
-                for (int q = 0; q < NQ; ++q) {
-                    if (lane_ok[q]) {
-                        const float2 u2 = *reinterpret_cast<const float2 *>(s_u + gb_[g] + 128 * q + lane_off);
-                        xs[2 * q] = u2.x;
-                        xs[2 * q + 1] = u2.y;
-                    } else {
-                        xs[2 * q] = -INFINITY;
-                        xs[2 * q + 1] = -INFINITY;
-                    }
-                }
-                const float th = uniform_f(s_th[i]);
-                if (KEEP) {
-                    const float m = uniform_f(s_med[i]);
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        if (lane_ok[q]) {
-                            float2 v2 = make_float2(__fsub_rn(xs[2 * q], m), __fsub_rn(xs[2 * q + 1], m));
-                            *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q +
-                                                        lane_off) = v2;
-                        }
-                }
-#pragma unroll
-                for (int v = 0; v < NV; ++v)
-                    if (xs[v] >= th) seedbits |= 1u << (g * NV + v);
-            }
-        }
-        // append this wave's seeds to the pooled list (list order is free;
-        // phase 4 restores raster order): DPP prefix of the lanes' counts,
-        // one LDS atomic per wave
-        {
-            const uint32_t ns = (uint32_t)__popc(seedbits);
-            const uint32_t incl = wave_incl_scan(ns);
-            const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            if (wtot) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&s_nseed[par], wtot);
-                uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
-#pragma unroll
-                for (int g = 0; g < GMAX; ++g) {
-                    if (g >= ng) break;
-                    uint32_t bits = (seedbits >> (g * NV)) & ((1u << NV) - 1u);
-                    const int colbase = (int)(gb_[g] - (uint32_t)row_[g] * W) + 2 * lane;
-                    const uint32_t keyhi = (uint32_t)(wave + kV2Waves * g) << 16;
-                    while (bits) {
-                        const int v = __ffs(bits) - 1;
-                        bits &= bits - 1;
-                        if (pos < (uint32_t)A.seed_cap)
-                            s_seed[par * A.seed_cap + pos] = keyhi | (uint32_t)(colbase + 128 * (v >> 1) + (v & 1));
-                        ++pos;
-                    }
-                }
-            }
-        }
-        __syncthreads();  // B1
-
-        // ---------------- phase 2: local maximum, charge, count ----------
-        const uint32_t nseed = s_nseed[par];
-        const bool overflow = nseed > (uint32_t)A.seed_cap;
-        if (!overflow) {
+        if (prev_ok && !ovf_p) {
+            // 3x3 local maximum with the raster tie-break, masked charge sum in
+            // row-major order, photon count; absent neighbours read a clamped
+            // in-range address and are ignored
             unsigned long long my_ph = 0;
-            for (uint32_t j = tid; j < nseed; j += kV2Threads) {
-                const uint32_t key = s_seed[par * A.seed_cap + j];
-                const int i = key >> 16, col = key & 0xFFFF;
-                const int row = i / nb, bank = i - (i / nb) * nb;
-                const float vp = __fsub_rn(s_u[row * W + col], s_med[i]);
-                float nv[3][3];
+            for (uint32_t j = tid; j < nseed_p; j += kV2Threads) {
+                const uint32_t key = s_seed[pp * cap + j];
+                const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
+                const int i = row * nb + bank;
+                // addresses first, then all 18 reads, then the arithmetic
+                int ua[3][3], ma[3][3];
                 bool ex[3][3];
+#pragma unroll
+                for (int dr = 0; dr < 3; ++dr) {
+                    const int rr = row + dr - 1;
+                    const int rc = min(max(rr, 0), R - 1);
+#pragma unroll
+                    for (int dc = 0; dc < 3; ++dc) {
+                        const int cc = col + dc - 1;
+                        ex[dr][dc] = rr >= 0 && rr < R && cc >= 0 && cc < W;
+                        const int ccl = min(max(cc, 0), W - 1);
+                        const int bk = ccl >= (bank + 1) * B ? bank + 1 : (ccl < bank * B ? bank - 1 : bank);
+                        ua[dr][dc] = rc * W + ccl;
+                        ma[dr][dc] = rc * nb + bk;
+                    }
+                }
+                float uv[3][3], mv[3][3];
+#pragma unroll
+                for (int dr = 0; dr < 3; ++dr)
+#pragma unroll
+                    for (int dc = 0; dc < 3; ++dc) {
+                        uv[dr][dc] = u_p[ua[dr][dc]];
+                        mv[dr][dc] = med_p[ma[dr][dc]];
+                    }
+                float nv[3][3];
+#pragma unroll
+                for (int dr = 0; dr < 3; ++dr)
+#pragma unroll
+                    for (int dc = 0; dc < 3; ++dc) nv[dr][dc] = __fsub_rn(uv[dr][dc], mv[dr][dc]);
+                const float vp = nv[1][1];
                 bool is_max = true;
 #pragma unroll
                 for (int dr = 0; dr < 3; ++dr)
 #pragma unroll
                     for (int dc = 0; dc < 3; ++dc) {
-                        const int rr = row + dr - 1, cc = col + dc - 1;
-                        ex[dr][dc] = rr >= 0 && rr < R && cc >= 0 && cc < W;
-                        nv[dr][dc] = 0.0f;
-                        if (ex[dr][dc]) {
-                            const int bk = cc >= (bank + 1) * B ? bank + 1 : (cc < bank * B ? bank - 1 : bank);
-                            nv[dr][dc] = __fsub_rn(s_u[rr * W + cc], s_med[rr * nb + bk]);
-                            if (!(dr == 1 && dc == 1)) {
-                                const bool later = dr > 1 || (dr == 1 && dc > 1);
-                                const float vq = nv[dr][dc];
-                                if (!(vp > vq || (vp == vq && later))) is_max = false;
-                            }
-                        }
+                        if (dr == 1 && dc == 1) continue;
+                        const bool later = dr > 1 || (dr == 1 && dc > 1);
+                        const float vq = nv[dr][dc];
+                        if (ex[dr][dc] && !(vp > vq || (vp == vq && later))) is_max = false;
                     }
                 float qsum = -1.0f;
                 if (is_max) {
@@ -521,38 +473,55 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                     for (int dr = 0; dr < 3; ++dr)
 #pragma unroll
                         for (int dc = 0; dc < 3; ++dc)
-                            if (ex[dr][dc]) qsum = __fadd_rn(qsum, nv[dr][dc] > A.t_nb ? nv[dr][dc] : 0.0f);
+                            qsum = __fadd_rn(qsum, (ex[dr][dc] && nv[dr][dc] > A.t_nb) ? nv[dr][dc] : 0.0f);
                     const int cb = col - bank * B;
-                    atomicOr(&s_bits[(par * A.rmax * nb + i) * 8 + (cb >> 5)], 1u << (cb & 31));
-                    atomicAdd(&s_cnt[par * A.rmax * nb + i], 1u);
+                    atomicOr(&s_bits[(pp * RN + i) * 8 + (cb >> 5)], 1u << (cb & 31));
+                    atomicAdd(&s_cnt[pp * RN + i], 1u);
                     my_ph += photon_count(qsum, A.photon_adu);
                 }
-                s_q[par * A.seed_cap + j] = qsum;
+                s_q[pp * cap + j] = qsum;
             }
             if (my_ph) atomicAdd(&s_photons, my_ph);
         }
-        __syncthreads();  // B2
+        __syncthreads();  // A -> B
 
-        // ---------------- phase 3: bank-row prefix, staging claim ---------
-        if (wave == 0) {
+        // ================= B: 1b(f) | 3(f-1) ======================================
+        if (cur_ok) {
+            constexpr int G = 64 / L;
+            const int grp = lane / L, gl = lane - grp * L;
+            const int i = wave * G + grp;
+            const bool act = i < BR;
+            const int row = act ? i / nb : 0;
+            const int bank = act ? i - row * nb : 0;
+            const float *src = u_c + row * W + bank * B;
+            float x[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int c = L * v + gl;
+                x[v] = (act && c < B) ? src[c] : INFINITY;
+            }
+            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 8.0f, act);
+            if (act && gl == 0) {
+                med_c[i] = m;
+                s_th[i] = seed_threshold(m, A.t_seed);
+            }
+        }
+        if (prev_ok && wave == kP3Wave) {
+            // bank-row prefix of frame f-1's hit counts, staging chunk claim
             uint32_t total = 0;
-            if (!overflow) {
-                for (int base = 0; base < BR; base += 64) {
-                    const int i = base + lane;
-                    const uint32_t c = i < BR ? s_cnt[par * A.rmax * nb + i] : 0u;
-                    uint32_t incl = c;
-                    for (int d = 1; d < 64; d <<= 1) {
-                        uint32_t y = __shfl_up(incl, d, 64);
-                        if (lane >= d) incl += y;
-                    }
+            if (!ovf_p) {
+                for (int b0 = 0; b0 < BR; b0 += 64) {
+                    const int i = b0 + lane;
+                    const uint32_t c = i < BR ? s_cnt[pp * RN + i] : 0u;
+                    const uint32_t incl = wave_incl_scan(c);
                     if (i < BR) s_pref[i] = total + incl - c;
-                    total += __shfl(incl, 63, 64);
+                    total += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
                 }
             }
             if (lane == 0) {
-                const uint64_t unit = f * (uint64_t)A.n_strips + strip;
+                const uint64_t unit = (f - 1) * (uint64_t)A.n_strips + strip;
                 uint64_t base = chunk_cur;
-                if (overflow) {
+                if (ovf_p) {
                     atomicOr(&A.state->fallback, 1u);
                     base = kNoBase;
                 } else if (total > 0) {
@@ -574,32 +543,91 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 A.unit_photons[unit] = s_photons;
                 s_photons = 0;
                 s_base = base;
-                s_nseed[par ^ 1] = 0;
             }
         }
-        __syncthreads();  // B3
+        __syncthreads();  // B -> C
 
-        // ---------------- phase 4: raster-ordered write of the hits --------
-        const uint64_t base = s_base;
-        if (base != kNoBase && !overflow) {
-            for (uint32_t j = tid; j < nseed; j += kV2Threads) {
-                const float qv = s_q[par * A.seed_cap + j];
-                if (qv < 0.0f) continue;
-                const uint32_t key = s_seed[par * A.seed_cap + j];
-                const int i = key >> 16, col = key & 0xFFFF;
-                const int row = i / nb, bank = i - (i / nb) * nb;
-                const int cb = col - bank * B;
-                const uint32_t *bw = s_bits + (par * A.rmax * nb + i) * 8;
-                uint32_t rank = 0;
-                for (int w = 0; w < (cb >> 5); ++w) rank += __popc(bw[w]);
-                rank += __popc(bw[cb >> 5] & ((1u << (cb & 31)) - 1u));
-                const uint32_t pix = row_base + (uint32_t)row * W + col;
-                A.pool[base + s_pref[i] + rank] = make_uint2(pix, __float_as_uint(qv));
+        // ================= C: 1c(f) | 4(f-1) ======================================
+        if (cur_ok) {
+            uint32_t seedbits = 0;  // bit (g*NV + v) set: seed at this lane's value-slot v of bank-row g
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                if (g >= ng) break;
+                const int i = wave + kV2Waves * g;
+                const int row = row_[g];
+                if (row >= own_lo && row < own_hi) {
+                    float xs[NV];  // absent pixels: -inf (never a seed)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q) {
+                        if (lane_ok[q]) {
+                            const float2 u2 = *reinterpret_cast<const float2 *>(u_c + gb_[g] + 128 * q + lane_off);
+                            xs[2 * q] = u2.x;
+                            xs[2 * q + 1] = u2.y;
+                        } else {
+                            xs[2 * q] = -INFINITY;
+                            xs[2 * q + 1] = -INFINITY;
+                        }
+                    }
+                    const float th = uniform_f(s_th[i]);
+                    if (KEEP) {
+                        const float m = uniform_f(med_c[i]);
+#pragma unroll
+                        for (int q = 0; q < NQ; ++q)
+                            if (lane_ok[q]) {
+                                float2 v2 = make_float2(__fsub_rn(xs[2 * q], m), __fsub_rn(xs[2 * q + 1], m));
+                                *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q +
+                                                            lane_off) = v2;
+                            }
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; ++v)
+                        if (xs[v] >= th) seedbits |= 1u << (g * NV + v);
+                }
+            }
+            // append to the pooled list (order is free; phase 4 restores
+            // raster order): DPP prefix of the lanes' counts, one LDS atomic
+            const uint32_t ns = (uint32_t)__popc(seedbits);
+            const uint32_t incl = wave_incl_scan(ns);
+            const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+            if (wtot) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&s_nseed[par], wtot);
+                uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
+#pragma unroll
+                for (int g = 0; g < GMAX; ++g) {
+                    if (g >= ng) break;
+                    uint32_t bits = (seedbits >> (g * NV)) & ((1u << NV) - 1u);
+                    const int colbase = bank_[g] * B + 2 * lane;
+                    while (bits) {
+                        const int v = __ffs(bits) - 1;
+                        bits &= bits - 1;
+                        if (pos < (uint32_t)cap)
+                            s_seed[par * cap + pos] = seed_key(row_[g], bank_[g], colbase + 128 * (v >> 1) + (v & 1));
+                        ++pos;
+                    }
+                }
             }
         }
-        // clear the other parity's bitmaps and counters for the next frame
-        for (int x = tid; x < A.rmax * nb * 8; x += kV2Threads) s_bits[(par ^ 1) * A.rmax * nb * 8 + x] = 0;
-        for (int x = tid; x < A.rmax * nb; x += kV2Threads) s_cnt[(par ^ 1) * A.rmax * nb + x] = 0;
+        if (prev_ok && !ovf_p) {
+            const uint64_t base = s_base;
+            if (base != kNoBase) {
+                for (uint32_t j = tid; j < nseed_p; j += kV2Threads) {
+                    const float qv = s_q[pp * cap + j];
+                    if (qv < 0.0f) continue;
+                    const uint32_t key = s_seed[pp * cap + j];
+                    const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
+                    const int i = row * nb + bank;
+                    const int cb = col - bank * B;
+                    const uint32_t *bw = s_bits + (pp * RN + i) * 8;
+                    uint32_t rank = 0;
+                    for (int w = 0; w < (cb >> 5); ++w) rank += __popc(bw[w]);
+                    rank += __popc(bw[cb >> 5] & ((1u << (cb & 31)) - 1u));
+                    const uint32_t pix = row_base + (uint32_t)row * W + col;
+                    A.pool[base + s_pref[i] + rank] = make_uint2(pix, __float_as_uint(qv));
+                }
+            }
+        }
+        __syncthreads();  // C -> next A
     }
 }
 

@@ -268,9 +268,10 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     d.n_strips = (int)strips.size();
     d.rmax = rmax;
     d.v2_max_unit_hits = (uint32_t)((own_rows_max + 1) / 2) * (uint32_t)((g.cols + 1) / 2);
-    // seed list: as large as the LDS allows up to 96 KB per workgroup (which also
-    // keeps one workgroup per compute unit), at least 1024 entries
-    const size_t lds_cap = std::min<size_t>((size_t)ctx->max_lds, 96 * 1024);
+    // seed lists: as large as the workgroup's LDS allows (the kernel's
+    // registers admit one workgroup per compute unit anyway), at least 1024
+    // entries; 256 bytes stay free for the kernel's static LDS
+    const size_t lds_cap = (size_t)ctx->max_lds > 256 ? (size_t)ctx->max_lds - 256 : 0;
     size_t base = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, 0);
     if (base + 4 * 4 * 1024 > lds_cap) return false;
     d.seed_cap = (int)std::min<size_t>((lds_cap - base) / 16, 16384);
