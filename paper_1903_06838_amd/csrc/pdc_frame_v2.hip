@@ -115,17 +115,25 @@ __device__ __forceinline__ int lane_count(const float (&x)[V], float p)
     return (int)t[0];
 }
 
+// [lo, hi) holds a single float (adjacent keys, both bounds finite or not).
+__device__ __forceinline__ bool done_single(float lo, float hi)
+{
+    return (uint32_t)(f2key(hi) - f2key(lo)) <= 1u;
+}
+
 // Exact element of rank k (0-based, ascending) among the nval finite values
 // held by an L-lane group (V values per lane, absent values +inf); every
 // group of the wave searches its own bank at once.  Bracketing search on
 // counts, count(x < lo) <= k < count(x < hi) throughout: the first step tests
 // est - w0 and est + w0 together (widening until they bracket), later steps
-// interpolate the pivot from the bracket counts and bisect when the
-// interpolated pivot is not strictly inside or the bracket stopped halving.  Once at most two values remain in [lo, hi) (or [lo, hi) holds a
-// single float), the answer is min{x >= lo} when k == count(x < lo), else
-// max{x < hi}.  Groups with act false return an unspecified value.
+// interpolate the pivot from the bracket counts and bisect in key space when
+// the interpolated pivot is not strictly inside or the bracket stopped
+// halving.  Once at most L values remain in [lo, hi) they are sorted across
+// the group's lanes and the answer is read off; a bracket that holds a single
+// float (possibly many copies of it) gives that float.  Groups with act false
+// return an unspecified value.
 template <int V, int L>
-__device__ float group_median(const float (&x)[V], int nval, int k, float w0, bool act)
+__device__ float group_median(const float (&x)[V], int nval, int k, float w0, bool act, float *gsc)
 {
     static_assert(V >= 3, "the start estimate takes triples of values per lane");
     // start: medians of three of each lane's values (up to eight triples),
@@ -187,17 +195,14 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float w0, bo
         const bool interp = 2 * n <= last_n && q > lo && q < hi;
         bool single = false;  // [lo, hi) holds one float only (never when interp holds)
         if (!interp) {
-            // bisect in value space; in key space only when no float lies
-            // strictly between the value midpoint and the bounds (adjacent
-            // floats) or a bound is infinite
-            q = lo + (hi - lo) * 0.5f;
-            if (!(q > lo && q < hi)) {
-                const int32_t klo = f2key(lo), khi = f2key(hi);
-                single = (uint32_t)(khi - klo) <= 1u;
-                q = key2f((klo >> 1) + (khi >> 1) + (klo & khi & 1));
-            }
+            // bisect in key space: at most 32 such steps reach a bracket that
+            // holds a single float, whatever the scale (a value-space midpoint
+            // would halve a bracket [0, h) through the whole exponent range)
+            const int32_t klo = f2key(lo), khi = f2key(hi);
+            single = (uint32_t)(khi - klo) <= 1u;
+            q = key2f((klo >> 1) + (khi >> 1) + (klo & khi & 1));
         }
-        done = done || n <= 2 || single;
+        done = done || n <= L || single;
         if (__ballot(!done) == 0) break;
         last_n = interp ? n : 4 * nval;
         const int cq = gsum_i<L>(lane_count<V>(x, q));
@@ -211,18 +216,76 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float w0, bo
             }
         }
     }
-    // min{x >= lo} = min{s x >= lo} with s = 1, or max{x < hi} = -min{s x >= b}
-    // with s = -1 and b the float just above -hi
-    const bool lowm = k == clo;
-    const float sg = lowm ? 1.0f : -1.0f;
-    const float bnd = lowm ? lo : key2f(f2key(-hi) + 1);
-    float r = INFINITY;
+    // Finish: the n <= L values in [lo, hi) are compacted into the group's
+    // lanes through LDS (gsc: L floats per group, in lane order), sorted
+    // across the lanes, and lane k - clo holds the answer.  A bracket that
+    // holds a single float (n > L possible) has the answer lo.
+    const int gl = __lane_id() & (L - 1);
+    uint32_t cm = 0;
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const float t = sg * x[v];
-        r = fminf(r, t >= bnd ? t : INFINITY);
+    for (int v = 0; v < V; ++v) cm |= (uint32_t)(x[v] >= lo && x[v] < hi) << v;
+    const int c = __popc(cm);
+    int incl = c;
+#define PDC_SCAN(ctrl, sh)                                                                       \
+    {                                                                                            \
+        const int o = __builtin_amdgcn_update_dpp(0, incl, ctrl, 0xF, 0xF, true);                 \
+        incl += gl >= sh ? o : 0;                                                                \
     }
-    return sg * gmin_f<L>(r);
+    PDC_SCAN(0x111, 1)
+    if (L >= 4) PDC_SCAN(0x112, 2)
+    if (L >= 8) PDC_SCAN(0x114, 4)
+    if (L >= 16) PDC_SCAN(0x118, 8)
+#undef PDC_SCAN
+    const bool gather = !done_single(lo, hi);
+    float *gb = gsc - gl;  // the group's L slots
+    int pos = incl - c;
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+        if ((cm >> v) & 1u) {
+            if (gather && pos < L) gb[pos] = x[v];
+            ++pos;
+        }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    const int n = chi - clo;
+    float y = (gather && gl < n) ? gb[gl] : INFINITY;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    // ascending bitonic sort over the group's lanes: merges of size 2b start
+    // with the mirror partner inside the block, then halve with xor partners
+#define PDC_CX(partner, lower)                                                                   \
+    {                                                                                            \
+        const float o_ = (partner);                                                              \
+        y = (lower) ? fminf(y, o_) : fmaxf(y, o_);                                               \
+    }
+#define PDC_DPP(ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), ctrl, 0xF, 0xF, false))
+    PDC_CX(PDC_DPP(0xB1), !(gl & 1))                      // merge 2: mirror (xor 1)
+    if (L >= 4) {
+        PDC_CX(PDC_DPP(0x1B), !(gl & 2))                  // merge 4: mirror in 4
+        PDC_CX(PDC_DPP(0xB1), !(gl & 1))
+    }
+    if (L >= 8) {
+        PDC_CX(PDC_DPP(0x141), !(gl & 4))                 // merge 8: row_half_mirror
+        PDC_CX(PDC_DPP(0x4E), !(gl & 2))                  // xor 2
+        PDC_CX(PDC_DPP(0xB1), !(gl & 1))
+    }
+    if (L >= 16) {
+        PDC_CX(PDC_DPP(0x140), !(gl & 8))                 // merge 16: row_mirror
+        {
+            const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x104, 0xF, 0xF, true));  // row_shl:4
+            const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x114, 0xF, 0xF, true));  // row_shr:4
+            PDC_CX((gl & 4) ? up : dn, !(gl & 4))         // xor 4
+        }
+        PDC_CX(PDC_DPP(0x4E), !(gl & 2))
+        PDC_CX(PDC_DPP(0xB1), !(gl & 1))
+    }
+#undef PDC_DPP
+#undef PDC_CX
+    const float pick = gl == k - clo ? y : -INFINITY;
+    const float r = -gmin_f<L>(-pick);
+    return gather ? r : lo;
 }
 
 // Smallest binary32 value th such that fl(th - m) > t (fl(x - m) is
@@ -240,7 +303,7 @@ __device__ __forceinline__ float seed_threshold(float m, float t)
 }
 
 struct V2Layout {
-    uint32_t u, med, th, bits, cnt, seed, q, nseed, pref, total;  // float offsets
+    uint32_t u, med, th, bits, cnt, seed, q, nseed, pref, gs, total;  // float offsets
 };
 
 // LDS of one workgroup (floats): u and med are double-buffered by frame
@@ -267,6 +330,8 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
     o += 2;
     L.pref = o;
     o += (uint32_t)rmax * nb + 1;
+    L.gs = o;
+    o += 1024;
     L.total = o;
     return L;
 }
@@ -274,7 +339,7 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
     size_t o = 2ull * rmax * W + 2ull * rmax * nb + (size_t)rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
-               4ull * seed_cap + 2 + (size_t)rmax * nb + 1;
+               4ull * seed_cap + 2 + (size_t)rmax * nb + 1 + 1024;
     return o * 4;
 }
 
@@ -307,6 +372,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     float *s_q = lds + Ly.q;
     uint32_t *s_nseed = reinterpret_cast<uint32_t *>(lds + Ly.nseed);
     uint32_t *s_pref = reinterpret_cast<uint32_t *>(lds + Ly.pref);
+    float *s_gs = lds + Ly.gs;  // one slot per thread: median finish scratch
 
     const int item = A.wg_item[blockIdx.x];
     const int strip = item % A.n_strips;
@@ -500,7 +566,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const int c = L * v + gl;
                 x[v] = (act && c < B) ? src[c] : INFINITY;
             }
-            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 8.0f, act);
+            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 8.0f, act, s_gs + tid);
             if (act && gl == 0) {
                 med_c[i] = m;
                 s_th[i] = seed_threshold(m, A.t_seed);
