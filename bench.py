@@ -42,7 +42,8 @@ METRIC = "Mpixel/s processed (% of HBM roofline), bit-exact hits; p99 frame late
 HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frame_kernel_cspad_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_06838_amd", "csrc", f)
-                  for f in ("pdc_kernels.hip", "pdc_runtime.cpp", "pdc_internal.h")]
+                  for f in ("pdc_frame_v2.hip", "pdc_kernels.hip", "pdc_runtime.cpp", "pdc_internal.h",
+                            "pdc_device.h")]
 MAIN_KERNEL_PREFIX = "frame_kernel"
 COPY_BYTES = 2 << 30
 
@@ -129,10 +130,20 @@ def cpu_baseline(pool, ped, gain, bank_cols, gpu_fh, gpu_fp, gpu_hits_fn):
     threads = min(16, os.cpu_count() or 1, P)
     bounds = np.linspace(0, P, threads + 1).astype(int)
     parts = [(bounds[i], bounds[i + 1]) for i in range(threads) if bounds[i + 1] > bounds[i]]
+    # repeated passes over the pool until at least min_s seconds of wall time
+    # (the first pass's results are the ones compared with the GPU)
+    min_s = 12.0
+    passes = 0
     t0 = time.perf_counter()
     with cf.ThreadPoolExecutor(len(parts)) as ex:
-        outs = list(ex.map(lambda ab: o.process(pool[ab[0]:ab[1]], ped, gain, bank_cols), parts))
-    wall = time.perf_counter() - t0
+        while True:
+            res = list(ex.map(lambda ab: o.process(pool[ab[0]:ab[1]], ped, gain, bank_cols), parts))
+            if passes == 0:
+                outs = res
+            passes += 1
+            wall = time.perf_counter() - t0
+            if wall >= min_s:
+                break
     fh = np.concatenate([r["frame_hits"] for r in outs])
     fp = np.concatenate([r["frame_photons"] for r in outs])
     hits = []
@@ -146,10 +157,11 @@ def cpu_baseline(pool, ped, gain, bank_cols, gpu_fh, gpu_fp, gpu_hits_fn):
     g = gpu_hits_fn(int(fh.sum()))
     exact = exact and g is not None and np.array_equal(
         np.ascontiguousarray(g).view(np.uint32), np.ascontiguousarray(hits).view(np.uint32))
-    rate = pool.size / wall / 1e6
+    rate = passes * pool.size / wall / 1e6
     return {"value": round(rate, 2), "unit": "Mpixel/s", "cores": len(parts), "kind": "oracle",
-            "sample": "%d CSPAD-like frames (32x185x388, occupancy 0.01), the distinct frames the "
-                      "10,000-frame GPU batch replicates; %.1f s wall" % (P, wall)}, exact
+            "sample": "%d passes over %d CSPAD-like frames (32x185x388, occupancy 0.01), the distinct "
+                      "frames the 10,000-frame GPU batch replicates: %d frames in %.1f s wall"
+                      % (passes, P, passes * P, wall)}, exact
 
 
 def latency(torch, pdc, ctx, det, frame, calls=300):

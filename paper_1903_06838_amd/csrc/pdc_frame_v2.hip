@@ -125,7 +125,7 @@ __device__ __forceinline__ bool done_single(float lo, float hi)
 // held by an L-lane group (V values per lane, absent values +inf); every
 // group of the wave searches its own bank at once.  Bracketing search on
 // counts, count(x < lo) <= k < count(x < hi) throughout: the first step tests
-// est - w0 and est + w0 together (widening until they bracket), later steps
+// est -/+ 6 rank widths rw together (widening until they bracket), later steps
 // interpolate the pivot from the bracket counts and bisect in key space when
 // the interpolated pivot is not strictly inside or the bracket stopped
 // halving.  Once at most L values remain in [lo, hi) they are sorted across
@@ -133,7 +133,7 @@ __device__ __forceinline__ bool done_single(float lo, float hi)
 // float (possibly many copies of it) gives that float.  Groups with act false
 // return an unspecified value.
 template <int V, int L>
-__device__ float group_median(const float (&x)[V], int nval, int k, float w0, bool act, float *gsc)
+__device__ float group_median(const float (&x)[V], int nval, int k, float rw, bool act, float *gsc)
 {
     static_assert(V >= 3, "the start estimate takes triples of values per lane");
     // start: medians of three of each lane's values (up to eight triples),
@@ -155,6 +155,7 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float w0, bo
     const int nl = gsum_i<L>(n3);
     const float est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
 
+    const float w0 = 6.0f * rw;
     float lo = est - w0, hi = est + w0;
     int clo, chi;
     {
@@ -163,12 +164,15 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float w0, bo
         chi = pk >> 16;
     }
     bool ok = !act || (clo <= k && k < chi);
-    float w = w0;
+    // widening: a start bracket that misses by m ranks moves its violated
+    // bound (m + 3) rank widths beyond, doubling the step on repeated misses
+    float sc = rw;
     for (int it = 0; it < 40; ++it) {
         if (__ballot(!ok) == 0) break;
-        w = w + w;
         const bool down = clo > k;
-        const float p = it < 38 ? (down ? est - w : est + w) : (down ? -INFINITY : INFINITY);
+        const float d = (float)((down ? clo - k : k + 1 - chi) + 3) * sc;
+        sc = sc + sc;
+        const float p = it < 38 ? (down ? lo - d : hi + d) : (down ? -INFINITY : INFINITY);
         const int cp = gsum_i<L>(lane_count<V>(x, p));
         if (!ok) {
             if (down) {
@@ -566,7 +570,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const int c = L * v + gl;
                 x[v] = (act && c < B) ? src[c] : INFINITY;
             }
-            const float m = group_median<V, L>(x, B, kmed, A.rank_width * 8.0f, act, s_gs + tid);
+            const float m = group_median<V, L>(x, B, kmed, A.rank_width, act, s_gs + tid);
             if (act && gl == 0) {
                 med_c[i] = m;
                 s_th[i] = seed_threshold(m, A.t_seed);
