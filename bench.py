@@ -13,7 +13,10 @@ frames replicated on the device (45.9 GB, far larger than the on-chip caches).
 Printed: ONE JSON line with the throughput (Mpixel/s), the roofline of the
 dominant kernel (algorithmic HBM bytes / its event-timed duration against the
 8 TB/s peak), the CPU oracle's rate on the 64-frame pool (which also checks the
-GPU hits of that pool), single-frame latency percentiles, and an occupancy
+GPU hits of that pool), single-frame latency percentiles, a four-detector
+serving run (Poisson arrivals at 1 and 20 kHz per detector, p50/p99 latency),
+the learned subpixel
+estimator against centroid + eta on 10 M simulated hits, and an occupancy
 sweep.
 
 Other modes:
@@ -185,6 +188,122 @@ def latency(torch, pdc, ctx, det, frame, calls=300):
             "kernel_ms_p50": q(kern, 50), "kernel_ms_p99": q(kern, 99), "calls": calls}
 
 
+def subpixel(torch, pdc, ctx, n_total=10_000_000, steps=4000, bs=2048, lr=2e-3, photon_adu=150.0, t_nb=9.0):
+    """Learned subpixel positions against centroid + eta on simulated hits:
+    10 M charge-sharing patches, 90/10 split; RMS error and hits/s, all
+    through the C ABI on the torch stream."""
+    import numpy as np
+
+    from paper_1903_06838_amd import synth
+
+    dev = torch.device("cuda:0")
+    # a stream of our own: torch's default stream has handle 0, which the
+    # library reads as "the context's stream", so events on it would time nothing
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    P, T = synth.make_patches(n_total, seed=31)
+    n_tr = n_total * 9 // 10
+    n_te = n_total - n_tr
+    dP = torch.from_numpy(P).to(dev)
+    dT = torch.from_numpy(T).to(dev)
+    del P
+    Pte, Tte = dP[n_tr:], T[n_tr:]
+    ev = lambda: torch.cuda.Event(enable_timing=True)  # recorded on `stream` (current)
+    # classical: eta table over the training split, centroid + eta on the test split
+    nb = 1023
+    table = torch.zeros((2, nb + 1), dtype=torch.float32, device=dev)
+    ws = torch.zeros(2 * nb, dtype=torch.int32, device=dev)
+    ce = torch.zeros((n_te, 2), dtype=torch.float32, device=dev)
+    pdc.eta_table(ctx, dP, n_tr, t_nb, nb, ws, table, stream)
+    pdc.centroid(ctx, Pte, n_te, t_nb, ce, eta_dev=table, nbins=nb, stream=stream)
+    e0, e1 = ev(), ev()
+    e0.record()
+    for _ in range(5):
+        pdc.centroid(ctx, Pte, n_te, t_nb, ce, eta_dev=table, nbins=nb, stream=stream)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_ce = e0.elapsed_time(e1) / 5
+    # learned: He-uniform start, Adam on minibatches of the training split
+    rng = np.random.default_rng(0)
+    shapes = [(25, 64), (64,), (64, 64), (64,), (64, 2), (2,)]
+    theta = np.concatenate([rng.uniform(-np.sqrt(6.0 / s[0]), np.sqrt(6.0 / s[0]), size=s).ravel()
+                            if len(s) == 2 else np.zeros(s) for s in shapes]).astype(np.float32)
+    net = pdc.mlp_create(ctx, theta)
+    try:
+        e0.record()
+        for it in range(steps):
+            o = (it * bs) % (n_tr - bs)
+            pdc.mlp_train_step(net, dP[o:o + bs], dT[o:o + bs], bs, photon_adu, lr, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_train = e0.elapsed_time(e1)
+        loss = pdc.mlp_last_loss(net)
+        y = torch.zeros((n_te, 2), dtype=torch.float32, device=dev)
+        pdc.mlp_infer(net, Pte, n_te, photon_adu, y, stream)
+        e0.record()
+        for _ in range(5):
+            pdc.mlp_infer(net, Pte, n_te, photon_adu, y, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_inf = e0.elapsed_time(e1) / 5
+    finally:
+        pdc.mlp_destroy(net)
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    rms = lambda a: float(np.sqrt(np.mean((a.cpu().numpy() - Tte) ** 2)))
+    inf_bytes = n_te * (25 * 4 + 2 * 4)
+    inf_flop = n_te * 2 * (25 * 64 + 64 * 64 + 64 * 2)
+    return {"hits": n_total, "train": n_tr, "test": n_te, "train_steps": steps, "batch": bs, "lr": lr,
+            "rms_px_mlp": round(rms(y), 5), "rms_px_centroid_eta": round(rms(ce), 5),
+            "final_train_loss": round(loss, 6),
+            "mlp_infer_hits_per_s": round(n_te / (ms_inf / 1e3), 1),
+            "mlp_infer_GBps": round(inf_bytes / (ms_inf / 1e3) / 1e9, 1),
+            "mlp_infer_TFLOPs_bf16": round(inf_flop / (ms_inf / 1e3) / 1e12, 2),
+            "centroid_eta_hits_per_s": round(n_te / (ms_ce / 1e3), 1),
+            "train_hits_per_s": round(steps * bs / (ms_train / 1e3), 1),
+            "data": "synthetic charge-sharing patches (uniform impact points, cloud sigma U(0.1, 0.4) px, "
+                    "3 ADU noise, 150 ADU photons)"}
+
+
+def serving(torch, pdc, ctx, rate_hz=20000.0, seconds=0.4, max_batch=64, max_inflight=2):
+    """Four detectors as Poisson frame streams (CSPAD-like, ePix100, Jungfrau-like
+    512x1024 with 256-pixel banks, ePix10k-like), each frame resident in a
+    16-frame device pool, served with continuous batching; latency = completion
+    seen by the host - arrival."""
+    import numpy as np
+
+    from paper_1903_06838_amd import synth
+
+    dets = [("cspad", synth.CSPAD), ("epix100", synth.EPIX100), ("jungfrau_0.5M", synth.Geometry(1, 512, 1024, 256)),
+            ("epix10k", synth.Geometry(1, 704, 768, 96))]
+    streams, handles = [], []
+    n = int(rate_hz * seconds)
+    for j, (name, g) in enumerate(dets):
+        ped, gain = synth.make_calibration(g, 60 + j)
+        pool = torch.from_numpy(synth.make_frames(g, ped, gain, 16, 0.01, 60 + j)).cuda()
+        det = pdc.calibrate(ctx, pdc.geometry(*g.shape, g.bank_cols), ped, gain, pdc.params())
+        handles.append(det)
+        arr = np.cumsum(np.random.default_rng(90 + j).exponential(1e9 / rate_hz, size=n)).astype(np.uint64)
+        streams.append(dict(det=det, pool=pool, arrival_ns=arr, hit_fraction=0.03))
+    res, _, summ = pdc.serve_run(ctx, streams, max_batch=max_batch, max_inflight=max_inflight)
+    out = {"rate_hz_per_detector": rate_hz, "seconds": seconds, "max_batch": max_batch,
+           "max_inflight": max_inflight, "frames": summ["frames_done"], "dropped": summ["frames_dropped"],
+           "batches": summ["batches"], "wall_s": round(summ["wall_ns"] / 1e9, 4), "detectors": {}}
+    px = 0
+    for (name, g), r in zip(dets, res):
+        ok = r["status"] == 1
+        lat = (r["done_ns"][ok] - r["arrival_ns"][ok]) / 1e6
+        px += int(ok.sum()) * g.pixels
+        out["detectors"][name] = {"pixels": g.pixels, "frames": int(ok.sum()),
+                                  "latency_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                                  "latency_ms_p99": round(float(np.percentile(lat, 99)), 4),
+                                  "mean_batch": round(float(r["batch_frames"][ok].mean()), 2)}
+    out["Mpixel_s"] = round(px / (summ["wall_ns"] / 1e9) / 1e6, 1)
+    out["offered_Mpixel_s"] = round(sum(g.pixels for _, g in dets) * rate_hz / 1e6, 1)
+    for det in handles:
+        pdc.release_detector(ctx, det)
+    return out
+
+
 # ---------------------------------------------------------------------------
 def ingest_pmc(fetch_csv, write_csv):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the frame kernel, scaled by
@@ -235,6 +354,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-latency", action="store_true")
+    ap.add_argument("--no-subpixel", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
@@ -324,6 +445,14 @@ def main():
         pdc.release_detector(ctx, edet)
         out["latency"] = lat
         log("latency: %s" % lat)
+
+    if not args.no_serve:
+        out["serving"] = [serving(torch, pdc, ctx, rate_hz=r) for r in (1000.0, 20000.0)]
+        log("serving: %s" % out["serving"])
+
+    if not args.no_subpixel:
+        out["subpixel"] = subpixel(torch, pdc, ctx)
+        log("subpixel: %s" % out["subpixel"])
 
     if not args.no_sweep:
         sweep = [{"occupancy": 0.01, "Mpixel_s": out["value"], "frac": out["roofline"]["frac"],

@@ -132,7 +132,10 @@ pdc_status pdc_release_detector(pdc_ctx *ctx, int32_t det);
  *   from it.  If the batch holds more, pdc_get_hits recomputes it with exact
  *   sizes, so the result is always complete.
  * hip_stream: a hipStream_t of the context's device, or NULL for the
- *   context's own stream.  The call returns once the work is enqueued.
+ *   context's own stream.  That stream is non-blocking: it is not ordered
+ *   with other streams (the HIP null stream included), so frames written on
+ *   another stream must be complete before the call (synchronize, or pass
+ *   the producing stream).  The call returns once the work is enqueued.
  * *batch_out: id for pdc_get_hits / pdc_get_corrected / pdc_release_batch.
  * n_frames may be 0.  Results of a frame do not depend on the other frames of
  * the batch.  EINVAL on a bad pointer or size, ESTATE on an unknown detector,
@@ -176,8 +179,9 @@ pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float 
  * position is (dy, dx) in pixel pitches relative to the centre of the hit
  * pixel.  Patch, position and table arguments named *_dev are DEVICE pointers
  * of the context's device; hip_stream is a hipStream_t of that device or NULL
- * for the context's stream; the calls return once the work is enqueued unless
- * stated otherwise.  EINVAL for a NULL pointer with n > 0 or an out-of-range
+ * for the context's (non-blocking) stream, which is not ordered with other
+ * streams: inputs and outputs touched on another stream must be complete
+ * first.  The calls return once the work is enqueued unless stated otherwise.  EINVAL for a NULL pointer with n > 0 or an out-of-range
  * scalar.
  * ------------------------------------------------------------------------ */
 
@@ -246,6 +250,66 @@ pdc_status pdc_mlp_train_step(pdc_mlp *net, const float *patches_dev, const floa
 /* L of the last pdc_mlp_train_step, at the parameters before its update
  * (synchronous).  ESTATE before the first step. */
 pdc_status pdc_mlp_last_loss(pdc_mlp *net, double *loss);
+
+/* ------------------------------------------------------------------------
+ * Serving loop: several detectors' frame streams, each frame arriving at its
+ * own time, processed on one GPU with continuous batching.  Each stream gets
+ * its own HIP stream, so batches of different detectors overlap on the
+ * device; a stream launches whatever has arrived (up to max_batch frames,
+ * contiguous in its pool) whenever it has fewer than max_inflight batches in
+ * flight and the device-memory budget admits the batch; arrivals beyond
+ * max_queue waiting frames are dropped.  Results of a frame never depend on
+ * the batch it was processed in (the per-frame contract above).  The run
+ * ends when every frame is done or dropped; it blocks the calling thread
+ * (a polling loop on the host clock).
+ * ------------------------------------------------------------------------ */
+#define PDC_SERVE_PENDING 0
+#define PDC_SERVE_DONE 1
+#define PDC_SERVE_DROPPED 2
+
+typedef struct {
+    uint64_t arrival_ns, launch_ns, done_ns;  /* host steady clock, from the start of the run */
+    uint32_t hits;                            /* hits of the frame */
+    uint32_t batch_frames;                    /* frames in the batch it was processed in */
+    uint64_t photons;                         /* photons of the frame */
+    int32_t status;                           /* PDC_SERVE_* */
+    int32_t reserved;
+} pdc_serve_frame;
+
+typedef struct {
+    int32_t det;                 /* detector id from pdc_calibrate */
+    uint32_t pool_frames;        /* frames in pool_dev (>= 1 when n_frames > 0) */
+    const uint16_t *pool_dev;    /* DEVICE frames [pool_frames][pixels_per_frame]; frame i of the
+                                    stream is pool frame i % pool_frames; borrowed for the run */
+    uint64_t pixels_per_frame;   /* n_tiles * rows * cols of the detector */
+    uint64_t n_frames;           /* frames of the stream */
+    const uint64_t *arrival_ns;  /* host [n_frames], non-decreasing, from the start of the run */
+    double hit_fraction;         /* hits per pixel to size batch buffers (exceeding it only costs
+                                    a recomputation) */
+    pdc_serve_frame *results;    /* host [n_frames], written by the run */
+    pdc_hit *hits;               /* host hit records of the stream in (frame, pixel) order with
+                                    frame = stream frame index, or NULL */
+    uint64_t hits_capacity;      /* records the hits array holds (excess hits are not kept) */
+    uint64_t hits_kept;          /* out: records written */
+} pdc_serve_stream;
+
+typedef struct {
+    uint32_t max_batch;          /* frames per launch, >= 1 */
+    uint32_t max_inflight;       /* batches in flight per stream, 1..64 */
+    uint64_t max_queue;          /* waiting frames per stream before arrivals are dropped (0: none) */
+    uint64_t hbm_budget;         /* bytes of in-flight batch buffers over all streams (0: none);
+                                    a stream with nothing in flight may always launch */
+} pdc_serve_config;
+
+typedef struct {
+    uint64_t frames_done, frames_dropped, batches, peak_bytes, wall_ns;
+} pdc_serve_summary;
+
+/* Run the serving loop over n_streams (1..64) streams.  EINVAL on a bad
+ * argument (NULL arrays, decreasing arrival times, zero sizes); errors of the
+ * calls it makes are returned as they are.  summary may be NULL. */
+pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_streams,
+                         const pdc_serve_config *cfg, pdc_serve_summary *summary);
 
 /* Test hook: D = A B for one 16x32 by 32x16 bfloat16 tile through the MFMA
  * operand loads the network kernels use.  A (uint16 bf16 bits [16][32]),

@@ -68,6 +68,7 @@ struct Buffers {
     BatchState *state = nullptr;
     BatchState *host_state = nullptr;  // pinned mirror
     hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr;
+    hipEvent_t ev_state = nullptr;  // after the state copy: the batch's last work on its stream
 };
 
 struct Batch {
@@ -104,6 +105,7 @@ void free_buffers(Buffers *b)
     if (b->ev_start) hipEventDestroy(b->ev_start);
     if (b->ev_main) hipEventDestroy(b->ev_main);
     if (b->ev_end) hipEventDestroy(b->ev_end);
+    if (b->ev_state) hipEventDestroy(b->ev_state);
     delete b;
 }
 
@@ -114,6 +116,7 @@ struct pdc_ctx {
     int n_cu = 0;
     int max_lds = 0;
     hipStream_t stream = nullptr;
+    hipStream_t copy_stream = nullptr;  // result copies: they wait for their batch only
     std::vector<Detector> dets;
     std::map<uint64_t, Batch> batches;
     std::vector<Buffers *> spare;
@@ -323,6 +326,7 @@ pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n
         HIP_TRY(ctx, hipEventCreate(&b->ev_start));
         HIP_TRY(ctx, hipEventCreate(&b->ev_main));
         HIP_TRY(ctx, hipEventCreate(&b->ev_end));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&b->ev_state, hipEventDisableTiming));
     }
     if (n_units > b->cap_units || !b->unit_count) {
         uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
@@ -445,6 +449,7 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
                                 bt.n_units, bt.upf, b->hits, b->cap_pool, s));
     HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
     HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_state, s));
     return PDC_OK;
 }
 
@@ -472,7 +477,7 @@ Batch *find_batch(pdc_ctx *ctx, uint64_t id)
 // capacity so that its hit list is complete.
 pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
 {
-    HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+    HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
     if (bt.checked) return PDC_OK;
     BatchState st = *bt.buf->host_state;
     if (st.fallback) {
@@ -486,7 +491,7 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
         bt.pool_cap = cap;
         rc = enqueue(ctx, bt);
         if (rc != PDC_OK) return rc;
-        HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+        HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
         st = *bt.buf->host_state;
     }
     if (st.overflow) {
@@ -497,7 +502,7 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
         bt.pool_cap = cap;
         rc = enqueue(ctx, bt);
         if (rc != PDC_OK) return rc;
-        HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+        HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
         if (bt.buf->host_state->overflow)
             return fail(ctx, PDC_EDEVICE, "staging overflow persisted after resizing");
     }
@@ -564,7 +569,9 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) != hipSuccess) lds = 65536;
         ctx->max_lds = lds;
     }
-    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&ctx->copy_stream, hipStreamNonBlocking) != hipSuccess) {
+        if (ctx->stream) hipStreamDestroy(ctx->stream);
         delete ctx;
         return fail(nullptr, PDC_EDEVICE, "stream creation failed");
     }
@@ -588,6 +595,7 @@ pdc_status pdc_destroy(pdc_ctx *ctx)
         }
     hipFree(ctx->fmt_buf);
     hipStreamDestroy(ctx->stream);
+    hipStreamDestroy(ctx->copy_stream);
     delete ctx;
     return PDC_OK;
 }
@@ -709,13 +717,15 @@ pdc_status pdc_get_hits(pdc_ctx *ctx, uint64_t batch, pdc_hit *dst, uint64_t dst
     pdc_status rc = finish_batch(ctx, *bt);
     if (rc != PDC_OK) return rc;
     Buffers *b = bt->buf;
+    hipStream_t cs = ctx->copy_stream;  // copies wait for this batch only
+    HIP_TRY(ctx, hipStreamWaitEvent(cs, b->ev_end, 0));
     const uint64_t total = b->host_state->total;
     const float E = ctx->dets[bt->det].p.photon_adu;
     const uint64_t n_out = std::min<uint64_t>(total, dst_capacity);
     if (n_out > 0) {
         if (dst_is_device) {
             HIP_TRY(ctx, launch_format_hits(b->hits, b->frame_offset, bt->n_frames, 0, n_out, E,
-                                            reinterpret_cast<HitRecord *>(dst), bt->stream));
+                                            reinterpret_cast<HitRecord *>(dst), cs));
         } else {
             const uint64_t chunk = (uint64_t)1 << 24;
             if (!ctx->fmt_buf) HIP_TRY(ctx, grow(&ctx->fmt_buf, ctx->fmt_cap, std::min(chunk, n_out)));
@@ -724,20 +734,20 @@ pdc_status pdc_get_hits(pdc_ctx *ctx, uint64_t batch, pdc_hit *dst, uint64_t dst
             for (uint64_t first = 0; first < n_out; first += ctx->fmt_cap) {
                 uint64_t n = std::min(ctx->fmt_cap, n_out - first);
                 HIP_TRY(ctx, launch_format_hits(b->hits, b->frame_offset, bt->n_frames, first, n, E,
-                                                ctx->fmt_buf, bt->stream));
+                                                ctx->fmt_buf, cs));
                 HIP_TRY(ctx, hipMemcpyAsync(dst + first, ctx->fmt_buf, n * sizeof(pdc_hit),
-                                            hipMemcpyDeviceToHost, bt->stream));
-                HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+                                            hipMemcpyDeviceToHost, cs));
+                HIP_TRY(ctx, hipStreamSynchronize(cs));
             }
         }
     }
     if (per_frame_hits && bt->n_frames)
         HIP_TRY(ctx, hipMemcpyAsync(per_frame_hits, b->frame_hits, bt->n_frames * sizeof(uint32_t),
-                                    hipMemcpyDeviceToHost, bt->stream));
+                                    hipMemcpyDeviceToHost, cs));
     if (per_frame_photons && bt->n_frames)
         HIP_TRY(ctx, hipMemcpyAsync(per_frame_photons, b->frame_photons, bt->n_frames * sizeof(uint64_t),
-                                    hipMemcpyDeviceToHost, bt->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+                                    hipMemcpyDeviceToHost, cs));
+    HIP_TRY(ctx, hipStreamSynchronize(cs));
     if (n_hits_total) *n_hits_total = total;
     return total > dst_capacity ? PDC_WARN_TRUNCATED : PDC_OK;
 }
@@ -754,11 +764,13 @@ pdc_status pdc_get_corrected(pdc_ctx *ctx, uint64_t batch, float *dst, int32_t d
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     pdc_status rc = finish_batch(ctx, *bt);
     if (rc != PDC_OK) return rc;
+    hipStream_t cs = ctx->copy_stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(cs, bt->buf->ev_end, 0));
     if (n > 0)
         HIP_TRY(ctx, hipMemcpyAsync(dst, bt->buf->corrected, n * sizeof(float),
                                     dst_is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
-                                    bt->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+                                    cs));
+    HIP_TRY(ctx, hipStreamSynchronize(cs));
     return PDC_OK;
 }
 
@@ -768,7 +780,7 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch)
     Batch *bt = find_batch(ctx, batch);
     if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+    HIP_TRY(ctx, hipEventSynchronize(bt->buf->ev_state));
     int32_t det = bt->det;
     ctx->spare.push_back(bt->buf);
     ctx->batches.erase(batch);
@@ -808,10 +820,12 @@ pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev,
     if (rc != PDC_OK) return rc;
     const Detector &d = ctx->dets[bt->det];
     Buffers *b = bt->buf;
+    hipStream_t cs = ctx->copy_stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(cs, b->ev_end, 0));
     const uint64_t n = std::min<uint64_t>(b->host_state->total, capacity);
     HIP_TRY(ctx, launch_capture_patches(b->corrected, b->hits, b->frame_offset, bt->n_frames, n, d.g.n_tiles,
-                                        d.g.rows, d.g.cols, patches_dev, bt->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(bt->stream));
+                                        d.g.rows, d.g.cols, patches_dev, cs));
+    HIP_TRY(ctx, hipStreamSynchronize(cs));
     if (n_out) *n_out = n;
     return PDC_OK;
 }

@@ -259,12 +259,14 @@ __device__ __forceinline__ void tile_forward(const float *patches, uint64_t n, u
                                              uint32_t (&pos1)[2][4], uint32_t (&pos2)[2][4])
 {
     const uint64_t nv = n - h0 < (uint64_t)kTile ? n - h0 : (uint64_t)kTile;
-    const int nflat = (int)nv * 25;
     const float *src = patches + h0 * 25;
-    for (int e = lane; e < kTile * 25; e += 64) {
-        const int r = e / 25, k = e - 25 * r;
-        const float v = e < nflat ? src[e] * inv_adu : 0.0f;
-        F.X[r * 32 + k] = f2bf(v);
+    // every element of the tile is written, the padding columns 25..31 and
+    // rows past n as zeros: LDS left over from earlier kernels may hold
+    // bit patterns that read as bf16 inf or NaN, and inf * 0 is NaN
+    for (int e = lane; e < kTile * 32; e += 64) {
+        const int r = e >> 5, k = e & 31;
+        const float v = (k < 25 && (uint64_t)r < nv) ? src[r * 25 + k] * inv_adu : 0.0f;
+        F.X[e] = f2bf(v);
     }
     wave_lds_sync();
     const int lo = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);

@@ -81,6 +81,7 @@ _sig = {
     "pdc_mlp_train_step": (_st, [_P, _P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.c_float, _P]),
     "pdc_mlp_last_loss": (_st, [_P, ctypes.POINTER(ctypes.c_double)]),
     "pdc_debug_mfma_probe": (_st, [_P, _P, _P, _P]),
+    "pdc_serve_run": (_st, [_P, _P, ctypes.c_int32, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -294,3 +295,59 @@ def debug_mfma_probe(ctx, a_bits: np.ndarray, b_bits: np.ndarray) -> np.ndarray:
     d = np.zeros((16, 16), np.float32)
     _check(_lib.pdc_debug_mfma_probe(ctx, a.ctypes.data, b.ctypes.data, d.ctypes.data), ctx)
     return d
+
+
+# ---------------------------------------------------------------------------
+# serving loop
+# ---------------------------------------------------------------------------
+SERVE_PENDING, SERVE_DONE, SERVE_DROPPED = 0, 1, 2
+SERVE_FRAME_DTYPE = np.dtype([("arrival_ns", "<u8"), ("launch_ns", "<u8"), ("done_ns", "<u8"), ("hits", "<u4"),
+                              ("batch_frames", "<u4"), ("photons", "<u8"), ("status", "<i4"), ("reserved", "<i4")])
+
+
+class ServeStream(ctypes.Structure):
+    _fields_ = [("det", ctypes.c_int32), ("pool_frames", ctypes.c_uint32), ("pool_dev", _P),
+                ("pixels_per_frame", ctypes.c_uint64), ("n_frames", ctypes.c_uint64), ("arrival_ns", _P),
+                ("hit_fraction", ctypes.c_double), ("results", _P), ("hits", _P),
+                ("hits_capacity", ctypes.c_uint64), ("hits_kept", ctypes.c_uint64)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("max_queue", ctypes.c_uint64),
+                ("hbm_budget", ctypes.c_uint64)]
+
+
+class ServeSummary(ctypes.Structure):
+    _fields_ = [("frames_done", ctypes.c_uint64), ("frames_dropped", ctypes.c_uint64), ("batches", ctypes.c_uint64),
+                ("peak_bytes", ctypes.c_uint64), ("wall_ns", ctypes.c_uint64)]
+
+
+def serve_run(ctx, streams, max_batch=64, max_inflight=2, max_queue=0, hbm_budget=0):
+    """streams: list of dicts with det, pool (device uint16 tensor [P, T, H, W]), arrival_ns (host
+    uint64 array), hit_fraction, keep_hits (capacity or 0).  Returns (results, hits, summary):
+    per stream a SERVE_FRAME_DTYPE array and a HIT_DTYPE array (or None)."""
+    descs = (ServeStream * len(streams))()
+    keep = []
+    for d, st in zip(descs, streams):
+        arr = np.ascontiguousarray(st["arrival_ns"], dtype=np.uint64)
+        res = np.zeros(len(arr), SERVE_FRAME_DTYPE)
+        cap = int(st.get("keep_hits", 0))
+        hits = np.zeros(cap, HIT_DTYPE) if cap else None
+        pool = st["pool"]
+        d.det = st["det"]
+        d.pool_frames = pool.shape[0]
+        d.pool_dev = _ptr(pool)
+        d.pixels_per_frame = int(np.prod(pool.shape[1:]))
+        d.n_frames = len(arr)
+        d.arrival_ns = arr.ctypes.data
+        d.hit_fraction = float(st.get("hit_fraction", 0.05))
+        d.results = res.ctypes.data
+        d.hits = hits.ctypes.data if cap else None
+        d.hits_capacity = cap
+        keep.append((arr, res, hits))
+    cfg = ServeConfig(max_batch, max_inflight, max_queue, hbm_budget)
+    summ = ServeSummary()
+    _check(_lib.pdc_serve_run(ctx, descs, len(streams), ctypes.byref(cfg), ctypes.byref(summ)), ctx)
+    out_hits = [h[:d.hits_kept] if h is not None else None for (_, _, h), d in zip(keep, descs)]
+    summary = {f: getattr(summ, f) for f, _ in ServeSummary._fields_}
+    return [r for _, r, _ in keep], out_hits, summary

@@ -98,7 +98,9 @@ def test_empty_batch(ctx):
     raw = np.zeros((0, *geom.shape), np.uint16)
     import torch
 
-    got = run_pdc(ctx, raw, ped, gain, 8, frames_dev=torch.zeros(1, dtype=torch.int16, device="cuda"))
+    fz = torch.zeros(1, dtype=torch.int16, device="cuda")
+    torch.cuda.synchronize()
+    got = run_pdc(ctx, raw, ped, gain, 8, frames_dev=fz)
     assert got["total"] == 0 and len(got["hits"]) == 0
 
 
@@ -138,6 +140,7 @@ def test_overflow_recompute_and_truncation(ctx):
     assert np.array_equal(hits_u32(hits), hits_u32(want["hits"][:cap]))
     # device destination
     dst = torch.zeros(want["total"] * 4, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
     _, total2, _, _, st2 = pdc.get_hits(ctx, b, raw.shape[0], capacity=want["total"], dst_dev=dst)
     assert st2 == pdc.OK and total2 == want["total"]
     assert np.array_equal(dst.cpu().numpy().view(np.uint32).reshape(-1, 4), hits_u32(want["hits"]))
@@ -210,6 +213,7 @@ def test_cspad_full_batch(ctx, occ_id):
     for i in range(0, N, P):
         n = min(P, N - i)
         frames[i:i + n].copy_(dpool[:n])
+    torch.cuda.synchronize()  # torch's copies run on its stream, the library on the context's
     del dpool
     det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
     b = pdc.process_frames(ctx, det, frames, N, int(want["total"] * (N / P) * 1.1) + 1, None)

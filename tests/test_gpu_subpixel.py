@@ -76,6 +76,7 @@ def test_centroid_bit_exact(ctx, t_nb):
     P = np.concatenate([_edge_patches(), P])
     n = len(P)
     out = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
     pdc.centroid(ctx, _dev(P), n, t_nb, out)
     torch.cuda.synchronize()
     want = S.centroid(P, t_nb)
@@ -94,8 +95,10 @@ def test_eta_table_and_correction_bit_exact(ctx, nbins):
     dP = _dev(P)
     table = torch.zeros((2, nbins + 1), dtype=torch.float32, device="cuda")
     ws = torch.zeros(2 * nbins, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
     pdc.eta_table(ctx, dP, n, T_NB, nbins, ws, table)
     out = torch.zeros((n, 2), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
     pdc.centroid(ctx, dP, n, T_NB, out, eta_dev=table, nbins=nbins)
     torch.cuda.synchronize()
     c = S.centroid(P, T_NB)
@@ -111,6 +114,7 @@ def test_eta_table_empty_is_zero(ctx):
 
     table = torch.full((2, 9), 7.0, dtype=torch.float32, device="cuda")
     ws = torch.zeros(16, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
     pdc.eta_table(ctx, None, 0, T_NB, 8, ws, table)
     torch.cuda.synchronize()
     assert not table.cpu().numpy().any()
@@ -136,6 +140,7 @@ def test_mlp_forward_matches_oracle(ctx):
     net = pdc.mlp_create(ctx, th)
     try:
         out = torch.zeros((len(P), 2), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
         pdc.mlp_infer(net, _dev(P), len(P), ADU, out)
         torch.cuda.synchronize()
         got = out.cpu().numpy()
@@ -147,6 +152,37 @@ def test_mlp_forward_matches_oracle(ctx):
     assert d.max() <= 2e-2, d.max()
     ref64, _ = S.mlp_forward(th.astype(np.float64), P, ADU, bf16_ops=False)
     assert np.sqrt(np.mean((got - ref64) ** 2)) <= 0.02
+
+
+def test_mlp_forward_after_frame_kernel(ctx):
+    """Regression: the frame kernel leaves +inf padding in LDS; the network's
+    tiles must not read stale LDS (inf * 0 = NaN, which ReLU would turn into
+    a silent 0)."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+    from tests.helpers import run_pdc
+
+    g = synth.Geometry(2, 40, 388, 194)
+    ped, gain = synth.make_calibration(g, 5)
+    raw = synth.make_frames(g, ped, gain, 8, 0.02, 5)
+    run_pdc(ctx, raw, ped, gain, g.bank_cols)
+    th = _theta(6)
+    P, _ = synth.make_patches(20011, seed=16)
+    net = pdc.mlp_create(ctx, th)
+    try:
+        out = torch.zeros((len(P), 2), dtype=torch.float32, device="cuda")
+        dP = _dev(P)
+        torch.cuda.synchronize()
+        pdc.mlp_infer(net, dP, len(P), ADU, out)
+        g2, _ = pdc.mlp_gradient(net, dP, _dev(np.zeros((len(P), 2), F32)), len(P), ADU)
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+    finally:
+        pdc.mlp_destroy(net)
+    want, _ = S.mlp_forward(th, P, ADU, bf16_ops=True)
+    assert np.isfinite(got).all() and np.isfinite(g2).all()
+    assert np.quantile(np.abs(got - want), 0.99) <= 1e-5
 
 
 @pytest.mark.parametrize("n", [1, 37, 2005, 150001])
@@ -223,8 +259,10 @@ def test_training_beats_centroid_eta(ctx):
     nb = 1023
     table = torch.zeros((2, nb + 1), dtype=torch.float32, device="cuda")
     ws = torch.zeros(2 * nb, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
     pdc.eta_table(ctx, dP, n_tr, T_NB, nb, ws, table)
     ce = torch.zeros((n_te, 2), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
     pdc.centroid(ctx, dPt, n_te, T_NB, ce, eta_dev=table, nbins=nb)
     net = pdc.mlp_create(ctx, S.init_params(0))
     try:
@@ -237,6 +275,7 @@ def test_training_beats_centroid_eta(ctx):
                 first = pdc.mlp_last_loss(net)
         last = pdc.mlp_last_loss(net)
         y = torch.zeros((n_te, 2), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
         pdc.mlp_infer(net, dPt, n_te, ADU, y)
         torch.cuda.synchronize()
     finally:
@@ -266,8 +305,10 @@ def test_capture_patches_from_frames2(ctx):
         b = pdc.process_frames(ctx, det, _dev(raw), N, 100000)
         cap = want["total"] + 5
         out = torch.full((cap, 25), -1.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
         n = pdc.capture_patches(ctx, b, out, cap)
         small = torch.full((7, 25), -1.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
         n7 = pdc.capture_patches(ctx, b, small, 7)
         pdc.release_batch(ctx, b)
     finally:
