@@ -359,6 +359,8 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     extern __shared__ float lds[];
     __shared__ unsigned long long s_photons;
     __shared__ uint64_t s_base;
+    __shared__ uint32_t s_p2ctr;
+    uint32_t *s_p2next = &s_p2ctr;  // next phase-2 seed chunk
 
     constexpr int NV = 2 * NQ;
     const int tid = threadIdx.x;
@@ -437,6 +439,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     for (int x = tid; x < 2 * RN; x += kV2Threads) s_cnt[x] = 0;
     if (tid < 2) s_nseed[tid] = 0;
     if (tid == 0) s_photons = 0;
+    if (tid == 0) s_p2ctr = 0;
 
     uint64_t chunk_cur = 0, chunk_end = 0;  // staging chunk, held by the phase-3 wave's lane 0
     uint32_t raw[GMAX][NQ];
@@ -453,19 +456,25 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     if (f_begin < f_end) load_raw(f_begin);
     __syncthreads();
 
-    // Software pipeline: iteration f runs frame f's phases 1a, 1b, 1c and
-    // frame f-1's phases 2, 3, 4 beside them (one iteration more drains it).
-    for (uint64_t f = f_begin; f <= f_end; ++f) {
-        const bool cur_ok = f < f_end, prev_ok = f > f_begin;
+    // Software pipeline, two frames deep: iteration f runs frame f's phases
+    // 1a (A), 1b (B) and 1c (C), frame f-1's phase 2 in B (claimed in chunks
+    // by waves as they finish their median groups) and its phase 3 in C, and
+    // frame f-2's phase 4 in A.  Two more iterations drain it.  Frame f and
+    // frame f-2 share LDS parity par; frame f-1 has parity pp.
+    for (uint64_t f = f_begin; f < f_end + 2; ++f) {
+        const bool cur_ok = f < f_end;
+        const bool p1_ok = f >= f_begin + 1 && f - 1 < f_end;
+        const bool p2_ok = f >= f_begin + 2;
         const int par = (int)(f & 1), pp = par ^ 1;
-        const uint32_t nseed_p = prev_ok ? s_nseed[pp] : 0u;
-        const bool ovf_p = nseed_p > (uint32_t)cap;
+        const uint32_t nseed_1 = p1_ok ? s_nseed[pp] : 0u;   // frame f-1
+        const uint32_t nseed_2 = p2_ok ? s_nseed[par] : 0u;  // frame f-2
+        const bool ovf_1 = nseed_1 > (uint32_t)cap, ovf_2 = nseed_2 > (uint32_t)cap;
         float *u_c = s_u + par * RW;
         const float *u_p = s_u + pp * RW;
         float *med_c = s_med + par * RN;
         const float *med_p = s_med + pp * RN;
 
-        // ================= A: 1a(f) | 2(f-1) ======================================
+        // ================= A: 1a(f) | 4(f-2) ======================================
         if (cur_ok) {
             uint32_t cur[GMAX][NQ];
 #pragma unroll
@@ -481,81 +490,35 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                         *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) =
                             make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
                                         dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
-            // lists of parity par were last used by frame f-2 (finished)
+        }
+        if (p2_ok && !ovf_2) {
+            const uint64_t base = s_base;
+            if (base != kNoBase) {
+                for (uint32_t j = tid; j < nseed_2; j += kV2Threads) {
+                    const float qv = s_q[par * cap + j];
+                    if (qv < 0.0f) continue;
+                    const uint32_t key = s_seed[par * cap + j];
+                    const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
+                    const int i = row * nb + bank;
+                    const int cb = col - bank * B;
+                    const uint32_t *bw = s_bits + (par * RN + i) * 8;
+                    uint32_t rank = 0;
+                    for (int w = 0; w < (cb >> 5); ++w) rank += __popc(bw[w]);
+                    rank += __popc(bw[cb >> 5] & ((1u << (cb & 31)) - 1u));
+                    const uint32_t pix = row_base + (uint32_t)row * W + col;
+                    A.pool[base + s_pref[i] + rank] = make_uint2(pix, __float_as_uint(qv));
+                }
+            }
+        }
+        __syncthreads();  // A -> B
+
+        // ================= B: 1b(f) | 2(f-1) ======================================
+        if (cur_ok) {
+            // frame f-2's lists (parity par) are finished: clear them for frame f
             for (int x = tid; x < RN * 8; x += kV2Threads) s_bits[par * RN * 8 + x] = 0;
             for (int x = tid; x < RN; x += kV2Threads) s_cnt[par * RN + x] = 0;
             if (tid == 0) s_nseed[par] = 0;
         }
-        if (prev_ok && !ovf_p) {
-            // 3x3 local maximum with the raster tie-break, masked charge sum in
-            // row-major order, photon count; absent neighbours read a clamped
-            // in-range address and are ignored
-            unsigned long long my_ph = 0;
-            for (uint32_t j = tid; j < nseed_p; j += kV2Threads) {
-                const uint32_t key = s_seed[pp * cap + j];
-                const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
-                const int i = row * nb + bank;
-                // addresses first, then all 18 reads, then the arithmetic
-                int ua[3][3], ma[3][3];
-                bool ex[3][3];
-#pragma unroll
-                for (int dr = 0; dr < 3; ++dr) {
-                    const int rr = row + dr - 1;
-                    const int rc = min(max(rr, 0), R - 1);
-#pragma unroll
-                    for (int dc = 0; dc < 3; ++dc) {
-                        const int cc = col + dc - 1;
-                        ex[dr][dc] = rr >= 0 && rr < R && cc >= 0 && cc < W;
-                        const int ccl = min(max(cc, 0), W - 1);
-                        const int bk = ccl >= (bank + 1) * B ? bank + 1 : (ccl < bank * B ? bank - 1 : bank);
-                        ua[dr][dc] = rc * W + ccl;
-                        ma[dr][dc] = rc * nb + bk;
-                    }
-                }
-                float uv[3][3], mv[3][3];
-#pragma unroll
-                for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                    for (int dc = 0; dc < 3; ++dc) {
-                        uv[dr][dc] = u_p[ua[dr][dc]];
-                        mv[dr][dc] = med_p[ma[dr][dc]];
-                    }
-                float nv[3][3];
-#pragma unroll
-                for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                    for (int dc = 0; dc < 3; ++dc) nv[dr][dc] = __fsub_rn(uv[dr][dc], mv[dr][dc]);
-                const float vp = nv[1][1];
-                bool is_max = true;
-#pragma unroll
-                for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                    for (int dc = 0; dc < 3; ++dc) {
-                        if (dr == 1 && dc == 1) continue;
-                        const bool later = dr > 1 || (dr == 1 && dc > 1);
-                        const float vq = nv[dr][dc];
-                        if (ex[dr][dc] && !(vp > vq || (vp == vq && later))) is_max = false;
-                    }
-                float qsum = -1.0f;
-                if (is_max) {
-                    qsum = 0.0f;
-#pragma unroll
-                    for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                        for (int dc = 0; dc < 3; ++dc)
-                            qsum = __fadd_rn(qsum, (ex[dr][dc] && nv[dr][dc] > A.t_nb) ? nv[dr][dc] : 0.0f);
-                    const int cb = col - bank * B;
-                    atomicOr(&s_bits[(pp * RN + i) * 8 + (cb >> 5)], 1u << (cb & 31));
-                    atomicAdd(&s_cnt[pp * RN + i], 1u);
-                    my_ph += photon_count(qsum, A.photon_adu);
-                }
-                s_q[pp * cap + j] = qsum;
-            }
-            if (my_ph) atomicAdd(&s_photons, my_ph);
-        }
-        __syncthreads();  // A -> B
-
-        // ================= B: 1b(f) | 3(f-1) ======================================
         if (cur_ok) {
             constexpr int G = 64 / L;
             const int grp = lane / L, gl = lane - grp * L;
@@ -576,48 +539,82 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 s_th[i] = seed_threshold(m, A.t_seed);
             }
         }
-        if (prev_ok && wave == kP3Wave) {
-            // bank-row prefix of frame f-1's hit counts, staging chunk claim
-            uint32_t total = 0;
-            if (!ovf_p) {
-                for (int b0 = 0; b0 < BR; b0 += 64) {
-                    const int i = b0 + lane;
-                    const uint32_t c = i < BR ? s_cnt[pp * RN + i] : 0u;
-                    const uint32_t incl = wave_incl_scan(c);
-                    if (i < BR) s_pref[i] = total + incl - c;
-                    total += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (p1_ok && !ovf_1) {
+            // frame f-1's seeds in chunks of 64, claimed by whole waves as they
+            // finish their median groups (waves without groups start at once)
+            unsigned long long my_ph = 0;
+            for (;;) {
+                uint32_t c0 = 0;
+                if (lane == 0) c0 = atomicAdd(s_p2next, 64u);
+                c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c0);
+                if (c0 >= nseed_1) break;
+                const uint32_t j = c0 + lane;
+                if (j < nseed_1) {
+                    const uint32_t key = s_seed[pp * cap + j];
+                    const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
+                    const int i = row * nb + bank;
+                    // addresses first, then all 18 reads, then the arithmetic
+                    int ua[3][3], ma[3][3];
+                    bool ex[3][3];
+#pragma unroll
+                    for (int dr = 0; dr < 3; ++dr) {
+                        const int rr = row + dr - 1;
+                        const int rc = min(max(rr, 0), R - 1);
+#pragma unroll
+                        for (int dc = 0; dc < 3; ++dc) {
+                            const int cc = col + dc - 1;
+                            ex[dr][dc] = rr >= 0 && rr < R && cc >= 0 && cc < W;
+                            const int ccl = min(max(cc, 0), W - 1);
+                            const int bk = ccl >= (bank + 1) * B ? bank + 1 : (ccl < bank * B ? bank - 1 : bank);
+                            ua[dr][dc] = rc * W + ccl;
+                            ma[dr][dc] = rc * nb + bk;
+                        }
+                    }
+                    float uv[3][3], mv[3][3];
+#pragma unroll
+                    for (int dr = 0; dr < 3; ++dr)
+#pragma unroll
+                        for (int dc = 0; dc < 3; ++dc) {
+                            uv[dr][dc] = u_p[ua[dr][dc]];
+                            mv[dr][dc] = med_p[ma[dr][dc]];
+                        }
+                    float nv[3][3];
+#pragma unroll
+                    for (int dr = 0; dr < 3; ++dr)
+#pragma unroll
+                        for (int dc = 0; dc < 3; ++dc) nv[dr][dc] = __fsub_rn(uv[dr][dc], mv[dr][dc]);
+                    const float vp = nv[1][1];
+                    bool is_max = true;
+#pragma unroll
+                    for (int dr = 0; dr < 3; ++dr)
+#pragma unroll
+                        for (int dc = 0; dc < 3; ++dc) {
+                            if (dr == 1 && dc == 1) continue;
+                            const bool later = dr > 1 || (dr == 1 && dc > 1);
+                            const float vq = nv[dr][dc];
+                            if (ex[dr][dc] && !(vp > vq || (vp == vq && later))) is_max = false;
+                        }
+                    float qsum = -1.0f;
+                    if (is_max) {
+                        qsum = 0.0f;
+#pragma unroll
+                        for (int dr = 0; dr < 3; ++dr)
+#pragma unroll
+                            for (int dc = 0; dc < 3; ++dc)
+                                qsum = __fadd_rn(qsum, (ex[dr][dc] && nv[dr][dc] > A.t_nb) ? nv[dr][dc] : 0.0f);
+                        const int cb = col - bank * B;
+                        atomicOr(&s_bits[(pp * RN + i) * 8 + (cb >> 5)], 1u << (cb & 31));
+                        atomicAdd(&s_cnt[pp * RN + i], 1u);
+                        my_ph += photon_count(qsum, A.photon_adu);
+                    }
+                    s_q[pp * cap + j] = qsum;
                 }
             }
-            if (lane == 0) {
-                const uint64_t unit = (f - 1) * (uint64_t)A.n_strips + strip;
-                uint64_t base = chunk_cur;
-                if (ovf_p) {
-                    atomicOr(&A.state->fallback, 1u);
-                    base = kNoBase;
-                } else if (total > 0) {
-                    if (chunk_cur + total > chunk_end) {
-                        const uint64_t sz = total > kChunkHits ? (uint64_t)total : kChunkHits;
-                        chunk_cur = atomicAdd(&A.state->cursor, (unsigned long long)sz);
-                        chunk_end = chunk_cur + sz;
-                    }
-                    if (chunk_cur + total <= A.pool_cap) {
-                        base = chunk_cur;
-                        chunk_cur += total;
-                    } else {
-                        base = kNoBase;
-                        atomicOr(&A.state->overflow, 1u);
-                    }
-                }
-                A.unit_base[unit] = base;
-                A.unit_count[unit] = total;
-                A.unit_photons[unit] = s_photons;
-                s_photons = 0;
-                s_base = base;
-            }
+            if (my_ph) atomicAdd(&s_photons, my_ph);
         }
         __syncthreads();  // B -> C
 
-        // ================= C: 1c(f) | 4(f-1) ======================================
+        // ================= C: 1c(f) | 3(f-1) ======================================
         if (cur_ok) {
             uint32_t seedbits = 0;  // bit (g*NV + v) set: seed at this lane's value-slot v of bank-row g
 #pragma unroll
@@ -678,25 +675,46 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 }
             }
         }
-        if (prev_ok && !ovf_p) {
-            const uint64_t base = s_base;
-            if (base != kNoBase) {
-                for (uint32_t j = tid; j < nseed_p; j += kV2Threads) {
-                    const float qv = s_q[pp * cap + j];
-                    if (qv < 0.0f) continue;
-                    const uint32_t key = s_seed[pp * cap + j];
-                    const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
-                    const int i = row * nb + bank;
-                    const int cb = col - bank * B;
-                    const uint32_t *bw = s_bits + (pp * RN + i) * 8;
-                    uint32_t rank = 0;
-                    for (int w = 0; w < (cb >> 5); ++w) rank += __popc(bw[w]);
-                    rank += __popc(bw[cb >> 5] & ((1u << (cb & 31)) - 1u));
-                    const uint32_t pix = row_base + (uint32_t)row * W + col;
-                    A.pool[base + s_pref[i] + rank] = make_uint2(pix, __float_as_uint(qv));
+        if (p1_ok && wave == kP3Wave) {
+            // bank-row prefix of frame f-1's hit counts, staging chunk claim
+            uint32_t total = 0;
+            if (!ovf_1) {
+                for (int b0 = 0; b0 < BR; b0 += 64) {
+                    const int i = b0 + lane;
+                    const uint32_t c = i < BR ? s_cnt[pp * RN + i] : 0u;
+                    const uint32_t incl = wave_incl_scan(c);
+                    if (i < BR) s_pref[i] = total + incl - c;
+                    total += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
                 }
             }
+            if (lane == 0) {
+                const uint64_t unit = (f - 1) * (uint64_t)A.n_strips + strip;
+                uint64_t base = chunk_cur;
+                if (ovf_1) {
+                    atomicOr(&A.state->fallback, 1u);
+                    base = kNoBase;
+                } else if (total > 0) {
+                    if (chunk_cur + total > chunk_end) {
+                        const uint64_t sz = total > kChunkHits ? (uint64_t)total : kChunkHits;
+                        chunk_cur = atomicAdd(&A.state->cursor, (unsigned long long)sz);
+                        chunk_end = chunk_cur + sz;
+                    }
+                    if (chunk_cur + total <= A.pool_cap) {
+                        base = chunk_cur;
+                        chunk_cur += total;
+                    } else {
+                        base = kNoBase;
+                        atomicOr(&A.state->overflow, 1u);
+                    }
+                }
+                A.unit_base[unit] = base;
+                A.unit_count[unit] = total;
+                A.unit_photons[unit] = s_photons;
+                s_photons = 0;
+                s_base = base;
+            }
         }
+        if (tid == 0) *s_p2next = 0;
         __syncthreads();  // C -> next A
     }
 }
