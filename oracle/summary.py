@@ -11,6 +11,10 @@ of the noise sigma): pedestal and noise come from dark frames.
   nbins + 1 the rest; for x >= lo the bin is 1 + floor(t) with
   t = fl(fl(x - lo) * s) in binary32 and s = fl(nbins / fl(hi - lo)), or
   nbins + 1 when t >= nbins (float32 takes the integer decision, as on the GPU).
+* cloud_sizes / size_spectra: for each hit, the number of pixels of its
+  in-tile 3x3 window whose Frames2 value is above t_nb (the charge-sharing
+  components of Fig. g: charges summed over 1, 2, 3, ... pixels), and the
+  charge spectrum of the hits of each size.
 * dark_stats: exact integer sums S1 = sum(adc), S2 = sum(adc^2) over the dark
   frames (adc = raw & 0x3FFF); pedestal = float32(S1 / n) and
   noise = float32(sqrt((n S2 - S1^2) / (n (n - 1)))), the quotient and the
@@ -51,6 +55,29 @@ def histogram(values, lo, hi, nbins):
     np.add.at(out, b, 1)
     out[nbins + 1] += np.count_nonzero(~inside)
     return out.astype(np.uint32)
+
+
+def cloud_sizes(frames2, hits, t_nb):
+    """frames2 float32 [N, T, H, W]; hits with fields frame and pixel; returns
+    int64 [len(hits)], each in 1..9 for a hit above a threshold >= t_nb."""
+    v = np.asarray(frames2, F32)
+    N, T, H, W = v.shape
+    t_nb = F32(t_nb)
+    out = np.zeros(len(hits), np.int64)
+    for i, (f, p) in enumerate(zip(np.asarray(hits["frame"]), np.asarray(hits["pixel"]))):
+        t, rem = divmod(int(p), H * W)
+        r, c = divmod(rem, W)
+        win = v[int(f), t, max(r - 1, 0):r + 2, max(c - 1, 0):c + 2]
+        out[i] = np.count_nonzero(win > t_nb)
+    return out
+
+
+def size_spectra(frames2, hits, t_nb, lo, hi, nbins):
+    """uint32 [9, nbins + 2]: row s - 1 is the charge histogram of the hits of
+    cloud size s."""
+    sizes = cloud_sizes(frames2, hits, t_nb)
+    q = np.asarray(hits["charge"], F32)
+    return np.stack([histogram(q[sizes == s], lo, hi, nbins) for s in range(1, 10)])
 
 
 def dark_stats(darks):

@@ -60,3 +60,26 @@ def test_dark_stats_matches_float64_moments():
     assert np.array_equal(ped, x.mean(axis=0).astype(F32))
     want = x.std(axis=0, ddof=1)
     assert np.max(np.abs(noise - want) / want) <= 2 ** -23
+
+
+def test_cloud_sizes_hand_worked():
+    # one frame, two 3x4 tiles; t_nb = 10
+    v = np.zeros((1, 2, 3, 4), F32)
+    v[0, 0] = [[50, 11, 0, 0],
+               [10, 12, 0, 9],
+               [0, 0, 0, 99]]
+    v[0, 1] = [[0, 0, 0, 0],
+               [0, 40, 40, 0],
+               [11, 11, 11, 0]]
+    hits = np.zeros(4, [("frame", "<u4"), ("pixel", "<u4"), ("charge", "<f4")])
+    hits["pixel"] = [0, 11, 12 + 5, 12 + 6]
+    hits["charge"] = [73, 99, 113, 113]
+    # corner (0,0): 50, 11, 12 above (10 is not); (2,3) of tile 0: only 99 (the
+    # window stops at the tile edge, tile 1 below is not counted); tile 1 (1,1):
+    # 40, 40, 11, 11, 11; (1,2): 40, 40, 11, 11
+    assert S.cloud_sizes(v, hits, 10.0).tolist() == [3, 1, 5, 4]
+    sp = S.size_spectra(v, hits, 10.0, 0.0, 200.0, 2)
+    assert sp.shape == (9, 4)
+    assert sp[2].tolist() == [0, 1, 0, 0] and sp[0].tolist() == [0, 1, 0, 0]
+    assert sp[4].tolist() == [0, 0, 1, 0] and sp[3].tolist() == [0, 0, 1, 0]
+    assert sp.sum() == 4
