@@ -311,6 +311,62 @@ typedef struct {
 pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_streams,
                          const pdc_serve_config *cfg, pdc_serve_summary *summary);
 
+/* ------------------------------------------------------------------------
+ * Summaries (Summarization section: photon-counting maps and histograms
+ * accumulated over frames; Fig. g: spectra of Frames2 and of the summed
+ * charges, split by the number of pixels summed; Dark and Gain section and
+ * the noise thresholds of the Results section: pedestal and noise from dark
+ * frames).
+ *
+ * Histograms have nbins + 2 uint32 counters: bin 0 counts values below lo
+ * (and NaN), bins 1..nbins the range, bin nbins + 1 the values at or above
+ * its end.  With s = nbins / (hi - lo) formed in binary32, a value x >= lo
+ * goes to bin 1 + floor(t), t = fl(fl(x - lo) * s), when t < nbins, else to
+ * bin nbins + 1.  1 <= nbins <= 2^24, lo < hi finite, and s must be a finite
+ * positive binary32 value (EINVAL otherwise).
+ *
+ * Counts are ADDED to the caller's device arrays (clear them first, e.g. with
+ * a fill kernel), with integer atomics: results do not depend on thread order,
+ * and a counter wraps modulo 2^32.  The work is enqueued on hip_stream (a
+ * hipStream_t of the context's device, or NULL for the context's
+ * non-blocking stream) after the batch's kernels; the call returns once it is
+ * enqueued, and pdc_release_batch waits for it.
+ * ------------------------------------------------------------------------ */
+
+/* Accumulate a batch's hits.  Each array may be NULL (then skipped):
+ *   count_map_dev uint32 [n_tiles*rows*cols]: += nphot at the hit's pixel
+ *     (photon-counting image summed over the batch's frames);
+ *   spectrum_dev uint32 [nbins + 2]: += 1 at the bin of the hit's charge;
+ *   size_spectra_dev uint32 [9][nbins + 2]: += 1 at [size - 1][bin(charge)],
+ *     size = number of pixels of the hit's in-tile 3x3 window with Frames2
+ *     above T_nb (1..9); needs PDC_KEEP_CORRECTED (ESTATE otherwise).
+ * lo, hi and nbins are checked only when a histogram is requested. */
+pdc_status pdc_accumulate_hits(pdc_ctx *ctx, uint64_t batch, uint32_t *count_map_dev, uint32_t *spectrum_dev,
+                               uint32_t *size_spectra_dev, float lo, float hi, int32_t nbins, void *hip_stream);
+
+/* Accumulate the histogram of every Frames2 value of a batch processed with
+ * PDC_KEEP_CORRECTED (ESTATE otherwise) into hist_dev uint32 [nbins + 2]. */
+pdc_status pdc_histogram_corrected(pdc_ctx *ctx, uint64_t batch, uint32_t *hist_dev, float lo, float hi,
+                                   int32_t nbins, void *hip_stream);
+
+/* Pedestal and noise per pixel from n_frames dark frames (DEVICE uint16
+ * [n_frames][n_tiles][rows][cols], bits 14-15 ignored), 2 <= n_frames < 2^32.
+ * With the exact integer sums S1 = sum adc and S2 = sum adc^2 over the frames
+ * (adc = raw & 0x3FFF): pedestal = S1 / n and noise (the sample standard
+ * deviation) = sqrt((n S2 - S1^2) / (n (n - 1))), each quotient and the root
+ * in IEEE double from the exact integers, then rounded to binary32.
+ * pedestal_host and noise_host (may be NULL) are host float32
+ * [n_tiles*rows*cols].  Synchronous; device scratch of 16 bytes per pixel is
+ * allocated for the call. */
+pdc_status pdc_dark_stats(pdc_ctx *ctx, const pdc_geometry *geom, const uint16_t *darks_dev, uint64_t n_frames,
+                          float *pedestal_host, float *noise_host, void *hip_stream);
+
+/* pdc_dark_stats followed by pdc_calibrate with that pedestal and the host
+ * gain plane: a detector calibrated from its dark frames.  noise_host may be
+ * NULL. */
+pdc_status pdc_calibrate_darks(pdc_ctx *ctx, const pdc_geometry *geom, const uint16_t *darks_dev, uint64_t n_frames,
+                               const float *gain, const pdc_params *params, float *noise_host, int32_t *det_out);
+
 /* Test hook: D = A B for one 16x32 by 32x16 bfloat16 tile through the MFMA
  * operand loads the network kernels use.  A (uint16 bf16 bits [16][32]),
  * B ([32][16]) and D (float32 [16][16]) are host arrays, row-major.

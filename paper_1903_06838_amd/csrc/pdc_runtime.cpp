@@ -17,6 +17,7 @@
 #include "pdc.h"
 #include "pdc_internal.h"
 #include "pdc_subpixel.h"
+#include "pdc_summary.h"
 
 using namespace pdc;
 
@@ -69,6 +70,8 @@ struct Buffers {
     BatchState *host_state = nullptr;  // pinned mirror
     hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr;
     hipEvent_t ev_state = nullptr;  // after the state copy: the batch's last work on its stream
+    hipEvent_t ev_use = nullptr;    // after summary work on a caller's stream
+    bool used = false;              // ev_use recorded since the batch was launched
 };
 
 struct Batch {
@@ -106,6 +109,7 @@ void free_buffers(Buffers *b)
     if (b->ev_main) hipEventDestroy(b->ev_main);
     if (b->ev_end) hipEventDestroy(b->ev_end);
     if (b->ev_state) hipEventDestroy(b->ev_state);
+    if (b->ev_use) hipEventDestroy(b->ev_use);
     delete b;
 }
 
@@ -327,6 +331,7 @@ pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n
         HIP_TRY(ctx, hipEventCreate(&b->ev_main));
         HIP_TRY(ctx, hipEventCreate(&b->ev_end));
         HIP_TRY(ctx, hipEventCreateWithFlags(&b->ev_state, hipEventDisableTiming));
+        HIP_TRY(ctx, hipEventCreateWithFlags(&b->ev_use, hipEventDisableTiming));
     }
     if (n_units > b->cap_units || !b->unit_count) {
         uint64_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
@@ -781,6 +786,8 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch)
     if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipEventSynchronize(bt->buf->ev_state));
+    if (bt->buf->used) HIP_TRY(ctx, hipEventSynchronize(bt->buf->ev_use));
+    bt->buf->used = false;
     int32_t det = bt->det;
     ctx->spare.push_back(bt->buf);
     ctx->batches.erase(batch);
@@ -1067,6 +1074,147 @@ pdc_status pdc_debug_mfma_probe(pdc_ctx *ctx, const uint16_t *A, const uint16_t 
     hipFree(dD);
     if (e != hipSuccess) return fail(ctx, PDC_EDEVICE, "mfma probe: %s", hipGetErrorString(e));
     return PDC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Summaries
+// ---------------------------------------------------------------------------
+namespace {
+
+pdc_status check_bins(pdc_ctx *ctx, float lo, float hi, int32_t nbins, float *scale)
+{
+    if (nbins < 1 || nbins > (1 << 24)) return fail(ctx, PDC_EINVAL, "nbins must be in [1, 2^24]");
+    if (!(std::isfinite(lo) && std::isfinite(hi) && lo < hi)) return fail(ctx, PDC_EINVAL, "need finite lo < hi");
+    volatile float w = hi - lo;  // binary32
+    volatile float sc = (float)nbins / w;
+    if (!std::isfinite(w) || !(std::isfinite(sc) && sc > 0.0f))
+        return fail(ctx, PDC_EINVAL, "nbins / (hi - lo) is not a finite positive binary32 value");
+    *scale = sc;
+    return PDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdc_status pdc_accumulate_hits(pdc_ctx *ctx, uint64_t batch, uint32_t *count_map_dev, uint32_t *spectrum_dev,
+                               uint32_t *size_spectra_dev, float lo, float hi, int32_t nbins, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (size_spectra_dev && !bt->keep)
+        return fail(ctx, PDC_ESTATE, "size spectra need a batch processed with PDC_KEEP_CORRECTED");
+    float scale = 1.0f;
+    if (spectrum_dev || size_spectra_dev) {
+        pdc_status rc = check_bins(ctx, lo, hi, nbins, &scale);
+        if (rc != PDC_OK) return rc;
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    const Detector &d = ctx->dets[bt->det];
+    Buffers *b = bt->buf;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(s, b->ev_end, 0));
+    AccumulateArgs a{};
+    a.hits = b->hits;
+    a.n = b->host_state->total;
+    a.photon_adu = d.p.photon_adu;
+    a.count_map = count_map_dev;
+    a.spectrum = spectrum_dev;
+    a.size_spectra = size_spectra_dev;
+    a.lo = lo;
+    a.scale = scale;
+    a.nbins = (uint32_t)nbins;
+    a.corrected = b->corrected;
+    a.frame_offset = b->frame_offset;
+    a.n_frames = bt->n_frames;
+    a.T = d.g.n_tiles;
+    a.H = d.g.rows;
+    a.W = d.g.cols;
+    a.t_nb = d.t_nb;
+    HIP_TRY(ctx, launch_accumulate_hits(a, (uint32_t)ctx->n_cu * 8, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_use, s));
+    b->used = true;
+    return PDC_OK;
+}
+
+pdc_status pdc_histogram_corrected(pdc_ctx *ctx, uint64_t batch, uint32_t *hist_dev, float lo, float hi,
+                                   int32_t nbins, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (!bt->keep) return fail(ctx, PDC_ESTATE, "batch was not processed with PDC_KEEP_CORRECTED");
+    if (!hist_dev) return fail(ctx, PDC_EINVAL, "hist_dev is NULL");
+    float scale = 1.0f;
+    pdc_status rc = check_bins(ctx, lo, hi, nbins, &scale);
+    if (rc != PDC_OK) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    const Detector &d = ctx->dets[bt->det];
+    Buffers *b = bt->buf;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(s, b->ev_end, 0));
+    const uint64_t n = bt->n_frames * (uint64_t)d.g.n_tiles * d.g.rows * d.g.cols;
+    HIP_TRY(ctx, launch_histogram(b->corrected, n, lo, scale, (uint32_t)nbins, hist_dev, (uint32_t)ctx->n_cu * 8, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_use, s));
+    b->used = true;
+    return PDC_OK;
+}
+
+pdc_status pdc_dark_stats(pdc_ctx *ctx, const pdc_geometry *geom, const uint16_t *darks_dev, uint64_t n_frames,
+                          float *pedestal_host, float *noise_host, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    pdc_status rc = check_geometry(geom);
+    if (rc != PDC_OK) return fail(ctx, rc, "%s", g_thread_error);
+    if (n_frames < 2 || n_frames >= ((uint64_t)1 << 32)) return fail(ctx, PDC_EINVAL, "need 2 <= n_frames < 2^32");
+    if (!darks_dev || !pedestal_host) return fail(ctx, PDC_EINVAL, "darks_dev and pedestal_host must be non-NULL");
+    const uint64_t px = (uint64_t)geom->n_tiles * geom->rows * geom->cols;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    unsigned long long *sums = nullptr;
+    HIP_TRY(ctx, hipMalloc((void **)&sums, 2 * px * sizeof(unsigned long long)));
+    std::vector<uint64_t> s12(2 * px);
+    hipError_t e = launch_dark_sums(darks_dev, n_frames, px, sums, sums + px, (uint32_t)ctx->n_cu, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(s12.data(), sums, 2 * px * sizeof(uint64_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipFree(sums);
+    if (e != hipSuccess) return fail(ctx, PDC_EDEVICE, "dark sums: %s", hipGetErrorString(e));
+    // pedestal = S1 / n and noise = sqrt((n S2 - S1^2) / (n (n - 1))): the
+    // quotients and the root in IEEE double from exact integers, then binary32
+    const double dn = (double)n_frames, dnn = (double)n_frames * (double)(n_frames - 1);
+    for (uint64_t p = 0; p < px; ++p) {
+        const uint64_t a = s12[p], q = s12[px + p];
+        volatile double m = (double)a / dn;  // a < 2^46: exact operands
+        pedestal_host[p] = (float)m;
+        if (noise_host) {
+            const unsigned __int128 num = (unsigned __int128)n_frames * q - (unsigned __int128)a * a;
+            volatile double v = (double)num / dnn;
+            noise_host[p] = (float)std::sqrt((double)v);
+        }
+    }
+    return PDC_OK;
+}
+
+pdc_status pdc_calibrate_darks(pdc_ctx *ctx, const pdc_geometry *geom, const uint16_t *darks_dev, uint64_t n_frames,
+                               const float *gain, const pdc_params *params, float *noise_host, int32_t *det_out)
+{
+    if (!ctx || !det_out) return fail(ctx, PDC_EINVAL, "ctx and det_out must be non-NULL");
+    pdc_status rc = check_geometry(geom);
+    if (rc != PDC_OK) return fail(ctx, rc, "%s", g_thread_error);
+    rc = check_params(params, nullptr, nullptr);
+    if (rc != PDC_OK) return fail(ctx, rc, "%s", g_thread_error);
+    const size_t px = (size_t)geom->n_tiles * geom->rows * geom->cols;
+    std::vector<float> ped(px);
+    rc = pdc_dark_stats(ctx, geom, darks_dev, n_frames, ped.data(), noise_host, nullptr);
+    if (rc != PDC_OK) return rc;
+    return pdc_calibrate(ctx, geom, ped.data(), gain, params, det_out);
 }
 
 }  // extern "C"

@@ -82,6 +82,12 @@ _sig = {
     "pdc_mlp_last_loss": (_st, [_P, ctypes.POINTER(ctypes.c_double)]),
     "pdc_debug_mfma_probe": (_st, [_P, _P, _P, _P]),
     "pdc_serve_run": (_st, [_P, _P, ctypes.c_int32, _P, _P]),
+    "pdc_accumulate_hits": (_st, [_P, ctypes.c_uint64, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
+                                  _P]),
+    "pdc_histogram_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
+    "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
+    "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
+                                  ctypes.POINTER(ctypes.c_int32)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -351,3 +357,41 @@ def serve_run(ctx, streams, max_batch=64, max_inflight=2, max_queue=0, hbm_budge
     out_hits = [h[:d.hits_kept] if h is not None else None for (_, _, h), d in zip(keep, descs)]
     summary = {f: getattr(summ, f) for f, _ in ServeSummary._fields_}
     return [r for _, r, _ in keep], out_hits, summary
+
+
+# ---------------------------------------------------------------------------
+# summaries
+# ---------------------------------------------------------------------------
+def accumulate_hits(ctx, batch: int, count_map_dev=None, spectrum_dev=None, size_spectra_dev=None,
+                    lo: float = 0.0, hi: float = 1.0, nbins: int = 1, stream=None) -> None:
+    """Add a batch's hits to device uint32 arrays: count map [pixels], charge
+    spectrum [nbins + 2], spectra by cloud size [9][nbins + 2] (any may be None)."""
+    _check(_lib.pdc_accumulate_hits(ctx, batch, _ptr(count_map_dev), _ptr(spectrum_dev), _ptr(size_spectra_dev),
+                                    lo, hi, nbins, _stream(stream)), ctx)
+
+
+def histogram_corrected(ctx, batch: int, hist_dev, lo: float, hi: float, nbins: int, stream=None) -> None:
+    """Add the histogram of a kept batch's Frames2 values to device uint32 [nbins + 2]."""
+    _check(_lib.pdc_histogram_corrected(ctx, batch, _ptr(hist_dev), lo, hi, nbins, _stream(stream)), ctx)
+
+
+def dark_stats(ctx, geom: Geometry, darks_dev, n_frames: int, stream=None):
+    """(pedestal, noise) float32 host arrays [n_tiles, rows, cols] from device dark frames."""
+    shape = (geom.n_tiles, geom.rows, geom.cols)
+    ped = np.zeros(shape, np.float32)
+    noise = np.zeros(shape, np.float32)
+    _check(_lib.pdc_dark_stats(ctx, ctypes.byref(geom), _ptr(darks_dev), n_frames, ped.ctypes.data,
+                               noise.ctypes.data, _stream(stream)), ctx)
+    return ped, noise
+
+
+def calibrate_darks(ctx, geom: Geometry, darks_dev, n_frames: int, gain: np.ndarray, prm: Params):
+    """Calibrate from dark frames; returns (detector id, noise float32 [n_tiles, rows, cols])."""
+    g = np.ascontiguousarray(gain, dtype=np.float32)
+    if g.size != geom.n_tiles * geom.rows * geom.cols:
+        raise ValueError("gain must hold n_tiles*rows*cols values")
+    noise = np.zeros((geom.n_tiles, geom.rows, geom.cols), np.float32)
+    det = ctypes.c_int32(-1)
+    _check(_lib.pdc_calibrate_darks(ctx, ctypes.byref(geom), _ptr(darks_dev), n_frames, g.ctypes.data,
+                                    ctypes.byref(prm), noise.ctypes.data, ctypes.byref(det)), ctx)
+    return det.value, noise

@@ -121,6 +121,10 @@ def test_null_context_paths(pdc):
     assert lib.pdc_batch_timing(None, 1, None, None) == pdc.EINVAL
     assert lib.pdc_calibrate(None, None, None, None, None, None) == pdc.EINVAL
     assert lib.pdc_create(0, None) == pdc.EINVAL
+    assert lib.pdc_accumulate_hits(None, 1, None, None, None, 0.0, 1.0, 1, None) == pdc.EINVAL
+    assert lib.pdc_histogram_corrected(None, 1, None, 0.0, 1.0, 1, None) == pdc.EINVAL
+    assert lib.pdc_dark_stats(None, None, None, 2, None, None, None) == pdc.EINVAL
+    assert lib.pdc_calibrate_darks(None, None, None, 2, None, None, None, None) == pdc.EINVAL
 
 
 def test_create_without_gpu_is_edevice(pdc):
