@@ -15,9 +15,10 @@ dominant kernel (algorithmic HBM bytes / its event-timed duration against the
 8 TB/s peak), the CPU oracle's rate on the 64-frame pool (which also checks the
 GPU hits of that pool), single-frame latency percentiles, a four-detector
 serving run (Poisson arrivals at 1 and 20 kHz per detector, p50/p99 latency),
-the learned subpixel
-estimator against centroid + eta on 10 M simulated hits, and an occupancy
-sweep.
+summaries (count map and charge spectrum of the batch's hits, the Frames2
+histogram and per-cloud-size spectra of a kept 2,000-frame batch, pedestal
+and noise from 1,000 dark frames), the learned subpixel estimator against
+centroid + eta on 10 M simulated hits, and an occupancy sweep.
 
 Other modes:
   --profile            short run for rocprofv3 (1 warm-up + --steps batches,
@@ -304,6 +305,90 @@ def serving(torch, pdc, ctx, rate_hz=20000.0, seconds=0.4, max_batch=64, max_inf
     return out
 
 
+def summaries(torch, pdc, ctx, geom, ped, gain, frames, n_frames, hit_cap, keep_frames=2000, dark_frames=1000):
+    """Summaries over CSPAD-like batches: count map + charge spectrum of the
+    headline batch's hits, Frames2 histogram and per-size spectra of a batch
+    kept in HBM, and pedestal/noise from dark frames.  Event-timed on a stream
+    of our own (torch's default stream reads as the context's stream)."""
+    import numpy as np
+
+    from paper_1903_06838_amd import synth
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    npix = geom.pixels
+    nb = 1000
+    out = {}
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        cmap = torch.zeros(npix, dtype=torch.int32, device=dev)
+        spec = torch.zeros(nb + 2, dtype=torch.int32, device=dev)
+        sizes = torch.zeros(9 * (nb + 2), dtype=torch.int32, device=dev)
+        hist = torch.zeros(nb + 2, dtype=torch.int32, device=dev)
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
+    b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
+    _, total, _, _, _ = pdc.get_hits(ctx, b, n_frames, capacity=0)
+    pdc.accumulate_hits(ctx, b, cmap, spec, None, -50.0, 450.0, nb, stream)  # warm-up
+    e0, e1 = ev(), ev()
+    reps = 5
+    e0.record(stream)
+    for _ in range(reps):
+        pdc.accumulate_hits(ctx, b, cmap, spec, None, -50.0, 450.0, nb, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    pdc.release_batch(ctx, b)
+    pdc.release_detector(ctx, det)
+    out["accumulate_hits"] = {"hits": total, "ms": round(ms, 4), "hits_per_s": round(total / (ms / 1e3), 1),
+                              "GBps_hit_reads": round(8.0 * total / (ms / 1e3) / 1e9, 1),
+                              "what": "count map (+= nphot per pixel) and 1000-bin charge spectrum"}
+    # a kept batch: Frames2 histogram and spectra split by cloud size
+    kdet = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain,
+                         pdc.params(flags=pdc.KEEP_CORRECTED))
+    b = pdc.process_frames(ctx, kdet, frames, keep_frames, hit_cap, stream)
+    _, ktotal, _, _, _ = pdc.get_hits(ctx, b, keep_frames, capacity=0)
+    pdc.histogram_corrected(ctx, b, hist, -50.0, 450.0, nb, stream)
+    e0.record(stream)
+    for _ in range(reps):
+        pdc.histogram_corrected(ctx, b, hist, -50.0, 450.0, nb, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_h = e0.elapsed_time(e1) / reps
+    e0.record(stream)
+    for _ in range(reps):
+        pdc.accumulate_hits(ctx, b, cmap, spec, sizes, -50.0, 450.0, nb, stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_s = e0.elapsed_time(e1) / reps
+    pdc.release_batch(ctx, b)
+    pdc.release_detector(ctx, kdet)
+    nval = keep_frames * npix
+    out["histogram_frames2"] = {"values": nval, "ms": round(ms_h, 4),
+                                "GBps": round(4.0 * nval / (ms_h / 1e3) / 1e9, 1),
+                                "frac_of_hbm_peak": round(4.0 * nval / (ms_h / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
+    out["size_spectra"] = {"hits": ktotal, "ms": round(ms_s, 4), "hits_per_s": round(ktotal / (ms_s / 1e3), 1)}
+    # darks: pedestal and noise
+    dped, dgain = ped, gain
+    pool = synth.make_frames(geom, dped, dgain, 16, 0.0, 1, 7)
+    dpool = torch.from_numpy(pool).to(dev)
+    darks = torch.empty((dark_frames, *geom.shape), dtype=torch.int16, device=dev)
+    for i in range(0, dark_frames, 16):
+        darks[i:i + 16].copy_(dpool[:min(16, dark_frames - i)])
+    torch.cuda.synchronize()
+    g = pdc.geometry(*geom.shape, geom.bank_cols)
+    pdc.dark_stats(ctx, g, darks, dark_frames, stream)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        p_, n_ = pdc.dark_stats(ctx, g, darks, dark_frames, stream)
+    ms_d = (time.perf_counter() - t0) * 1e3 / 3
+    out["dark_stats"] = {"frames": dark_frames, "pixels": npix, "ms_wall": round(ms_d, 3),
+                         "GBps_wall": round(2.0 * dark_frames * npix / (ms_d / 1e3) / 1e9, 1),
+                         "noise_median_adu": round(float(np.median(n_)), 4),
+                         "note": "synchronous call: device sums, 37 MB copy to the host, host finish"}
+    del darks, dpool
+    return out
+
+
 # ---------------------------------------------------------------------------
 def ingest_pmc(fetch_csv, write_csv):
     """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the frame kernel, scaled by
@@ -356,6 +441,7 @@ def main():
     ap.add_argument("--no-latency", action="store_true")
     ap.add_argument("--no-subpixel", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-summaries", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
@@ -449,6 +535,10 @@ def main():
     if not args.no_serve:
         out["serving"] = [serving(torch, pdc, ctx, rate_hz=r) for r in (1000.0, 20000.0)]
         log("serving: %s" % out["serving"])
+
+    if not args.no_summaries:
+        out["summaries"] = summaries(torch, pdc, ctx, geom, ped, gain, frames, N, hit_cap)
+        log("summaries: %s" % out["summaries"])
 
     if not args.no_subpixel:
         out["subpixel"] = subpixel(torch, pdc, ctx)

@@ -5,9 +5,9 @@
 
 namespace pdc {
 
-// Histograms of up to this many bins are gathered in LDS per workgroup (32 KiB,
-// so that several workgroups share a CU).
-constexpr uint64_t kLdsBins = 8192;
+// Histograms of up to this many bins are gathered in LDS per workgroup (48 KiB
+// at most: three such workgroups share a CU).
+constexpr uint64_t kLdsBins = 12288;
 // Frames one thread sums for the dark statistics (keeps its 32-bit sum exact).
 constexpr uint64_t kDarkChunkMax = 1ull << 18;
 

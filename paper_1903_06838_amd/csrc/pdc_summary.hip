@@ -57,7 +57,34 @@ __device__ __forceinline__ void lds_flush(const uint32_t *h, uint32_t n, uint32_
     }
 }
 
-// One thread per hit (grid-stride).  count_map[pixel] += nphot;
+// Frame of hit i: the largest f < n_frames with frame_offset[f] <= i, given
+// f0 <= that frame.  Gallops forward from f0, then bisects, so hits visited in
+// increasing order cost O(log(frames skipped)) loads each.
+__device__ __forceinline__ uint64_t frame_from(const unsigned long long *frame_offset, uint64_t n_frames, uint64_t i,
+                                               uint64_t f0)
+{
+    uint64_t lo = f0, step = 1;
+    uint64_t hi = n_frames;  // frame_offset[n_frames] = total > i is never read
+    while (lo + step < n_frames) {
+        if (frame_offset[lo + step] <= i) {
+            lo += step;
+            step *= 2;
+        } else {
+            hi = lo + step;
+            break;
+        }
+    }
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (frame_offset[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Each workgroup takes a contiguous range of hits, 256 consecutive hits per
+// step (coalesced), so each thread meets its hits in increasing order.
+// count_map[pixel] += nphot;
 // spectrum[bin(charge)] += 1; size_spectra[(size - 1) * (nbins + 2) +
 // bin(charge)] += 1 where size counts the pixels of the hit's in-tile 3x3
 // window whose Frames2 value is above t_nb.
@@ -72,8 +99,10 @@ __global__ __launch_bounds__(kThreads) void accumulate_hits_kernel(AccumulateArg
         lds_clear(s_h, (SPEC ? nb2 : 0u) + (SIZES ? 9u * nb2 : 0u));
         __syncthreads();
     }
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.n; i += stride) {
+    const uint64_t per = ((a.n + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+    const uint64_t i_end = (blockIdx.x + 1) * per < a.n ? (blockIdx.x + 1) * per : a.n;
+    uint64_t f = 0;
+    for (uint64_t i = blockIdx.x * per + threadIdx.x; i < i_end; i += blockDim.x) {
         const uint2 hit = a.hits[i];
         const float q = __uint_as_float(hit.y);
         if (MAP) {
@@ -87,17 +116,12 @@ __global__ __launch_bounds__(kThreads) void accumulate_hits_kernel(AccumulateArg
             else atomicAdd(a.spectrum + b, 1u);
         }
         if (SIZES) {
-            uint64_t lo = 0, hi = a.n_frames;  // frame: largest f with frame_offset[f] <= i
-            while (hi - lo > 1) {
-                const uint64_t mid = (lo + hi) / 2;
-                if (a.frame_offset[mid] <= i) lo = mid;
-                else hi = mid;
-            }
+            f = frame_from(a.frame_offset, a.n_frames, i, f);
             const uint32_t W = (uint32_t)a.W, H = (uint32_t)a.H;
             const int c = (int)(hit.x % W);
             const uint32_t rt = hit.x / W;
             const int t = (int)(rt / H), r = (int)(rt - (uint32_t)t * H);
-            const float *fr = a.corrected + (lo * (uint64_t)a.T + (uint64_t)t) * (uint64_t)H * W;
+            const float *fr = a.corrected + (f * (uint64_t)a.T + (uint64_t)t) * (uint64_t)H * W;
             uint32_t size = 0;
 #pragma unroll
             for (int dr = -1; dr <= 1; ++dr)

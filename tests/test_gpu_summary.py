@@ -83,6 +83,29 @@ def test_accumulate_hits(ctx, nbins):
     assert got.sum() == want["total"] and got[1].sum() > 0 and got[2].sum() > 0
 
 
+def test_size_spectra_many_sparse_frames(ctx):
+    """600 small frames at about one photon each, many with no hit at all: the
+    frame of each hit is found across runs of empty frames."""
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(1, 16, 32, 16)
+    ped, gain = synth.make_calibration(geom, 12)
+    raw = synth.make_frames(geom, ped, gain, 600, 0.002, 12)
+    raw[200:450] = synth.make_frames(geom, ped, gain, 250, 0.0, 12, occ_id=3)  # 250 frames without photons
+    want = oracle_threads(raw, ped, gain, geom.bank_cols, keep_corrected=True)
+    assert np.count_nonzero(want["frame_hits"] == 0) > 300 and want["total"] > 100
+    nb = 50
+    sizes = _zeros(9 * (nb + 2))
+    det, dev, bs = _batches(ctx, geom, raw, ped, gain, True, [0, 600])
+    try:
+        pdc.accumulate_hits(ctx, bs[0], None, None, sizes, 0.0, 300.0, nb)
+        pdc.release_batch(ctx, bs[0])
+    finally:
+        pdc.release_detector(ctx, det)
+    got = _host(sizes).reshape(9, nb + 2)
+    assert np.array_equal(got, S.size_spectra(want["corrected"], want["hits"], T_NB, 0.0, 300.0, nb))
+
+
 def test_accumulate_map_only_without_keep(ctx):
     from paper_1903_06838_amd import pdc
 
@@ -107,7 +130,7 @@ def test_accumulate_map_only_without_keep(ctx):
 @pytest.mark.parametrize("geom,n,nbins", [
     (synth.Geometry(1, 5, 9, 3), 3, 64),          # 135 values: a ragged tail of 3
     (synth.Geometry(2, 40, 388, 194), 6, 1000),
-    (synth.Geometry(2, 40, 388, 194), 2, 9000),   # bins beyond LDS
+    (synth.Geometry(2, 40, 388, 194), 2, 13000),  # bins beyond LDS
 ])
 def test_histogram_corrected(ctx, geom, n, nbins):
     from paper_1903_06838_amd import pdc
