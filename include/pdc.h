@@ -72,15 +72,40 @@ typedef struct {
     int32_t gain_mode;
 } pdc_geometry;
 
+/* Common-mode estimator (cm_mode of pdc_params).
+ * PDC_CM_MEDIAN: m = the bank's lower median, v = u - m (the contract above).
+ * PDC_CM_BANK_MEAN, PDC_CM_TILE_MEAN: the thresholded mean of Fig. c over
+ *   each bank or each tile (for a one-tile detector, the frame), applied
+ *   cm_stages times in sequence (the stacked stages of the performance
+ *   model).  Stage s, on the current values v of a region of P pixels:
+ *     noise pixels: v < T_cm = n_cm * sigma;  N0 = their number;
+ *     S = their binary32 sum: pixel i of the region (raster order within the
+ *       region) is added to partial sum i mod Q (Q = 64 for a bank, 256 for
+ *       a tile), partials start at +0.0 and take their pixels in increasing
+ *       i, and the Q partials are added in a balanced binary tree (pairs
+ *       (0,1), (2,3), ... first);
+ *     CM_s = S / max((float)N0, sqrtf((float)P));  v = v - CM_s.
+ *   Frames2 is v after the last stage; hit finding is unchanged.  Each
+ *   operation is one binary32 operation rounded to nearest even. */
+#define PDC_CM_MEDIAN 0
+#define PDC_CM_BANK_MEAN 1
+#define PDC_CM_TILE_MEAN 2
+
 /* Thresholds and photon scale (Results, Accuracy: the two noise thresholds,
  * typically 3 to 5 sigma).  sigma > 0, n_seed >= 0, n_nb >= 0 finite, with
- * T_nb <= T_seed; photon_adu in [2^-24, 2^24]; flags is 0 or PDC_KEEP_CORRECTED. */
+ * T_nb <= T_seed; photon_adu in [2^-24, 2^24]; flags is 0 or PDC_KEEP_CORRECTED.
+ * cm_mode is a PDC_CM_* value; with a mean mode, 1 <= cm_stages <= 3 and
+ * n_cm >= 0 finite (the segmentation threshold of Fig. c, typically 3);
+ * both are ignored by PDC_CM_MEDIAN. */
 typedef struct {
     float sigma;
     float n_seed;
     float n_nb;
     float photon_adu;
     uint32_t flags;
+    int32_t cm_mode;
+    int32_t cm_stages;
+    float n_cm;
 } pdc_params;
 
 /* One photon hit (16 bytes).  frame is relative to the batch. */
@@ -167,7 +192,8 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
 
 /* Timing of a finished batch from HIP events recorded on its stream:
  * *main_ms = the fused frame kernel alone, *total_ms = every kernel of the
- * batch (frame kernel, scans, hit scatter).  Either pointer may be NULL. */
+ * batch (common-mode pass of the mean modes, frame kernel, scans, hit
+ * scatter).  Either pointer may be NULL. */
 pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms);
 
 /* ------------------------------------------------------------------------

@@ -23,7 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpdc.so")
 
-SOURCES = ["pdc_kernels.hip", "pdc_frame_v2.hip", "pdc_subpixel.hip", "pdc_summary.hip", "pdc_runtime.cpp", "pdc_serve.cpp"]
+SOURCES = ["pdc_kernels.hip", "pdc_frame_v2.hip", "pdc_subpixel.hip", "pdc_summary.hip", "pdc_cmmean.hip", "pdc_runtime.cpp", "pdc_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

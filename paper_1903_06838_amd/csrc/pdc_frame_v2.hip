@@ -353,7 +353,7 @@ __device__ __forceinline__ uint32_t seed_key(int row, int bank, int col)
     return ((uint32_t)row << 18) | ((uint32_t)bank << 11) | (uint32_t)col;
 }
 
-template <int NQ, int GMAX, int L, int V, bool KEEP>
+template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM>
 __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 {
     extern __shared__ float lds[];
@@ -519,7 +519,27 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             for (int x = tid; x < RN; x += kV2Threads) s_cnt[par * RN + x] = 0;
             if (tid == 0) s_nseed[par] = 0;
         }
-        if (cur_ok) {
+        if (CMM && cur_ok) {
+            // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
+            // replaces u in place and the bank-row's median slot holds 0
+            constexpr int G = 64 / L;
+            const int grp = lane / L, gl = lane - grp * L;
+            const int i = wave * G + grp;
+            if (i < BR) {
+                const int row = i / nb;
+                const int bank = i - row * nb;
+                const uint32_t reg = A.cm_tile ? (uint32_t)t : ((uint32_t)t * H + lr0 + row) * (uint32_t)nb + bank;
+                const float *cv = A.cm + (f * A.cm_regions + reg) * 3;
+                const float c0 = cv[0], c1 = cv[1], c2 = cv[2];
+                float *dst = u_c + row * W + bank * B;
+                for (int c = gl; c < B; c += L) dst[c] = __fsub_rn(__fsub_rn(__fsub_rn(dst[c], c0), c1), c2);
+                if (gl == 0) {
+                    med_c[i] = 0.0f;
+                    s_th[i] = seed_threshold(0.0f, A.t_seed);
+                }
+            }
+        }
+        if (!CMM && cur_ok) {
             constexpr int G = 64 / L;
             const int grp = lane / L, gl = lane - grp * L;
             const int i = wave * G + grp;
@@ -719,21 +739,21 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     }
 }
 
+template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM>
+static hipError_t launch_v2_k(const V2Args &a, uint32_t grid, size_t lds, hipStream_t s)
+{
+    auto k = frame_kernel_v2<NQ, GMAX, L, V, KEEP, CMM>;
+    hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kV2Threads), lds, s, a);
+    return hipGetLastError();
+}
+
 template <int NQ, int GMAX, int L, int V>
 static hipError_t launch_v2_t(const V2Args &a, uint32_t grid, size_t lds, bool keep, hipStream_t s)
 {
-    if (keep) {
-        auto k = frame_kernel_v2<NQ, GMAX, L, V, true>;
-        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kV2Threads), lds, s, a);
-    } else {
-        auto k = frame_kernel_v2<NQ, GMAX, L, V, false>;
-        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(grid), dim3(kV2Threads), lds, s, a);
-    }
-    return hipGetLastError();
+    return keep ? launch_v2_k<NQ, GMAX, L, V, true, false>(a, grid, lds, s)
+                : launch_v2_k<NQ, GMAX, L, V, false, false>(a, grid, lds, s);
 }
 
 // Lanes per bank-row in the median phase and values per lane (L, V): 16 lanes
@@ -745,6 +765,15 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
                                   hipStream_t s)
 {
     if (a.B < 1 || a.rmax * a.nb > 16 * gmax) return hipErrorInvalidValue;
+    if (a.cm) {  // the thresholded-mean variant: no median search (L and V only set the lane layout)
+        if (nq == 2 && gmax == 4 && a.B <= 256)
+            return keep ? launch_v2_k<2, 4, 16, 16, true, true>(a, grid, lds, s)
+                        : launch_v2_k<2, 4, 16, 16, false, true>(a, grid, lds, s);
+        if (nq == 1 && gmax == 8 && a.B <= 128)
+            return keep ? launch_v2_k<1, 8, 8, 16, true, true>(a, grid, lds, s)
+                        : launch_v2_k<1, 8, 8, 16, false, true>(a, grid, lds, s);
+        return hipErrorInvalidValue;
+    }
     if (nq == 2 && gmax == 4 && a.B <= 256) {
         if (a.B <= 16 * 13) return launch_v2_t<2, 4, 16, 13>(a, grid, lds, keep, s);
         return launch_v2_t<2, 4, 16, 16>(a, grid, lds, keep, s);

@@ -44,6 +44,9 @@ struct FrameKernelArgs {
     uint64_t *unit_base;          // [n_units] staging start or kNoBase
     BatchState *state;
     float *corrected;             // Frames2 or nullptr
+    const float *cm;              // thresholded-mean mode: [n_frames][cm_regions][3], else nullptr
+    uint32_t cm_regions;          // regions per frame: banks (T*H*nb) or tiles (T)
+    int32_t cm_tile;              // 1: a region is a tile, 0: a bank
 };
 
 // Persistent kernel (v2): strips of own rows [r0, r1) of a tile.
@@ -72,11 +75,32 @@ struct V2Args {
     uint64_t *unit_base;
     BatchState *state;
     float *corrected;
+    const float *cm;              // as in FrameKernelArgs
+    uint32_t cm_regions;
+    int32_t cm_tile;
 };
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);
+// a.cm != nullptr selects the thresholded-mean variant (no median search)
 hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
                                   hipStream_t s);
+
+// Thresholded-mean common mode (Fig. c), computed ahead of the frame kernels:
+// cm[f][region][s] for stages s < stages, zeros after.  Bank regions take 64
+// interleaved partial sums per region, tile regions 256, each partial adding
+// its pixels in raster order from +0, then a balanced tree over the partials.
+struct CmArgs {
+    const uint16_t *frames;       // [n_frames][T][H][W]
+    const float *ped, *k;         // [T][H][W]
+    uint64_t n_frames;
+    int32_t T, H, W, B, nb;
+    int32_t stages;               // 1..3
+    float t_cm;                   // pixels below it are noise
+    float guard;                  // fl(sqrt(fl(region size)))
+    float *cm;
+};
+hipError_t launch_cm_bank(const CmArgs &a, uint32_t n_cu, hipStream_t s);
+hipError_t launch_cm_tile(const CmArgs &a, uint32_t n_cu, hipStream_t s);
 
 size_t frame_kernel_v1_lds_bytes(int strip_rows, int W, int nb, int sort_width, int sort_rows,
                                  uint32_t max_unit_hits);

@@ -93,8 +93,19 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
         }
         __syncthreads();
 
+        // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
+        if (A.cm) {
+            const float *cf = A.cm + f * (uint64_t)A.cm_regions * 3;
+            for (int i = tid; i < nrows * W; i += kV1Threads) {
+                const int row = i / W, c = i - row * W;
+                const uint32_t reg = A.cm_tile ? (uint32_t)t : ((uint32_t)t * H + lr0 + row) * (uint32_t)nb + c / B;
+                const float *cv = cf + (uint64_t)reg * 3;
+                s_v[i] = __fsub_rn(__fsub_rn(__fsub_rn(s_v[i], cv[0]), cv[1]), cv[2]);
+            }
+            __syncthreads();
+        }
         // bank medians, a group of rows at a time; v = u - m in place
-        for (int g0 = 0; g0 < nrows; g0 += A.sort_rows) {
+        for (int g0 = 0; g0 < (A.cm ? 0 : nrows); g0 += A.sort_rows) {
             const int gr = min(A.sort_rows, nrows - g0);
             const int total = gr * nb * Pw;
             for (int i = tid; i < total; i += kV1Threads) {

@@ -40,7 +40,13 @@ class Geometry(ctypes.Structure):
 
 class Params(ctypes.Structure):
     _fields_ = [("sigma", ctypes.c_float), ("n_seed", ctypes.c_float), ("n_nb", ctypes.c_float),
-                ("photon_adu", ctypes.c_float), ("flags", ctypes.c_uint32)]
+                ("photon_adu", ctypes.c_float), ("flags", ctypes.c_uint32), ("cm_mode", ctypes.c_int32),
+                ("cm_stages", ctypes.c_int32), ("n_cm", ctypes.c_float)]
+
+
+CM_MEDIAN = 0
+CM_BANK_MEAN = 1
+CM_TILE_MEAN = 2
 
 
 class PdcError(RuntimeError):
@@ -126,8 +132,9 @@ def geometry(n_tiles, rows, cols, bank_cols, gain_mode=0) -> Geometry:
     return Geometry(n_tiles, rows, cols, bank_cols, gain_mode)
 
 
-def params(sigma=3.0, n_seed=5.0, n_nb=3.0, photon_adu=150.0, flags=0) -> Params:
-    return Params(sigma, n_seed, n_nb, photon_adu, flags)
+def params(sigma=3.0, n_seed=5.0, n_nb=3.0, photon_adu=150.0, flags=0, cm_mode=CM_MEDIAN, cm_stages=1,
+           n_cm=3.0) -> Params:
+    return Params(sigma, n_seed, n_nb, photon_adu, flags, cm_mode, cm_stages, n_cm)
 
 
 def create(device: int = 0):
