@@ -15,7 +15,8 @@ dominant kernel (algorithmic HBM bytes / its event-timed duration against the
 8 TB/s peak), the CPU oracle's rate on the 64-frame pool (which also checks the
 GPU hits of that pool), single-frame latency percentiles, a four-detector
 serving run (Poisson arrivals at 1 and 20 kHz per detector, p50/p99 latency),
-summaries (count map and charge spectrum of the batch's hits, the Frames2
+the thresholded-mean common mode of Fig. c (bank and tile regions, three
+stacked stages) on the same batch, summaries (count map and charge spectrum of the batch's hits, the Frames2
 histogram and per-cloud-size spectra of a kept 2,000-frame batch, pedestal
 and noise from 1,000 dark frames), the learned subpixel estimator against
 centroid + eta on 10 M simulated hits, and an occupancy sweep.
@@ -442,6 +443,7 @@ def main():
     ap.add_argument("--no-subpixel", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-summaries", action="store_true")
+    ap.add_argument("--no-cm-mean", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
@@ -535,6 +537,21 @@ def main():
     if not args.no_serve:
         out["serving"] = [serving(torch, pdc, ctx, rate_hz=r) for r in (1000.0, 20000.0)]
         log("serving: %s" % out["serving"])
+
+    if not args.no_cm_mean:
+        cmr = []
+        for mode, name in ((pdc.CM_BANK_MEAN, "bank"), (pdc.CM_TILE_MEAN, "tile")):
+            cdet = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain,
+                                 pdc.params(cm_mode=mode, cm_stages=3))
+            ms_c, m_c, t_c, h_c, _, _ = run_steps(torch, pdc, ctx, cdet, frames, N, est, max(2, args.steps // 2), 1)
+            pdc.release_detector(ctx, cdet)
+            cmr.append({"region": name, "stages": 3, "ms_per_step": round(ms_c, 4),
+                        "Mpixel_s": round(N * npix / (ms_c / 1e3) / 1e6, 1), "hits": h_c,
+                        "frame_kernel_ms": round(sum(m_c) / len(m_c), 4),
+                        "all_kernels_ms": round(sum(t_c) / len(t_c), 4),
+                        "frame_kernel_roofline_frac": roofline(N, npix, h_c, m_c)["frac"]})
+        out["cm_mean"] = cmr
+        log("cm_mean: %s" % cmr)
 
     if not args.no_summaries:
         out["summaries"] = summaries(torch, pdc, ctx, geom, ped, gain, frames, N, hit_cap)

@@ -39,98 +39,145 @@ __device__ __forceinline__ uint32_t sum64(uint32_t n)
     return n;
 }
 
-// One wave per (frame, bank-row); lane j holds columns j + 64 k, k < KV.
-template <int KV>
+// One wave per (bank-row, group of F consecutive frames); lane j holds columns
+// j + 64 k, k < KV, of the bank-row in each of the F frames.  The bank-row's
+// dark and 1/gain are loaded once for the F frames.
+template <int KV, int F>
 __global__ __launch_bounds__(kCmThreads) void cm_bank_kernel(CmArgs a)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t nreg = (uint64_t)a.T * a.H * a.nb;
-    const uint64_t total = a.n_frames * nreg;
+    const uint64_t nfg = (a.n_frames + F - 1) / F;
+    const uint64_t total = nfg * nreg;
     const uint64_t npix = (uint64_t)a.T * a.H * a.W;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kCmThreads) >> 6;
     for (uint64_t w = ((uint64_t)blockIdx.x * kCmThreads + threadIdx.x) >> 6; w < total; w += nwaves) {
-        const uint64_t f = w / nreg;
-        const uint32_t reg = (uint32_t)(w - f * nreg);
+        const uint64_t fg = w / nreg;
+        const uint32_t reg = (uint32_t)(w - fg * nreg);
         const uint32_t rowi = reg / (uint32_t)a.nb;  // t * H + r
         const uint32_t bank = reg - rowi * (uint32_t)a.nb;
         const uint32_t p0 = rowi * (uint32_t)a.W + bank * (uint32_t)a.B;
-        const uint16_t *fr = a.frames + f * npix + p0;
-        float x[KV];
+        const uint64_t f0 = fg * F;
+        const int nf = (int)(a.n_frames - f0 < (uint64_t)F ? a.n_frames - f0 : (uint64_t)F);
+        float pd[KV], kk[KV];
         bool ok[KV];
 #pragma unroll
         for (int k = 0; k < KV; ++k) {
             const int c = lane + 64 * k;
             ok[k] = c < a.B;
-            x[k] = ok[k] ? dark_gain(fr[c], a.ped[p0 + c], a.k[p0 + c]) : 0.0f;
+            pd[k] = ok[k] ? a.ped[p0 + c] : 0.0f;
+            kk[k] = ok[k] ? a.k[p0 + c] : 0.0f;
         }
-        float cs[3] = {0.0f, 0.0f, 0.0f};
+        float x[F][KV];
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const uint16_t *fr = a.frames + (f0 + j) * npix + p0;
+#pragma unroll
+            for (int k = 0; k < KV; ++k)
+                x[j][k] = (j < nf && ok[k]) ? dark_gain(fr[lane + 64 * k], pd[k], kk[k]) : 0.0f;
+        }
+        float cs[F][3];
+#pragma unroll
+        for (int j = 0; j < F; ++j) cs[j][0] = cs[j][1] = cs[j][2] = 0.0f;
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             if (s >= a.stages) break;
-            float part = 0.0f;
-            uint32_t n0 = 0;
 #pragma unroll
-            for (int k = 0; k < KV; ++k)
-                if (ok[k] && x[k] < a.t_cm) {
-                    part = __fadd_rn(part, x[k]);
-                    ++n0;
-                }
-            const float sum = tree64(part);
-            const uint32_t n = sum64(n0);
-            const float c = __fdiv_rn(sum, fmaxf((float)n, a.guard));
-            cs[s] = c;
+            for (int j = 0; j < F; ++j) {
+                float part = 0.0f;
+                uint32_t n0 = 0;
 #pragma unroll
-            for (int k = 0; k < KV; ++k) x[k] = __fsub_rn(x[k], c);
+                for (int k = 0; k < KV; ++k)
+                    if (ok[k] && x[j][k] < a.t_cm) {
+                        part = __fadd_rn(part, x[j][k]);
+                        ++n0;
+                    }
+                const float sum = tree64(part);
+                const uint32_t n = sum64(n0);
+                const float c = __fdiv_rn(sum, fmaxf((float)n, a.guard));
+                cs[j][s] = c;
+#pragma unroll
+                for (int k = 0; k < KV; ++k) x[j][k] = __fsub_rn(x[j][k], c);
+            }
         }
-        if (lane == 0) {
-            float *o = a.cm + w * 3;
-            o[0] = cs[0];
-            o[1] = cs[1];
-            o[2] = cs[2];
+        if (lane < F && lane < nf) {
+            float c0 = 0.0f, c1 = 0.0f, c2 = 0.0f;
+#pragma unroll
+            for (int j = 0; j < F; ++j)
+                if (j == lane) {
+                    c0 = cs[j][0];
+                    c1 = cs[j][1];
+                    c2 = cs[j][2];
+                }
+            float *o = a.cm + ((f0 + lane) * nreg + reg) * 3;
+            o[0] = c0;
+            o[1] = c1;
+            o[2] = c2;
         }
     }
 }
 
-// Stage s of the tile regions: one workgroup per (frame, tile); thread j owns
-// partial j (pixels p = j + 256 k of the tile); waves hold partials 64w..64w+63.
+// Stage s of the tile regions: one workgroup per (tile, group of F frames);
+// thread j owns partial j (pixels p = j + 256 k of the tile) of each frame;
+// waves hold partials 64w..64w+63.  Dark and 1/gain are read once per F frames.
+template <int F>
 __global__ __launch_bounds__(kCmThreads) void cm_tile_kernel(CmArgs a, int s)
 {
-    __shared__ float s_part[kCmThreads / 64];
-    __shared__ uint32_t s_cnt[kCmThreads / 64];
+    __shared__ float s_part[kCmThreads / 64][F];
+    __shared__ uint32_t s_cnt[kCmThreads / 64][F];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const uint64_t items = a.n_frames * (uint64_t)a.T;
+    const uint64_t nfg = (a.n_frames + F - 1) / F;
+    const uint64_t items = nfg * (uint64_t)a.T;
     const uint32_t HW = (uint32_t)a.H * (uint32_t)a.W;
     const uint64_t npix = (uint64_t)a.T * HW;
     for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
-        const uint64_t f = it / (uint64_t)a.T;
-        const uint32_t t = (uint32_t)(it - f * (uint64_t)a.T);
-        float *cv = a.cm + it * 3;
-        const float c0 = s > 0 ? cv[0] : 0.0f;
-        const float c1 = s > 1 ? cv[1] : 0.0f;
-        const uint16_t *fr = a.frames + f * npix + (uint64_t)t * HW;
+        const uint64_t fg = it / (uint64_t)a.T;
+        const uint32_t t = (uint32_t)(it - fg * (uint64_t)a.T);
+        const uint64_t f0 = fg * F;
+        const int nf = (int)(a.n_frames - f0 < (uint64_t)F ? a.n_frames - f0 : (uint64_t)F);
+        float c0[F], c1[F], part[F];
+        uint32_t n0[F];
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
+            c0[j] = (s > 0 && j < nf) ? cv[0] : 0.0f;
+            c1[j] = (s > 1 && j < nf) ? cv[1] : 0.0f;
+            part[j] = 0.0f;
+            n0[j] = 0;
+        }
+        const uint16_t *fr = a.frames + f0 * npix + (uint64_t)t * HW;
         const float *pd = a.ped + (uint64_t)t * HW;
         const float *kk = a.k + (uint64_t)t * HW;
-        float part = 0.0f;
-        uint32_t n0 = 0;
+#pragma unroll 4
         for (uint32_t p = threadIdx.x; p < HW; p += kCmThreads) {
-            float y = dark_gain(fr[p], pd[p], kk[p]);
-            if (s > 0) y = __fsub_rn(y, c0);
-            if (s > 1) y = __fsub_rn(y, c1);
-            if (y < a.t_cm) {
-                part = __fadd_rn(part, y);
-                ++n0;
+            const float pp = pd[p], kp = kk[p];
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                if (j >= nf) break;
+                float y = dark_gain(fr[j * npix + p], pp, kp);
+                if (s > 0) y = __fsub_rn(y, c0[j]);
+                if (s > 1) y = __fsub_rn(y, c1[j]);
+                if (y < a.t_cm) {
+                    part[j] = __fadd_rn(part[j], y);
+                    ++n0[j];
+                }
             }
         }
-        part = tree64(part);
-        n0 = sum64(n0);
-        if (lane == 0) {
-            s_part[wave] = part;
-            s_cnt[wave] = n0;
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const float ps = tree64(part[j]);
+            const uint32_t ns = sum64(n0[j]);
+            if (lane == 0) {
+                s_part[wave][j] = ps;
+                s_cnt[wave][j] = ns;
+            }
         }
         __syncthreads();
-        if (threadIdx.x == 0) {
-            const float sum = __fadd_rn(__fadd_rn(s_part[0], s_part[1]), __fadd_rn(s_part[2], s_part[3]));
-            const uint32_t n = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+        if (threadIdx.x < nf) {
+            const int j = threadIdx.x;
+            const float sum = __fadd_rn(__fadd_rn(s_part[0][j], s_part[1][j]), __fadd_rn(s_part[2][j], s_part[3][j]));
+            const uint32_t n = s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
+            float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
             cv[s] = __fdiv_rn(sum, fmaxf((float)n, a.guard));
             if (s == 0) {
                 cv[1] = 0.0f;
@@ -144,34 +191,42 @@ __global__ __launch_bounds__(kCmThreads) void cm_tile_kernel(CmArgs a, int s)
 uint32_t cm_grid(uint64_t items, uint64_t per_block, uint32_t n_cu)
 {
     const uint64_t want = (items + per_block - 1) / per_block;
-    const uint64_t cap = 16ull * n_cu;
+    const uint64_t cap = 64ull * n_cu;
     return (uint32_t)(want < 1 ? 1 : (want > cap ? cap : want));
 }
 
 }  // namespace
 
+template <int KV, int F>
+static void launch_bank_t(const CmArgs &a, uint32_t n_cu, hipStream_t s)
+{
+    const uint64_t total = (a.n_frames + F - 1) / F * (uint64_t)a.T * a.H * a.nb;
+    const uint32_t grid = cm_grid(total, kCmThreads / 64, n_cu);
+    hipLaunchKernelGGL((cm_bank_kernel<KV, F>), dim3(grid), dim3(kCmThreads), 0, s, a);
+}
+
+// Frames per wave: as many as keep F * KV values per lane at 32.
 hipError_t launch_cm_bank(const CmArgs &a, uint32_t n_cu, hipStream_t s)
 {
-    const uint64_t total = a.n_frames * (uint64_t)a.T * a.H * a.nb;
-    if (total == 0) return hipSuccess;
-    const uint32_t grid = cm_grid(total, kCmThreads / 64, n_cu);
+    if (a.n_frames == 0 || (uint64_t)a.T * a.H * a.nb == 0) return hipSuccess;
     const int kv = (a.B + 63) / 64;
-    if (kv <= 1) hipLaunchKernelGGL(cm_bank_kernel<1>, dim3(grid), dim3(kCmThreads), 0, s, a);
-    else if (kv <= 2) hipLaunchKernelGGL(cm_bank_kernel<2>, dim3(grid), dim3(kCmThreads), 0, s, a);
-    else if (kv <= 4) hipLaunchKernelGGL(cm_bank_kernel<4>, dim3(grid), dim3(kCmThreads), 0, s, a);
-    else if (kv <= 8) hipLaunchKernelGGL(cm_bank_kernel<8>, dim3(grid), dim3(kCmThreads), 0, s, a);
-    else if (kv <= 16) hipLaunchKernelGGL(cm_bank_kernel<16>, dim3(grid), dim3(kCmThreads), 0, s, a);
+    if (kv <= 1) launch_bank_t<1, 16>(a, n_cu, s);
+    else if (kv <= 2) launch_bank_t<2, 16>(a, n_cu, s);
+    else if (kv <= 4) launch_bank_t<4, 8>(a, n_cu, s);
+    else if (kv <= 8) launch_bank_t<8, 4>(a, n_cu, s);
+    else if (kv <= 16) launch_bank_t<16, 2>(a, n_cu, s);
     else return hipErrorInvalidValue;  // bank_cols <= 1024
     return hipGetLastError();
 }
 
 hipError_t launch_cm_tile(const CmArgs &a, uint32_t n_cu, hipStream_t s)
 {
-    const uint64_t items = a.n_frames * (uint64_t)a.T;
+    constexpr int F = 8;
+    const uint64_t items = (a.n_frames + F - 1) / F * (uint64_t)a.T;
     if (items == 0) return hipSuccess;
     const uint32_t grid = cm_grid(items, 1, n_cu);
     for (int st = 0; st < a.stages; ++st)
-        hipLaunchKernelGGL(cm_tile_kernel, dim3(grid), dim3(kCmThreads), 0, s, a, st);
+        hipLaunchKernelGGL(cm_tile_kernel<F>, dim3(grid), dim3(kCmThreads), 0, s, a, st);
     return hipGetLastError();
 }
 

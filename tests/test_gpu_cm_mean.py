@@ -61,6 +61,8 @@ CASES = [
     (synth.Geometry(1, 9, 2048, 1), 0.05, 1, M.BANK, 2),     # one-pixel banks
     (synth.Geometry(1, 33, 2048, 128), 0.01, 2, M.TILE, 1),
     (synth.Geometry(1, 1, 1, 1), 0.5, 3, M.TILE, 3),
+    (synth.Geometry(2, 12, 96, 48), 0.03, 37, M.BANK, 3),    # several frame groups and a ragged one
+    (synth.Geometry(2, 12, 96, 48), 0.03, 19, M.TILE, 2),
 ]
 
 
