@@ -190,3 +190,50 @@ def make_patches(n: int, seed: int, sigma_lo: float = 0.1, sigma_hi: float = 0.4
         pat += rng.normal(0.0, noise_sigma, size=pat.shape)
         out[a:b] = pat.astype(np.float32)
     return out, truth.astype(np.float32)
+
+
+# ---------------------------------------------------------------------------
+# Auto-ranging (multi-gain) detectors
+# ---------------------------------------------------------------------------
+# Gain code of each range in the raw word's bits 14-15 and the invalid code.
+GAIN_CODES = {1: ((0, 1, 2), 3),      # ePix10k-like
+              2: ((0, 1, 3), 2)}      # Jungfrau-like
+# Relative gains of the three ranges (high, medium, low).
+RANGE_GAINS = (1.0, 1.0 / 3.0, 1.0 / 100.0)
+
+
+def make_calibration_multigain(geom: Geometry, cfg_id: int, sim: SimParams = SimParams()):
+    """Per-range pedestal and gain planes, float32 [3, T, H, W]."""
+    rng = _rng(cfg_id, 50)
+    ped = rng.normal(sim.ped_mean, sim.ped_sigma, size=(3, *geom.shape)).astype(np.float32)
+    g = rng.uniform(sim.gain_lo, sim.gain_hi, size=(3, *geom.shape))
+    gain = (g * np.asarray(RANGE_GAINS)[:, None, None, None]).astype(np.float32)
+    return ped, gain
+
+
+def make_frames_multigain(geom: Geometry, ped: np.ndarray, gain: np.ndarray, n_frames: int, occupancy: float,
+                          cfg_id: int, gain_mode: int, range_frac=(0.80, 0.12, 0.06), invalid_frac: float = 0.02,
+                          sim: SimParams = SimParams()) -> np.ndarray:
+    """n_frames raw words uint16 [N, T, H, W]: every pixel is forced into a
+    range drawn with probabilities range_frac (an invalid code with
+    probability invalid_frac); its ADC value is that range's pedestal plus
+    gain times the signal, bank common mode and noise, clipped to 14 bits."""
+    codes, bad = GAIN_CODES[gain_mode]
+    T, H, W = geom.shape
+    nb = W // geom.bank_cols
+    p = np.asarray(list(range_frac) + [invalid_frac], np.float64)
+    p = p / p.sum()
+    out = np.empty((n_frames, T, H, W), np.uint16)
+    for f in range(n_frames):
+        rng = _rng(cfg_id, 60 + gain_mode, f)
+        sig, _ = photon_signal(geom, rng, occupancy, sim)
+        pick = rng.choice(4, size=(T, H, W), p=p)
+        r = np.minimum(pick, 2)
+        pr = np.take_along_axis(ped.astype(np.float64), r[None], 0)[0]
+        gr = np.take_along_axis(gain.astype(np.float64), r[None], 0)[0]
+        cm = np.repeat(rng.normal(0.0, sim.cm_sigma, size=(T, H, nb)), geom.bank_cols, axis=2)
+        noise = rng.normal(0.0, sim.noise_sigma, size=(T, H, W))
+        adc = np.clip(np.rint(pr + gr * sig + cm + noise), 0, ADC_MAX).astype(np.uint16)
+        code = np.where(pick == 3, bad, np.asarray(codes)[r]).astype(np.uint16)
+        out[f] = adc | (code << np.uint16(14))
+    return out
