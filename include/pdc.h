@@ -63,7 +63,7 @@ typedef struct pdc_ctx pdc_ctx;
  * separate sensors: 3x3 windows stop at tile edges).  Common-mode banks are
  * one row of bank_cols contiguous columns; cols % bank_cols == 0.
  * Limits: 1 <= n_tiles, rows; 1 <= bank_cols <= cols <= 2048; bank_cols <= 1024;
- * n_tiles*rows*cols < 2^31.  gain_mode must be 0 (single gain range). */
+ * n_tiles*rows*cols < 2^31.  gain_mode is a PDC_GAIN_* value. */
 typedef struct {
     int32_t n_tiles;
     int32_t rows;
@@ -71,6 +71,23 @@ typedef struct {
     int32_t bank_cols;
     int32_t gain_mode;
 } pdc_geometry;
+
+/* Gain ranges (Dark and Gain section, Fig. b: several darks and gains for
+ * auto-ranging detectors).  PDC_GAIN_SINGLE: one range, bits 14-15 of a raw
+ * word ignored.  Otherwise bits 14-15 report the pixel's range and the
+ * calibration holds one pedestal and one gain plane per range (3 ranges):
+ *   PDC_GAIN_EPIX10K:  codes 0, 1, 2 -> ranges 0, 1, 2; code 3 invalid
+ *   PDC_GAIN_JUNGFRAU: codes 0, 1, 3 -> ranges 0, 1, 2; code 2 invalid
+ * u = ((float)adc - pedestal[r][p]) * k[r][p] with r the reported range.  A
+ * pixel with an invalid code has no u: it takes no part in the common mode
+ * (the median is then the element of rank (n-1)/2 of the bank's n valid
+ * values, m = 0 when n = 0; the thresholded mean does not count it as noise,
+ * its guard still uses the region's size), its Frames2 value is +0.0 (it
+ * never seeds and adds nothing to a charge), and it is counted per frame
+ * (pdc_get_invalid_counts).  One threshold pair applies to every range. */
+#define PDC_GAIN_SINGLE 0
+#define PDC_GAIN_EPIX10K 1
+#define PDC_GAIN_JUNGFRAU 2
 
 /* Common-mode estimator (cm_mode of pdc_params).
  * PDC_CM_MEDIAN: m = the bank's lower median, v = u - m (the contract above).
@@ -131,7 +148,8 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out);
 pdc_status pdc_destroy(pdc_ctx *ctx);
 
 /* Host-only validation of what pdc_calibrate would accept (no device use).
- * pedestal and gain are host arrays float32 [n_tiles][rows][cols].  Each
+ * pedestal and gain are host arrays float32 [n_ranges][n_tiles][rows][cols]
+ * (n_ranges = 1 for PDC_GAIN_SINGLE, else 3).  Each
  * pedestal must be finite with |x| <= 2^24 and (x == 0 or |x| >= 2^-64); each
  * gain finite in [2^-24, 2^24].  These bounds keep every intermediate finite,
  * normal or +0 (no -0, no subnormal, no NaN).  EINVAL names the first
@@ -186,6 +204,10 @@ pdc_status pdc_get_hits(pdc_ctx *ctx, uint64_t batch, pdc_hit *dst, uint64_t dst
  * [n_frames][n_tiles][rows][cols] into host or device memory.  ESTATE if the
  * flag was not set. */
 pdc_status pdc_get_corrected(pdc_ctx *ctx, uint64_t batch, float *dst, int32_t dst_is_device);
+
+/* Per-frame number of pixels with an invalid gain code (uint32 [n_frames],
+ * host), zeros for a single-range detector.  Waits for the batch. */
+pdc_status pdc_get_invalid_counts(pdc_ctx *ctx, uint64_t batch, uint32_t *per_frame_invalid);
 
 /* Wait for the batch and return its buffers to the context for reuse. */
 pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
@@ -389,7 +411,7 @@ pdc_status pdc_dark_stats(pdc_ctx *ctx, const pdc_geometry *geom, const uint16_t
 
 /* pdc_dark_stats followed by pdc_calibrate with that pedestal and the host
  * gain plane: a detector calibrated from its dark frames.  noise_host may be
- * NULL. */
+ * NULL.  Single-range detectors only (EINVAL otherwise). */
 pdc_status pdc_calibrate_darks(pdc_ctx *ctx, const pdc_geometry *geom, const uint16_t *darks_dev, uint64_t n_frames,
                                const float *gain, const pdc_params *params, float *noise_host, int32_t *det_out);
 

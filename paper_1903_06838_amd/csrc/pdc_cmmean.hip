@@ -73,8 +73,16 @@ __global__ __launch_bounds__(kCmThreads) void cm_bank_kernel(CmArgs a)
         for (int j = 0; j < F; ++j) {
             const uint16_t *fr = a.frames + (f0 + j) * npix + p0;
 #pragma unroll
-            for (int k = 0; k < KV; ++k)
-                x[j][k] = (j < nf && ok[k]) ? dark_gain(fr[lane + 64 * k], pd[k], kk[k]) : 0.0f;
+            for (int k = 0; k < KV; ++k) {
+                x[j][k] = 0.0f;
+                if (j < nf && ok[k]) {
+                    const uint32_t w = fr[lane + 64 * k];
+                    bool bad;
+                    x[j][k] = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, pd[k], kk[k], a.ped, a.k, npix,
+                                                             p0 + lane + 64 * k, bad)
+                                          : dark_gain(w, pd[k], kk[k]);
+                }
+            }
         }
         float cs[F][3];
 #pragma unroll
@@ -154,7 +162,12 @@ __global__ __launch_bounds__(kCmThreads) void cm_tile_kernel(CmArgs a, int s)
 #pragma unroll
             for (int j = 0; j < F; ++j) {
                 if (j >= nf) break;
-                float y = dark_gain(fr[j * npix + p], pp, kp);
+                const uint32_t w = fr[j * npix + p];
+                bool bad;
+                // an invalid pixel is +inf: never below t_cm, and stays +inf
+                float y = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, pp, kp, a.ped, a.k, npix,
+                                                         (uint64_t)t * HW + p, bad)
+                                      : dark_gain(w, pp, kp);
                 if (s > 0) y = __fsub_rn(y, c0[j]);
                 if (s > 1) y = __fsub_rn(y, c1[j]);
                 if (y < a.t_cm) {

@@ -28,6 +28,32 @@ __device__ __forceinline__ float dark_gain(uint32_t raw, float ped, float k)
     return __fmul_rn(t, k);
 }
 
+// Gain range reported by a raw word's bits 14-15 on an auto-ranging detector
+// (Dark and Gain section: one dark and one gain plane per range), or -1 for
+// an invalid code.  mode 1 (ePix10k-like): codes 0, 1, 2 -> ranges 0, 1, 2,
+// code 3 invalid; mode 2 (Jungfrau-like): codes 0, 1, 3 -> ranges 0, 1, 2,
+// code 2 invalid.
+__device__ __forceinline__ int gain_range(uint32_t raw, int mode)
+{
+    const int c = (int)((raw >> 14) & 3u);
+    if (mode == 1) return c == 3 ? -1 : c;
+    return c == 2 ? -1 : (c == 3 ? 2 : c);
+}
+
+// Frames1 of one pixel of an auto-ranging detector: range 0 uses the given
+// (resident) plane values, ranges 1 and 2 read their planes at p + r * stride;
+// an invalid code gives +inf, which no valid value reaches.
+__device__ __forceinline__ float dark_gain_ranged(uint32_t raw, int mode, float ped0, float k0, const float *ped,
+                                                  const float *k, uint64_t stride, uint64_t p, bool &invalid)
+{
+    const int r = gain_range(raw, mode);
+    invalid = r < 0;
+    if (r == 0) return dark_gain(raw, ped0, k0);
+    if (r < 0) return __builtin_inff();
+    const uint64_t o = p + (uint64_t)r * stride;
+    return dark_gain(raw, ped[o], k[o]);
+}
+
 // Order-preserving map of binary32 to int32 (-0 just below +0) and back.
 __device__ __forceinline__ int32_t f2key(float x)
 {

@@ -353,7 +353,7 @@ __device__ __forceinline__ uint32_t seed_key(int row, int bank, int col)
     return ((uint32_t)row << 18) | ((uint32_t)bank << 11) | (uint32_t)col;
 }
 
-template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM>
+template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG>
 __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 {
     extern __shared__ float lds[];
@@ -482,14 +482,36 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) cur[g][q] = raw[g][q];
             if (f + 1 < f_end) load_raw(f + 1);
+            if constexpr (!MG) {
 #pragma unroll
-            for (int g = 0; g < GMAX; ++g)
+                for (int g = 0; g < GMAX; ++g)
 #pragma unroll
-                for (int q = 0; q < NQ; ++q)
-                    if (g < ng && lane_ok[q])
-                        *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) =
-                            make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
-                                        dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
+                    for (int q = 0; q < NQ; ++q)
+                        if (g < ng && lane_ok[q])
+                            *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) =
+                                make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
+                                            dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
+            } else {
+                // auto-ranging: range 0 from the resident planes, ranges 1 and
+                // 2 from memory, invalid codes as +inf (counted on own rows)
+                uint32_t ninv = 0;
+#pragma unroll
+                for (int g = 0; g < GMAX; ++g)
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (g < ng && lane_ok[q]) {
+                            const uint64_t o = row_base + gb_[g] + 128 * q + lane_off;
+                            bool b0, b1;
+                            const float u0 = dark_gain_ranged(cur[g][q] & 0xFFFFu, A.gain_mode, pd[g][q][0],
+                                                              kk[g][q][0], A.ped, A.k, npix, o, b0);
+                            const float u1 = dark_gain_ranged(cur[g][q] >> 16, A.gain_mode, pd[g][q][1],
+                                                              kk[g][q][1], A.ped, A.k, npix, o + 1, b1);
+                            *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) = make_float2(u0, u1);
+                            if (row_[g] >= own_lo && row_[g] < own_hi) ninv += (uint32_t)b0 + (uint32_t)b1;
+                        }
+                const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(ninv), 63);
+                if (lane == 0 && tot) atomicAdd(A.invalid + f, tot);
+            }
         }
         if (p2_ok && !ovf_2) {
             const uint64_t base = s_base;
@@ -532,7 +554,11 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const float *cv = A.cm + (f * A.cm_regions + reg) * 3;
                 const float c0 = cv[0], c1 = cv[1], c2 = cv[2];
                 float *dst = u_c + row * W + bank * B;
-                for (int c = gl; c < B; c += L) dst[c] = __fsub_rn(__fsub_rn(__fsub_rn(dst[c], c0), c1), c2);
+                for (int c = gl; c < B; c += L) {
+                    const float u = dst[c];
+                    // an invalid pixel (+inf) becomes 0, so that v = 0
+                    dst[c] = (MG && !(u < INFINITY)) ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, c0), c1), c2);
+                }
                 if (gl == 0) {
                     med_c[i] = 0.0f;
                     s_th[i] = seed_threshold(0.0f, A.t_seed);
@@ -553,7 +579,30 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const int c = L * v + gl;
                 x[v] = (act && c < B) ? src[c] : INFINITY;
             }
-            const float m = group_median<V, L>(x, B, kmed, A.rank_width, act, s_gs + tid);
+            int nv = B, kq = kmed;
+            bool actv = act;
+            if constexpr (MG) {
+                // the median of the valid values only (invalid ones are +inf)
+                int nl = 0;
+#pragma unroll
+                for (int v = 0; v < V; ++v) nl += x[v] < INFINITY ? 1 : 0;
+                nv = gsum_i<L>(nl);
+                kq = nv > 0 ? (nv - 1) / 2 : 0;
+                actv = act && nv > 0;
+            }
+            float m = group_median<V, L>(x, nv, kq, A.rank_width, actv, s_gs + tid);
+            if constexpr (MG) {
+                if (!actv) m = 0.0f;
+                // invalid pixels take the median: v = fl(m - m) = +0
+                if (act) {
+                    float *dst = u_c + row * W + bank * B;
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        const int c = L * v + gl;
+                        if (c < B && !(x[v] < INFINITY)) dst[c] = m;
+                    }
+                }
+            }
             if (act && gl == 0) {
                 med_c[i] = m;
                 s_th[i] = seed_threshold(m, A.t_seed);
@@ -739,10 +788,10 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     }
 }
 
-template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM>
+template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG = false>
 static hipError_t launch_v2_k(const V2Args &a, uint32_t grid, size_t lds, hipStream_t s)
 {
-    auto k = frame_kernel_v2<NQ, GMAX, L, V, KEEP, CMM>;
+    auto k = frame_kernel_v2<NQ, GMAX, L, V, KEEP, CMM, MG>;
     hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(grid), dim3(kV2Threads), lds, s, a);
@@ -765,6 +814,22 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
                                   hipStream_t s)
 {
     if (a.B < 1 || a.rmax * a.nb > 16 * gmax) return hipErrorInvalidValue;
+    if (a.gain_mode) {  // auto-ranging variants: one lane layout per strip shape
+        const bool cm = a.cm != nullptr;
+        if (nq == 2 && gmax == 4 && a.B <= 256) {
+            if (cm) return keep ? launch_v2_k<2, 4, 16, 16, true, true, true>(a, grid, lds, s)
+                                : launch_v2_k<2, 4, 16, 16, false, true, true>(a, grid, lds, s);
+            return keep ? launch_v2_k<2, 4, 16, 16, true, false, true>(a, grid, lds, s)
+                        : launch_v2_k<2, 4, 16, 16, false, false, true>(a, grid, lds, s);
+        }
+        if (nq == 1 && gmax == 8 && a.B <= 128) {
+            if (cm) return keep ? launch_v2_k<1, 8, 8, 16, true, true, true>(a, grid, lds, s)
+                                : launch_v2_k<1, 8, 8, 16, false, true, true>(a, grid, lds, s);
+            return keep ? launch_v2_k<1, 8, 8, 16, true, false, true>(a, grid, lds, s)
+                        : launch_v2_k<1, 8, 8, 16, false, false, true>(a, grid, lds, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.cm) {  // the thresholded-mean variant: no median search (L and V only set the lane layout)
         if (nq == 2 && gmax == 4 && a.B <= 256)
             return keep ? launch_v2_k<2, 4, 16, 16, true, true>(a, grid, lds, s)

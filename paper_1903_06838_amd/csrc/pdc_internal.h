@@ -47,6 +47,8 @@ struct FrameKernelArgs {
     const float *cm;              // thresholded-mean mode: [n_frames][cm_regions][3], else nullptr
     uint32_t cm_regions;          // regions per frame: banks (T*H*nb) or tiles (T)
     int32_t cm_tile;              // 1: a region is a tile, 0: a bank
+    int32_t gain_mode;            // 0 single range; 1, 2 auto-ranging (ped, k hold 3 planes)
+    uint32_t *invalid;            // [n_frames] invalid-code pixels, cleared before the launch
 };
 
 // Persistent kernel (v2): strips of own rows [r0, r1) of a tile.
@@ -78,6 +80,8 @@ struct V2Args {
     const float *cm;              // as in FrameKernelArgs
     uint32_t cm_regions;
     int32_t cm_tile;
+    int32_t gain_mode;
+    uint32_t *invalid;
 };
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);
@@ -97,6 +101,7 @@ struct CmArgs {
     int32_t stages;               // 1..3
     float t_cm;                   // pixels below it are noise
     float guard;                  // fl(sqrt(fl(region size)))
+    int32_t gain_mode;            // as in FrameKernelArgs
     float *cm;
 };
 hipError_t launch_cm_bank(const CmArgs &a, uint32_t n_cu, hipStream_t s);

@@ -86,11 +86,21 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
         const uint16_t *fr = A.frames + f * npix;
         const uint32_t tile_base = (uint32_t)t * (uint32_t)H * (uint32_t)W;
 
-        // load + correct: u
+        // load + correct: u (auto-ranging: the reported range's planes, +inf
+        // for an invalid code, counted on own rows)
+        uint32_t ninv = 0;
         for (int i = tid; i < nrows * W; i += kV1Threads) {
             uint32_t p = tile_base + (uint32_t)lr0 * W + i;
-            s_v[i] = dark_gain(fr[p], A.ped[p], A.k[p]);
+            if (A.gain_mode) {
+                bool bad;
+                s_v[i] = dark_gain_ranged(fr[p], A.gain_mode, A.ped[p], A.k[p], A.ped, A.k, npix, p, bad);
+                const int row = lr0 + i / W;
+                if (bad && row >= r0 && row < r1) ++ninv;
+            } else {
+                s_v[i] = dark_gain(fr[p], A.ped[p], A.k[p]);
+            }
         }
+        if (ninv) atomicAdd(A.invalid + f, ninv);
         __syncthreads();
 
         // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
@@ -100,7 +110,8 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
                 const int row = i / W, c = i - row * W;
                 const uint32_t reg = A.cm_tile ? (uint32_t)t : ((uint32_t)t * H + lr0 + row) * (uint32_t)nb + c / B;
                 const float *cv = cf + (uint64_t)reg * 3;
-                s_v[i] = __fsub_rn(__fsub_rn(__fsub_rn(s_v[i], cv[0]), cv[1]), cv[2]);
+                const float u = s_v[i];
+                s_v[i] = !(u < INFINITY) ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, cv[0]), cv[1]), cv[2]);
             }
             __syncthreads();
         }
@@ -133,8 +144,24 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
             for (int i = tid; i < gr * W; i += kV1Threads) {
                 int row = i / W;
                 int c = i - row * W;
-                float m = s_sort[(size_t)(row * nb + c / B) * Pw + kmed];
-                s_v[(g0 + row) * W + c] = __fsub_rn(s_v[(g0 + row) * W + c], m);
+                const float *seg = s_sort + (size_t)(row * nb + c / B) * Pw;
+                float m;
+                if (A.gain_mode) {
+                    // the lower median of the valid values: invalid ones (+inf)
+                    // sort last; an all-invalid bank has m = 0
+                    int lo = 0, hi = B;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (seg[mid] < INFINITY) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    m = lo > 0 ? seg[(lo - 1) / 2] : 0.0f;
+                } else {
+                    m = seg[kmed];
+                }
+                float u = s_v[(g0 + row) * W + c];
+                if (!(u < INFINITY)) u = m;  // invalid: v = fl(m - m) = +0
+                s_v[(g0 + row) * W + c] = __fsub_rn(u, m);
             }
             __syncthreads();
         }

@@ -70,6 +70,8 @@ struct Buffers {
     float *corrected = nullptr;
     float *cm = nullptr;               // [n_frames][regions][3] common-mode values
     uint64_t cap_cm = 0;
+    uint32_t *invalid = nullptr;       // [n_frames] pixels with an invalid gain code
+    uint64_t cap_inv = 0;
     BatchState *state = nullptr;
     BatchState *host_state = nullptr;  // pinned mirror
     hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr;
@@ -109,6 +111,7 @@ void free_buffers(Buffers *b)
     hipFree(b->hits);
     hipFree(b->corrected);
     hipFree(b->cm);
+    hipFree(b->invalid);
     hipFree(b->state);
     if (b->host_state) hipHostFree(b->host_state);
     if (b->ev_start) hipEventDestroy(b->ev_start);
@@ -174,7 +177,7 @@ pdc_status check_geometry(const pdc_geometry *g)
                     g->bank_cols);
     if ((int64_t)g->n_tiles * g->rows * g->cols >= (int64_t)1 << 31)
         return fail(nullptr, PDC_EINVAL, "n_tiles*rows*cols must be < 2^31");
-    if (g->gain_mode != 0) return fail(nullptr, PDC_EINVAL, "gain_mode must be 0");
+    if (g->gain_mode < 0 || g->gain_mode > 2) return fail(nullptr, PDC_EINVAL, "gain_mode must be 0, 1 or 2");
     return PDC_OK;
 }
 
@@ -204,10 +207,12 @@ pdc_status check_params(const pdc_params *p, float *t_seed, float *t_nb)
     return PDC_OK;
 }
 
+int n_ranges(const pdc_geometry &g) { return g.gain_mode ? 3 : 1; }
+
 pdc_status check_planes(const pdc_geometry *g, const float *ped, const float *gain)
 {
     if (!ped || !gain) return fail(nullptr, PDC_EINVAL, "pedestal and gain must be non-NULL");
-    const int64_t n = (int64_t)g->n_tiles * g->rows * g->cols;
+    const int64_t n = (int64_t)n_ranges(*g) * g->n_tiles * g->rows * g->cols;
     for (int64_t i = 0; i < n; ++i) {
         float d = ped[i];
         if (!(std::isfinite(d) && std::fabs(d) <= 0x1p24f && (d == 0.0f || std::fabs(d) >= 0x1p-64f)))
@@ -376,6 +381,9 @@ pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n
     if (cm_floats > b->cap_cm) {
         HIP_TRY(ctx, grow(&b->cm, b->cap_cm, cm_floats));
     }
+    if (n_frames > b->cap_inv || !b->invalid) {
+        HIP_TRY(ctx, grow(&b->invalid, b->cap_inv, n_frames));
+    }
     return PDC_OK;
 }
 
@@ -406,6 +414,7 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     hipStream_t s = bt.stream;
     HIP_TRY(ctx, launch_init_state(b->state, s));
     HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
+    if (d.g.gain_mode) HIP_TRY(ctx, launch_fill_u32(b->invalid, bt.n_frames, s));
     const float *cm = nullptr;
     if (d.p.cm_mode && bt.n_frames > 0) {
         CmArgs c{};
@@ -421,6 +430,7 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         c.stages = d.p.cm_stages;
         c.t_cm = d.t_cm;
         c.guard = d.cm_guard;
+        c.gain_mode = d.g.gain_mode;
         c.cm = b->cm;
         if (d.p.cm_mode == PDC_CM_BANK_MEAN) HIP_TRY(ctx, launch_cm_bank(c, (uint32_t)ctx->n_cu, s));
         else HIP_TRY(ctx, launch_cm_tile(c, (uint32_t)ctx->n_cu, s));
@@ -458,6 +468,8 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.cm = cm;
         a.cm_regions = d.cm_regions;
         a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+        a.gain_mode = d.g.gain_mode;
+        a.invalid = b->invalid;
         HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
     } else if (bt.n_units > 0) {
         FrameKernelArgs a{};
@@ -490,6 +502,8 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.cm = cm;
         a.cm_regions = d.cm_regions;
         a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+        a.gain_mode = d.g.gain_mode;
+        a.invalid = b->invalid;
         HIP_TRY(ctx, launch_frame_kernel_v1(a, batch_grid(d, bt), d.lds_bytes, bt.keep, s));
     }
     HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
@@ -685,7 +699,7 @@ pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pe
                             : (uint32_t)((uint64_t)geom->n_tiles * geom->rows * (geom->cols / geom->bank_cols));
     }
     if (!plan_v1(d)) return fail(ctx, PDC_EINVAL, "geometry does not fit the kernel's on-chip budget");
-    const size_t n = (size_t)geom->n_tiles * geom->rows * geom->cols;
+    const size_t n = (size_t)n_ranges(*geom) * geom->n_tiles * geom->rows * geom->cols;
     std::vector<float> k(n);
     for (size_t i = 0; i < n; ++i) {
         volatile float r = 1.0f / gain[i];  // binary32 division
@@ -1267,11 +1281,35 @@ pdc_status pdc_calibrate_darks(pdc_ctx *ctx, const pdc_geometry *geom, const uin
     if (rc != PDC_OK) return fail(ctx, rc, "%s", g_thread_error);
     rc = check_params(params, nullptr, nullptr);
     if (rc != PDC_OK) return fail(ctx, rc, "%s", g_thread_error);
+    if (geom->gain_mode != 0)
+        return fail(ctx, PDC_EINVAL, "calibration from darks takes single-range detectors (gain_mode 0)");
     const size_t px = (size_t)geom->n_tiles * geom->rows * geom->cols;
     std::vector<float> ped(px);
     rc = pdc_dark_stats(ctx, geom, darks_dev, n_frames, ped.data(), noise_host, nullptr);
     if (rc != PDC_OK) return rc;
     return pdc_calibrate(ctx, geom, ped.data(), gain, params, det_out);
+}
+
+pdc_status pdc_get_invalid_counts(pdc_ctx *ctx, uint64_t batch, uint32_t *per_frame_invalid)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (!per_frame_invalid && bt->n_frames) return fail(ctx, PDC_EINVAL, "per_frame_invalid is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    if (bt->n_frames == 0) return PDC_OK;
+    if (ctx->dets[bt->det].g.gain_mode == 0) {
+        std::memset(per_frame_invalid, 0, bt->n_frames * sizeof(uint32_t));
+        return PDC_OK;
+    }
+    hipStream_t cs = ctx->copy_stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(cs, bt->buf->ev_end, 0));
+    HIP_TRY(ctx, hipMemcpyAsync(per_frame_invalid, bt->buf->invalid, bt->n_frames * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, cs));
+    HIP_TRY(ctx, hipStreamSynchronize(cs));
+    return PDC_OK;
 }
 
 }  // extern "C"

@@ -91,6 +91,7 @@ _sig = {
     "pdc_accumulate_hits": (_st, [_P, ctypes.c_uint64, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32,
                                   _P]),
     "pdc_histogram_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
+    "pdc_get_invalid_counts": (_st, [_P, ctypes.c_uint64, _P]),
     "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
     "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
                                   ctypes.POINTER(ctypes.c_int32)]),
@@ -155,12 +156,19 @@ def check_calibration(geom: Geometry, pedestal: np.ndarray, gain: np.ndarray, pr
                                       ctypes.byref(prm))
 
 
+GAIN_SINGLE = 0
+GAIN_EPIX10K = 1
+GAIN_JUNGFRAU = 2
+
+
 def calibrate(ctx, geom: Geometry, pedestal: np.ndarray, gain: np.ndarray, prm: Params) -> int:
+    """pedestal, gain: float32 [n_tiles, rows, cols], or [3, n_tiles, rows, cols]
+    for an auto-ranging gain_mode."""
     ped = np.ascontiguousarray(pedestal, dtype=np.float32)
     g = np.ascontiguousarray(gain, dtype=np.float32)
-    n = geom.n_tiles * geom.rows * geom.cols
+    n = (3 if geom.gain_mode else 1) * geom.n_tiles * geom.rows * geom.cols
     if ped.size != n or g.size != n:
-        raise ValueError("pedestal/gain must hold n_tiles*rows*cols values")
+        raise ValueError("pedestal/gain must hold n_ranges*n_tiles*rows*cols values")
     det = ctypes.c_int32(-1)
     _check(_lib.pdc_calibrate(ctx, ctypes.byref(geom), ped.ctypes.data, g.ctypes.data,
                               ctypes.byref(prm), ctypes.byref(det)), ctx)
@@ -209,6 +217,12 @@ def get_corrected(ctx, batch: int, dst) -> None:
     """dst: host float32 numpy array or device float32 tensor of n_frames*T*H*W."""
     is_dev = 0 if isinstance(dst, np.ndarray) else 1
     _check(_lib.pdc_get_corrected(ctx, batch, _ptr(dst), is_dev), ctx)
+
+
+def get_invalid_counts(ctx, batch: int, n_frames: int) -> np.ndarray:
+    out = np.zeros(n_frames, np.uint32)
+    _check(_lib.pdc_get_invalid_counts(ctx, batch, out.ctypes.data if n_frames else None), ctx)
+    return out
 
 
 def release_batch(ctx, batch: int) -> None:
