@@ -265,7 +265,7 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
 {
     const pdc_geometry &g = d.g;
     d.v2_ok = false;
-    if (g.gain_mode != 0 || (g.cols & 1) || (g.bank_cols & 1) || g.bank_cols > 256 || g.bank_cols < 2)
+    if ((g.cols & 1) || (g.bank_cols & 1) || g.bank_cols > 256 || g.bank_cols < 2)
         return false;
     const int nb = g.cols / g.bank_cols;
     d.nq = g.bank_cols > 128 ? 2 : 1;
@@ -1309,6 +1309,20 @@ pdc_status pdc_get_invalid_counts(pdc_ctx *ctx, uint64_t batch, uint32_t *per_fr
     HIP_TRY(ctx, hipMemcpyAsync(per_frame_invalid, bt->buf->invalid, bt->n_frames * sizeof(uint32_t),
                                 hipMemcpyDeviceToHost, cs));
     HIP_TRY(ctx, hipStreamSynchronize(cs));
+    return PDC_OK;
+}
+
+// Test hook: the kernel a batch ran on (1 general, 2 persistent), after any
+// recomputation.  Waits for the batch.
+pdc_status pdc_debug_batch_path(pdc_ctx *ctx, uint64_t batch, int32_t *path)
+{
+    if (!ctx || !path) return fail(ctx, PDC_EINVAL, "ctx and path must be non-NULL");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    *path = bt->path;
     return PDC_OK;
 }
 

@@ -92,6 +92,7 @@ _sig = {
                                   _P]),
     "pdc_histogram_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
     "pdc_get_invalid_counts": (_st, [_P, ctypes.c_uint64, _P]),
+    "pdc_debug_batch_path": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
     "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
                                   ctypes.POINTER(ctypes.c_int32)]),
@@ -223,6 +224,13 @@ def get_invalid_counts(ctx, batch: int, n_frames: int) -> np.ndarray:
     out = np.zeros(n_frames, np.uint32)
     _check(_lib.pdc_get_invalid_counts(ctx, batch, out.ctypes.data if n_frames else None), ctx)
     return out
+
+
+def debug_batch_path(ctx, batch: int) -> int:
+    """1: general kernel, 2: persistent kernel."""
+    p = ctypes.c_int32(0)
+    _check(_lib.pdc_debug_batch_path(ctx, batch, ctypes.byref(p)), ctx)
+    return p.value
 
 
 def release_batch(ctx, batch: int) -> None:

@@ -38,7 +38,7 @@ def _run(ctx, raw, ped, gain, bank_cols, mode, stages, keep=True, n_cm=3.0):
     try:
         b = pdc.process_frames(ctx, det, torch.from_numpy(raw).cuda(), N, max(1024, raw.size // 10))
         hits, total, fh, fp, _ = pdc.get_hits(ctx, b, N)
-        out = dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp)
+        out = dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp, path=pdc.debug_batch_path(ctx, b))
         if keep:
             corr = np.empty(raw.shape, np.float32)
             pdc.get_corrected(ctx, b, corr)
@@ -73,6 +73,8 @@ def test_cm_mean_parity(ctx, geom, occ, n, region, stages):
     want = M.process(raw, ped, gain, geom.bank_cols, region, stages, keep_corrected=True)
     got = _run(ctx, raw, ped, gain, geom.bank_cols, region, stages)
     assert want["total"] > 0
+    if geom.bank_cols in (194, 96):
+        assert got["path"] == 2  # the persistent kernel
     assert_same(got, want, corrected=True)
 
 
@@ -113,6 +115,7 @@ def test_cm_mean_general_kernel():
         got_t = _run(c, raw, ped, gain, 194, M.TILE, 2)
     finally:
         pdc.destroy(c)
+    assert got["path"] == got_t["path"] == 1
     assert_same(got, want, corrected=True)
     assert_same(got_t, M.process(raw, ped, gain, 194, M.TILE, 2, keep_corrected=True), corrected=True)
 
