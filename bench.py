@@ -15,7 +15,9 @@ dominant kernel (algorithmic HBM bytes / its event-timed duration against the
 8 TB/s peak), the CPU oracle's rate on the 64-frame pool (which also checks the
 GPU hits of that pool), single-frame latency percentiles, a four-detector
 serving run (Poisson arrivals at 1 and 20 kHz per detector, p50/p99 latency),
-the thresholded-mean common mode of Fig. c (bank and tile regions, three
+a mixed batch of three detectors (ePix100, ePix10k-like and
+Jungfrau-like with gain ranges, 4,000 frames each) enqueued together, the
+thresholded-mean common mode of Fig. c (bank and tile regions, three
 stacked stages) on the same batch, summaries (count map and charge spectrum of the batch's hits, the Frames2
 histogram and per-cloud-size spectra of a kept 2,000-frame batch, pedestal
 and noise from 1,000 dark frames), the learned subpixel estimator against
@@ -306,6 +308,97 @@ def serving(torch, pdc, ctx, rate_hz=20000.0, seconds=0.4, max_batch=64, max_inf
     return out
 
 
+def mixed(torch, pdc, ctx, frames_each=4000, steps=3):
+    """Mixed-geometry batch: ePix100 704x768 (single gain, 96-pixel banks),
+    ePix10k-like 352x384 (three gain ranges, 96-pixel banks) and
+    Jungfrau-like 512x1024 (three gain ranges, 256-pixel banks), 4,000 frames
+    each at occupancies spread over 0.001..0.02, enqueued together with
+    pdc_process_mixed (launches on forked streams, each on the whole chip, and
+    again each sized to its share of the chip) against the three processed one
+    after another."""
+    import numpy as np
+
+    from paper_1903_06838_amd import synth
+
+    dev = torch.device("cuda:0")
+    spec = [("epix100", synth.EPIX100, 0), ("epix10k", synth.Geometry(1, 352, 384, 96), 1),
+            ("jungfrau_0.5M", synth.Geometry(1, 512, 1024, 256), 2)]
+    occs = (0.001, 0.007, 0.013, 0.02)
+    frames, calib, px = [], [], 0
+    for j, (name, g, gm) in enumerate(spec):
+        parts = []
+        if gm:
+            ped, gain = synth.make_calibration_multigain(g, 70 + j)
+        else:
+            ped, gain = synth.make_calibration(g, 70 + j)
+        for i, occ in enumerate(occs):
+            if gm:
+                parts.append(synth.make_frames_multigain(g, ped, gain, 4, occ, 70 + 10 * i + j, gm,
+                                                         range_frac=(0.95, 0.03, 0.01), invalid_frac=0.01))
+            else:
+                parts.append(synth.make_frames(g, ped, gain, 4, occ, 70 + j, i))
+        pool = torch.from_numpy(np.concatenate(parts)).to(dev)
+        fr = torch.empty((frames_each, *g.shape), dtype=torch.int16, device=dev)
+        for i in range(0, frames_each, pool.shape[0]):
+            n = min(pool.shape[0], frames_each - i)
+            fr[i:i + n].copy_(pool[:n])
+        frames.append(fr)
+        calib.append((ped, gain))
+        px += frames_each * g.pixels
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+
+    def setup(c):
+        dets = [pdc.calibrate(c, pdc.geometry(*g.shape, g.bank_cols, gm), *calib[j], pdc.params())
+                for j, (_, g, gm) in enumerate(spec)]
+        items = [(d, f, frames_each, int(0.03 * frames_each * g.pixels) + 4096)
+                 for d, f, (_, g, _) in zip(dets, frames, spec)]
+        return dets, items
+
+    def time_mixed(c, items):
+        for k in range(steps + 1):  # one warm-up
+            if k == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            for b in pdc.process_mixed(c, items, stream):
+                pdc.release_batch(c, b)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps
+
+    dets, items = setup(ctx)
+    ms_mixed = time_mixed(ctx, items)
+    alone = {}
+    for i, (name, g, gm) in enumerate(spec):
+        d, f, n, cap = items[i]
+        for k in range(steps + 1):
+            if k == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            pdc.release_batch(ctx, pdc.process_frames(ctx, d, f, n, cap, stream))
+        torch.cuda.synchronize()
+        alone[name] = round((time.perf_counter() - t0) * 1e3 / steps, 3)
+    for d in dets:
+        pdc.release_detector(ctx, d)
+    # the same with each launch sized to its share of the chip
+    os.environ["PDC_MIX_SHARE"] = "1"
+    try:
+        c2 = pdc.create(0)
+    finally:
+        del os.environ["PDC_MIX_SHARE"]
+    dets2, items2 = setup(c2)
+    ms_share = time_mixed(c2, items2)
+    for d in dets2:
+        pdc.release_detector(c2, d)
+    pdc.destroy(c2)
+    del frames
+    return {"frames_per_detector": frames_each, "pixels": px, "ms_mixed": round(ms_mixed, 3),
+            "Mpixel_s_mixed": round(px / (ms_mixed / 1e3) / 1e6, 1),
+            "ms_mixed_shared_chip": round(ms_share, 3), "ms_alone": alone,
+            "ms_alone_sum": round(sum(alone.values()), 3),
+            "Mpixel_s_one_after_another": round(px / (sum(alone.values()) / 1e3) / 1e6, 1),
+            "occupancies": list(occs), "gain_ranges": "95/3/1 % of pixels, 1 % invalid codes"}
+
+
 def summaries(torch, pdc, ctx, geom, ped, gain, frames, n_frames, hit_cap, keep_frames=2000, dark_frames=1000):
     """Summaries over CSPAD-like batches: count map + charge spectrum of the
     headline batch's hits, Frames2 histogram and per-size spectra of a batch
@@ -444,6 +537,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-summaries", action="store_true")
     ap.add_argument("--no-cm-mean", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--profile", action="store_true")
     ap.add_argument("--ingest-pmc", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
@@ -552,6 +646,10 @@ def main():
                         "frame_kernel_roofline_frac": roofline(N, npix, h_c, m_c)["frac"]})
         out["cm_mean"] = cmr
         log("cm_mean: %s" % cmr)
+
+    if not args.no_mixed:
+        out["mixed"] = mixed(torch, pdc, ctx)
+        log("mixed: %s" % out["mixed"])
 
     if not args.no_summaries:
         out["summaries"] = summaries(torch, pdc, ctx, geom, ped, gain, frames, N, hit_cap)

@@ -187,6 +187,25 @@ pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_
                               uint64_t n_frames, uint64_t hit_capacity, void *hip_stream,
                               uint64_t *batch_out);
 
+/* Batches of several detectors (mixed geometries, gain modes and
+ * common-mode settings) enqueued at once: item i becomes batch batch_out[i]
+ * exactly as pdc_process_frames would make it, on one of up to 8 internal
+ * streams forked from hip_stream (NULL: the context's stream) and joined back
+ * into it, so the detectors' kernels may overlap and work enqueued later on
+ * hip_stream waits for all of them.  Each persistent launch takes the whole
+ * chip (PDC_MIX_SHARE=1 in the environment at pdc_create sizes each for the
+ * share of the chip its pixels are of the whole instead).  1 <= n_items <= 64.
+ * On an error no batch is left outstanding. */
+typedef struct {
+    int32_t det;
+    const uint16_t *frames_dev;  /* DEVICE [n_frames][n_tiles][rows][cols], borrowed as above */
+    uint64_t n_frames;
+    uint64_t hit_capacity;
+} pdc_mixed_item;
+
+pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, void *hip_stream,
+                             uint64_t *batch_out);
+
 /* Wait for the batch and copy its results, hits in (frame, pixel) order.
  * dst: room for dst_capacity records, in host memory (dst_is_device = 0) or
  *   device memory of the context's device (dst_is_device = 1); may be NULL

@@ -86,6 +86,7 @@ struct Batch {
     int32_t det = -1;
     int path = 1;            // 1: general kernel, 2: persistent kernel
     int n_fg = 1;            // frame groups (path 2)
+    double share = 1.0;      // fraction of the chip's compute units the batch is sized for
     int32_t upf = 0;         // units per frame
     const uint16_t *frames = nullptr;
     uint64_t n_frames = 0;
@@ -131,6 +132,9 @@ struct pdc_ctx {
     int max_lds = 0;
     hipStream_t stream = nullptr;
     hipStream_t copy_stream = nullptr;  // result copies: they wait for their batch only
+    std::vector<hipStream_t> mix_streams;  // concurrent batches of pdc_process_mixed
+    bool mix_share = false;                // PDC_MIX_SHARE=1: size each mixed launch to its share of the chip
+    std::vector<hipEvent_t> mix_events;
     std::vector<Detector> dets;
     std::map<uint64_t, Batch> batches;
     std::vector<Buffers *> spare;
@@ -523,7 +527,8 @@ void set_path(const Detector &d, Batch &bt, int path)
 {
     bt.path = path;
     if (path == 2) {
-        bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)d.fg_max, bt.n_frames));
+        const uint64_t fg = (uint64_t)std::max(1.0, std::floor((double)d.fg_max * bt.share));
+        bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(fg, bt.n_frames));
         bt.upf = d.n_strips;
     } else {
         bt.n_fg = 1;
@@ -628,6 +633,8 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
     {
         const char *fv = std::getenv("PDC_FORCE_GENERAL");
         ctx->force_v1 = fv && fv[0] == '1';
+        const char *ms = std::getenv("PDC_MIX_SHARE");
+        ctx->mix_share = ms && ms[0] == '1';
     }
     {
         int lds = 0;
@@ -661,6 +668,8 @@ pdc_status pdc_destroy(pdc_ctx *ctx)
     hipFree(ctx->fmt_buf);
     hipStreamDestroy(ctx->stream);
     hipStreamDestroy(ctx->copy_stream);
+    for (hipStream_t st : ctx->mix_streams) hipStreamDestroy(st);
+    for (hipEvent_t ev : ctx->mix_events) hipEventDestroy(ev);
     delete ctx;
     return PDC_OK;
 }
@@ -733,8 +742,69 @@ pdc_status pdc_release_detector(pdc_ctx *ctx, int32_t det)
     return PDC_OK;
 }
 
+pdc_status process_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                         uint64_t hit_capacity, void *hip_stream, double share, uint64_t *batch_out);
+
 pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
                               uint64_t hit_capacity, void *hip_stream, uint64_t *batch_out)
+{
+    return process_batch(ctx, det, frames_dev, n_frames, hit_capacity, hip_stream, 1.0, batch_out);
+}
+
+pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, void *hip_stream,
+                             uint64_t *batch_out)
+{
+    if (!ctx || !items || !batch_out || n_items < 1 || n_items > 64)
+        return fail(ctx, PDC_EINVAL, "ctx, items and batch_out must be non-NULL, 1 <= n_items <= 64");
+    for (int i = 0; i < n_items; ++i) {
+        const int32_t det = items[i].det;
+        if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+            return fail(ctx, PDC_ESTATE, "item %d: unknown detector %d", i, det);
+        if (items[i].n_frames > 0 && !items[i].frames_dev) return fail(ctx, PDC_EINVAL, "item %d: frames_dev is NULL", i);
+    }
+    if ((int)ctx->batches.size() + n_items > kMaxOutstandingBatches)
+        return fail(ctx, PDC_ESTATE, "too many outstanding batches (release some)");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const int n_str = std::min(n_items, 8);
+    while ((int)ctx->mix_streams.size() < n_str) {
+        hipStream_t st = nullptr;
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ctx->mix_streams.push_back(st);
+    }
+    while ((int)ctx->mix_events.size() < n_str + 1) {
+        hipEvent_t ev = nullptr;
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ctx->mix_events.push_back(ev);
+    }
+    // each batch is sized for the share of the chip its pixels are of the whole
+    double work = 0.0;
+    for (int i = 0; i < n_items; ++i) {
+        const pdc_geometry &g = ctx->dets[items[i].det].g;
+        work += (double)items[i].n_frames * g.n_tiles * g.rows * g.cols;
+    }
+    hipStream_t hs = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, hipEventRecord(ctx->mix_events[0], hs));  // fork
+    for (int j = 0; j < n_str; ++j) HIP_TRY(ctx, hipStreamWaitEvent(ctx->mix_streams[j], ctx->mix_events[0], 0));
+    for (int i = 0; i < n_items; ++i) {
+        const pdc_geometry &g = ctx->dets[items[i].det].g;
+        const double px = (double)items[i].n_frames * g.n_tiles * g.rows * g.cols;
+        const double share = ctx->mix_share && work > 0.0 ? std::min(1.0, px / work) : 1.0;
+        pdc_status rc = process_batch(ctx, items[i].det, items[i].frames_dev, items[i].n_frames,
+                                      items[i].hit_capacity, ctx->mix_streams[i % n_str], share, &batch_out[i]);
+        if (rc != PDC_OK) {
+            for (int j = 0; j < i; ++j) pdc_release_batch(ctx, batch_out[j]);
+            return rc;
+        }
+    }
+    for (int j = 0; j < n_str; ++j) {  // join
+        HIP_TRY(ctx, hipEventRecord(ctx->mix_events[1 + j], ctx->mix_streams[j]));
+        HIP_TRY(ctx, hipStreamWaitEvent(hs, ctx->mix_events[1 + j], 0));
+    }
+    return PDC_OK;
+}
+
+pdc_status process_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                         uint64_t hit_capacity, void *hip_stream, double share, uint64_t *batch_out)
 {
     if (!ctx || !batch_out) return fail(ctx, PDC_EINVAL, "ctx and batch_out must be non-NULL");
     if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
@@ -750,6 +820,7 @@ pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_
     bt.det = det;
     bt.frames = frames_dev;
     bt.n_frames = n_frames;
+    bt.share = share;
     set_path(d, bt, d.v2_ok ? 2 : 1);
     bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;

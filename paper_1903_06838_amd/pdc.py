@@ -92,6 +92,7 @@ _sig = {
                                   _P]),
     "pdc_histogram_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
     "pdc_get_invalid_counts": (_st, [_P, ctypes.c_uint64, _P]),
+    "pdc_process_mixed": (_st, [_P, _P, ctypes.c_int32, _P, _P]),
     "pdc_debug_batch_path": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
     "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
@@ -188,6 +189,21 @@ def process_frames(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int, 
     _check(_lib.pdc_process_frames(ctx, det, _ptr(frames_dev), n_frames, hit_capacity, stream,
                                    ctypes.byref(b)), ctx)
     return b.value
+
+
+class MixedItem(ctypes.Structure):
+    _fields_ = [("det", ctypes.c_int32), ("frames_dev", ctypes.c_void_p), ("n_frames", ctypes.c_uint64),
+                ("hit_capacity", ctypes.c_uint64)]
+
+
+def process_mixed(ctx, items, stream=None) -> list:
+    """items: (det, frames_dev, n_frames, hit_capacity) tuples; returns batch ids."""
+    arr = (MixedItem * len(items))(*[MixedItem(d, _ptr(f), n, c) for d, f, n, c in items])
+    out = (ctypes.c_uint64 * len(items))()
+    if stream is not None and not isinstance(stream, int):
+        stream = stream.cuda_stream
+    _check(_lib.pdc_process_mixed(ctx, arr, len(items), stream, out), ctx)
+    return list(out)
 
 
 def get_hits(ctx, batch: int, n_frames: int, capacity: int | None = None, dst_dev=None):

@@ -1,0 +1,109 @@
+"""Mixed batches (pdc_process_mixed): several detectors with different
+geometries, gain modes and common-mode settings enqueued at once, running
+concurrently; every batch equals its oracle bit for bit and work enqueued
+afterwards on the caller's stream sees all of them finished."""
+import numpy as np
+import pytest
+
+from oracle import cm_mean as M
+from oracle import multigain as G
+from paper_1903_06838_amd import synth
+from tests.helpers import assert_same, oracle_threads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_1903_06838_amd import pdc
+
+    c = pdc.create(0)
+    yield c
+    pdc.destroy(c)
+
+
+FEW_LOW_GAIN = dict(range_frac=(0.95, 0.03, 0.01), invalid_frac=0.01)
+
+
+def _detectors():
+    """(geometry, gain_mode, cm_mode, raw, ped, gain, want)"""
+    out = []
+    g = synth.Geometry(1, 64, 768, 96)                 # ePix100-like rows, single gain, median
+    ped, gain = synth.make_calibration(g, 41)
+    raw = synth.make_frames(g, ped, gain, 5, 0.01, 41)
+    out.append((g, 0, 0, raw, ped, gain, oracle_threads(raw, ped, gain, 96, keep_corrected=True)))
+    g = synth.Geometry(2, 40, 388, 194)                # CSPAD-like, bank mean with 2 stages
+    ped, gain = synth.make_calibration(g, 45)
+    raw = synth.make_frames(g, ped, gain, 6, 0.01, 45)
+    out.append((g, 0, 1, raw, ped, gain, M.process(raw, ped, gain, 194, M.BANK, 2, keep_corrected=True)))
+    g = synth.Geometry(1, 64, 384, 96)                 # ePix10k-like, three gain ranges
+    ped, gain = synth.make_calibration_multigain(g, 42)
+    raw = synth.make_frames_multigain(g, ped, gain, 7, 0.02, 42, 1, **FEW_LOW_GAIN)
+    out.append((g, 1, 0, raw, ped, gain, G.process(raw, ped, gain, 96, 1, keep_corrected=True)))
+    g = synth.Geometry(1, 48, 1024, 256)               # Jungfrau-like, three gain ranges
+    ped, gain = synth.make_calibration_multigain(g, 43)
+    raw = synth.make_frames_multigain(g, ped, gain, 4, 0.005, 43, 2, **FEW_LOW_GAIN)
+    out.append((g, 2, 0, raw, ped, gain, G.process(raw, ped, gain, 256, 2, keep_corrected=True)))
+    return out
+
+
+def test_mixed_batch_equals_oracle(ctx):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    dets, items, devs = [], [], []
+    cases = _detectors()
+    try:
+        for g, gm, cm, raw, ped, gain, _ in cases:
+            prm = pdc.params(flags=pdc.KEEP_CORRECTED, cm_mode=cm, cm_stages=2)
+            d = pdc.calibrate(ctx, pdc.geometry(*g.shape, g.bank_cols, gm), ped, gain, prm)
+            dets.append(d)
+            dev = torch.from_numpy(raw).cuda()
+            devs.append(dev)
+            items.append((d, dev, raw.shape[0], 1 << 16))
+        stream = torch.cuda.Stream()
+        batches = pdc.process_mixed(ctx, items, stream)
+        # work enqueued after the call on the same stream waits for every batch
+        flag = torch.zeros(1, device="cuda")
+        with torch.cuda.stream(stream):
+            flag += 1
+        stream.synchronize()
+        for b, (g, gm, cm, raw, ped, gain, want) in zip(batches, cases):
+            hits, total, fh, fp, _ = pdc.get_hits(ctx, b, raw.shape[0])
+            corr = np.empty(raw.shape, np.float32)
+            pdc.get_corrected(ctx, b, corr)
+            got = dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp, corrected=corr)
+            assert_same(got, want, corrected=True)
+            assert pdc.debug_batch_path(ctx, b) == 2, (g, gm, cm)
+            if gm:
+                assert np.array_equal(pdc.get_invalid_counts(ctx, b, raw.shape[0]), want["invalid"])
+            pdc.release_batch(ctx, b)
+    finally:
+        for d in dets:
+            pdc.release_detector(ctx, d)
+
+
+def test_mixed_rejects_bad_items(ctx):
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    g = synth.Geometry(1, 8, 16, 8)
+    ped, gain = synth.make_calibration(g, 44)
+    d = pdc.calibrate(ctx, pdc.geometry(*g.shape, 8), ped, gain, pdc.params())
+    try:
+        dev = torch.zeros((2, 1, 8, 16), dtype=torch.int16, device="cuda")
+        torch.cuda.synchronize()  # torch fills on its stream, the library runs on its own
+        with pytest.raises(pdc.PdcError) as e:
+            pdc.process_mixed(ctx, [(d, dev, 2, 1024), (d + 100, dev, 2, 1024)])
+        assert e.value.status == pdc.ESTATE
+        with pytest.raises(pdc.PdcError):
+            pdc.process_mixed(ctx, [(d, None, 2, 1024)])
+        b = pdc.process_mixed(ctx, [(d, dev, 2, 1024)])[0]
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, d)
