@@ -92,12 +92,16 @@ def run_steps(torch, pdc, ctx, det, frames, n_frames, hit_cap, steps, warmup):
     hit_cap = int(total * 1.02) + 1024
     for _ in range(warmup):
         b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
+        pdc.get_hits(ctx, b, n_frames, capacity=0)
         pdc.release_batch(ctx, b)
     mains, totals = [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
+        # the step ends with the batch's final per-frame results: this also
+        # runs any recomputation the batch needs (seed lists or staging full)
+        pdc.get_hits(ctx, b, n_frames, capacity=0)
         m, t = pdc.batch_timing(ctx, b)
         mains.append(m)
         totals.append(t)
@@ -360,7 +364,8 @@ def mixed(torch, pdc, ctx, frames_each=4000, steps=3):
             if k == 1:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-            for b in pdc.process_mixed(c, items, stream):
+            for b, it in zip(pdc.process_mixed(c, items, stream), items):
+                pdc.get_hits(c, b, it[2], capacity=0)
                 pdc.release_batch(c, b)
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) * 1e3 / steps
@@ -374,7 +379,9 @@ def mixed(torch, pdc, ctx, frames_each=4000, steps=3):
             if k == 1:
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-            pdc.release_batch(ctx, pdc.process_frames(ctx, d, f, n, cap, stream))
+            b = pdc.process_frames(ctx, d, f, n, cap, stream)
+            pdc.get_hits(ctx, b, n, capacity=0)
+            pdc.release_batch(ctx, b)
         torch.cuda.synchronize()
         alone[name] = round((time.perf_counter() - t0) * 1e3 / steps, 3)
     for d in dets:
