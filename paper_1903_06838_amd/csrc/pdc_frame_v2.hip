@@ -541,7 +541,65 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             for (int x = tid; x < RN; x += kV2Threads) s_cnt[par * RN + x] = 0;
             if (tid == 0) s_nseed[par] = 0;
         }
-        if (CMM && cur_ok) {
+        if (CMM && cur_ok && A.cm_mode == 1) {
+            // thresholded mean of each bank-row (Fig. c), stacked stages: lane j
+            // of the group holds partial sums j + L q (q < 64 / L) of the
+            // bank's 64 interleaved partials (column c goes to partial c mod 64,
+            // in increasing c); the group's DPP tree adds partials of equal q in
+            // lane order, the lane then adds its Q results in a balanced tree,
+            // which is the balanced tree over all 64.  v replaces u in place
+            // and the median slot holds 0.
+            constexpr int G = 64 / L, Q = 64 / L;
+            const int grp = lane / L, gl = lane - grp * L;
+            const int i = wave * G + grp;
+            const bool act = i < BR;
+            const int row = act ? i / nb : 0;
+            const int bank = act ? i - row * nb : 0;
+            float *dst = u_c + row * W + bank * B;
+            float x[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const int c = L * v + gl;
+                x[v] = (act && c < B) ? dst[c] : INFINITY;  // +inf: absent or invalid, never noise
+            }
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                if (s >= A.cm_stages) break;
+                float P[Q];
+                int n = 0;
+#pragma unroll
+                for (int q = 0; q < Q; ++q) P[q] = 0.0f;
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (x[v] < A.t_cm) {
+                        P[v % Q] = __fadd_rn(P[v % Q], x[v]);
+                        ++n;
+                    }
+                float T[Q];
+#pragma unroll
+                for (int q = 0; q < Q; ++q) T[q] = gsum_f<L>(P[q]);
+#pragma unroll
+                for (int w = 1; w < Q; w *= 2)
+#pragma unroll
+                    for (int q = 0; q + w < Q; q += 2 * w) T[q] = __fadd_rn(T[q], T[q + w]);
+                const int n0 = gsum_i<L>(n);
+                const float cm = __fdiv_rn(T[0], fmaxf((float)n0, A.cm_guard));
+#pragma unroll
+                for (int v = 0; v < V; ++v) x[v] = __fsub_rn(x[v], cm);
+            }
+            if (act) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int c = L * v + gl;
+                    if (c < B) dst[c] = x[v] < INFINITY ? x[v] : 0.0f;  // invalid: v = 0
+                }
+                if (gl == 0) {
+                    med_c[i] = 0.0f;
+                    s_th[i] = seed_threshold(0.0f, A.t_seed);
+                }
+            }
+        }
+        if (CMM && cur_ok && A.cm_mode == 2) {
             // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
             // replaces u in place and the bank-row's median slot holds 0
             constexpr int G = 64 / L;
@@ -815,7 +873,7 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
 {
     if (a.B < 1 || a.rmax * a.nb > 16 * gmax) return hipErrorInvalidValue;
     if (a.gain_mode) {  // auto-ranging variants: one lane layout per strip shape
-        const bool cm = a.cm != nullptr;
+        const bool cm = a.cm_mode != 0;
         if (nq == 2 && gmax == 4 && a.B <= 256) {
             if (cm) return keep ? launch_v2_k<2, 4, 16, 16, true, true, true>(a, grid, lds, s)
                                 : launch_v2_k<2, 4, 16, 16, false, true, true>(a, grid, lds, s);
@@ -830,7 +888,7 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
         }
         return hipErrorInvalidValue;
     }
-    if (a.cm) {  // the thresholded-mean variant: no median search (L and V only set the lane layout)
+    if (a.cm_mode) {  // the thresholded-mean variant: no median search
         if (nq == 2 && gmax == 4 && a.B <= 256)
             return keep ? launch_v2_k<2, 4, 16, 16, true, true>(a, grid, lds, s)
                         : launch_v2_k<2, 4, 16, 16, false, true>(a, grid, lds, s);

@@ -77,15 +77,19 @@ struct V2Args {
     uint64_t *unit_base;
     BatchState *state;
     float *corrected;
-    const float *cm;              // as in FrameKernelArgs
+    const float *cm;              // as in FrameKernelArgs (cm_mode 2)
     uint32_t cm_regions;
     int32_t cm_tile;
+    int32_t cm_mode;              // 0 median; 1 bank thresholded mean computed in the kernel;
+                                  // 2 thresholded-mean stage values read from cm
+    int32_t cm_stages;            // cm_mode 1: stages, noise threshold and guard
+    float t_cm, cm_guard;
     int32_t gain_mode;
     uint32_t *invalid;
 };
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);
-// a.cm != nullptr selects the thresholded-mean variant (no median search)
+// a.cm_mode != 0 selects the thresholded-mean variant (no median search)
 hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
                                   hipStream_t s);
 

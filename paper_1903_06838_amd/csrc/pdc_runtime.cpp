@@ -420,7 +420,9 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
     if (d.g.gain_mode) HIP_TRY(ctx, launch_fill_u32(b->invalid, bt.n_frames, s));
     const float *cm = nullptr;
-    if (d.p.cm_mode && bt.n_frames > 0) {
+    // the persistent kernel computes a bank's thresholded mean itself
+    const bool cm_inline = d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2;
+    if (d.p.cm_mode && !cm_inline && bt.n_frames > 0) {
         CmArgs c{};
         c.frames = bt.frames;
         c.ped = d.d_ped;
@@ -472,6 +474,10 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.cm = cm;
         a.cm_regions = d.cm_regions;
         a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+        a.cm_mode = d.p.cm_mode == PDC_CM_MEDIAN ? 0 : (cm_inline ? 1 : 2);
+        a.cm_stages = d.p.cm_stages;
+        a.t_cm = d.t_cm;
+        a.cm_guard = d.cm_guard;
         a.gain_mode = d.g.gain_mode;
         a.invalid = b->invalid;
         HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
