@@ -441,8 +441,9 @@ pdc_status pdc_calibrate_darks(pdc_ctx *ctx, const pdc_geometry *geom, const uin
 pdc_status pdc_debug_mfma_probe(pdc_ctx *ctx, const uint16_t *A, const uint16_t *B, float *D);
 
 /* Test hook: the kernel that produced a batch's results, 1 for the general
- * kernel, 2 for the persistent one (after any recomputation).  Waits for the
- * batch. */
+ * kernel, 2 for the persistent one, 3 for the persistent one with the units
+ * whose seed lists overflowed redone by the general kernel (after any
+ * recomputation).  Waits for the batch. */
 pdc_status pdc_debug_batch_path(pdc_ctx *ctx, uint64_t batch, int32_t *path);
 
 #ifdef __cplusplus

@@ -818,7 +818,9 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const uint64_t unit = (f - 1) * (uint64_t)A.n_strips + strip;
                 uint64_t base = chunk_cur;
                 if (ovf_1) {
+                    // the seed list was full: the general kernel redoes this unit
                     atomicOr(&A.state->fallback, 1u);
+                    if (A.fb_units) A.fb_units[atomicAdd(&A.state->n_fallback, 1ull)] = unit;
                     base = kNoBase;
                 } else if (total > 0) {
                     if (chunk_cur + total > chunk_end) {

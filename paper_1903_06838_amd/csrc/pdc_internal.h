@@ -18,6 +18,12 @@ struct BatchState {
     unsigned int overflow;        // 1 if some unit could not be staged
     unsigned int fallback;        // 1 if the fast kernel left some unit to the general kernel
     unsigned long long total;     // total hits of the batch (set by the frame scan)
+    unsigned long long n_fallback;  // units listed in the batch's fallback list
+};
+
+// Persistent kernel (v2): strips of own rows [r0, r1) of a tile.
+struct V2Strip {
+    int32_t tile, r0, r1, pad;
 };
 
 // A work unit is (frame, strip): rows [r0, r0 + strip_rows) of one tile.
@@ -44,16 +50,16 @@ struct FrameKernelArgs {
     uint64_t *unit_base;          // [n_units] staging start or kNoBase
     BatchState *state;
     float *corrected;             // Frames2 or nullptr
+    // unit-list mode: recompute only units unit_list[0..n_list) whose rows come
+    // from the persistent kernel's strip table (units_per_frame = its strips)
+    const uint64_t *unit_list;
+    uint64_t n_list;
+    const V2Strip *strips;
     const float *cm;              // thresholded-mean mode: [n_frames][cm_regions][3], else nullptr
     uint32_t cm_regions;          // regions per frame: banks (T*H*nb) or tiles (T)
     int32_t cm_tile;              // 1: a region is a tile, 0: a bank
     int32_t gain_mode;            // 0 single range; 1, 2 auto-ranging (ped, k hold 3 planes)
     uint32_t *invalid;            // [n_frames] invalid-code pixels, cleared before the launch
-};
-
-// Persistent kernel (v2): strips of own rows [r0, r1) of a tile.
-struct V2Strip {
-    int32_t tile, r0, r1, pad;
 };
 
 struct V2Args {
@@ -77,6 +83,7 @@ struct V2Args {
     uint64_t *unit_base;
     BatchState *state;
     float *corrected;
+    uint64_t *fb_units;           // units left to the general kernel (seed lists full), or nullptr
     const float *cm;              // as in FrameKernelArgs (cm_mode 2)
     uint32_t cm_regions;
     int32_t cm_tile;

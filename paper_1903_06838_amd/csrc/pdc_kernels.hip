@@ -21,6 +21,7 @@ __global__ void init_state_kernel(BatchState *st)
         st->overflow = 0;
         st->fallback = 0;
         st->total = 0;
+        st->n_fallback = 0;
     }
 }
 
@@ -73,13 +74,22 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
 
     uint64_t chunk_cur = 0, chunk_end = 0;  // staging chunk (used by thread 0)
 
-    for (uint64_t unit = blockIdx.x; unit < A.n_units; unit += gridDim.x) {
+    const uint64_t n_iter = A.unit_list ? A.n_list : A.n_units;
+    for (uint64_t it = blockIdx.x; it < n_iter; it += gridDim.x) {
+        const uint64_t unit = A.unit_list ? A.unit_list[it] : it;
         const uint64_t f = unit / (uint64_t)A.units_per_frame;
         const int su = (int)(unit - f * (uint64_t)A.units_per_frame);
-        const int t = su / A.strips_per_tile;
-        const int s = su - t * A.strips_per_tile;
-        const int r0 = s * A.strip_rows;
-        const int r1 = min(r0 + A.strip_rows, H);
+        int t, r0, r1;
+        if (A.strips) {  // a persistent-kernel strip
+            const V2Strip S = A.strips[su];
+            t = S.tile;
+            r0 = S.r0;
+            r1 = S.r1;
+        } else {
+            t = su / A.strips_per_tile;
+            r0 = (su - t * A.strips_per_tile) * A.strip_rows;
+            r1 = min(r0 + A.strip_rows, H);
+        }
         const int lr0 = max(r0 - 1, 0);
         const int lr1 = min(r1 + 1, H);
         const int nrows = lr1 - lr0;
@@ -100,7 +110,7 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
                 s_v[i] = dark_gain(fr[p], A.ped[p], A.k[p]);
             }
         }
-        if (ninv) atomicAdd(A.invalid + f, ninv);
+        if (ninv && !A.unit_list) atomicAdd(A.invalid + f, ninv);  // list mode: counted already
         __syncthreads();
 
         // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
@@ -261,10 +271,12 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
 hipError_t launch_frame_kernel_v1(const FrameKernelArgs &a, uint32_t grid, size_t lds_bytes,
                                   bool keep_corrected, hipStream_t s)
 {
-    if (keep_corrected)
-        hipLaunchKernelGGL(frame_kernel_v1<true>, dim3(grid), dim3(kV1Threads), lds_bytes, s, a);
-    else
-        hipLaunchKernelGGL(frame_kernel_v1<false>, dim3(grid), dim3(kV1Threads), lds_bytes, s, a);
+    auto k = keep_corrected ? frame_kernel_v1<true> : frame_kernel_v1<false>;
+    if (lds_bytes > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute((const void *)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k, dim3(grid), dim3(kV1Threads), lds_bytes, s, a);
     return hipGetLastError();
 }
 

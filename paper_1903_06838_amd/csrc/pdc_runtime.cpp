@@ -48,6 +48,10 @@ struct Detector {
     uint32_t v2_max_unit_hits = 0;
     size_t v2_lds = 0;
     float rank_width = 0;
+    // general kernel over persistent-kernel strips, for units whose seed lists overflowed
+    bool fb_ok = false;
+    int fb_strip_rows = 0, fb_sort_rows = 0;
+    size_t fb_lds = 0;
     V2Strip *d_strips = nullptr;
     int32_t *d_items = nullptr;           // block -> item tables for 1..fg_max frame groups
     std::vector<uint32_t> item_off;       // offset of the table for g frame groups (index g)
@@ -72,6 +76,8 @@ struct Buffers {
     uint64_t cap_cm = 0;
     uint32_t *invalid = nullptr;       // [n_frames] pixels with an invalid gain code
     uint64_t cap_inv = 0;
+    uint64_t *fb_units = nullptr;      // [n_units] units left to the general kernel
+    uint64_t cap_fb = 0;
     BatchState *state = nullptr;
     BatchState *host_state = nullptr;  // pinned mirror
     hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr;
@@ -95,6 +101,7 @@ struct Batch {
     hipStream_t stream = nullptr;
     bool keep = false;
     bool checked = false;  // overflow handled, totals final
+    int fb = 0;            // 1: overflowing units recomputed by the general kernel, 2: whole batch
     Buffers *buf = nullptr;
 };
 
@@ -113,6 +120,7 @@ void free_buffers(Buffers *b)
     hipFree(b->corrected);
     hipFree(b->cm);
     hipFree(b->invalid);
+    hipFree(b->fb_units);
     hipFree(b->state);
     if (b->host_state) hipHostFree(b->host_state);
     if (b->ev_start) hipEventDestroy(b->ev_start);
@@ -308,6 +316,21 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     d.seed_cap = (int)std::min<size_t>((lds_cap - base) / 16, 16384);
     d.v2_lds = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, d.seed_cap);
     d.fg_max = std::max(1, ctx->n_cu / d.n_strips);
+    // the general kernel sized for one of these strips (own rows + halo), to
+    // redo the units whose seed lists overflow
+    d.fb_ok = false;
+    {
+        const int sw = (int)next_pow2(g.bank_cols);
+        for (int srt = own_rows_max + 2; srt >= 1 && !d.fb_ok; --srt) {
+            const size_t lds = frame_kernel_v1_lds_bytes(own_rows_max, g.cols, nb, sw, srt, d.v2_max_unit_hits);
+            if (lds <= lds_cap) {
+                d.fb_ok = true;
+                d.fb_strip_rows = own_rows_max;
+                d.fb_sort_rows = srt;
+                d.fb_lds = lds;
+            }
+        }
+    }
     d.rank_width = d.p.sigma / (0.4f * (float)g.bank_cols);
     // block -> item tables: items (fg, strip) in raster order are split into
     // contiguous runs per XCD (blocks are dealt to the 8 XCDs round-robin), so
@@ -388,6 +411,9 @@ pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n
     if (n_frames > b->cap_inv || !b->invalid) {
         HIP_TRY(ctx, grow(&b->invalid, b->cap_inv, n_frames));
     }
+    if (n_units > b->cap_fb || !b->fb_units) {
+        HIP_TRY(ctx, grow(&b->fb_units, b->cap_fb, n_units));
+    }
     return PDC_OK;
 }
 
@@ -411,6 +437,82 @@ uint32_t batch_grid(const Detector &d, const Batch &bt)
     return bt.path == 2 ? (uint32_t)(bt.n_fg * d.n_strips) : v1_grid(bt.n_units);
 }
 
+// Thresholded-mean stage values of every frame of the batch into b->cm.
+hipError_t launch_cm_pass(pdc_ctx *ctx, const Detector &d, const Batch &bt)
+{
+    if (bt.n_frames == 0) return hipSuccess;
+    CmArgs c{};
+    c.frames = bt.frames;
+    c.ped = d.d_ped;
+    c.k = d.d_k;
+    c.n_frames = bt.n_frames;
+    c.T = d.g.n_tiles;
+    c.H = d.g.rows;
+    c.W = d.g.cols;
+    c.B = d.g.bank_cols;
+    c.nb = d.g.cols / d.g.bank_cols;
+    c.stages = d.p.cm_stages;
+    c.t_cm = d.t_cm;
+    c.guard = d.cm_guard;
+    c.gain_mode = d.g.gain_mode;
+    c.cm = bt.buf->cm;
+    if (d.p.cm_mode == PDC_CM_BANK_MEAN) return launch_cm_bank(c, (uint32_t)ctx->n_cu, bt.stream);
+    return launch_cm_tile(c, (uint32_t)ctx->n_cu, bt.stream);
+}
+
+// Arguments of the general kernel common to whole-batch and unit-list runs.
+void fill_v1_args(const Detector &d, const Batch &bt, FrameKernelArgs &a)
+{
+    Buffers *b = bt.buf;
+    a.frames = bt.frames;
+    a.ped = d.d_ped;
+    a.k = d.d_k;
+    a.n_frames = bt.n_frames;
+    a.n_units = bt.n_units;
+    a.T = d.g.n_tiles;
+    a.H = d.g.rows;
+    a.W = d.g.cols;
+    a.B = d.g.bank_cols;
+    a.nb = d.g.cols / d.g.bank_cols;
+    a.strip_rows = d.strip_rows;
+    a.strips_per_tile = d.strips_per_tile;
+    a.units_per_frame = d.units_per_frame;
+    a.sort_width = d.sort_width;
+    a.sort_rows = d.sort_rows;
+    a.max_unit_hits = d.max_unit_hits;
+    a.t_seed = d.t_seed;
+    a.t_nb = d.t_nb;
+    a.photon_adu = d.p.photon_adu;
+    a.pool = b->pool;
+    a.pool_cap = bt.pool_cap;
+    a.unit_count = b->unit_count;
+    a.unit_photons = b->unit_photons;
+    a.unit_base = b->unit_base;
+    a.state = b->state;
+    a.corrected = bt.keep ? b->corrected : nullptr;
+    a.cm = d.p.cm_mode ? b->cm : nullptr;
+    a.cm_regions = d.cm_regions;
+    a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+    a.gain_mode = d.g.gain_mode;
+    a.invalid = b->invalid;
+}
+
+// Per-frame sums, offsets and the raster-ordered list, then the state copy.
+pdc_status enqueue_tail(pdc_ctx *ctx, Batch &bt)
+{
+    Buffers *b = bt.buf;
+    hipStream_t s = bt.stream;
+    HIP_TRY(ctx, launch_frame_sums(b->unit_count, b->unit_photons, bt.n_frames, bt.upf,
+                                   b->unit_local, b->frame_hits, b->frame_photons, s));
+    HIP_TRY(ctx, launch_frame_scan(b->frame_hits, bt.n_frames, b->frame_offset, b->state, s));
+    HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
+                                bt.n_units, bt.upf, b->hits, b->cap_pool, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
+    HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_state, s));
+    return PDC_OK;
+}
+
 pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
 {
     Detector &d = ctx->dets[bt.det];
@@ -419,29 +521,9 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     HIP_TRY(ctx, launch_init_state(b->state, s));
     HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
     if (d.g.gain_mode) HIP_TRY(ctx, launch_fill_u32(b->invalid, bt.n_frames, s));
-    const float *cm = nullptr;
     // the persistent kernel computes a bank's thresholded mean itself
     const bool cm_inline = d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2;
-    if (d.p.cm_mode && !cm_inline && bt.n_frames > 0) {
-        CmArgs c{};
-        c.frames = bt.frames;
-        c.ped = d.d_ped;
-        c.k = d.d_k;
-        c.n_frames = bt.n_frames;
-        c.T = d.g.n_tiles;
-        c.H = d.g.rows;
-        c.W = d.g.cols;
-        c.B = d.g.bank_cols;
-        c.nb = d.g.cols / d.g.bank_cols;
-        c.stages = d.p.cm_stages;
-        c.t_cm = d.t_cm;
-        c.guard = d.cm_guard;
-        c.gain_mode = d.g.gain_mode;
-        c.cm = b->cm;
-        if (d.p.cm_mode == PDC_CM_BANK_MEAN) HIP_TRY(ctx, launch_cm_bank(c, (uint32_t)ctx->n_cu, s));
-        else HIP_TRY(ctx, launch_cm_tile(c, (uint32_t)ctx->n_cu, s));
-        cm = b->cm;
-    }
+    if (d.p.cm_mode && !cm_inline) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));
     HIP_TRY(ctx, hipEventRecord(b->ev_cm, s));
     if (bt.n_units > 0 && bt.path == 2) {
         V2Args a{};
@@ -471,7 +553,8 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.unit_base = b->unit_base;
         a.state = b->state;
         a.corrected = bt.keep ? b->corrected : nullptr;
-        a.cm = cm;
+        a.fb_units = d.fb_ok ? b->fb_units : nullptr;
+        a.cm = cm_inline ? nullptr : b->cm;
         a.cm_regions = d.cm_regions;
         a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
         a.cm_mode = d.p.cm_mode == PDC_CM_MEDIAN ? 0 : (cm_inline ? 1 : 2);
@@ -483,49 +566,33 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
     } else if (bt.n_units > 0) {
         FrameKernelArgs a{};
-        a.frames = bt.frames;
-        a.ped = d.d_ped;
-        a.k = d.d_k;
-        a.n_frames = bt.n_frames;
-        a.n_units = bt.n_units;
-        a.T = d.g.n_tiles;
-        a.H = d.g.rows;
-        a.W = d.g.cols;
-        a.B = d.g.bank_cols;
-        a.nb = d.g.cols / d.g.bank_cols;
-        a.strip_rows = d.strip_rows;
-        a.strips_per_tile = d.strips_per_tile;
-        a.units_per_frame = d.units_per_frame;
-        a.sort_width = d.sort_width;
-        a.sort_rows = d.sort_rows;
-        a.max_unit_hits = d.max_unit_hits;
-        a.t_seed = d.t_seed;
-        a.t_nb = d.t_nb;
-        a.photon_adu = d.p.photon_adu;
-        a.pool = b->pool;
-        a.pool_cap = bt.pool_cap;
-        a.unit_count = b->unit_count;
-        a.unit_photons = b->unit_photons;
-        a.unit_base = b->unit_base;
-        a.state = b->state;
-        a.corrected = bt.keep ? b->corrected : nullptr;
-        a.cm = cm;
-        a.cm_regions = d.cm_regions;
-        a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
-        a.gain_mode = d.g.gain_mode;
-        a.invalid = b->invalid;
+        fill_v1_args(d, bt, a);
         HIP_TRY(ctx, launch_frame_kernel_v1(a, batch_grid(d, bt), d.lds_bytes, bt.keep, s));
     }
     HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
-    HIP_TRY(ctx, launch_frame_sums(b->unit_count, b->unit_photons, bt.n_frames, bt.upf,
-                                   b->unit_local, b->frame_hits, b->frame_photons, s));
-    HIP_TRY(ctx, launch_frame_scan(b->frame_hits, bt.n_frames, b->frame_offset, b->state, s));
-    HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
-                                bt.n_units, bt.upf, b->hits, b->cap_pool, s));
-    HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
-    HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipEventRecord(b->ev_state, s));
-    return PDC_OK;
+    return enqueue_tail(ctx, bt);
+}
+
+// Redo the units the persistent kernel listed as overflowing with the general
+// kernel over the same strips, then the scans and scatter again.
+pdc_status enqueue_partial(pdc_ctx *ctx, Batch &bt, uint64_t n_list)
+{
+    Detector &d = ctx->dets[bt.det];
+    Buffers *b = bt.buf;
+    hipStream_t s = bt.stream;
+    if (d.p.cm_mode == PDC_CM_BANK_MEAN) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));  // the kernel computed it inline
+    FrameKernelArgs a{};
+    fill_v1_args(d, bt, a);
+    a.n_units = bt.n_units;
+    a.units_per_frame = d.n_strips;
+    a.strip_rows = d.fb_strip_rows;
+    a.sort_rows = d.fb_sort_rows;
+    a.max_unit_hits = d.v2_max_unit_hits;
+    a.unit_list = b->fb_units;
+    a.n_list = n_list;
+    a.strips = d.d_strips;
+    HIP_TRY(ctx, launch_frame_kernel_v1(a, v1_grid(n_list), d.fb_lds, bt.keep, s));
+    return enqueue_tail(ctx, bt);
 }
 
 // Choose the kernel for a batch and size its unit arrays.
@@ -555,13 +622,38 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
 {
     HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
     if (bt.checked) return PDC_OK;
+    Detector &d = ctx->dets[bt.det];
     BatchState st = *bt.buf->host_state;
-    if (st.fallback) {
-        // some strip-frame had more seed pixels than the fast kernel holds on
-        // chip: recompute the whole batch with the general kernel
-        Detector &d = ctx->dets[bt.det];
-        set_path(d, bt, 1);
-        uint64_t cap = pool_capacity(d, 1, st.total, batch_grid(d, bt));
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        if (st.fallback && bt.path == 2 && d.fb_ok) {
+            // some strip-frames had more seed pixels than the persistent kernel
+            // holds on chip: the general kernel redoes just those units
+            pdc_status rc = enqueue_partial(ctx, bt, st.n_fallback);
+            if (rc != PDC_OK) return rc;
+            bt.fb = 1;
+            HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
+            st = *bt.buf->host_state;
+        } else if (st.fallback) {
+            // no general-kernel plan for these strips: redo the whole batch
+            set_path(d, bt, 1);
+            bt.fb = 2;
+            const uint64_t cap = pool_capacity(d, 1, st.total, batch_grid(d, bt));
+            pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
+            if (rc != PDC_OK) return rc;
+            bt.pool_cap = cap;
+            rc = enqueue(ctx, bt);
+            if (rc != PDC_OK) return rc;
+            HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
+            st = *bt.buf->host_state;
+        }
+        if (!st.overflow) {
+            bt.checked = true;
+            return PDC_OK;
+        }
+        // staging overflow: run again with room for the exact total (and for
+        // the chunks of a unit-list recomputation)
+        uint64_t cap = pool_capacity(d, bt.path, st.total, batch_grid(d, bt));
+        if (bt.fb == 1) cap += (uint64_t)v1_grid(st.n_fallback) * (kChunkHits + d.v2_max_unit_hits);
         pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
         if (rc != PDC_OK) return rc;
         bt.pool_cap = cap;
@@ -570,20 +662,7 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
         HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
         st = *bt.buf->host_state;
     }
-    if (st.overflow) {
-        Detector &d = ctx->dets[bt.det];
-        uint64_t cap = pool_capacity(d, bt.path, st.total, batch_grid(d, bt));
-        pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
-        if (rc != PDC_OK) return rc;
-        bt.pool_cap = cap;
-        rc = enqueue(ctx, bt);
-        if (rc != PDC_OK) return rc;
-        HIP_TRY(ctx, hipEventSynchronize(bt.buf->ev_state));
-        if (bt.buf->host_state->overflow)
-            return fail(ctx, PDC_EDEVICE, "staging overflow persisted after resizing");
-    }
-    bt.checked = true;
-    return PDC_OK;
+    return fail(ctx, PDC_EDEVICE, "staging overflow persisted after resizing");
 }
 
 void maybe_free_detector(pdc_ctx *ctx, int32_t det)
@@ -1399,7 +1478,7 @@ pdc_status pdc_debug_batch_path(pdc_ctx *ctx, uint64_t batch, int32_t *path)
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     pdc_status rc = finish_batch(ctx, *bt);
     if (rc != PDC_OK) return rc;
-    *path = bt->path;
+    *path = bt->path == 2 && bt->fb == 1 ? 3 : bt->path;
     return PDC_OK;
 }
 

@@ -78,6 +78,19 @@ def test_cm_mean_parity(ctx, geom, occ, n, region, stages):
     assert_same(got, want, corrected=True)
 
 
+def test_tile_mean_overflow_redoes_units(ctx):
+    """Large per-bank offsets that a tile's mean cannot follow leave many
+    pixels above threshold: strip-frames whose seed lists overflow are redone
+    by the general kernel from the pass's values, bit for bit."""
+    geom = synth.Geometry(2, 60, 388, 194)
+    ped, gain = synth.make_calibration(geom, 25)
+    raw = synth.make_frames(geom, ped, gain, 3, 0.01, 25, sim=synth.SimParams(cm_sigma=50.0))
+    want = M.process(raw, ped, gain, 194, M.TILE, 2, keep_corrected=True)
+    got = _run(ctx, raw, ped, gain, 194, M.TILE, 2)
+    assert got["path"] == 3
+    assert_same(got, want, corrected=True)
+
+
 def test_cm_mean_guard_at_high_occupancy(ctx):
     """At 1.5 photons per pixel most banks have fewer noise pixels than
     sqrt(bank_cols): the guard sets the denominator."""

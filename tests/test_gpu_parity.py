@@ -265,12 +265,29 @@ def test_flood_frame_falls_back_exactly(ctx):
     """A frame where a third of the pixels carry photons has more seed pixels per
     strip than the persistent kernel holds on chip; the batch is recomputed by
     the general kernel and still matches."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
     geom = synth.Geometry(2, 60, 388, 194)
     ped, gain = synth.make_calibration(geom, 41)
     raw = synth.make_frames(geom, ped, gain, 2, 0.4, 41)
-    want = oracle_threads(raw, ped, gain, geom.bank_cols)
+    raw = np.concatenate([raw, synth.make_frames(geom, ped, gain, 3, 0.01, 42)])  # flood and ordinary frames
+    want = oracle_threads(raw, ped, gain, geom.bank_cols, keep_corrected=True)
     assert want["total"] > 1000
-    assert_same(run_pdc(ctx, raw, ped, gain, geom.bank_cols), want)
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, 194), ped, gain, pdc.params(flags=pdc.KEEP_CORRECTED))
+    try:
+        b = pdc.process_frames(ctx, det, torch.from_numpy(raw).cuda(), raw.shape[0], 1 << 14)
+        hits, total, fh, fp, _ = pdc.get_hits(ctx, b, raw.shape[0])
+        corr = np.empty(raw.shape, np.float32)
+        pdc.get_corrected(ctx, b, corr)
+        # only the flood frames' strips are redone by the general kernel
+        assert pdc.debug_batch_path(ctx, b) == 3
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
+    assert_same(dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp, corrected=corr), want,
+                corrected=True)
 
 
 def test_median_with_outliers_and_plateaus(ctx):
