@@ -7,10 +7,10 @@
 //   phase 1a (each wave, its own bank-rows): load raw words (prefetched one
 //     frame ahead), correct them (Fig. b) and write u to LDS;
 //   phase 1b (all waves): every bank-row's lower median, exactly, by a
-//     bracketing count search with L lanes per bank-row (common mode, Fig. c),
-//     and the seed threshold it implies;
-//   phase 1c (each wave, its own bank-rows): Frames2 if kept, seed pixels
-//     appended to a workgroup list;
+//     bracketing count search with L lanes per bank-row (common mode, Fig. c);
+//     the same lanes then test their values against the seed threshold the
+//     median implies and append the seed pixels to a workgroup list;
+//   phase 1c (each wave, its own bank-rows): Frames2 if kept;
 //   phase 2 (all waves, over the pooled seeds): 3x3 local maximum with the
 //     raster tie-break, masked 3x3 charge sum, photon count (Fig. e and the
 //     charge summing section); hits mark a per-bank-row column bitmap;
@@ -311,7 +311,8 @@ struct V2Layout {
 };
 
 // LDS of one workgroup (floats): u and med are double-buffered by frame
-// parity, bits/cnt/seed/q/nseed likewise; th and pref are single.
+// parity, bits/cnt/seed/q likewise; the seed counts are kept for three frames
+// (frame f mod 3); th and pref are single.
 __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
 {
     V2Layout L;
@@ -331,7 +332,7 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
     L.q = o;
     o += 2u * seed_cap;
     L.nseed = o;
-    o += 2;
+    o += 3;
     L.pref = o;
     o += (uint32_t)rmax * nb + 1;
     L.gs = o;
@@ -343,7 +344,7 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
     size_t o = 2ull * rmax * W + 2ull * rmax * nb + (size_t)rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
-               4ull * seed_cap + 2 + (size_t)rmax * nb + 1 + 1024;
+               4ull * seed_cap + 3 + (size_t)rmax * nb + 1 + 1024;
     return o * 4;
 }
 
@@ -371,7 +372,6 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const int RW = A.rmax * W, RN = A.rmax * nb, cap = A.seed_cap;
     float *s_u = lds + Ly.u;
     float *s_med = lds + Ly.med;
-    float *s_th = lds + Ly.th;
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(lds + Ly.bits);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(lds + Ly.cnt);
     uint32_t *s_seed = reinterpret_cast<uint32_t *>(lds + Ly.seed);
@@ -437,7 +437,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     }
     for (int x = tid; x < 2 * RN * 8; x += kV2Threads) s_bits[x] = 0;
     for (int x = tid; x < 2 * RN; x += kV2Threads) s_cnt[x] = 0;
-    if (tid < 2) s_nseed[tid] = 0;
+    if (tid < 3) s_nseed[tid] = 0;
     if (tid == 0) s_photons = 0;
     if (tid == 0) s_p2ctr = 0;
 
@@ -456,18 +456,48 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     if (f_begin < f_end) load_raw(f_begin);
     __syncthreads();
 
+    // Seeds of a bank-row held by an L-lane group in phase B (lane gl holds
+    // columns L v + gl in xs, +inf where absent or invalid): u >= th, own rows
+    // only, appended to the pooled list of frame parity par (order is free;
+    // phase 4 restores raster order) with a DPP prefix of the lanes' counts
+    // and one LDS atomic per wave.  All lanes of the wave must call it.
+    const float th0 = seed_threshold(0.0f, A.t_seed);
+    auto append_seeds = [&](const float(&xs)[V], float th, bool own, int row, int bank, int gl, int par_, int slot) {
+        uint32_t sb = 0;
+        if (own) {
+#pragma unroll
+            for (int v = 0; v < V; ++v)
+                if (L * v + gl < B && xs[v] < INFINITY && xs[v] >= th) sb |= 1u << v;
+        }
+        const uint32_t ns = (uint32_t)__popc(sb);
+        const uint32_t incl = wave_incl_scan(ns);
+        const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (wtot) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_nseed[slot], wtot);
+            uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
+            while (sb) {
+                const int v = __ffs(sb) - 1;
+                sb &= sb - 1;
+                if (pos < (uint32_t)cap) s_seed[par_ * cap + pos] = seed_key(row, bank, bank * B + L * v + gl);
+                ++pos;
+            }
+        }
+    };
+
     // Software pipeline, two frames deep: iteration f runs frame f's phases
-    // 1a (A), 1b (B) and 1c (C), frame f-1's phase 2 in B (claimed in chunks
-    // by waves as they finish their median groups) and its phase 3 in C, and
-    // frame f-2's phase 4 in A.  Two more iterations drain it.  Frame f and
-    // frame f-2 share LDS parity par; frame f-1 has parity pp.
+    // 1a (A), 1b with the seed list (B) and 1c (C), frame f-1's phase 2 in B
+    // (claimed in chunks by waves as they finish their median groups) and its
+    // phase 3 in C, and frame f-2's phase 4 in A.  Two more iterations drain
+    // it.  Frame f and frame f-2 share LDS parity par; frame f-1 has parity pp.
     for (uint64_t f = f_begin; f < f_end + 2; ++f) {
         const bool cur_ok = f < f_end;
         const bool p1_ok = f >= f_begin + 1 && f - 1 < f_end;
         const bool p2_ok = f >= f_begin + 2;
         const int par = (int)(f & 1), pp = par ^ 1;
-        const uint32_t nseed_1 = p1_ok ? s_nseed[pp] : 0u;   // frame f-1
-        const uint32_t nseed_2 = p2_ok ? s_nseed[par] : 0u;  // frame f-2
+        const int sc0 = (int)(f % 3), sc1 = (int)((f + 2) % 3), sc2 = (int)((f + 1) % 3);  // seed counts of f, f-1, f-2
+        const uint32_t nseed_1 = p1_ok ? s_nseed[sc1] : 0u;  // frame f-1
+        const uint32_t nseed_2 = p2_ok ? s_nseed[sc2] : 0u;  // frame f-2
         const bool ovf_1 = nseed_1 > (uint32_t)cap, ovf_2 = nseed_2 > (uint32_t)cap;
         float *u_c = s_u + par * RW;
         const float *u_p = s_u + pp * RW;
@@ -539,8 +569,9 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             // frame f-2's lists (parity par) are finished: clear them for frame f
             for (int x = tid; x < RN * 8; x += kV2Threads) s_bits[par * RN * 8 + x] = 0;
             for (int x = tid; x < RN; x += kV2Threads) s_cnt[par * RN + x] = 0;
-            if (tid == 0) s_nseed[par] = 0;
         }
+        // frame f-2's seed count was read before barrier A: its slot serves frame f+1
+        if (tid == 0) s_nseed[sc2] = 0;
         if (CMM && cur_ok && A.cm_mode == 1) {
             // thresholded mean of each bank-row (Fig. c), stacked stages: lane j
             // of the group holds partial sums j + L q (q < 64 / L) of the
@@ -593,11 +624,9 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                     const int c = L * v + gl;
                     if (c < B) dst[c] = x[v] < INFINITY ? x[v] : 0.0f;  // invalid: v = 0
                 }
-                if (gl == 0) {
-                    med_c[i] = 0.0f;
-                    s_th[i] = seed_threshold(0.0f, A.t_seed);
-                }
+                if (gl == 0) med_c[i] = 0.0f;
             }
+            append_seeds(x, th0, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (CMM && cur_ok && A.cm_mode == 2) {
             // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
@@ -605,23 +634,31 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             constexpr int G = 64 / L;
             const int grp = lane / L, gl = lane - grp * L;
             const int i = wave * G + grp;
-            if (i < BR) {
-                const int row = i / nb;
-                const int bank = i - row * nb;
+            const bool act = i < BR;
+            const int row = act ? i / nb : 0;
+            const int bank = act ? i - row * nb : 0;
+            float x[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) x[v] = INFINITY;
+            if (act) {
                 const uint32_t reg = A.cm_tile ? (uint32_t)t : ((uint32_t)t * H + lr0 + row) * (uint32_t)nb + bank;
                 const float *cv = A.cm + (f * A.cm_regions + reg) * 3;
                 const float c0 = cv[0], c1 = cv[1], c2 = cv[2];
                 float *dst = u_c + row * W + bank * B;
-                for (int c = gl; c < B; c += L) {
-                    const float u = dst[c];
-                    // an invalid pixel (+inf) becomes 0, so that v = 0
-                    dst[c] = (MG && !(u < INFINITY)) ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, c0), c1), c2);
+#pragma unroll
+                for (int v = 0; v < V; ++v) {
+                    const int c = L * v + gl;
+                    if (c < B) {
+                        const float u = dst[c];
+                        // an invalid pixel (+inf) becomes 0, so that v = 0
+                        const float y = __fsub_rn(__fsub_rn(__fsub_rn(u, c0), c1), c2);
+                        x[v] = y;
+                        dst[c] = (MG && !(u < INFINITY)) ? 0.0f : y;
+                    }
                 }
-                if (gl == 0) {
-                    med_c[i] = 0.0f;
-                    s_th[i] = seed_threshold(0.0f, A.t_seed);
-                }
+                if (gl == 0) med_c[i] = 0.0f;
             }
+            append_seeds(x, th0, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (!CMM && cur_ok) {
             constexpr int G = 64 / L;
@@ -661,10 +698,9 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                     }
                 }
             }
-            if (act && gl == 0) {
-                med_c[i] = m;
-                s_th[i] = seed_threshold(m, A.t_seed);
-            }
+            if (act && gl == 0) med_c[i] = m;
+            append_seeds(x, seed_threshold(m, A.t_seed), act && row >= own_lo && row < own_hi, row, bank, gl, par,
+                         sc0);
         }
         if (p1_ok && !ovf_1) {
             // frame f-1's seeds in chunks of 64, claimed by whole waves as they
@@ -741,64 +777,22 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         }
         __syncthreads();  // B -> C
 
-        // ================= C: 1c(f) | 3(f-1) ======================================
-        if (cur_ok) {
-            uint32_t seedbits = 0;  // bit (g*NV + v) set: seed at this lane's value-slot v of bank-row g
+        // ================= C: Frames2(f) | 3(f-1) ================================
+        if (KEEP && cur_ok) {
 #pragma unroll
             for (int g = 0; g < GMAX; ++g) {
                 if (g >= ng) break;
                 const int i = wave + kV2Waves * g;
                 const int row = row_[g];
                 if (row >= own_lo && row < own_hi) {
-                    float xs[NV];  // absent pixels: -inf (never a seed)
+                    const float m = uniform_f(med_c[i]);
 #pragma unroll
-                    for (int q = 0; q < NQ; ++q) {
+                    for (int q = 0; q < NQ; ++q)
                         if (lane_ok[q]) {
                             const float2 u2 = *reinterpret_cast<const float2 *>(u_c + gb_[g] + 128 * q + lane_off);
-                            xs[2 * q] = u2.x;
-                            xs[2 * q + 1] = u2.y;
-                        } else {
-                            xs[2 * q] = -INFINITY;
-                            xs[2 * q + 1] = -INFINITY;
+                            *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q + lane_off) =
+                                make_float2(__fsub_rn(u2.x, m), __fsub_rn(u2.y, m));
                         }
-                    }
-                    const float th = uniform_f(s_th[i]);
-                    if (KEEP) {
-                        const float m = uniform_f(med_c[i]);
-#pragma unroll
-                        for (int q = 0; q < NQ; ++q)
-                            if (lane_ok[q]) {
-                                float2 v2 = make_float2(__fsub_rn(xs[2 * q], m), __fsub_rn(xs[2 * q + 1], m));
-                                *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q +
-                                                            lane_off) = v2;
-                            }
-                    }
-#pragma unroll
-                    for (int v = 0; v < NV; ++v)
-                        if (xs[v] >= th) seedbits |= 1u << (g * NV + v);
-                }
-            }
-            // append to the pooled list (order is free; phase 4 restores
-            // raster order): DPP prefix of the lanes' counts, one LDS atomic
-            const uint32_t ns = (uint32_t)__popc(seedbits);
-            const uint32_t incl = wave_incl_scan(ns);
-            const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-            if (wtot) {
-                uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&s_nseed[par], wtot);
-                uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
-#pragma unroll
-                for (int g = 0; g < GMAX; ++g) {
-                    if (g >= ng) break;
-                    uint32_t bits = (seedbits >> (g * NV)) & ((1u << NV) - 1u);
-                    const int colbase = bank_[g] * B + 2 * lane;
-                    while (bits) {
-                        const int v = __ffs(bits) - 1;
-                        bits &= bits - 1;
-                        if (pos < (uint32_t)cap)
-                            s_seed[par * cap + pos] = seed_key(row_[g], bank_[g], colbase + 128 * (v >> 1) + (v & 1));
-                        ++pos;
-                    }
                 }
             }
         }
