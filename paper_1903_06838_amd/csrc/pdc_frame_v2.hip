@@ -522,23 +522,33 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                                 make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
                                             dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
             } else {
-                // auto-ranging: range 0 from the resident planes, ranges 1 and
-                // 2 from memory, invalid codes as +inf (counted on own rows)
-                uint32_t ninv = 0;
+                // auto-ranging: range 0 from the resident planes and invalid
+                // codes as +inf (counted on own rows) first; the rarer pixels in
+                // ranges 1 and 2 then read their planes from memory
+                uint32_t ninv = 0, slow = 0;  // slow: bit 2 (g NQ + q) + h for ranges 1, 2
 #pragma unroll
                 for (int g = 0; g < GMAX; ++g)
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
                         if (g < ng && lane_ok[q]) {
-                            const uint64_t o = row_base + gb_[g] + 128 * q + lane_off;
-                            bool b0, b1;
-                            const float u0 = dark_gain_ranged(cur[g][q] & 0xFFFFu, A.gain_mode, pd[g][q][0],
-                                                              kk[g][q][0], A.ped, A.k, npix, o, b0);
-                            const float u1 = dark_gain_ranged(cur[g][q] >> 16, A.gain_mode, pd[g][q][1],
-                                                              kk[g][q][1], A.ped, A.k, npix, o + 1, b1);
+                            const uint32_t w = cur[g][q];
+                            const int r0 = gain_range(w & 0xFFFFu, A.gain_mode), r1 = gain_range(w >> 16, A.gain_mode);
+                            const float u0 = r0 == 0 ? dark_gain(w & 0xFFFFu, pd[g][q][0], kk[g][q][0]) : INFINITY;
+                            const float u1 = r1 == 0 ? dark_gain(w >> 16, pd[g][q][1], kk[g][q][1]) : INFINITY;
                             *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) = make_float2(u0, u1);
-                            if (row_[g] >= own_lo && row_[g] < own_hi) ninv += (uint32_t)b0 + (uint32_t)b1;
+                            if (row_[g] >= own_lo && row_[g] < own_hi) ninv += (uint32_t)(r0 < 0) + (uint32_t)(r1 < 0);
+                            slow |= ((uint32_t)(r0 > 0) | ((uint32_t)(r1 > 0) << 1)) << (2 * (g * NQ + q));
                         }
+                while (slow) {
+                    const int bit = __ffs(slow) - 1;
+                    slow &= slow - 1;
+                    const int gq = bit >> 1, h = bit & 1;
+                    const int g = gq / NQ, q = gq - g * NQ;
+                    const uint32_t off = gb_[g] + 128 * q + lane_off + h;
+                    const uint32_t w = (cur[g][q] >> (16 * h)) & 0xFFFFu;
+                    const uint64_t o = row_base + off + (uint64_t)gain_range(w, A.gain_mode) * npix;
+                    u_c[off] = dark_gain(w, A.ped[o], A.k[o]);
+                }
                 const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)wave_incl_scan(ninv), 63);
                 if (lane == 0 && tot) atomicAdd(A.invalid + f, tot);
             }
@@ -873,12 +883,18 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
         if (nq == 2 && gmax == 4 && a.B <= 256) {
             if (cm) return keep ? launch_v2_k<2, 4, 16, 16, true, true, true>(a, grid, lds, s)
                                 : launch_v2_k<2, 4, 16, 16, false, true, true>(a, grid, lds, s);
+            if (a.B <= 16 * 13)
+                return keep ? launch_v2_k<2, 4, 16, 13, true, false, true>(a, grid, lds, s)
+                            : launch_v2_k<2, 4, 16, 13, false, false, true>(a, grid, lds, s);
             return keep ? launch_v2_k<2, 4, 16, 16, true, false, true>(a, grid, lds, s)
                         : launch_v2_k<2, 4, 16, 16, false, false, true>(a, grid, lds, s);
         }
         if (nq == 1 && gmax == 8 && a.B <= 128) {
             if (cm) return keep ? launch_v2_k<1, 8, 8, 16, true, true, true>(a, grid, lds, s)
                                 : launch_v2_k<1, 8, 8, 16, false, true, true>(a, grid, lds, s);
+            if (a.B <= 8 * 12)
+                return keep ? launch_v2_k<1, 8, 8, 12, true, false, true>(a, grid, lds, s)
+                            : launch_v2_k<1, 8, 8, 12, false, false, true>(a, grid, lds, s);
             return keep ? launch_v2_k<1, 8, 8, 16, true, false, true>(a, grid, lds, s)
                         : launch_v2_k<1, 8, 8, 16, false, false, true>(a, grid, lds, s);
         }
