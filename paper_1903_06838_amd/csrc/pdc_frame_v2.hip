@@ -348,6 +348,18 @@ size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
     return o * 4;
 }
 
+// Item (frame group, strip) of block b among n: blocks are dealt to the 8 XCDs
+// round-robin (block b to XCD b mod 8) and the items, in raster order, go to
+// the blocks of one XCD after another, so neighbouring strips (which share halo
+// rows) share an L2.
+__device__ __forceinline__ int block_item(int b, int n)
+{
+    const int x = b & 7;
+    int before = 0;
+    for (int y = 0; y < x; ++y) before += (n - y + 7) >> 3;  // blocks of XCD y
+    return before + (b >> 3);
+}
+
 // Seed key: loaded row (7 bits), bank (7 bits), column (11 bits).
 __device__ __forceinline__ uint32_t seed_key(int row, int bank, int col)
 {
@@ -380,7 +392,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     uint32_t *s_pref = reinterpret_cast<uint32_t *>(lds + Ly.pref);
     float *s_gs = lds + Ly.gs;  // one slot per thread: median finish scratch
 
-    const int item = A.wg_item[blockIdx.x];
+    const int item = block_item((int)blockIdx.x, (int)gridDim.x);
     const int strip = item % A.n_strips;
     const int fg = item / A.n_strips;
     const V2Strip S = A.strips[strip];

@@ -72,7 +72,6 @@ struct V2Args {
     int32_t n_fgroups;            // frame groups (frames split into contiguous ranges)
     int32_t rmax;                 // max loaded rows of a strip (own rows + halos)
     int32_t seed_cap;             // seeds per strip-frame held in LDS
-    const int32_t *wg_item;       // [grid] item = fgroup * n_strips + strip
     const V2Strip *strips;        // [n_strips], raster order
     float t_seed, t_nb, photon_adu;
     float rank_width;             // expected value spacing near a bank median (ADU per rank)

@@ -44,7 +44,8 @@ struct Detector {
     size_t lds_bytes = 0;
     // persistent kernel (v2): resident calibration per strip
     bool v2_ok = false;
-    int nq = 0, gmax = 0, n_strips = 0, rmax = 0, seed_cap = 0, fg_max = 0;
+    int nq = 0, gmax = 0, n_strips = 0, rmax = 0, seed_cap = 0;
+    int n_cu = 0;                         // compute units of the device (frame-group choice)
     uint32_t v2_max_unit_hits = 0;
     size_t v2_lds = 0;
     float rank_width = 0;
@@ -53,8 +54,6 @@ struct Detector {
     int fb_strip_rows = 0, fb_sort_rows = 0;
     size_t fb_lds = 0;
     V2Strip *d_strips = nullptr;
-    int32_t *d_items = nullptr;           // block -> item tables for 1..fg_max frame groups
-    std::vector<uint32_t> item_off;       // offset of the table for g frame groups (index g)
     int pending = 0;
     bool release_requested = false;
 };
@@ -315,7 +314,6 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     if (base + 4 * 4 * 1024 > lds_cap) return false;
     d.seed_cap = (int)std::min<size_t>((lds_cap - base) / 16, 16384);
     d.v2_lds = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, d.seed_cap);
-    d.fg_max = std::max(1, ctx->n_cu / d.n_strips);
     // the general kernel sized for one of these strips (own rows + halo), to
     // redo the units whose seed lists overflow
     d.fb_ok = false;
@@ -332,24 +330,9 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
         }
     }
     d.rank_width = d.p.sigma / (0.4f * (float)g.bank_cols);
-    // block -> item tables: items (fg, strip) in raster order are split into
-    // contiguous runs per XCD (blocks are dealt to the 8 XCDs round-robin), so
-    // neighbouring strips, which share halo rows, share an L2.
-    std::vector<int32_t> items;
-    d.item_off.assign(d.fg_max + 1, 0);
-    for (int nfg = 1; nfg <= d.fg_max; ++nfg) {
-        d.item_off[nfg] = (uint32_t)items.size();
-        const int n = nfg * d.n_strips;
-        std::vector<int32_t> tab(n);
-        int next = 0;
-        for (int x = 0; x < 8; ++x)
-            for (int b = x; b < n; b += 8) tab[b] = next++;
-        items.insert(items.end(), tab.begin(), tab.end());
-    }
+    d.n_cu = ctx->n_cu;
     if (hipMalloc((void **)&d.d_strips, strips.size() * sizeof(V2Strip)) != hipSuccess) return false;
-    if (hipMalloc((void **)&d.d_items, items.size() * sizeof(int32_t)) != hipSuccess) return false;
-    if (hipMemcpy(d.d_strips, strips.data(), strips.size() * sizeof(V2Strip), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(d.d_items, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    if (hipMemcpy(d.d_strips, strips.data(), strips.size() * sizeof(V2Strip), hipMemcpyHostToDevice) != hipSuccess)
         return false;
     d.v2_ok = true;
     return true;
@@ -540,7 +523,6 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.n_fgroups = bt.n_fg;
         a.rmax = d.rmax;
         a.seed_cap = d.seed_cap;
-        a.wg_item = d.d_items + d.item_off[bt.n_fg];
         a.strips = d.d_strips;
         a.t_seed = d.t_seed;
         a.t_nb = d.t_nb;
@@ -595,12 +577,35 @@ pdc_status enqueue_partial(pdc_ctx *ctx, Batch &bt, uint64_t n_list)
     return enqueue_tail(ctx, bt);
 }
 
+// Frame groups of a persistent launch: each workgroup takes one strip for a
+// contiguous range of frames, one workgroup per compute unit at a time; the
+// count is chosen so that the last round of workgroups still fills the chip
+// (CSPAD's 224 strips alone would leave 32 of 256 units idle), with at least 4
+// frames per group.
+int frame_groups(int n_cu, int n_strips, uint64_t n_frames)
+{
+    const int max_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, n_frames / 4));
+    int best = 1;
+    double best_eff = 0.0;
+    for (int g = 1; g <= max_fg; ++g) {
+        const int64_t wgs = (int64_t)g * n_strips;
+        const int64_t rounds = (wgs + n_cu - 1) / n_cu;
+        const double eff = (double)wgs / (double)(rounds * n_cu);
+        if (eff > best_eff + 1e-9) {
+            best_eff = eff;
+            best = g;
+        }
+    }
+    return best;
+}
+
 // Choose the kernel for a batch and size its unit arrays.
 void set_path(const Detector &d, Batch &bt, int path)
 {
     bt.path = path;
     if (path == 2) {
-        const uint64_t fg = (uint64_t)std::max(1.0, std::floor((double)d.fg_max * bt.share));
+        const int fgb = frame_groups(d.n_cu, d.n_strips, bt.n_frames);
+        const uint64_t fg = (uint64_t)std::max(1.0, std::floor((double)fgb * bt.share));
         bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(fg, bt.n_frames));
         bt.upf = d.n_strips;
     } else {
@@ -672,7 +677,6 @@ void maybe_free_detector(pdc_ctx *ctx, int32_t det)
         hipFree(d.d_ped);
         hipFree(d.d_k);
         hipFree(d.d_strips);
-        hipFree(d.d_items);
         d = Detector{};
     }
 }
@@ -748,7 +752,6 @@ pdc_status pdc_destroy(pdc_ctx *ctx)
             hipFree(d.d_ped);
             hipFree(d.d_k);
             hipFree(d.d_strips);
-            hipFree(d.d_items);
         }
     hipFree(ctx->fmt_buf);
     hipStreamDestroy(ctx->stream);
