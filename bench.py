@@ -572,6 +572,9 @@ def main():
 
     pool, frames = make_batch(torch, synth, geom, ped, gain, 1, args.pool, N, dev)
     est = int(0.01 * 1.2 * npix * N) + 4096
+    # tile shape: the frame-group count of the persistent launch, tuned on this batch
+    tune_mult, tune_ms = pdc.autotune(ctx, det, frames, N, est, torch.cuda.current_stream())
+    log("autotune: frame groups x%d (frame kernel ms x1/x2/x4: %s)" % (tune_mult, [round(float(x), 3) for x in tune_ms]))
     ms, mains, totals, hits, (fh, fp), hit_cap = run_steps(
         torch, pdc, ctx, det, frames, N, est, args.steps, args.warmup)
     log("headline: %.3f ms/step, frame kernel %.3f ms, all kernels %.3f ms, %d hits"
@@ -596,7 +599,9 @@ def main():
            "config": {"workload": "CSPAD-like 32x185x388 uint16, 194-pixel banks, %d frames per "
                                   "batch (64 distinct, replicated in HBM), occupancy 0.01" % N,
                       "frames": N, "tiles": 32, "rows": 185, "cols": 388, "bank_cols": 194,
-                      "occupancy": 0.01, "thresholds": "5 sigma seed, 3 sigma neighbours, sigma 3 ADU"},
+                      "occupancy": 0.01, "thresholds": "5 sigma seed, 3 sigma neighbours, sigma 3 ADU",
+                      "frame_groups_autotuned": {"multiplier": tune_mult,
+                                                 "frame_kernel_ms_x1_x2_x4": [round(float(x), 3) for x in tune_ms]}},
            "roofline": roofline(N, npix, hits, mains),
            "hits_per_step": hits,
            "all_kernels_ms": round(sum(totals) / len(totals), 4)}

@@ -206,6 +206,16 @@ typedef struct {
 pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, void *hip_stream,
                              uint64_t *batch_out);
 
+/* Tile-shape autotuner: times the persistent kernel on n_frames of the
+ * caller's frames (DEVICE, as for pdc_process_frames) with its frame-group
+ * count at 1, 2 and 4 times the smallest count that fills whole rounds of the
+ * chip, and keeps the fastest for the detector's later batches (results do not
+ * depend on it).  *mult_out (may be NULL) receives the multiplier, ms_out
+ * (host float[3], may be NULL) the frame-kernel times.  Synchronous; runs 9
+ * batches. */
+pdc_status pdc_autotune(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                        uint64_t hit_capacity, void *hip_stream, int32_t *mult_out, float *ms_out);
+
 /* Wait for the batch and copy its results, hits in (frame, pixel) order.
  * dst: room for dst_capacity records, in host memory (dst_is_device = 0) or
  *   device memory of the context's device (dst_is_device = 1); may be NULL

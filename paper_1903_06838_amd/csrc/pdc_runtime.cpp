@@ -46,6 +46,7 @@ struct Detector {
     bool v2_ok = false;
     int nq = 0, gmax = 0, n_strips = 0, rmax = 0, seed_cap = 0;
     int n_cu = 0;                         // compute units of the device (frame-group choice)
+    int fg_mult = 1;                      // frame groups x this (pdc_autotune)
     uint32_t v2_max_unit_hits = 0;
     size_t v2_lds = 0;
     float rank_width = 0;
@@ -582,7 +583,7 @@ pdc_status enqueue_partial(pdc_ctx *ctx, Batch &bt, uint64_t n_list)
 // count is chosen so that the last round of workgroups still fills the chip
 // (CSPAD's 224 strips alone would leave 32 of 256 units idle), with at least 4
 // frames per group.
-int frame_groups(int n_cu, int n_strips, uint64_t n_frames)
+int frame_groups(int n_cu, int n_strips, uint64_t n_frames, int mult)
 {
     const int max_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, n_frames / 4));
     int best = 1;
@@ -596,7 +597,9 @@ int frame_groups(int n_cu, int n_strips, uint64_t n_frames)
             best = g;
         }
     }
-    return best;
+    // more rounds of the same fill, if tuned so (finer dynamic balancing)
+    const uint64_t cap = std::max<uint64_t>(1, n_frames / 4);
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)best * (uint64_t)std::max(1, mult), cap));
 }
 
 // Choose the kernel for a batch and size its unit arrays.
@@ -604,7 +607,7 @@ void set_path(const Detector &d, Batch &bt, int path)
 {
     bt.path = path;
     if (path == 2) {
-        const int fgb = frame_groups(d.n_cu, d.n_strips, bt.n_frames);
+        const int fgb = frame_groups(d.n_cu, d.n_strips, bt.n_frames, d.fg_mult);
         const uint64_t fg = (uint64_t)std::max(1.0, std::floor((double)fgb * bt.share));
         bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(fg, bt.n_frames));
         bt.upf = d.n_strips;
@@ -1482,6 +1485,49 @@ pdc_status pdc_debug_batch_path(pdc_ctx *ctx, uint64_t batch, int32_t *path)
     pdc_status rc = finish_batch(ctx, *bt);
     if (rc != PDC_OK) return rc;
     *path = bt->path == 2 && bt->fb == 1 ? 3 : bt->path;
+    return PDC_OK;
+}
+
+// Time the persistent kernel on the caller's frames with frame groups x 1, 2
+// and 4 (each a whole number of rounds of the chip) and keep the fastest.
+pdc_status pdc_autotune(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                        uint64_t hit_capacity, void *hip_stream, int32_t *mult_out, float *ms_out)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    if (n_frames < 1 || !frames_dev) return fail(ctx, PDC_EINVAL, "need frames_dev and n_frames >= 1");
+    static const int kMults[3] = {1, 2, 4};
+    float best_ms = 0.0f;
+    int best = 1;
+    for (int j = 0; j < 3; ++j) {
+        ctx->dets[det].fg_mult = kMults[j];
+        float ms = 0.0f;
+        for (int rep = 0; rep < 3; ++rep) {  // one warm-up, then the faster of two
+            uint64_t b = 0;
+            pdc_status rc = pdc_process_frames(ctx, det, frames_dev, n_frames, hit_capacity, hip_stream, &b);
+            if (rc != PDC_OK) {
+                ctx->dets[det].fg_mult = 1;
+                return rc;
+            }
+            float main_ms = 0.0f;
+            rc = pdc_get_hits(ctx, b, nullptr, 0, 0, nullptr, nullptr, nullptr);
+            if (rc >= 0) rc = pdc_batch_timing(ctx, b, &main_ms, nullptr);
+            pdc_release_batch(ctx, b);
+            if (rc < 0) {
+                ctx->dets[det].fg_mult = 1;
+                return rc;
+            }
+            if (rep == 1 || (rep == 2 && main_ms < ms)) ms = main_ms;
+        }
+        if (ms_out) ms_out[j] = ms;
+        if (j == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = kMults[j];
+        }
+    }
+    ctx->dets[det].fg_mult = best;
+    if (mult_out) *mult_out = best;
     return PDC_OK;
 }
 

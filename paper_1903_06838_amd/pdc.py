@@ -93,6 +93,8 @@ _sig = {
     "pdc_histogram_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, _P]),
     "pdc_get_invalid_counts": (_st, [_P, ctypes.c_uint64, _P]),
     "pdc_process_mixed": (_st, [_P, _P, ctypes.c_int32, _P, _P]),
+    "pdc_autotune": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64, _P,
+                           ctypes.POINTER(ctypes.c_int32), _P]),
     "pdc_debug_batch_path": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
     "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
@@ -204,6 +206,15 @@ def process_mixed(ctx, items, stream=None) -> list:
         stream = stream.cuda_stream
     _check(_lib.pdc_process_mixed(ctx, arr, len(items), stream, out), ctx)
     return list(out)
+
+
+def autotune(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int, stream=None):
+    """Returns (chosen frame-group multiplier, frame-kernel ms for x1, x2, x4)."""
+    m = ctypes.c_int32(0)
+    ms = np.zeros(3, np.float32)
+    _check(_lib.pdc_autotune(ctx, det, _ptr(frames_dev), n_frames, hit_capacity, _stream(stream), ctypes.byref(m),
+                             ms.ctypes.data), ctx)
+    return m.value, ms
 
 
 def get_hits(ctx, batch: int, n_frames: int, capacity: int | None = None, dst_dev=None):

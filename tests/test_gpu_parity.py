@@ -329,3 +329,26 @@ def test_median_brackets_straddling_zero(ctx):
     ge = rng.uniform(0.95, 1.05, size=eg.shape).astype(np.float32)
     want = oracle_threads(rawe, pe, ge, 96, keep_corrected=True)
     assert_same(run_pdc(ctx, rawe, pe, ge, 96, keep_corrected=True), want, corrected=True)
+
+
+def test_autotune_keeps_results(ctx):
+    """The frame-group autotuner picks one of its multipliers and the batches
+    after it still equal the oracle bit for bit."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(2, 40, 388, 194)
+    raw, ped, gain = _case(geom, 0.02, 64, 51)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols)
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, 194), ped, gain, pdc.params())
+    try:
+        dev = torch.from_numpy(raw).cuda()
+        mult, ms = pdc.autotune(ctx, det, dev, raw.shape[0], 1 << 16)
+        assert mult in (1, 2, 4) and np.all(ms > 0)
+        b = pdc.process_frames(ctx, det, dev, raw.shape[0], 1 << 16)
+        hits, total, fh, fp, _ = pdc.get_hits(ctx, b, raw.shape[0])
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
+    assert_same(dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp), want)
