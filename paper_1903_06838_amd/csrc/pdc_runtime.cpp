@@ -579,27 +579,27 @@ pdc_status enqueue_partial(pdc_ctx *ctx, Batch &bt, uint64_t n_list)
 }
 
 // Frame groups of a persistent launch: each workgroup takes one strip for a
-// contiguous range of frames, one workgroup per compute unit at a time; the
-// count is chosen so that the last round of workgroups still fills the chip
-// (CSPAD's 224 strips alone would leave 32 of 256 units idle), with at least 4
-// frames per group.
+// contiguous range of frames, one workgroup per compute unit at a time, and
+// spends two extra pipeline iterations draining.  The count minimises
+// rounds x (frames per group + 2), the iterations a compute unit runs: large
+// batches get enough groups to fill whole rounds of the chip (CSPAD's 224
+// strips alone would leave 32 of 256 units idle), small ones stay in one round.
 int frame_groups(int n_cu, int n_strips, uint64_t n_frames, int mult)
 {
-    const int max_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, n_frames / 4));
+    const int max_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, n_frames));
     int best = 1;
-    double best_eff = 0.0;
+    uint64_t best_cost = ~0ull;
     for (int g = 1; g <= max_fg; ++g) {
-        const int64_t wgs = (int64_t)g * n_strips;
-        const int64_t rounds = (wgs + n_cu - 1) / n_cu;
-        const double eff = (double)wgs / (double)(rounds * n_cu);
-        if (eff > best_eff + 1e-9) {
-            best_eff = eff;
+        const uint64_t wgs = (uint64_t)g * n_strips;
+        const uint64_t rounds = (wgs + n_cu - 1) / n_cu;
+        const uint64_t cost = rounds * ((n_frames + g - 1) / g + 2);
+        if (cost < best_cost) {
+            best_cost = cost;
             best = g;
         }
     }
     // more rounds of the same fill, if tuned so (finer dynamic balancing)
-    const uint64_t cap = std::max<uint64_t>(1, n_frames / 4);
-    return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)best * (uint64_t)std::max(1, mult), cap));
+    return (int)std::max<uint64_t>(1, std::min<uint64_t>((uint64_t)best * (uint64_t)std::max(1, mult), n_frames));
 }
 
 // Choose the kernel for a batch and size its unit arrays.
