@@ -175,24 +175,33 @@ def cpu_baseline(pool, ped, gain, bank_cols, gpu_fh, gpu_fp, gpu_hits_fn):
                       % (passes, P, passes * P, wall)}, exact
 
 
-def latency(torch, pdc, ctx, det, frame, calls=300):
-    """Single-frame process_frames + get_hits, host-observed and kernel-only."""
+def latency(torch, pdc, ctx, det, frame, calls=300, use_graph=False):
+    """Small-batch process_frames (or a replay of its captured graph) + get_hits,
+    host-observed and kernel-only."""
     import numpy as np
 
-    stream = torch.cuda.current_stream()
+    n = frame.shape[0]
+    stream = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    graph = pdc.graph_create(ctx, det, frame, n, 1 << 20) if use_graph else None
     host, kern = [], []
     for i in range(calls + 20):
         t0 = time.perf_counter()
-        b = pdc.process_frames(ctx, det, frame, 1, 1 << 20, stream)
-        pdc.get_hits(ctx, b, 1)
+        if graph is not None:
+            b = pdc.graph_launch(ctx, graph, stream)
+        else:
+            b = pdc.process_frames(ctx, det, frame, n, 1 << 20, stream)
+        pdc.get_hits(ctx, b, n)
         t1 = time.perf_counter()
         _, tk = pdc.batch_timing(ctx, b)
         pdc.release_batch(ctx, b)
         if i >= 20:
             host.append((t1 - t0) * 1e3)
             kern.append(tk)
+    if graph is not None:
+        pdc.graph_destroy(ctx, graph)
     q = lambda a, p: round(float(np.percentile(a, p)), 4)
-    return {"host_ms_p50": q(host, 50), "host_ms_p99": q(host, 99),
+    return {"frames": n, "graph": use_graph, "host_ms_p50": q(host, 50), "host_ms_p99": q(host, 99),
             "kernel_ms_p50": q(kern, 50), "kernel_ms_p99": q(kern, 99), "calls": calls}
 
 
@@ -630,7 +639,10 @@ def main():
         log("cpu baseline: %s; GPU bit-exact on the pool: %s" % (cb, exact))
 
     if not args.no_latency:
-        lat = {"cspad_frame": latency(torch, pdc, ctx, det, frames[:1])}
+        lat = {"cspad_frame": latency(torch, pdc, ctx, det, frames[:1]),
+               "cspad_frame_graph": latency(torch, pdc, ctx, det, frames[:1], use_graph=True),
+               "cspad_16_frames": latency(torch, pdc, ctx, det, frames[:16]),
+               "cspad_16_frames_graph": latency(torch, pdc, ctx, det, frames[:16], use_graph=True)}
         eg = synth.EPIX100
         eped, egain = synth.make_calibration(eg, 0)
         edet = pdc.calibrate(ctx, pdc.geometry(*eg.shape, eg.bank_cols), eped, egain, pdc.params())

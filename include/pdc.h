@@ -58,6 +58,7 @@ typedef int32_t pdc_status;
 #define PDC_KEEP_CORRECTED 1u
 
 typedef struct pdc_ctx pdc_ctx;
+typedef struct pdc_graph pdc_graph;
 
 /* Detector geometry.  A frame is n_tiles tiles of rows x cols pixels (tiles are
  * separate sensors: 3x3 windows stop at tile edges).  Common-mode banks are
@@ -141,7 +142,11 @@ const char *pdc_last_error(const pdc_ctx *ctx);
 
 /* Open a context on HIP device `device`.  The library owns every device buffer
  * it allocates; they are freed by pdc_destroy.  EDEVICE if the device does not
- * exist or is not gfx950. */
+ * exist or is not gfx950.  Test hooks read from the environment here:
+ * PDC_FORCE_GENERAL=1 runs every batch on the general kernel;
+ * PDC_DEBUG_TIGHT_POOL=1 sizes a batch's first hit staging to hit_capacity
+ * alone (no per-workgroup slack), so a small capacity forces the staging
+ * overflow and its exact recomputation. */
 pdc_status pdc_create(int32_t device, pdc_ctx **out);
 
 /* Wait for outstanding work, free everything.  NULL is accepted. */
@@ -246,6 +251,34 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
  * batch (common-mode pass of the mean modes, frame kernel, scans, hit
  * scatter).  Either pointer may be NULL. */
 pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms);
+
+/* HIP graph of one batch (the pipeline of the Fig. a chain, as
+ * pdc_process_frames enqueues it), for loops that process the same number of
+ * frames from the same device buffer over and over: the kernels are captured
+ * once and each launch replays them with one call.
+ * pdc_graph_create captures a batch of n_frames (>= 1) frames at frames_dev
+ * for detector det, with buffers sized from hit_capacity, and returns the graph
+ * in *out.  The graph owns its device buffers and holds the detector (which
+ * pdc_release_detector frees only after pdc_graph_destroy).  The captured
+ * nodes are kernels only (no memset or copy nodes).
+ * pdc_graph_launch enqueues the graph on hip_stream (NULL: the context's
+ * stream) and returns a batch id in *batch_out that the batch calls
+ * (pdc_get_hits, pdc_get_corrected, summaries, pdc_release_batch, ...) take
+ * as for pdc_process_frames.  The frames are read from frames_dev when the
+ * graph runs: write the next frames there, ordered before the launch on
+ * hip_stream, and leave them unchanged until the batch is released.  One batch
+ * per graph at a time: ESTATE until the previous one is released.  A batch that
+ * needs recomputing from the start (staging overflow beyond hit_capacity, or
+ * no general-kernel plan for overflowing seed lists) is moved to buffers of its
+ * own, so results stay exact and the graph stays valid.  Batch timing reports
+ * the whole graph as main_ms.
+ * pdc_graph_destroy frees the graph; ESTATE while its batch is outstanding.
+ * pdc_destroy frees graphs still alive.  A graph is used from its context's
+ * thread, as the context is. */
+pdc_status pdc_graph_create(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                            uint64_t hit_capacity, pdc_graph **out);
+pdc_status pdc_graph_launch(pdc_graph *graph, void *hip_stream, uint64_t *batch_out);
+pdc_status pdc_graph_destroy(pdc_graph *graph);
 
 /* ------------------------------------------------------------------------
  * Subpixel position of hits (Photon Subpixel Resolution section and its

@@ -11,6 +11,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <set>
 #include <string>
 #include <vector>
 
@@ -102,6 +103,8 @@ struct Batch {
     bool keep = false;
     bool checked = false;  // overflow handled, totals final
     int fb = 0;            // 1: overflowing units recomputed by the general kernel, 2: whole batch
+    bool capture = false;  // being captured into a graph: kernels only, no events or copies
+    pdc_graph *graph = nullptr;  // launched from this graph, whose buffers it holds
     Buffers *buf = nullptr;
 };
 
@@ -151,6 +154,20 @@ struct pdc_ctx {
     HitRecord *fmt_buf = nullptr;  // staging for host-destination get_hits
     uint64_t fmt_cap = 0;
     bool force_v1 = false;         // PDC_FORCE_GENERAL=1 in the environment
+    bool tight_pool = false;       // PDC_DEBUG_TIGHT_POOL=1: first staging holds hit_capacity only
+    hipStream_t capture_stream = nullptr;  // private stream for graph capture
+    std::set<pdc_graph *> graphs;
+};
+
+// A captured batch: the kernels of one batch of fixed size over a fixed frame
+// buffer, replayed by pdc_graph_launch into buffers the graph owns.
+struct pdc_graph {
+    pdc_ctx *ctx = nullptr;
+    Batch proto;                 // shape of the captured batch (path, groups, capacity, ...)
+    Buffers *buf = nullptr;      // the buffers its kernels read and write
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t batch = 0;          // outstanding batch launched from it, 0 if none
 };
 
 namespace {
@@ -481,6 +498,16 @@ void fill_v1_args(const Detector &d, const Batch &bt, FrameKernelArgs &a)
     a.invalid = b->invalid;
 }
 
+// End of a batch's work on its stream: the timing event, then the state copy
+// that finish_batch reads.
+pdc_status record_end(pdc_ctx *ctx, Buffers *b, hipStream_t s)
+{
+    HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
+    HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipEventRecord(b->ev_state, s));
+    return PDC_OK;
+}
+
 // Per-frame sums, offsets and the raster-ordered list, then the state copy.
 pdc_status enqueue_tail(pdc_ctx *ctx, Batch &bt)
 {
@@ -491,10 +518,8 @@ pdc_status enqueue_tail(pdc_ctx *ctx, Batch &bt)
     HIP_TRY(ctx, launch_frame_scan(b->frame_hits, bt.n_frames, b->frame_offset, b->state, s));
     HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
                                 bt.n_units, bt.upf, b->hits, b->cap_pool, s));
-    HIP_TRY(ctx, hipEventRecord(b->ev_end, s));
-    HIP_TRY(ctx, hipMemcpyAsync(b->host_state, b->state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipEventRecord(b->ev_state, s));
-    return PDC_OK;
+    if (bt.capture) return PDC_OK;
+    return record_end(ctx, b, s);
 }
 
 pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
@@ -503,12 +528,12 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     Buffers *b = bt.buf;
     hipStream_t s = bt.stream;
     HIP_TRY(ctx, launch_init_state(b->state, s));
-    HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
+    if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
     if (d.g.gain_mode) HIP_TRY(ctx, launch_fill_u32(b->invalid, bt.n_frames, s));
     // the persistent kernel computes a bank's thresholded mean itself
     const bool cm_inline = d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2;
     if (d.p.cm_mode && !cm_inline) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));
-    HIP_TRY(ctx, hipEventRecord(b->ev_cm, s));
+    if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_cm, s));
     if (bt.n_units > 0 && bt.path == 2) {
         V2Args a{};
         a.frames = bt.frames;
@@ -552,7 +577,7 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         fill_v1_args(d, bt, a);
         HIP_TRY(ctx, launch_frame_kernel_v1(a, batch_grid(d, bt), d.lds_bytes, bt.keep, s));
     }
-    HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
+    if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
     return enqueue_tail(ctx, bt);
 }
 
@@ -624,6 +649,44 @@ Batch *find_batch(pdc_ctx *ctx, uint64_t id)
     return it == ctx->batches.end() ? nullptr : &it->second;
 }
 
+// Frames2 and common-mode floats a batch's buffers hold.
+uint64_t corr_floats(const Detector &d, const Batch &bt)
+{
+    return bt.keep ? bt.n_frames * (uint64_t)d.g.n_tiles * d.g.rows * d.g.cols : 0;
+}
+uint64_t cm_floats(const Detector &d, const Batch &bt)
+{
+    return d.p.cm_mode ? bt.n_frames * (uint64_t)d.cm_regions * 3 : 0;
+}
+
+Buffers *take_buffers(pdc_ctx *ctx)
+{
+    if (ctx->spare.empty()) return new (std::nothrow) Buffers;
+    Buffers *b = ctx->spare.back();
+    ctx->spare.pop_back();
+    return b;
+}
+
+// Move a batch launched from a graph onto buffers of its own before it is
+// recomputed from the start, which may grow them: the graph's kernels keep
+// the addresses they were captured with.  The graph is free again.
+pdc_status detach_from_graph(pdc_ctx *ctx, Batch &bt)
+{
+    if (!bt.graph) return PDC_OK;
+    Buffers *b = take_buffers(ctx);
+    if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    const Detector &d = ctx->dets[bt.det];
+    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, bt.n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt));
+    if (rc != PDC_OK) {
+        ctx->spare.push_back(b);
+        return rc;
+    }
+    bt.graph->batch = 0;
+    bt.graph = nullptr;
+    bt.buf = b;
+    return PDC_OK;
+}
+
 // Wait for a batch; if its staging pool overflowed, run it again with exact
 // capacity so that its hit list is complete.
 pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
@@ -643,10 +706,12 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
             st = *bt.buf->host_state;
         } else if (st.fallback) {
             // no general-kernel plan for these strips: redo the whole batch
+            pdc_status rc = detach_from_graph(ctx, bt);
+            if (rc != PDC_OK) return rc;
             set_path(d, bt, 1);
             bt.fb = 2;
             const uint64_t cap = pool_capacity(d, 1, st.total, batch_grid(d, bt));
-            pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
+            rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
             if (rc != PDC_OK) return rc;
             bt.pool_cap = cap;
             rc = enqueue(ctx, bt);
@@ -662,7 +727,9 @@ pdc_status finish_batch(pdc_ctx *ctx, Batch &bt)
         // the chunks of a unit-list recomputation)
         uint64_t cap = pool_capacity(d, bt.path, st.total, batch_grid(d, bt));
         if (bt.fb == 1) cap += (uint64_t)v1_grid(st.n_fallback) * (kChunkHits + d.v2_max_unit_hits);
-        pdc_status rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
+        pdc_status rc = detach_from_graph(ctx, bt);
+        if (rc != PDC_OK) return rc;
+        rc = ensure_buffers(ctx, bt.buf, bt.n_units, bt.n_frames, cap, 0);
         if (rc != PDC_OK) return rc;
         bt.pool_cap = cap;
         rc = enqueue(ctx, bt);
@@ -727,6 +794,8 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
         ctx->force_v1 = fv && fv[0] == '1';
         const char *ms = std::getenv("PDC_MIX_SHARE");
         ctx->mix_share = ms && ms[0] == '1';
+        const char *tp = std::getenv("PDC_DEBUG_TIGHT_POOL");
+        ctx->tight_pool = tp && tp[0] == '1';
     }
     {
         int lds = 0;
@@ -748,8 +817,16 @@ pdc_status pdc_destroy(pdc_ctx *ctx)
     if (!ctx) return PDC_OK;
     hipSetDevice(ctx->device);
     hipDeviceSynchronize();
-    for (auto &kv : ctx->batches) free_buffers(kv.second.buf);
+    for (auto &kv : ctx->batches)
+        if (!kv.second.graph) free_buffers(kv.second.buf);
     for (Buffers *b : ctx->spare) free_buffers(b);
+    for (pdc_graph *g : ctx->graphs) {
+        hipGraphExecDestroy(g->exec);
+        hipGraphDestroy(g->graph);
+        free_buffers(g->buf);
+        delete g;
+    }
+    if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
     for (Detector &d : ctx->dets)
         if (d.live) {
             hipFree(d.d_ped);
@@ -915,18 +992,10 @@ pdc_status process_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, 
     set_path(d, bt, d.v2_ok ? 2 : 1);
     bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
-    bt.pool_cap = pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
-    Buffers *b = nullptr;
-    if (!ctx->spare.empty()) {
-        b = ctx->spare.back();
-        ctx->spare.pop_back();
-    } else {
-        b = new (std::nothrow) Buffers;
-        if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
-    }
-    const uint64_t corr = bt.keep ? n_frames * (uint64_t)d.g.n_tiles * d.g.rows * d.g.cols : 0;
-    const uint64_t cmf = d.p.cm_mode ? n_frames * (uint64_t)d.cm_regions * 3 : 0;
-    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr, cmf);
+    bt.pool_cap = ctx->tight_pool ? hit_capacity : pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
+    Buffers *b = take_buffers(ctx);
+    if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt));
     if (rc != PDC_OK) {
         ctx->spare.push_back(b);
         return rc;
@@ -1022,7 +1091,10 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch)
     if (bt->buf->used) HIP_TRY(ctx, hipEventSynchronize(bt->buf->ev_use));
     bt->buf->used = false;
     int32_t det = bt->det;
-    ctx->spare.push_back(bt->buf);
+    if (bt->graph)
+        bt->graph->batch = 0;  // the buffers stay with the graph
+    else
+        ctx->spare.push_back(bt->buf);
     ctx->batches.erase(batch);
     ctx->dets[det].pending -= 1;
     maybe_free_detector(ctx, det);
@@ -1041,6 +1113,117 @@ pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float 
     HIP_TRY(ctx, hipEventElapsedTime(&t, bt->buf->ev_start, bt->buf->ev_end));
     if (main_ms) *main_ms = a;
     if (total_ms) *total_ms = t;
+    return PDC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// graph capture of a batch
+// ---------------------------------------------------------------------------
+
+pdc_status pdc_graph_create(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                            uint64_t hit_capacity, pdc_graph **out)
+{
+    if (!ctx || !out) return fail(ctx, PDC_EINVAL, "ctx and out must be non-NULL");
+    *out = nullptr;
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    if (!frames_dev || n_frames < 1 || n_frames > ((uint64_t)1 << 31))
+        return fail(ctx, PDC_EINVAL, "frames_dev must be non-NULL and 1 <= n_frames <= 2^31");
+    Detector &d = ctx->dets[det];
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    std::unique_ptr<pdc_graph> g(new (std::nothrow) pdc_graph);
+    if (!g) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    g->ctx = ctx;
+    Batch &bt = g->proto;
+    bt.det = det;
+    bt.frames = frames_dev;
+    bt.n_frames = n_frames;
+    set_path(d, bt, d.v2_ok ? 2 : 1);
+    bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+    bt.pool_cap = ctx->tight_pool ? hit_capacity : pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
+    g->buf = new (std::nothrow) Buffers;
+    if (!g->buf) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    pdc_status rc = ensure_buffers(ctx, g->buf, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt));
+    if (rc != PDC_OK) {
+        free_buffers(g->buf);
+        return rc;
+    }
+    bt.buf = g->buf;
+    bt.stream = ctx->capture_stream;
+    bt.capture = true;
+    // relaxed: the launch helpers may set kernel attributes while capturing
+    hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) {
+        free_buffers(g->buf);
+        return fail(ctx, PDC_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
+    }
+    rc = enqueue(ctx, bt);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (rc == PDC_OK && e != hipSuccess) rc = fail(ctx, PDC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+    if (rc == PDC_OK) {
+        e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) rc = fail(ctx, PDC_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+    }
+    if (rc != PDC_OK) {
+        if (graph) hipGraphDestroy(graph);
+        free_buffers(g->buf);
+        return rc;
+    }
+    g->graph = graph;
+    bt.capture = false;
+    bt.stream = nullptr;
+    d.pending += 1;  // the graph holds the detector's planes
+    ctx->graphs.insert(g.get());
+    *out = g.release();
+    return PDC_OK;
+}
+
+pdc_status pdc_graph_launch(pdc_graph *g, void *hip_stream, uint64_t *batch_out)
+{
+    if (!g || !batch_out) return fail(g ? g->ctx : nullptr, PDC_EINVAL, "graph and batch_out must be non-NULL");
+    pdc_ctx *ctx = g->ctx;
+    if (g->batch) return fail(ctx, PDC_ESTATE, "batch %llu of this graph is not released", (unsigned long long)g->batch);
+    if ((int)ctx->batches.size() >= kMaxOutstandingBatches)
+        return fail(ctx, PDC_ESTATE, "too many outstanding batches (release some)");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Batch bt = g->proto;
+    bt.id = ctx->next_batch;
+    bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    bt.buf = g->buf;
+    bt.graph = g;
+    Buffers *b = g->buf;
+    // the graph holds kernels only: events and the state copy go around it
+    HIP_TRY(ctx, hipEventRecord(b->ev_start, bt.stream));
+    HIP_TRY(ctx, hipEventRecord(b->ev_cm, bt.stream));
+    HIP_TRY(ctx, hipGraphLaunch(g->exec, bt.stream));
+    HIP_TRY(ctx, hipEventRecord(b->ev_main, bt.stream));
+    pdc_status rc = record_end(ctx, b, bt.stream);
+    if (rc != PDC_OK) return rc;
+    ++ctx->next_batch;
+    ctx->dets[bt.det].pending += 1;
+    ctx->batches[bt.id] = bt;
+    g->batch = bt.id;
+    *batch_out = bt.id;
+    return PDC_OK;
+}
+
+pdc_status pdc_graph_destroy(pdc_graph *g)
+{
+    if (!g) return PDC_OK;
+    pdc_ctx *ctx = g->ctx;
+    if (g->batch) return fail(ctx, PDC_ESTATE, "batch %llu of this graph is not released", (unsigned long long)g->batch);
+    // released batches have finished with the buffers (pdc_release_batch waits)
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipGraphExecDestroy(g->exec);
+    hipGraphDestroy(g->graph);
+    free_buffers(g->buf);
+    ctx->graphs.erase(g);
+    const int32_t det = g->proto.det;
+    delete g;
+    ctx->dets[det].pending -= 1;
+    maybe_free_detector(ctx, det);
     return PDC_OK;
 }
 

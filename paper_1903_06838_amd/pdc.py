@@ -99,6 +99,9 @@ _sig = {
     "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
     "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
                                   ctypes.POINTER(ctypes.c_int32)]),
+    "pdc_graph_create": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(_P)]),
+    "pdc_graph_launch": (_st, [_P, _P, ctypes.POINTER(ctypes.c_uint64)]),
+    "pdc_graph_destroy": (_st, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -262,6 +265,25 @@ def debug_batch_path(ctx, batch: int) -> int:
 
 def release_batch(ctx, batch: int) -> None:
     _check(_lib.pdc_release_batch(ctx, batch), ctx)
+
+
+def graph_create(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int):
+    """Capture a batch of n_frames frames read from frames_dev (device tensor or
+    address) into a HIP graph; returns the graph handle."""
+    g = _P()
+    _check(_lib.pdc_graph_create(ctx, det, _ptr(frames_dev), n_frames, hit_capacity, ctypes.byref(g)), ctx)
+    return g.value
+
+
+def graph_launch(ctx, graph, stream=None) -> int:
+    """Replay the graph on stream (torch stream, raw handle or None); returns a batch id."""
+    b = ctypes.c_uint64(0)
+    _check(_lib.pdc_graph_launch(graph, _stream(stream), ctypes.byref(b)), ctx)
+    return b.value
+
+
+def graph_destroy(ctx, graph) -> None:
+    _check(_lib.pdc_graph_destroy(graph), ctx)
 
 
 def batch_timing(ctx, batch: int):

@@ -125,6 +125,9 @@ def test_null_context_paths(pdc):
     assert lib.pdc_histogram_corrected(None, 1, None, 0.0, 1.0, 1, None) == pdc.EINVAL
     assert lib.pdc_dark_stats(None, None, None, 2, None, None, None) == pdc.EINVAL
     assert lib.pdc_calibrate_darks(None, None, None, 2, None, None, None, None) == pdc.EINVAL
+    assert lib.pdc_graph_create(None, 0, None, 1, 0, None) == pdc.EINVAL
+    assert lib.pdc_graph_launch(None, None, ctypes.byref(b)) == pdc.EINVAL
+    assert lib.pdc_graph_destroy(None) == pdc.OK
 
 
 def test_create_without_gpu_is_edevice(pdc):
