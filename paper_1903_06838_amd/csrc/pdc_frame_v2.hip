@@ -84,18 +84,6 @@ __device__ __forceinline__ float gsum_f(float x)
     return x;
 }
 
-template <int L>
-__device__ __forceinline__ float gmin_f(float x)
-{
-#define PDC_GM(ctrl) x = fminf(x, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), ctrl, 0xF, 0xF, false)))
-    PDC_GM(0xB1);
-    if (L >= 4) PDC_GM(0x4E);
-    if (L >= 8) PDC_GM(0x141);
-    if (L >= 16) PDC_GM(0x140);
-#undef PDC_GM
-    return x;
-}
-
 // Number of the lane's values below p.  For finite p, x < p exactly when
 // fl(x - p) has its sign bit set (a nonzero difference never rounds to +0,
 // x == p gives +0, x = +inf gives +inf); p is clamped to the finite range,
@@ -258,38 +246,48 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // ascending bitonic sort over the group's lanes: merges of size 2b start
-    // with the mirror partner inside the block, then halve with xor partners
-#define PDC_CX(partner, lower)                                                                   \
-    {                                                                                            \
-        const float o_ = (partner);                                                              \
-        y = (lower) ? fminf(y, o_) : fmaxf(y, o_);                                               \
-    }
-#define PDC_DPP(ctrl) __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), ctrl, 0xF, 0xF, false))
-    PDC_CX(PDC_DPP(0xB1), !(gl & 1))                      // merge 2: mirror (xor 1)
+    // with the mirror partner inside the block, then halve with xor partners.
+    // A compare-exchange is one median of three: med3(y, partner, -inf) is
+    // the smaller of the two (kept by the lower lane of the pair), med3(y,
+    // partner, +inf) the larger; no NaN is present.
+    const float e1 = (gl & 1) ? INFINITY : -INFINITY;
+    const float e2 = (gl & 2) ? INFINITY : -INFINITY;
+    const float e4 = (gl & 4) ? INFINITY : -INFINITY;
+    const float e8 = (gl & 8) ? INFINITY : -INFINITY;
+#define PDC_CX(partner, e) y = __builtin_amdgcn_fmed3f(y, (partner), (e));
+#define PDC_DPP(ctrl) __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), ctrl, 0xF, 0xF, false))
+    PDC_CX(PDC_DPP(0xB1), e1)                      // merge 2: mirror (xor 1)
     if (L >= 4) {
-        PDC_CX(PDC_DPP(0x1B), !(gl & 2))                  // merge 4: mirror in 4
-        PDC_CX(PDC_DPP(0xB1), !(gl & 1))
+        PDC_CX(PDC_DPP(0x1B), e2)                  // merge 4: mirror in 4
+        PDC_CX(PDC_DPP(0xB1), e1)
     }
     if (L >= 8) {
-        PDC_CX(PDC_DPP(0x141), !(gl & 4))                 // merge 8: row_half_mirror
-        PDC_CX(PDC_DPP(0x4E), !(gl & 2))                  // xor 2
-        PDC_CX(PDC_DPP(0xB1), !(gl & 1))
+        PDC_CX(PDC_DPP(0x141), e4)                 // merge 8: row_half_mirror
+        PDC_CX(PDC_DPP(0x4E), e2)                  // xor 2
+        PDC_CX(PDC_DPP(0xB1), e1)
     }
     if (L >= 16) {
-        PDC_CX(PDC_DPP(0x140), !(gl & 8))                 // merge 16: row_mirror
+        PDC_CX(PDC_DPP(0x140), e8)                 // merge 16: row_mirror
         {
             const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x104, 0xF, 0xF, true));  // row_shl:4
             const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x114, 0xF, 0xF, true));  // row_shr:4
-            PDC_CX((gl & 4) ? up : dn, !(gl & 4))         // xor 4
+            PDC_CX((gl & 4) ? up : dn, e4)         // xor 4
         }
-        PDC_CX(PDC_DPP(0x4E), !(gl & 2))
-        PDC_CX(PDC_DPP(0xB1), !(gl & 1))
+        PDC_CX(PDC_DPP(0x4E), e2)
+        PDC_CX(PDC_DPP(0xB1), e1)
     }
 #undef PDC_DPP
 #undef PDC_CX
-    const float pick = gl == k - clo ? y : -INFINITY;
-    const float r = -gmin_f<L>(-pick);
-    return gather ? r : lo;
+    // exactly one lane of the group (k - clo < n <= L) holds the answer: an
+    // OR over the group of its bits and zeros elsewhere broadcasts it
+    int rb = gl == k - clo ? __float_as_int(y) : 0;
+#define PDC_GX(ctrl) rb |= __builtin_amdgcn_update_dpp(0, rb, ctrl, 0xF, 0xF, false);
+    PDC_GX(0xB1)
+    if (L >= 4) PDC_GX(0x4E)
+    if (L >= 8) PDC_GX(0x141)
+    if (L >= 16) PDC_GX(0x140)
+#undef PDC_GX
+    return gather ? __int_as_float(rb) : lo;
 }
 
 // Smallest binary32 value th such that fl(th - m) > t (fl(x - m) is
@@ -682,7 +680,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             }
             append_seeds(x, th0, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
-        if (!CMM && cur_ok) {
+        if (!CMM && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
             constexpr int G = 64 / L;
             const int grp = lane / L, gl = lane - grp * L;
             const int i = wave * G + grp;
@@ -690,11 +688,17 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             const int row = act ? i / nb : 0;
             const int bank = act ? i - row * nb : 0;
             const float *src = u_c + row * W + bank * B;
+            // every lane reads (inside the u buffers or the LDS that follows
+            // them; an inactive group reads row 0) and columns past the bank
+            // become +inf; lim is opaque so that the compares stay here
+            // rather than as loop-invariant masks
+            int lim = B - gl;
+            asm volatile("" : "+v"(lim));
             float x[V];
 #pragma unroll
             for (int v = 0; v < V; ++v) {
-                const int c = L * v + gl;
-                x[v] = (act && c < B) ? src[c] : INFINITY;
+                const float t = src[L * v + gl];
+                x[v] = L * v < lim ? t : INFINITY;
             }
             int nv = B, kq = kmed;
             bool actv = act;
