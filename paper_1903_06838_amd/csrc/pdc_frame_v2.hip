@@ -120,28 +120,42 @@ __device__ __forceinline__ bool done_single(float lo, float hi)
 // the group's lanes and the answer is read off; a bracket that holds a single
 // float (possibly many copies of it) gives that float.  Groups with act false
 // return an unspecified value.
-template <int V, int L>
-__device__ float group_median(const float (&x)[V], int nval, int k, float rw, bool act, float *gsc)
+template <int V, int L, bool SPARSE>
+__device__ float group_median(const float (&x)[V], int nval, int k, float rw, bool act, float *gsc, int B)
 {
     static_assert(V >= 3, "the start estimate takes triples of values per lane");
     // start: medians of three of each lane's values (up to eight triples),
-    // averaged over the group
+    // averaged over the group.  Dense banks (no +inf inside the first B
+    // columns) take the triples that every lane holds; with invalid pixels
+    // (SPARSE) each lane takes the finite ones.  Only the number of search
+    // steps depends on the start, never the result.
     constexpr int NT = V / 3 < 8 ? V / 3 : 8;
-    float s3 = 0.0f;
-    int n3 = 0;
+    float est;
+    if constexpr (!SPARSE) {
+        const int nt = min(NT, B / (3 * L));  // triples inside the bank on every lane
+        float s3 = 0.0f;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const float a = x[3 * t];
-        const float b = x[3 * t + 1] < INFINITY ? x[3 * t + 1] : a;
-        const float c = x[3 * t + 2] < INFINITY ? x[3 * t + 2] : b;
-        if (a < INFINITY) {
-            s3 += __builtin_amdgcn_fmed3f(a, b, c);
-            ++n3;
+        for (int t = 0; t < NT; ++t)
+            if (t < nt) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
+        const float ssum = gsum_f<L>(s3);
+        est = nt > 0 ? ssum * __builtin_amdgcn_rcpf((float)(nt * L)) : 0.0f;
+    } else {
+        float s3 = 0.0f;
+        int n3 = 0;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const float a = x[3 * t];
+            const float b = x[3 * t + 1] < INFINITY ? x[3 * t + 1] : a;
+            const float c = x[3 * t + 2] < INFINITY ? x[3 * t + 2] : b;
+            if (a < INFINITY) {
+                s3 += __builtin_amdgcn_fmed3f(a, b, c);
+                ++n3;
+            }
         }
+        const float ssum = gsum_f<L>(s3);
+        const int nl = gsum_i<L>(n3);
+        est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
     }
-    const float ssum = gsum_f<L>(s3);
-    const int nl = gsum_i<L>(n3);
-    const float est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
 
     const float w0 = 6.0f * rw;
     float lo = est - w0, hi = est + w0;
@@ -453,17 +467,17 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 
     uint64_t chunk_cur = 0, chunk_end = 0;  // staging chunk, held by the phase-3 wave's lane 0
     uint32_t raw[GMAX][NQ];
-    auto load_raw = [&](uint64_t f) {
+    auto load_raw = [&](uint64_t f, const bool(&lok)[NQ]) {
         const uint32_t *fr = reinterpret_cast<const uint32_t *>(A.frames + f * npix + row_base);
 #pragma unroll
         for (int g = 0; g < GMAX; ++g) {
             const bool gv = g < ng;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                raw[g][q] = (gv && lane_ok[q]) ? __builtin_nontemporal_load(fr + ((gb_[g] + 128 * q + lane_off) >> 1)) : 0u;
+                raw[g][q] = (gv && lok[q]) ? __builtin_nontemporal_load(fr + ((gb_[g] + 128 * q + lane_off) >> 1)) : 0u;
         }
     };
-    if (f_begin < f_end) load_raw(f_begin);
+    if (f_begin < f_end) load_raw(f_begin, lane_ok);
     __syncthreads();
 
     // Seeds of a bank-row held by an L-lane group in phase B (lane gl holds
@@ -477,7 +491,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         if (own) {
 #pragma unroll
             for (int v = 0; v < V; ++v)
-                if (L * v + gl < B && xs[v] < INFINITY && xs[v] >= th) sb |= 1u << v;
+                if (xs[v] < INFINITY && xs[v] >= th) sb |= 1u << v;  // columns past the bank hold +inf
         }
         const uint32_t ns = (uint32_t)__popc(sb);
         const uint32_t incl = wave_incl_scan(ns);
@@ -513,6 +527,16 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         const float *u_p = s_u + pp * RW;
         float *med_c = s_med + par * RN;
         const float *med_p = s_med + pp * RN;
+        // the lane masks are recomputed each frame from an opaque copy of the
+        // lane offset: hoisted out of the loop they would be kept in scalar
+        // registers, which this kernel does not have to spare
+        bool lok[NQ];
+        {
+            uint32_t lo = lane_off;
+            asm volatile("" : "+v"(lo));
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) lok[q] = 128u * q + lo < (uint32_t)B;
+        }
 
         // ================= A: 1a(f) | 4(f-2) ======================================
         if (cur_ok) {
@@ -521,13 +545,13 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             for (int g = 0; g < GMAX; ++g)
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) cur[g][q] = raw[g][q];
-            if (f + 1 < f_end) load_raw(f + 1);
+            if (f + 1 < f_end) load_raw(f + 1, lok);
             if constexpr (!MG) {
 #pragma unroll
                 for (int g = 0; g < GMAX; ++g)
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
-                        if (g < ng && lane_ok[q])
+                        if (g < ng && lok[q])
                             *reinterpret_cast<float2 *>(u_c + gb_[g] + 128 * q + lane_off) =
                                 make_float2(dark_gain(cur[g][q] & 0xFFFFu, pd[g][q][0], kk[g][q][0]),
                                             dark_gain(cur[g][q] >> 16, pd[g][q][1], kk[g][q][1]));
@@ -540,7 +564,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 for (int g = 0; g < GMAX; ++g)
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
-                        if (g < ng && lane_ok[q]) {
+                        if (g < ng && lok[q]) {
                             const uint32_t w = cur[g][q];
                             const int r0 = gain_range(w & 0xFFFFu, A.gain_mode), r1 = gain_range(w >> 16, A.gain_mode);
                             const float u0 = r0 == 0 ? dark_gain(w & 0xFFFFu, pd[g][q][0], kk[g][q][0]) : INFINITY;
@@ -711,7 +735,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 kq = nv > 0 ? (nv - 1) / 2 : 0;
                 actv = act && nv > 0;
             }
-            float m = group_median<V, L>(x, nv, kq, A.rank_width, actv, s_gs + tid);
+            float m = group_median<V, L, MG>(x, nv, kq, A.rank_width, actv, s_gs + tid, B);
             if constexpr (MG) {
                 if (!actv) m = 0.0f;
                 // invalid pixels take the median: v = fl(m - m) = +0
@@ -814,7 +838,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                     const float m = uniform_f(med_c[i]);
 #pragma unroll
                     for (int q = 0; q < NQ; ++q)
-                        if (lane_ok[q]) {
+                        if (lok[q]) {
                             const float2 u2 = *reinterpret_cast<const float2 *>(u_c + gb_[g] + 128 * q + lane_off);
                             *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q + lane_off) =
                                 make_float2(__fsub_rn(u2.x, m), __fsub_rn(u2.y, m));
