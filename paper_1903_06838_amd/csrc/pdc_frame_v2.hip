@@ -131,14 +131,11 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
     // steps depends on the start, never the result.
     constexpr int NT = V / 3 < 8 ? V / 3 : 8;
     float est;
-    if constexpr (!SPARSE) {
-        const int nt = min(NT, B / (3 * L));  // triples inside the bank on every lane
+    if (!SPARSE && B >= 3 * L * NT) {  // uniform: every lane's NT triples lie inside the bank
         float s3 = 0.0f;
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-            if (t < nt) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
-        const float ssum = gsum_f<L>(s3);
-        est = nt > 0 ? ssum * __builtin_amdgcn_rcpf((float)(nt * L)) : 0.0f;
+        for (int t = 0; t < NT; ++t) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
+        est = gsum_f<L>(s3) * (1.0f / (float)(NT * L));
     } else {
         float s3 = 0.0f;
         int n3 = 0;
