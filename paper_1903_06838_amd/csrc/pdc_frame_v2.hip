@@ -405,17 +405,16 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const int strip = item % A.n_strips;
     const int fg = item / A.n_strips;
     const V2Strip S = A.strips[strip];
-    const int t = S.tile;
-    const int lr0 = max(S.r0 - 1, 0);
-    const int lr1 = min(S.r1 + 1, H);
-    const int R = lr1 - lr0;
-    const int own_lo = S.r0 - lr0, own_hi = S.r1 - lr0;
+    const int lr0 = S.lg0;  // global rows
+    const int R = S.lg1 - lr0;
+    const int own_lo = S.g0 - lr0, own_hi = S.g1 - lr0;
+    const int bnd = S.gb == INT32_MAX ? R : S.gb - lr0;  // loaded row where a second tile starts
     const int BR = R * nb;
     const uint64_t npix = (uint64_t)A.T * H * W;
     const uint64_t f_begin = (A.n_frames * (uint64_t)fg) / A.n_fgroups;
     const uint64_t f_end = (A.n_frames * (uint64_t)(fg + 1)) / A.n_fgroups;
     const int kmed = (B - 1) / 2;
-    const uint32_t row_base = ((uint32_t)t * H + lr0) * (uint32_t)W;  // pixel index of loaded row 0
+    const uint32_t row_base = (uint32_t)lr0 * (uint32_t)W;  // pixel index of loaded row 0
     constexpr int kP3Wave = kV2Waves - 1;  // wave that runs phase 3
 
     // lane l of pair-slot q holds bank columns 128q + 2l and 128q + 2l + 1
@@ -682,7 +681,8 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 #pragma unroll
             for (int v = 0; v < V; ++v) x[v] = INFINITY;
             if (act) {
-                const uint32_t reg = A.cm_tile ? (uint32_t)t : ((uint32_t)t * H + lr0 + row) * (uint32_t)nb + bank;
+                const uint32_t grow = (uint32_t)(lr0 + row);  // global row
+                const uint32_t reg = A.cm_tile ? grow / (uint32_t)H : grow * (uint32_t)nb + bank;
                 const float *cv = A.cm + (f * A.cm_regions + reg) * 3;
                 const float c0 = cv[0], c1 = cv[1], c2 = cv[2];
                 float *dst = u_c + row * W + bank * B;
@@ -770,10 +770,12 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                     for (int dr = 0; dr < 3; ++dr) {
                         const int rr = row + dr - 1;
                         const int rc = min(max(rr, 0), R - 1);
+                        // in the loaded rows and in the seed's tile
+                        const bool rin = rr >= 0 && rr < R && ((rr >= bnd) == (row >= bnd));
 #pragma unroll
                         for (int dc = 0; dc < 3; ++dc) {
                             const int cc = col + dc - 1;
-                            ex[dr][dc] = rr >= 0 && rr < R && cc >= 0 && cc < W;
+                            ex[dr][dc] = rin && cc >= 0 && cc < W;
                             const int ccl = min(max(cc, 0), W - 1);
                             const int bk = ccl >= (bank + 1) * B ? bank + 1 : (ccl < bank * B ? bank - 1 : bank);
                             ua[dr][dc] = rc * W + ccl;

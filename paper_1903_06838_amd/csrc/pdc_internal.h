@@ -21,9 +21,13 @@ struct BatchState {
     unsigned long long n_fallback;  // units listed in the batch's fallback list
 };
 
-// Persistent kernel (v2): strips of own rows [r0, r1) of a tile.
+// Persistent kernel (v2): a strip owns frame rows [g0, g1), counted over all
+// tiles (global row t * H + r), and loads rows [lg0, lg1): one halo row on
+// each side that lies in the same tile.  A strip may cross one tile edge, at
+// global row gb (a multiple of H; INT32_MAX if none): rows on either side of
+// it are not neighbours.
 struct V2Strip {
-    int32_t tile, r0, r1, pad;
+    int32_t lg0, lg1, g0, g1, gb, pad0, pad1, pad2;
 };
 
 // A work unit is (frame, strip): rows [r0, r0 + strip_rows) of one tile.

@@ -79,19 +79,24 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
         const uint64_t unit = A.unit_list ? A.unit_list[it] : it;
         const uint64_t f = unit / (uint64_t)A.units_per_frame;
         const int su = (int)(unit - f * (uint64_t)A.units_per_frame);
-        int t, r0, r1;
-        if (A.strips) {  // a persistent-kernel strip
+        // rows r0..r1 (own) and lr0..lr1 (loaded) count from tile_base; rows
+        // on either side of row gb belong to different tiles
+        int t, r0, r1, lr0, lr1, gb = INT32_MAX;
+        if (A.strips) {  // a persistent-kernel strip: global rows, may cross one tile edge
             const V2Strip S = A.strips[su];
-            t = S.tile;
-            r0 = S.r0;
-            r1 = S.r1;
+            t = 0;
+            r0 = S.g0;
+            r1 = S.g1;
+            lr0 = S.lg0;
+            lr1 = S.lg1;
+            gb = S.gb;
         } else {
             t = su / A.strips_per_tile;
             r0 = (su - t * A.strips_per_tile) * A.strip_rows;
             r1 = min(r0 + A.strip_rows, H);
+            lr0 = max(r0 - 1, 0);
+            lr1 = min(r1 + 1, H);
         }
-        const int lr0 = max(r0 - 1, 0);
-        const int lr1 = min(r1 + 1, H);
         const int nrows = lr1 - lr0;
         const uint16_t *fr = A.frames + f * npix;
         const uint32_t tile_base = (uint32_t)t * (uint32_t)H * (uint32_t)W;
@@ -118,7 +123,8 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
             const float *cf = A.cm + f * (uint64_t)A.cm_regions * 3;
             for (int i = tid; i < nrows * W; i += kV1Threads) {
                 const int row = i / W, c = i - row * W;
-                const uint32_t reg = A.cm_tile ? (uint32_t)t : ((uint32_t)t * H + lr0 + row) * (uint32_t)nb + c / B;
+                const uint32_t grow = (uint32_t)t * H + lr0 + row;  // global row
+                const uint32_t reg = A.cm_tile ? grow / (uint32_t)H : grow * (uint32_t)nb + c / B;
                 const float *cv = cf + (uint64_t)reg * 3;
                 const float u = s_v[i];
                 s_v[i] = !(u < INFINITY) ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, cv[0]), cv[1]), cv[2]);
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
                         for (int dc = -1; dc <= 1; ++dc) {
                             if (dr == 0 && dc == 0) continue;
                             int rr = r + dr, cc = c + dc;
-                            if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+                            if (rr < lr0 || rr >= lr1 || cc < 0 || cc >= W || ((rr >= gb) != (r >= gb))) continue;
                             float vq = s_v[(rr - lr0) * W + cc];
                             uint32_t q = tile_base + (uint32_t)rr * W + cc;
                             if (!(vp > vq || (vp == vq && p < q))) is_max = false;
@@ -212,7 +218,8 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
                         for (int dr = -1; dr <= 1; ++dr)
                             for (int dc = -1; dc <= 1; ++dc) {
                                 int rr = r + dr, cc = c + dc;
-                                if (rr < 0 || rr >= H || cc < 0 || cc >= W) continue;
+                                if (rr < lr0 || rr >= lr1 || cc < 0 || cc >= W || ((rr >= gb) != (r >= gb)))
+                                    continue;
                                 float vj = s_v[(rr - lr0) * W + cc];
                                 qsum = __fadd_rn(qsum, vj > A.t_nb ? vj : 0.0f);
                             }

@@ -303,27 +303,43 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     const int rmax_lim = max_bank_rows / nb;
     if (rmax_lim < 3) return false;
     const int own_max = rmax_lim - 2;
-    int n_st = (g.rows + own_max - 1) / own_max;
-    // more strips per tile only while all strips still fit on the chip at once
-    while ((int64_t)g.n_tiles * (n_st + 1) <= ctx->n_cu && (g.rows + n_st) / (n_st + 1) >= 8 &&
-           (int64_t)g.n_tiles * n_st * 2 <= ctx->n_cu && false)
-        ++n_st;
-    if (n_st > g.rows) n_st = g.rows;
+    // Strips of at most own_max own rows over the frame's rows counted across
+    // tiles (global row t * H + r): a strip may cross a tile edge, which
+    // evens out strips when H is not a multiple of own_max (CSPAD: 198 strips
+    // of 29-30 rows rather than 224 of 26-27); the halo row on each side is
+    // loaded only when it lies in the same tile.  With tiles shorter than a
+    // strip each tile is cut on its own, so a strip holds at most one edge.
+    const int64_t TH = (int64_t)g.n_tiles * g.rows;
+    std::vector<std::pair<int, int>> own;  // [g0, g1)
+    if (g.rows >= own_max) {
+        const int64_t n_st = (TH + own_max - 1) / own_max;
+        for (int64_t j = 0; j < n_st; ++j) own.emplace_back((int)(TH * j / n_st), (int)(TH * (j + 1) / n_st));
+    } else {
+        for (int t = 0; t < g.n_tiles; ++t) own.emplace_back(t * g.rows, (t + 1) * g.rows);
+    }
     std::vector<V2Strip> strips;
     int rmax = 0, own_rows_max = 0;
-    for (int t = 0; t < g.n_tiles; ++t)
-        for (int j = 0; j < n_st; ++j) {
-            int r0 = (int)((int64_t)g.rows * j / n_st), r1 = (int)((int64_t)g.rows * (j + 1) / n_st);
-            if (r1 <= r0) continue;
-            strips.push_back(V2Strip{t, r0, r1, 0});
-            int lr0 = std::max(r0 - 1, 0), lr1 = std::min(r1 + 1, g.rows);
-            rmax = std::max(rmax, lr1 - lr0);
-            own_rows_max = std::max(own_rows_max, r1 - r0);
-        }
+    for (const auto &o : own) {
+        const int g0 = o.first, g1 = o.second;
+        if (g1 <= g0) continue;
+        const int t0 = g0 / g.rows, t1 = (g1 - 1) / g.rows;
+        if (t1 > t0 + 1) return false;
+        V2Strip S{};
+        S.g0 = g0;
+        S.g1 = g1;
+        S.lg0 = g0 % g.rows ? g0 - 1 : g0;
+        S.lg1 = g1 % g.rows ? g1 + 1 : g1;
+        S.gb = t1 > t0 ? t1 * g.rows : INT32_MAX;
+        strips.push_back(S);
+        rmax = std::max(rmax, S.lg1 - S.lg0);
+        own_rows_max = std::max(own_rows_max, g1 - g0);
+    }
     if (rmax * nb > max_bank_rows) return false;
     d.n_strips = (int)strips.size();
     d.rmax = rmax;
-    d.v2_max_unit_hits = (uint32_t)((own_rows_max + 1) / 2) * (uint32_t)((g.cols + 1) / 2);
+    // local maxima of a strip's own rows: at most every other row and column
+    // of each tile part (two parts when the strip crosses a tile edge)
+    d.v2_max_unit_hits = (uint32_t)((own_rows_max + 3) / 2) * (uint32_t)((g.cols + 1) / 2);
     // seed lists: as large as the workgroup's LDS allows (the kernel's
     // registers admit one workgroup per compute unit anyway), at least 1024
     // entries; 256 bytes stay free for the kernel's static LDS

@@ -290,6 +290,41 @@ def test_flood_frame_falls_back_exactly(ctx):
                 corrected=True)
 
 
+def test_strips_across_tile_edges(ctx):
+    """Two 40-row tiles are cut into strips of 26-27 rows, so one strip holds
+    rows of both tiles: photons on either side of the edge, in the same and
+    adjacent columns, are not neighbours (each tile's pixel is its own hit),
+    and a flood frame makes that strip overflow its seed list, so the general
+    kernel redoes it, edge included.  Every result matches the oracle."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(2, 40, 388, 194)
+    ped, gain = synth.make_calibration(geom, 51)
+    raw = synth.make_frames(geom, ped, gain, 4, 0.01, 51)
+    for c in range(3, 380, 9):  # tile 0's last row against tile 1's first row
+        raw[:2, 0, 39, c] = np.minimum(raw[:2, 0, 39, c].astype(np.int32) + 900, 0x3FFF)
+        raw[:2, 1, 0, c + (c % 2)] = np.minimum(raw[:2, 1, 0, c + (c % 2)].astype(np.int32) + 1500, 0x3FFF)
+    raw = np.concatenate([raw, synth.make_frames(geom, ped, gain, 1, 0.45, 52)])
+    want = oracle_threads(raw, ped, gain, 194, keep_corrected=True)
+    h = want["hits"]
+    edge = h[(h["frame"] < 2) & (((h["pixel"] // 388) == 39) | ((h["pixel"] // 388) == 40))]
+    assert len(edge) >= 80  # both sides of the edge hold hits in the same columns
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, 194), ped, gain, pdc.params(flags=pdc.KEEP_CORRECTED))
+    try:
+        b = pdc.process_frames(ctx, det, torch.from_numpy(raw).cuda(), raw.shape[0], 1 << 16)
+        hits, total, fh, fp, _ = pdc.get_hits(ctx, b, raw.shape[0])
+        corr = np.empty(raw.shape, np.float32)
+        pdc.get_corrected(ctx, b, corr)
+        assert pdc.debug_batch_path(ctx, b) == 3
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
+    assert_same(dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp, corrected=corr), want,
+                corrected=True)
+
+
 def test_median_with_outliers_and_plateaus(ctx):
     """Banks whose median sits on a long run of equal values, banks with far
     outliers on one side, and banks of identical values."""
