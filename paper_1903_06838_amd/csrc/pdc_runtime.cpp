@@ -623,8 +623,8 @@ pdc_status enqueue_partial(pdc_ctx *ctx, Batch &bt, uint64_t n_list)
 // contiguous range of frames, one workgroup per compute unit at a time, and
 // spends two extra pipeline iterations draining.  The count minimises
 // rounds x (frames per group + 2), the iterations a compute unit runs: large
-// batches get enough groups to fill whole rounds of the chip (CSPAD's 224
-// strips alone would leave 32 of 256 units idle), small ones stay in one round.
+// batches get enough groups to fill whole rounds of the chip (CSPAD's 198
+// strips alone would leave 58 of 256 units idle), small ones stay in one round.
 int frame_groups(int n_cu, int n_strips, uint64_t n_frames, int mult)
 {
     const int max_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(64, n_frames));
