@@ -68,8 +68,14 @@ CASES = [
 
 @pytest.mark.parametrize("geom,occ,n,region,stages", CASES, ids=lambda x: str(x))
 def test_cm_mean_parity(ctx, geom, occ, n, region, stages):
+    # a tile's mean cannot follow per-bank offsets: with the default 10 ADU
+    # offsets about a third of the pixels become seeds and the busiest strips
+    # overflow their lists (that case has its own test below), so the tile
+    # cases that check for the persistent kernel keep the offsets small
+    small = region == M.TILE and geom.bank_cols in (194, 96)
+    sim = synth.SimParams(cm_sigma=1.0) if small else synth.SimParams()
     ped, gain = synth.make_calibration(geom, 21)
-    raw = synth.make_frames(geom, ped, gain, n, occ, 21)
+    raw = synth.make_frames(geom, ped, gain, n, occ, 21, sim=sim)
     want = M.process(raw, ped, gain, geom.bank_cols, region, stages, keep_corrected=True)
     got = _run(ctx, raw, ped, gain, geom.bank_cols, region, stages)
     assert want["total"] > 0

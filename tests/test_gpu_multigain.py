@@ -68,10 +68,10 @@ CASES = [
 # The thresholded mean is pulled far down by the noisy low-gain pixels, so
 # the mean-mode cases use fewer of them: with 20 % of pixels in the lower
 # ranges their seeds overflow the persistent kernel's on-chip lists and the
-# batch is recomputed on the general kernel (still bit-exact).  With 2 % the
-# oracle's busiest 27-row strip of the bank-mean case holds about 2,800 seeds,
-# well inside the list (about 4,000 for that strip height).
-FEW_LOW_GAIN = dict(range_frac=(0.97, 0.015, 0.005), invalid_frac=0.01)
+# batch is recomputed on the general kernel (still bit-exact).  With 1.1 % the
+# oracle's busiest 27-row strip of the bank-mean case holds about 2,200 seeds,
+# inside the list (about 2,700 for that strip height).
+FEW_LOW_GAIN = dict(range_frac=(0.985, 0.008, 0.003), invalid_frac=0.01)
 
 
 @pytest.mark.parametrize("geom,gm,cm,stages,occ,n,path", CASES, ids=lambda x: str(x))
