@@ -562,8 +562,8 @@ def main():
         ingest_pmc(*args.ingest_pmc)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (--gpus 1); frames shard across GPUs "
-              "with no exchange, but multi-GPU runs are not part of it", file=sys.stderr)
+        print("bench.py: the benchmark runs on one GPU only (--gpus 1); frames shard across GPUs "
+              "with no exchange between them, and no multi-GPU run is implemented", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
