@@ -262,7 +262,8 @@ pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float 
  * pdc_release_detector frees only after pdc_graph_destroy).  The captured
  * nodes are kernels only (no memset or copy nodes).
  * pdc_graph_launch enqueues the graph on hip_stream (NULL: the context's
- * stream) and returns a batch id in *batch_out that the batch calls
+ * stream) and returns a batch id in *batch_out (one per item for a mixed
+ * graph, below) that the batch calls
  * (pdc_get_hits, pdc_get_corrected, summaries, pdc_release_batch, ...) take
  * as for pdc_process_frames.  The frames are read from frames_dev when the
  * graph runs: write the next frames there, ordered before the launch on
@@ -279,6 +280,17 @@ pdc_status pdc_graph_create(pdc_ctx *ctx, int32_t det, const uint16_t *frames_de
                             uint64_t hit_capacity, pdc_graph **out);
 pdc_status pdc_graph_launch(pdc_graph *graph, void *hip_stream, uint64_t *batch_out);
 pdc_status pdc_graph_destroy(pdc_graph *graph);
+
+/* One graph over batches of several detectors (mixed geometries, gain modes
+ * and common-mode settings), captured as pdc_process_mixed enqueues them:
+ * item i's kernels run on one of up to 8 internal streams forked inside the
+ * graph and joined back, so one pdc_graph_launch replays all of them and
+ * returns n_items batch ids in batch_out[0..n_items) (item order).  Each
+ * item's frames_dev is read at replay time as for pdc_graph_create.  All of
+ * the graph's batches must be released before the next launch.  1 <= n_items
+ * <= 64; pdc_graph_items returns a graph's item count (0 for NULL). */
+pdc_status pdc_graph_create_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, pdc_graph **out);
+int32_t pdc_graph_items(const pdc_graph *graph);
 
 /* ------------------------------------------------------------------------
  * Subpixel position of hits (Photon Subpixel Resolution section and its

@@ -105,6 +105,7 @@ struct Batch {
     int fb = 0;            // 1: overflowing units recomputed by the general kernel, 2: whole batch
     bool capture = false;  // being captured into a graph: kernels only, no events or copies
     pdc_graph *graph = nullptr;  // launched from this graph, whose buffers it holds
+    int gitem = 0;               // its item in that graph
     Buffers *buf = nullptr;
 };
 
@@ -159,15 +160,22 @@ struct pdc_ctx {
     std::set<pdc_graph *> graphs;
 };
 
-// A captured batch: the kernels of one batch of fixed size over a fixed frame
-// buffer, replayed by pdc_graph_launch into buffers the graph owns.
+// Captured batches: the kernels of one or more batches (items) of fixed size
+// over fixed frame buffers, replayed by pdc_graph_launch into buffers the
+// graph owns.
 struct pdc_graph {
     pdc_ctx *ctx = nullptr;
-    Batch proto;                 // shape of the captured batch (path, groups, capacity, ...)
-    Buffers *buf = nullptr;      // the buffers its kernels read and write
+    std::vector<Batch> proto;      // shape of each captured batch (path, groups, capacity, ...)
+    std::vector<Buffers *> buf;    // the buffers each item's kernels read and write
+    std::vector<uint64_t> batch;   // outstanding batch of each item, 0 if none
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    uint64_t batch = 0;          // outstanding batch launched from it, 0 if none
+    bool busy() const
+    {
+        for (uint64_t b : batch)
+            if (b) return true;
+        return false;
+    }
 };
 
 namespace {
@@ -697,7 +705,7 @@ pdc_status detach_from_graph(pdc_ctx *ctx, Batch &bt)
         ctx->spare.push_back(b);
         return rc;
     }
-    bt.graph->batch = 0;
+    bt.graph->batch[bt.gitem] = 0;
     bt.graph = nullptr;
     bt.buf = b;
     return PDC_OK;
@@ -839,7 +847,7 @@ pdc_status pdc_destroy(pdc_ctx *ctx)
     for (pdc_graph *g : ctx->graphs) {
         hipGraphExecDestroy(g->exec);
         hipGraphDestroy(g->graph);
-        free_buffers(g->buf);
+        for (Buffers *b : g->buf) free_buffers(b);
         delete g;
     }
     if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
@@ -1108,7 +1116,7 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch)
     bt->buf->used = false;
     int32_t det = bt->det;
     if (bt->graph)
-        bt->graph->batch = 0;  // the buffers stay with the graph
+        bt->graph->batch[bt->gitem] = 0;  // the buffers stay with the graph
     else
         ctx->spare.push_back(bt->buf);
     ctx->batches.erase(batch);
@@ -1136,47 +1144,101 @@ pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float 
 // graph capture of a batch
 // ---------------------------------------------------------------------------
 
-pdc_status pdc_graph_create(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
-                            uint64_t hit_capacity, pdc_graph **out)
+// Capture items[0..n) into one graph: one item on the capture stream itself,
+// several on the mixed-batch streams forked from it and joined back.
+static pdc_status graph_capture(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, pdc_graph **out)
 {
-    if (!ctx || !out) return fail(ctx, PDC_EINVAL, "ctx and out must be non-NULL");
+    if (!ctx || !out || !items || n_items < 1 || n_items > 64)
+        return fail(ctx, PDC_EINVAL, "ctx, items and out must be non-NULL, 1 <= n_items <= 64");
     *out = nullptr;
-    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
-        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
-    if (!frames_dev || n_frames < 1 || n_frames > ((uint64_t)1 << 31))
-        return fail(ctx, PDC_EINVAL, "frames_dev must be non-NULL and 1 <= n_frames <= 2^31");
-    Detector &d = ctx->dets[det];
+    for (int i = 0; i < n_items; ++i) {
+        const int32_t det = items[i].det;
+        if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+            return fail(ctx, PDC_ESTATE, "item %d: unknown detector %d", i, det);
+        if (!items[i].frames_dev || items[i].n_frames < 1 || items[i].n_frames > ((uint64_t)1 << 31))
+            return fail(ctx, PDC_EINVAL, "item %d: frames_dev must be non-NULL and 1 <= n_frames <= 2^31", i);
+    }
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (!ctx->capture_stream) HIP_TRY(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    const int n_str = n_items > 1 ? std::min(n_items, 8) : 0;
+    while ((int)ctx->mix_streams.size() < n_str) {
+        hipStream_t st = nullptr;
+        HIP_TRY(ctx, hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        ctx->mix_streams.push_back(st);
+    }
+    while ((int)ctx->mix_events.size() < n_str + 1) {
+        hipEvent_t ev = nullptr;
+        HIP_TRY(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        ctx->mix_events.push_back(ev);
+    }
     std::unique_ptr<pdc_graph> g(new (std::nothrow) pdc_graph);
     if (!g) return fail(ctx, PDC_ENOMEM, "host allocation failed");
     g->ctx = ctx;
-    Batch &bt = g->proto;
-    bt.det = det;
-    bt.frames = frames_dev;
-    bt.n_frames = n_frames;
-    set_path(d, bt, d.v2_ok ? 2 : 1);
-    bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
-    bt.pool_cap = ctx->tight_pool ? hit_capacity : pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
-    g->buf = new (std::nothrow) Buffers;
-    if (!g->buf) return fail(ctx, PDC_ENOMEM, "host allocation failed");
-    pdc_status rc = ensure_buffers(ctx, g->buf, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt));
-    if (rc != PDC_OK) {
-        free_buffers(g->buf);
-        return rc;
+    g->proto.resize(n_items);
+    g->buf.assign(n_items, nullptr);
+    g->batch.assign(n_items, 0);
+    auto drop = [&]() {
+        for (Buffers *b : g->buf) free_buffers(b);
+    };
+    double work = 0.0;
+    for (int i = 0; i < n_items; ++i) {
+        const pdc_geometry &gg = ctx->dets[items[i].det].g;
+        work += (double)items[i].n_frames * gg.n_tiles * gg.rows * gg.cols;
     }
-    bt.buf = g->buf;
-    bt.stream = ctx->capture_stream;
-    bt.capture = true;
+    for (int i = 0; i < n_items; ++i) {
+        const Detector &d = ctx->dets[items[i].det];
+        Batch &bt = g->proto[i];
+        bt.det = items[i].det;
+        bt.gitem = i;
+        bt.frames = items[i].frames_dev;
+        bt.n_frames = items[i].n_frames;
+        const double px = (double)items[i].n_frames * d.g.n_tiles * d.g.rows * d.g.cols;
+        bt.share = n_items > 1 && ctx->mix_share && work > 0.0 ? std::min(1.0, px / work) : 1.0;
+        set_path(d, bt, d.v2_ok ? 2 : 1);
+        bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+        const uint64_t hc = items[i].hit_capacity;
+        bt.pool_cap = ctx->tight_pool ? hc : pool_capacity(d, bt.path, hc, batch_grid(d, bt));
+        g->buf[i] = new (std::nothrow) Buffers;
+        if (!g->buf[i]) {
+            drop();
+            return fail(ctx, PDC_ENOMEM, "host allocation failed");
+        }
+        pdc_status rc = ensure_buffers(ctx, g->buf[i], bt.n_units, bt.n_frames, bt.pool_cap, corr_floats(d, bt),
+                                       cm_floats(d, bt));
+        if (rc != PDC_OK) {
+            drop();
+            return rc;
+        }
+        bt.buf = g->buf[i];
+        bt.capture = true;
+        bt.stream = n_str ? ctx->mix_streams[i % n_str] : ctx->capture_stream;
+    }
+    hipStream_t cs = ctx->capture_stream;
     // relaxed: the launch helpers may set kernel attributes while capturing
-    hipError_t e = hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeRelaxed);
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed);
     if (e != hipSuccess) {
-        free_buffers(g->buf);
+        drop();
         return fail(ctx, PDC_EDEVICE, "hipStreamBeginCapture: %s", hipGetErrorString(e));
     }
-    rc = enqueue(ctx, bt);
+    pdc_status rc = PDC_OK;
+    // the forked streams join the capture by waiting for an event recorded in
+    // it, and are joined back (also after a failed enqueue, so that no stream
+    // is left capturing)
+    int forked = 0;
+    if (n_str) {
+        e = hipEventRecord(ctx->mix_events[0], cs);
+        for (; e == hipSuccess && forked < n_str; ++forked)
+            e = hipStreamWaitEvent(ctx->mix_streams[forked], ctx->mix_events[0], 0);
+        if (e != hipSuccess) rc = fail(ctx, PDC_EDEVICE, "graph fork: %s", hipGetErrorString(e));
+    }
+    for (int i = 0; rc == PDC_OK && i < n_items; ++i) rc = enqueue(ctx, g->proto[i]);
+    for (int j = 0; j < forked; ++j) {
+        e = hipEventRecord(ctx->mix_events[1 + j], ctx->mix_streams[j]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->mix_events[1 + j], 0);
+        if (e != hipSuccess && rc == PDC_OK) rc = fail(ctx, PDC_EDEVICE, "graph join: %s", hipGetErrorString(e));
+    }
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    e = hipStreamEndCapture(cs, &graph);
     if (rc == PDC_OK && e != hipSuccess) rc = fail(ctx, PDC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
     if (rc == PDC_OK) {
         e = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
@@ -1184,44 +1246,69 @@ pdc_status pdc_graph_create(pdc_ctx *ctx, int32_t det, const uint16_t *frames_de
     }
     if (rc != PDC_OK) {
         if (graph) hipGraphDestroy(graph);
-        free_buffers(g->buf);
+        drop();
         return rc;
     }
     g->graph = graph;
-    bt.capture = false;
-    bt.stream = nullptr;
-    d.pending += 1;  // the graph holds the detector's planes
+    for (Batch &bt : g->proto) {
+        bt.capture = false;
+        bt.stream = nullptr;
+        ctx->dets[bt.det].pending += 1;  // the graph holds the detector's planes
+    }
     ctx->graphs.insert(g.get());
     *out = g.release();
     return PDC_OK;
+}
+
+pdc_status pdc_graph_create(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                            uint64_t hit_capacity, pdc_graph **out)
+{
+    const pdc_mixed_item item{det, frames_dev, n_frames, hit_capacity};
+    return graph_capture(ctx, &item, 1, out);
+}
+
+pdc_status pdc_graph_create_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, pdc_graph **out)
+{
+    return graph_capture(ctx, items, n_items, out);
+}
+
+int32_t pdc_graph_items(const pdc_graph *g)
+{
+    return g ? (int32_t)g->proto.size() : 0;
 }
 
 pdc_status pdc_graph_launch(pdc_graph *g, void *hip_stream, uint64_t *batch_out)
 {
     if (!g || !batch_out) return fail(g ? g->ctx : nullptr, PDC_EINVAL, "graph and batch_out must be non-NULL");
     pdc_ctx *ctx = g->ctx;
-    if (g->batch) return fail(ctx, PDC_ESTATE, "batch %llu of this graph is not released", (unsigned long long)g->batch);
-    if ((int)ctx->batches.size() >= kMaxOutstandingBatches)
+    if (g->busy()) return fail(ctx, PDC_ESTATE, "a batch of this graph is not released");
+    const int n = (int)g->proto.size();
+    if ((int)ctx->batches.size() + n > kMaxOutstandingBatches)
         return fail(ctx, PDC_ESTATE, "too many outstanding batches (release some)");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    Batch bt = g->proto;
-    bt.id = ctx->next_batch;
-    bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    bt.buf = g->buf;
-    bt.graph = g;
-    Buffers *b = g->buf;
-    // the graph holds kernels only: events and the state copy go around it
-    HIP_TRY(ctx, hipEventRecord(b->ev_start, bt.stream));
-    HIP_TRY(ctx, hipEventRecord(b->ev_cm, bt.stream));
-    HIP_TRY(ctx, hipGraphLaunch(g->exec, bt.stream));
-    HIP_TRY(ctx, hipEventRecord(b->ev_main, bt.stream));
-    pdc_status rc = record_end(ctx, b, bt.stream);
-    if (rc != PDC_OK) return rc;
-    ++ctx->next_batch;
-    ctx->dets[bt.det].pending += 1;
-    ctx->batches[bt.id] = bt;
-    g->batch = bt.id;
-    *batch_out = bt.id;
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    // the graph holds kernels only: events and the state copies go around it
+    for (int i = 0; i < n; ++i) {
+        HIP_TRY(ctx, hipEventRecord(g->buf[i]->ev_start, s));
+        HIP_TRY(ctx, hipEventRecord(g->buf[i]->ev_cm, s));
+    }
+    HIP_TRY(ctx, hipGraphLaunch(g->exec, s));
+    for (int i = 0; i < n; ++i) {
+        HIP_TRY(ctx, hipEventRecord(g->buf[i]->ev_main, s));
+        pdc_status rc = record_end(ctx, g->buf[i], s);
+        if (rc != PDC_OK) return rc;
+    }
+    for (int i = 0; i < n; ++i) {
+        Batch bt = g->proto[i];
+        bt.id = ctx->next_batch++;
+        bt.stream = s;
+        bt.buf = g->buf[i];
+        bt.graph = g;
+        ctx->dets[bt.det].pending += 1;
+        ctx->batches[bt.id] = bt;
+        g->batch[i] = bt.id;
+        batch_out[i] = bt.id;
+    }
     return PDC_OK;
 }
 
@@ -1229,17 +1316,20 @@ pdc_status pdc_graph_destroy(pdc_graph *g)
 {
     if (!g) return PDC_OK;
     pdc_ctx *ctx = g->ctx;
-    if (g->batch) return fail(ctx, PDC_ESTATE, "batch %llu of this graph is not released", (unsigned long long)g->batch);
+    if (g->busy()) return fail(ctx, PDC_ESTATE, "a batch of this graph is not released");
     // released batches have finished with the buffers (pdc_release_batch waits)
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipGraphExecDestroy(g->exec);
     hipGraphDestroy(g->graph);
-    free_buffers(g->buf);
+    for (Buffers *b : g->buf) free_buffers(b);
     ctx->graphs.erase(g);
-    const int32_t det = g->proto.det;
+    std::vector<int32_t> dets;
+    for (const Batch &bt : g->proto) dets.push_back(bt.det);
     delete g;
-    ctx->dets[det].pending -= 1;
-    maybe_free_detector(ctx, det);
+    for (int32_t det : dets) {
+        ctx->dets[det].pending -= 1;
+        maybe_free_detector(ctx, det);
+    }
     return PDC_OK;
 }
 

@@ -102,6 +102,8 @@ _sig = {
     "pdc_graph_create": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(_P)]),
     "pdc_graph_launch": (_st, [_P, _P, ctypes.POINTER(ctypes.c_uint64)]),
     "pdc_graph_destroy": (_st, [_P]),
+    "pdc_graph_create_mixed": (_st, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "pdc_graph_items": (ctypes.c_int32, [_P]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -275,11 +277,22 @@ def graph_create(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int):
     return g.value
 
 
-def graph_launch(ctx, graph, stream=None) -> int:
-    """Replay the graph on stream (torch stream, raw handle or None); returns a batch id."""
-    b = ctypes.c_uint64(0)
-    _check(_lib.pdc_graph_launch(graph, _stream(stream), ctypes.byref(b)), ctx)
-    return b.value
+def graph_create_mixed(ctx, items):
+    """One graph over several detectors' batches; items: (det, frames_dev,
+    n_frames, hit_capacity) tuples as for process_mixed."""
+    arr = (MixedItem * len(items))(*[MixedItem(d, _ptr(f), n, c) for d, f, n, c in items])
+    g = _P()
+    _check(_lib.pdc_graph_create_mixed(ctx, arr, len(items), ctypes.byref(g)), ctx)
+    return g.value
+
+
+def graph_launch(ctx, graph, stream=None):
+    """Replay the graph on stream (torch stream, raw handle or None); returns a
+    batch id, or the list of batch ids (item order) of a mixed graph."""
+    n = _lib.pdc_graph_items(graph)
+    out = (ctypes.c_uint64 * max(n, 1))()
+    _check(_lib.pdc_graph_launch(graph, _stream(stream), out), ctx)
+    return out[0] if n == 1 else list(out)
 
 
 def graph_destroy(ctx, graph) -> None:

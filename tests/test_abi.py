@@ -128,6 +128,8 @@ def test_null_context_paths(pdc):
     assert lib.pdc_graph_create(None, 0, None, 1, 0, None) == pdc.EINVAL
     assert lib.pdc_graph_launch(None, None, ctypes.byref(b)) == pdc.EINVAL
     assert lib.pdc_graph_destroy(None) == pdc.OK
+    assert lib.pdc_graph_create_mixed(None, None, 1, None) == pdc.EINVAL
+    assert lib.pdc_graph_items(None) == 0
 
 
 def test_create_without_gpu_is_edevice(pdc):

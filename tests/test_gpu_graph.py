@@ -231,3 +231,66 @@ def test_graph_common_mode_and_multigain(ctx, gm, cm, stages):
         if graph is not None:
             pdc.graph_destroy(ctx, graph)
         pdc.release_detector(ctx, det)
+
+
+def test_mixed_graph_replays_equal_oracle(ctx):
+    """One graph over three detectors (ePix100-like rows with the median,
+    CSPAD-like with the 2-stage bank mean, Jungfrau-like with three gain
+    ranges): each of three replays, with new frames written into the captured
+    buffers and eager work in between, equals the oracles for every detector;
+    the graph takes no launch while one of its batches is outstanding."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    n = 3
+    specs = []
+    g = synth.Geometry(1, 64, 768, 96)
+    ped, gain = synth.make_calibration(g, 81)
+    sets = [synth.make_frames(g, ped, gain, n, 0.01, sd) for sd in (81, 82)]
+    specs.append((g, 0, 0, 1, ped, gain, sets, [oracle_threads(r, ped, gain, 96, keep_corrected=True) for r in sets]))
+    g = synth.Geometry(2, 40, 388, 194)
+    ped, gain = synth.make_calibration(g, 83)
+    sets = [synth.make_frames(g, ped, gain, n, 0.02, sd) for sd in (83, 84)]
+    specs.append((g, 0, 1, 2, ped, gain, sets, [M.process(r, ped, gain, 194, M.BANK, 2, keep_corrected=True)
+                                                for r in sets]))
+    g = synth.Geometry(1, 48, 1024, 256)
+    ped, gain = synth.make_calibration_multigain(g, 85)
+    sets = [synth.make_frames_multigain(g, ped, gain, n, 0.01, sd, 2, **FEW_LOW_GAIN) for sd in (85, 86)]
+    specs.append((g, 2, 0, 1, ped, gain, sets, [G.process(r, ped, gain, 256, 2, keep_corrected=True) for r in sets]))
+
+    dets, graph = [], None
+    try:
+        for g, gm, cm, st, ped, gain, _, _ in specs:
+            prm = pdc.params(flags=pdc.KEEP_CORRECTED, cm_mode=cm, cm_stages=st)
+            dets.append(pdc.calibrate(ctx, pdc.geometry(*g.shape, g.bank_cols, gm), ped, gain, prm))
+        devs = [[torch.from_numpy(r).cuda() for r in sp[6]] for sp in specs]
+        bufs = [torch.empty_like(dv[0]) for dv in devs]
+        torch.cuda.synchronize()
+        graph = pdc.graph_create_mixed(ctx, [(d, b, n, 1 << 18) for d, b in zip(dets, bufs)])
+        s = torch.cuda.Stream()
+        other = devs[0][1]
+        for k in (0, 1, 0):
+            with torch.cuda.stream(s):
+                for b, dv in zip(bufs, devs):
+                    b.copy_(dv[k])
+            batches = pdc.graph_launch(ctx, graph, s)
+            assert len(batches) == len(specs)
+            with pytest.raises(pdc.PdcError) as e:
+                pdc.graph_launch(ctx, graph, s)
+            assert e.value.status == pdc.ESTATE
+            for b, sp in zip(batches, specs):
+                got = _results(ctx, b, n, shape=sp[6][k].shape, invalid=bool(sp[1]))
+                pdc.release_batch(ctx, b)
+                _same(got, sp[7][k])
+            # the program's own eager work between replays
+            eb = pdc.process_frames(ctx, dets[0], other, n, 1 << 16)
+            pdc.get_hits(ctx, eb, n, capacity=0)
+            pdc.release_batch(ctx, eb)
+            (other.float() + 1).sum().item()
+            torch.cuda.synchronize()
+    finally:
+        if graph is not None:
+            pdc.graph_destroy(ctx, graph)
+        for d in dets:
+            pdc.release_detector(ctx, d)
