@@ -1,7 +1,7 @@
 // Persistent frame kernel for gfx950.
 //
-// One workgroup (16 waves) owns a strip of rows of one tile for a range of
-// frames.  The strip's dark and 1/gain planes are loaded once into registers
+// One workgroup (16 waves) owns a strip of rows (which may cross one tile
+// edge) for a range of frames.  The strip's dark and 1/gain planes are loaded once into registers
 // and stay there for every frame; only the 2-byte raw words stream from HBM.
 // Per frame:
 //   phase 1a (each wave, its own bank-rows): load raw words (prefetched one
@@ -10,7 +10,7 @@
 //     bracketing count search with L lanes per bank-row (common mode, Fig. c);
 //     the same lanes then test their values against the seed threshold the
 //     median implies and append the seed pixels to a workgroup list;
-//   phase 1c (each wave, its own bank-rows): Frames2 if kept;
+//   phase 1c (each wave, its own bank-rows): Frames2 if kept, one frame later;
 //   phase 2 (all waves, over the pooled seeds): 3x3 local maximum with the
 //     raster tie-break, masked 3x3 charge sum, photon count (Fig. e and the
 //     charge summing section); hits mark a per-bank-row column bitmap;
@@ -316,11 +316,12 @@ __device__ __forceinline__ float seed_threshold(float m, float t)
 }
 
 struct V2Layout {
-    uint32_t u, med, th, bits, cnt, seed, q, nseed, pref, gs, total;  // float offsets
+    uint32_t u, med, th, bits, cnt, seed, hl, nseed, hcnt, pref, gs, total;  // float offsets
 };
 
-// LDS of one workgroup (floats): u and med are double-buffered by frame
-// parity, bits/cnt/seed/q likewise; the seed counts are kept for three frames
+// LDS of one workgroup (floats): u, med, bits, cnt, the seed lists and the
+// hit lists (key and charge of each local maximum, half a seed list long)
+// are double-buffered by frame parity, the seed counts kept for three frames
 // (frame f mod 3); th and pref are single.
 __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
 {
@@ -338,10 +339,13 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
     o += 2u * rmax * nb;
     L.seed = o;
     o += 2u * seed_cap;
-    L.q = o;
-    o += 2u * seed_cap;
+    o = (o + 1u) & ~1u;  // 8-byte hit entries
+    L.hl = o;
+    o += 2u * 2u * (uint32_t)(seed_cap / 2);
     L.nseed = o;
     o += 3;
+    L.hcnt = o;
+    o += 2;
     L.pref = o;
     o += (uint32_t)rmax * nb + 1;
     L.gs = o;
@@ -353,7 +357,7 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
     size_t o = 2ull * rmax * W + 2ull * rmax * nb + (size_t)rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
-               4ull * seed_cap + 3 + (size_t)rmax * nb + 1 + 1024;
+               4ull * seed_cap + 1 + 3 + 2 + (size_t)rmax * nb + 1 + 1024;
     return o * 4;
 }
 
@@ -378,11 +382,13 @@ __device__ __forceinline__ uint32_t seed_key(int row, int bank, int col)
 template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG>
 __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 {
-    extern __shared__ float lds[];
+    extern __shared__ __align__(16) float lds[];
     __shared__ unsigned long long s_photons;
     __shared__ uint64_t s_base;
-    __shared__ uint32_t s_p2ctr;
+    __shared__ uint64_t s_chunk[2];  // staging chunk in use: next free entry, end
+    __shared__ uint32_t s_p2ctr, s_p4ctr;
     uint32_t *s_p2next = &s_p2ctr;  // next phase-2 seed chunk
+    uint32_t *s_p4next = &s_p4ctr;  // next phase-4 hit chunk
 
     constexpr int NV = 2 * NQ;
     const int tid = threadIdx.x;
@@ -390,13 +396,14 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int W = A.W, B = A.B, nb = A.nb, H = A.H;
     const V2Layout Ly = v2_layout(A.rmax, W, nb, A.seed_cap);
-    const int RW = A.rmax * W, RN = A.rmax * nb, cap = A.seed_cap;
+    const int RW = A.rmax * W, RN = A.rmax * nb, cap = A.seed_cap, hcap = A.seed_cap / 2;
     float *s_u = lds + Ly.u;
     float *s_med = lds + Ly.med;
     uint32_t *s_bits = reinterpret_cast<uint32_t *>(lds + Ly.bits);
     uint32_t *s_cnt = reinterpret_cast<uint32_t *>(lds + Ly.cnt);
     uint32_t *s_seed = reinterpret_cast<uint32_t *>(lds + Ly.seed);
-    float *s_q = lds + Ly.q;
+    uint2 *s_hl = reinterpret_cast<uint2 *>(lds + Ly.hl);
+    uint32_t *s_hcnt = reinterpret_cast<uint32_t *>(lds + Ly.hcnt);
     uint32_t *s_nseed = reinterpret_cast<uint32_t *>(lds + Ly.nseed);
     uint32_t *s_pref = reinterpret_cast<uint32_t *>(lds + Ly.pref);
     float *s_gs = lds + Ly.gs;  // one slot per thread: median finish scratch
@@ -415,7 +422,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     const uint64_t f_end = (A.n_frames * (uint64_t)(fg + 1)) / A.n_fgroups;
     const int kmed = (B - 1) / 2;
     const uint32_t row_base = (uint32_t)lr0 * (uint32_t)W;  // pixel index of loaded row 0
-    constexpr int kP3Wave = kV2Waves - 1;  // wave that runs phase 3
+    constexpr int kP3Wave = 0;  // wave that runs phase 3 (the first to issue on its SIMD)
 
     // lane l of pair-slot q holds bank columns 128q + 2l and 128q + 2l + 1
     bool lane_ok[NQ];
@@ -458,10 +465,12 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     for (int x = tid; x < 2 * RN * 8; x += kV2Threads) s_bits[x] = 0;
     for (int x = tid; x < 2 * RN; x += kV2Threads) s_cnt[x] = 0;
     if (tid < 3) s_nseed[tid] = 0;
+    if (tid < 2) s_hcnt[tid] = 0;
     if (tid == 0) s_photons = 0;
     if (tid == 0) s_p2ctr = 0;
+    if (tid == 0) s_p4ctr = 0;
 
-    uint64_t chunk_cur = 0, chunk_end = 0;  // staging chunk, held by the phase-3 wave's lane 0
+    if (tid == 0) s_chunk[0] = s_chunk[1] = 0;
     uint32_t raw[GMAX][NQ];
     auto load_raw = [&](uint64_t f, const bool(&lok)[NQ]) {
         const uint32_t *fr = reinterpret_cast<const uint32_t *>(A.frames + f * npix + row_base);
@@ -478,11 +487,12 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 
     // Seeds of a bank-row held by an L-lane group in phase B (lane gl holds
     // columns L v + gl in xs, +inf where absent or invalid): u >= th, own rows
-    // only, appended to the pooled list of frame parity par (order is free;
-    // phase 4 restores raster order) with a DPP prefix of the lanes' counts
-    // and one LDS atomic per wave.  All lanes of the wave must call it.
+    // only, appended to the pooled list sbuf (frame parity; order is free,
+    // phase 4 restores raster order) counted in slot (frame mod 3), with a
+    // DPP prefix of the lanes' counts and one LDS atomic per wave.  All lanes
+    // of the wave must call it.
     const float th0 = seed_threshold(0.0f, A.t_seed);
-    auto append_seeds = [&](const float(&xs)[V], float th, bool own, int row, int bank, int gl, int par_, int slot) {
+    auto append_seeds = [&](const float(&xs)[V], float th, bool own, int row, int bank, int gl, int sbuf, int slot) {
         uint32_t sb = 0;
         if (own) {
 #pragma unroll
@@ -499,17 +509,21 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             while (sb) {
                 const int v = __ffs(sb) - 1;
                 sb &= sb - 1;
-                if (pos < (uint32_t)cap) s_seed[par_ * cap + pos] = seed_key(row, bank, bank * B + L * v + gl);
+                if (pos < (uint32_t)cap) s_seed[sbuf * cap + pos] = seed_key(row, bank, bank * B + L * v + gl);
                 ++pos;
             }
         }
     };
 
-    // Software pipeline, two frames deep: iteration f runs frame f's phases
-    // 1a (A), 1b with the seed list (B) and 1c (C), frame f-1's phase 2 in B
-    // (claimed in chunks by waves as they finish their median groups) and its
-    // phase 3 in C, and frame f-2's phase 4 in A.  Two more iterations drain
-    // it.  Frame f and frame f-2 share LDS parity par; frame f-1 has parity pp.
+    // Software pipeline, two barriers per frame: iteration f runs
+    //   A: frame f's phase 1a, frame f-1's Frames2, frame f-2's phase 3 (one
+    //      wave, beside the others' 1a);
+    //   B: frame f's phase 1b with the seed list, then, claimed in chunks by
+    //      waves as they finish their median groups, frame f-1's phase 2
+    //      (which lists its hits) and frame f-2's phase 4 (over that list).
+    // Two more iterations drain it.  u, medians, seed lists, hit lists, hit
+    // bitmaps and counts are double-buffered by frame parity (par for f and
+    // f-2, pp for f-1); the seed counts are kept for three frames (f mod 3).
     for (uint64_t f = f_begin; f < f_end + 2; ++f) {
         const bool cur_ok = f < f_end;
         const bool p1_ok = f >= f_begin + 1 && f - 1 < f_end;
@@ -518,7 +532,10 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         const int sc0 = (int)(f % 3), sc1 = (int)((f + 2) % 3), sc2 = (int)((f + 1) % 3);  // seed counts of f, f-1, f-2
         const uint32_t nseed_1 = p1_ok ? s_nseed[sc1] : 0u;  // frame f-1
         const uint32_t nseed_2 = p2_ok ? s_nseed[sc2] : 0u;  // frame f-2
-        const bool ovf_1 = nseed_1 > (uint32_t)cap, ovf_2 = nseed_2 > (uint32_t)cap;
+        const uint32_t nhit_2 = p2_ok ? s_hcnt[par] : 0u;    // frame f-2's listed hits
+        // a seed list or a hit list that was full: the general kernel redoes the unit
+        const bool ovf_1 = nseed_1 > (uint32_t)cap;
+        const bool ovf_2 = nseed_2 > (uint32_t)cap || nhit_2 > (uint32_t)hcap;
         float *u_c = s_u + par * RW;
         const float *u_p = s_u + pp * RW;
         float *med_c = s_med + par * RN;
@@ -534,7 +551,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             for (int q = 0; q < NQ; ++q) lok[q] = 128u * q + lo < (uint32_t)B;
         }
 
-        // ================= A: 1a(f) | 4(f-2) ======================================
+        // ================= A: 1a(f) | Frames2(f-1) | 3(f-2) =======================
         if (cur_ok) {
             uint32_t cur[GMAX][NQ];
 #pragma unroll
@@ -583,35 +600,88 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 if (lane == 0 && tot) atomicAdd(A.invalid + f, tot);
             }
         }
-        if (p2_ok && !ovf_2) {
-            const uint64_t base = s_base;
-            if (base != kNoBase) {
-                for (uint32_t j = tid; j < nseed_2; j += kV2Threads) {
-                    const float qv = s_q[par * cap + j];
-                    if (qv < 0.0f) continue;
-                    const uint32_t key = s_seed[par * cap + j];
-                    const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
-                    const int i = row * nb + bank;
-                    const int cb = col - bank * B;
-                    const uint32_t *bw = s_bits + (par * RN + i) * 8;
-                    uint32_t rank = 0;
-                    for (int w = 0; w < (cb >> 5); ++w) rank += __popc(bw[w]);
-                    rank += __popc(bw[cb >> 5] & ((1u << (cb & 31)) - 1u));
-                    const uint32_t pix = row_base + (uint32_t)row * W + col;
-                    A.pool[base + s_pref[i] + rank] = make_uint2(pix, __float_as_uint(qv));
+        // frame f-1's hit bitmaps and counts (parity pp) are rebuilt by its
+        // local maxima in B; their last reader, frame f-3, finished in B of f-1
+        if (p1_ok) {
+            for (int x = tid; x < RN * 8; x += kV2Threads) s_bits[pp * RN * 8 + x] = 0;
+            for (int x = tid; x < RN; x += kV2Threads) s_cnt[pp * RN + x] = 0;
+        }
+        if (tid == 0) {
+            s_nseed[sc0] = 0;  // frame f-3's count, last read before B of f-1
+            s_hcnt[pp] = 0;    // frame f-3's hits were written in B of f-1
+            *s_p2next = 0;
+            *s_p4next = 0;
+        }
+        if (KEEP && p1_ok) {
+            // Frames2 of frame f-1 (its u and medians, parity pp, are intact)
+#pragma unroll
+            for (int g = 0; g < GMAX; ++g) {
+                if (g >= ng) break;
+                const int i = wave + kV2Waves * g;
+                const int row = row_[g];
+                if (row >= own_lo && row < own_hi) {
+                    const float m = uniform_f(med_p[i]);
+#pragma unroll
+                    for (int q = 0; q < NQ; ++q)
+                        if (lok[q]) {
+                            const float2 u2 = *reinterpret_cast<const float2 *>(u_p + gb_[g] + 128 * q + lane_off);
+                            *reinterpret_cast<float2 *>(A.corrected + (f - 1) * npix + row_base + gb_[g] + 128 * q +
+                                                        lane_off) = make_float2(__fsub_rn(u2.x, m), __fsub_rn(u2.y, m));
+                        }
                 }
+            }
+        }
+        if (p2_ok && wave == kP3Wave) {
+            // bank-row prefix of frame f-2's hit counts (parity par), staging
+            // chunk claim; the wave that runs it issues first, so it also
+            // finishes its own phase 1a first
+            uint32_t total = 0;
+            if (!ovf_2) {
+                for (int b0 = 0; b0 < BR; b0 += 64) {
+                    const int i = b0 + lane;
+                    const uint32_t c = i < BR ? s_cnt[par * RN + i] : 0u;
+                    const uint32_t incl = wave_incl_scan(c);
+                    if (i < BR) s_pref[i] = total + incl - c;
+                    total += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+                }
+            }
+            if (lane == 0) {
+                // the chunk lives in LDS: in registers it would be spilled to
+                // scratch, whose reload waits for the frame prefetch
+                uint64_t chunk_cur = s_chunk[0], chunk_end = s_chunk[1];
+                const uint64_t unit = (f - 2) * (uint64_t)A.n_strips + strip;
+                uint64_t base = chunk_cur;
+                if (ovf_2) {
+                    // the seed list was full: the general kernel redoes this unit
+                    atomicOr(&A.state->fallback, 1u);
+                    if (A.fb_units) A.fb_units[atomicAdd(&A.state->n_fallback, 1ull)] = unit;
+                    base = kNoBase;
+                } else if (total > 0) {
+                    if (chunk_cur + total > chunk_end) {
+                        const uint64_t sz = total > kChunkHits ? (uint64_t)total : kChunkHits;
+                        chunk_cur = atomicAdd(&A.state->cursor, (unsigned long long)sz);
+                        chunk_end = chunk_cur + sz;
+                    }
+                    if (chunk_cur + total <= A.pool_cap) {
+                        base = chunk_cur;
+                        chunk_cur += total;
+                    } else {
+                        base = kNoBase;
+                        atomicOr(&A.state->overflow, 1u);
+                    }
+                }
+                A.unit_base[unit] = base;
+                A.unit_count[unit] = total;
+                A.unit_photons[unit] = s_photons;  // frame f-2's, summed in B of f-1
+                s_photons = 0;
+                s_base = base;
+                s_chunk[0] = chunk_cur;
+                s_chunk[1] = chunk_end;
             }
         }
         __syncthreads();  // A -> B
 
-        // ================= B: 1b(f) | 2(f-1) ======================================
-        if (cur_ok) {
-            // frame f-2's lists (parity par) are finished: clear them for frame f
-            for (int x = tid; x < RN * 8; x += kV2Threads) s_bits[par * RN * 8 + x] = 0;
-            for (int x = tid; x < RN; x += kV2Threads) s_cnt[par * RN + x] = 0;
-        }
-        // frame f-2's seed count was read before barrier A: its slot serves frame f+1
-        if (tid == 0) s_nseed[sc2] = 0;
+        // ================= B: 1b(f) | 2(f-1) | 4(f-2) =============================
         if (CMM && cur_ok && A.cm_mode == 1) {
             // thresholded mean of each bank-row (Fig. c), stacked stages: lane j
             // of the group holds partial sums j + L q (q < 64 / L) of the
@@ -746,8 +816,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 }
             }
             if (act && gl == 0) med_c[i] = m;
-            append_seeds(x, seed_threshold(m, A.t_seed), act && row >= own_lo && row < own_hi, row, bank, gl, par,
-                         sc0);
+            append_seeds(x, seed_threshold(m, A.t_seed), act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (p1_ok && !ovf_1) {
             // frame f-1's seeds in chunks of 64, claimed by whole waves as they
@@ -806,9 +875,8 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                             const float vq = nv[dr][dc];
                             if (ex[dr][dc] && !(vp > vq || (vp == vq && later))) is_max = false;
                         }
-                    float qsum = -1.0f;
                     if (is_max) {
-                        qsum = 0.0f;
+                        float qsum = 0.0f;
 #pragma unroll
                         for (int dr = 0; dr < 3; ++dr)
 #pragma unroll
@@ -818,76 +886,42 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                         atomicOr(&s_bits[(pp * RN + i) * 8 + (cb >> 5)], 1u << (cb & 31));
                         atomicAdd(&s_cnt[pp * RN + i], 1u);
                         my_ph += photon_count(qsum, A.photon_adu);
+                        // the hit list (any order; past its end the unit is redone)
+                        const uint32_t h = atomicAdd(&s_hcnt[pp], 1u);
+                        if (h < (uint32_t)hcap) s_hl[pp * hcap + h] = make_uint2(key, __float_as_uint(qsum));
                     }
-                    s_q[pp * cap + j] = qsum;
                 }
             }
             if (my_ph) atomicAdd(&s_photons, my_ph);
         }
-        __syncthreads();  // B -> C
-
-        // ================= C: Frames2(f) | 3(f-1) ================================
-        if (KEEP && cur_ok) {
-#pragma unroll
-            for (int g = 0; g < GMAX; ++g) {
-                if (g >= ng) break;
-                const int i = wave + kV2Waves * g;
-                const int row = row_[g];
-                if (row >= own_lo && row < own_hi) {
-                    const float m = uniform_f(med_c[i]);
-#pragma unroll
-                    for (int q = 0; q < NQ; ++q)
-                        if (lok[q]) {
-                            const float2 u2 = *reinterpret_cast<const float2 *>(u_c + gb_[g] + 128 * q + lane_off);
-                            *reinterpret_cast<float2 *>(A.corrected + f * npix + row_base + gb_[g] + 128 * q + lane_off) =
-                                make_float2(__fsub_rn(u2.x, m), __fsub_rn(u2.y, m));
-                        }
+        if (p2_ok && !ovf_2) {
+            // frame f-2's hits in raster position (bank-row prefix + hits left
+            // of the hit in its bank-row), claimed in chunks of 64 like phase 2
+            const uint64_t base = s_base;
+            if (base != kNoBase) {
+                for (;;) {
+                    uint32_t c0 = 0;
+                    if (lane == 0) c0 = atomicAdd(s_p4next, 64u);
+                    c0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)c0);
+                    if (c0 >= nhit_2) break;
+                    const uint32_t j = c0 + lane;
+                    if (j < nhit_2) {
+                        const uint2 e = s_hl[par * hcap + j];
+                        const uint32_t key = e.x;
+                        const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
+                        const int i = row * nb + bank;
+                        const int cb = col - bank * B;
+                        const uint32_t *bw = s_bits + (par * RN + i) * 8;
+                        uint32_t rank = 0;
+                        for (int w = 0; w < (cb >> 5); ++w) rank += __popc(bw[w]);
+                        rank += __popc(bw[cb >> 5] & ((1u << (cb & 31)) - 1u));
+                        const uint32_t pix = row_base + (uint32_t)row * W + col;
+                        A.pool[base + s_pref[i] + rank] = make_uint2(pix, e.y);
+                    }
                 }
             }
         }
-        if (p1_ok && wave == kP3Wave) {
-            // bank-row prefix of frame f-1's hit counts, staging chunk claim
-            uint32_t total = 0;
-            if (!ovf_1) {
-                for (int b0 = 0; b0 < BR; b0 += 64) {
-                    const int i = b0 + lane;
-                    const uint32_t c = i < BR ? s_cnt[pp * RN + i] : 0u;
-                    const uint32_t incl = wave_incl_scan(c);
-                    if (i < BR) s_pref[i] = total + incl - c;
-                    total += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
-                }
-            }
-            if (lane == 0) {
-                const uint64_t unit = (f - 1) * (uint64_t)A.n_strips + strip;
-                uint64_t base = chunk_cur;
-                if (ovf_1) {
-                    // the seed list was full: the general kernel redoes this unit
-                    atomicOr(&A.state->fallback, 1u);
-                    if (A.fb_units) A.fb_units[atomicAdd(&A.state->n_fallback, 1ull)] = unit;
-                    base = kNoBase;
-                } else if (total > 0) {
-                    if (chunk_cur + total > chunk_end) {
-                        const uint64_t sz = total > kChunkHits ? (uint64_t)total : kChunkHits;
-                        chunk_cur = atomicAdd(&A.state->cursor, (unsigned long long)sz);
-                        chunk_end = chunk_cur + sz;
-                    }
-                    if (chunk_cur + total <= A.pool_cap) {
-                        base = chunk_cur;
-                        chunk_cur += total;
-                    } else {
-                        base = kNoBase;
-                        atomicOr(&A.state->overflow, 1u);
-                    }
-                }
-                A.unit_base[unit] = base;
-                A.unit_count[unit] = total;
-                A.unit_photons[unit] = s_photons;
-                s_photons = 0;
-                s_base = base;
-            }
-        }
-        if (tid == 0) *s_p2next = 0;
-        __syncthreads();  // C -> next A
+        __syncthreads();  // B -> next A
     }
 }
 
