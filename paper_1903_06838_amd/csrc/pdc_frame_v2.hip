@@ -316,13 +316,13 @@ __device__ __forceinline__ float seed_threshold(float m, float t)
 }
 
 struct V2Layout {
-    uint32_t u, med, th, bits, cnt, seed, hl, nseed, hcnt, pref, gs, total;  // float offsets
+    uint32_t u, med, bits, cnt, seed, hl, nseed, hcnt, pref, gs, total;  // float offsets
 };
 
 // LDS of one workgroup (floats): u, med, bits, cnt, the seed lists and the
 // hit lists (key and charge of each local maximum, half a seed list long)
 // are double-buffered by frame parity, the seed counts kept for three frames
-// (frame f mod 3); th and pref are single.
+// (frame f mod 3); pref is single.
 __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
 {
     V2Layout L;
@@ -331,8 +331,6 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
     o += 2u * rmax * W;
     L.med = o;
     o += 2u * rmax * nb;
-    L.th = o;
-    o += (uint32_t)rmax * nb;
     L.bits = o;
     o += 2u * rmax * nb * 8;
     L.cnt = o;
@@ -356,8 +354,8 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
-    size_t o = 2ull * rmax * W + 2ull * rmax * nb + (size_t)rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb +
-               4ull * seed_cap + 1 + 3 + 2 + (size_t)rmax * nb + 1 + 1024;
+    size_t o = 2ull * rmax * W + 2ull * rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb + 4ull * seed_cap + 1 +
+               3 + 2 + (size_t)rmax * nb + 1 + 1024;
     return o * 4;
 }
 
