@@ -294,3 +294,49 @@ def test_mixed_graph_replays_equal_oracle(ctx):
             pdc.graph_destroy(ctx, graph)
         for d in dets:
             pdc.release_detector(ctx, d)
+
+
+def test_mixed_graph_items_move_off_graph_on_overflow():
+    """No staging slack and capacity 0: every item of a two-detector graph
+    overflows and is recomputed on buffers of its own, each item freeing its
+    place in the graph, so the graph launches again before those batches are
+    released; every result equals the oracle."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    n = 3
+    g1 = synth.Geometry(2, 40, 388, 194)
+    p1, k1 = synth.make_calibration(g1, 91)
+    r1 = synth.make_frames(g1, p1, k1, n, 0.03, 91)
+    g2 = synth.Geometry(1, 30, 192, 96)
+    p2, k2 = synth.make_calibration(g2, 92)
+    r2 = synth.make_frames(g2, p2, k2, n, 0.05, 92)
+    w1 = oracle_threads(r1, p1, k1, 194)
+    w2 = oracle_threads(r2, p2, k2, 96)
+    os.environ["PDC_DEBUG_TIGHT_POOL"] = "1"
+    try:
+        c = pdc.create(0)
+    finally:
+        del os.environ["PDC_DEBUG_TIGHT_POOL"]
+    try:
+        d1 = pdc.calibrate(c, pdc.geometry(*g1.shape, 194), p1, k1, pdc.params())
+        d2 = pdc.calibrate(c, pdc.geometry(*g2.shape, 96), p2, k2, pdc.params())
+        f1, f2 = torch.from_numpy(r1).cuda(), torch.from_numpy(r2).cuda()
+        torch.cuda.synchronize()
+        graph = pdc.graph_create_mixed(c, [(d1, f1, n, 0), (d2, f2, n, 0)])
+        first = pdc.graph_launch(c, graph)
+        for b, w in zip(first, (w1, w2)):
+            assert_same(_results(c, b, n, keep=False), w)
+        second = pdc.graph_launch(c, graph)  # both items left the graph's buffers
+        for b, w in zip(second, (w1, w2)):
+            assert_same(_results(c, b, n, keep=False), w)
+        for b, w in zip(first, (w1, w2)):  # the first batches kept their own results
+            assert_same(_results(c, b, n, keep=False), w)
+        for b in first + second:
+            pdc.release_batch(c, b)
+        pdc.graph_destroy(c, graph)
+        pdc.release_detector(c, d1)
+        pdc.release_detector(c, d2)
+    finally:
+        pdc.destroy(c)
