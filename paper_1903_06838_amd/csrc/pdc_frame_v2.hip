@@ -113,7 +113,7 @@ __device__ __forceinline__ bool done_single(float lo, float hi)
 // held by an L-lane group (V values per lane, absent values +inf); every
 // group of the wave searches its own bank at once.  Bracketing search on
 // counts, count(x < lo) <= k < count(x < hi) throughout: the first step tests
-// est -/+ 6 rank widths rw together (widening until they bracket), later steps
+// est -/+ 5 rank widths rw together (widening until they bracket), later steps
 // interpolate the pivot from the bracket counts and bisect in key space when
 // the interpolated pivot is not strictly inside or the bracket stopped
 // halving.  Once at most L values remain in [lo, hi) they are sorted across
@@ -154,7 +154,7 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
         est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
     }
 
-    const float w0 = 6.0f * rw;
+    const float w0 = 5.0f * rw;
     float lo = est - w0, hi = est + w0;
     int clo, chi;
     {
