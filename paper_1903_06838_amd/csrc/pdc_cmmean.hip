@@ -201,6 +201,77 @@ __global__ __launch_bounds__(kCmThreads) void cm_tile_kernel(CmArgs a, int s)
     }
 }
 
+// Stage s of the tile regions when every tile and frame starts on a 4-pixel
+// boundary (single gain range): one wave per (tile, group of F frames); lane
+// l owns partials 4l .. 4l + 3, that is pixels 256 k + 4 l + i, which it reads
+// as one 8-byte group of raw words and one 16-byte group of dark and 1/gain
+// values per k.  The partials' tree is the same balanced one: its first two
+// levels inside the lane, (q0 + q1) + (q2 + q3), the other six across lanes.
+template <int F>
+__global__ __launch_bounds__(kCmThreads) void cm_tile_wide_kernel(CmArgs a, int s)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t nfg = (a.n_frames + F - 1) / F;
+    const uint64_t items = nfg * (uint64_t)a.T;
+    const uint32_t HW = (uint32_t)a.H * (uint32_t)a.W;
+    const uint64_t npix = (uint64_t)a.T * HW;
+    const uint64_t nwaves = ((uint64_t)gridDim.x * kCmThreads) >> 6;
+    for (uint64_t it = ((uint64_t)blockIdx.x * kCmThreads + threadIdx.x) >> 6; it < items; it += nwaves) {
+        const uint64_t fg = it / (uint64_t)a.T;
+        const uint32_t t = (uint32_t)(it - fg * (uint64_t)a.T);
+        const uint64_t f0 = fg * F;
+        const int nf = (int)(a.n_frames - f0 < (uint64_t)F ? a.n_frames - f0 : (uint64_t)F);
+        float c0[F], c1[F], part[F][4];
+        uint32_t n0[F];
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
+            c0[j] = (s > 0 && j < nf) ? cv[0] : 0.0f;
+            c1[j] = (s > 1 && j < nf) ? cv[1] : 0.0f;
+            part[j][0] = part[j][1] = part[j][2] = part[j][3] = 0.0f;
+            n0[j] = 0;
+        }
+        const uint16_t *fr = a.frames + f0 * npix + (uint64_t)t * HW;
+        const float *pd = a.ped + (uint64_t)t * HW;
+        const float *kk = a.k + (uint64_t)t * HW;
+        for (uint32_t p = 4u * (uint32_t)lane; p < HW; p += 256u) {  // HW is a multiple of 4
+            const float4 pp = *reinterpret_cast<const float4 *>(pd + p);
+            const float4 kp = *reinterpret_cast<const float4 *>(kk + p);
+            const float pv[4] = {pp.x, pp.y, pp.z, pp.w}, kv[4] = {kp.x, kp.y, kp.z, kp.w};
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                if (j >= nf) break;
+                const uint2 w = *reinterpret_cast<const uint2 *>(fr + (uint64_t)j * npix + p);
+                const uint32_t r[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    float y = dark_gain(r[i], pv[i], kv[i]);
+                    if (s > 0) y = __fsub_rn(y, c0[j]);
+                    if (s > 1) y = __fsub_rn(y, c1[j]);
+                    if (y < a.t_cm) {
+                        part[j][i] = __fadd_rn(part[j][i], y);
+                        ++n0[j];
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < F; ++j) {
+            const float q = __fadd_rn(__fadd_rn(part[j][0], part[j][1]), __fadd_rn(part[j][2], part[j][3]));
+            const float sum = tree64(q);
+            const uint32_t n = sum64(n0[j]);
+            if (lane == 0 && j < nf) {
+                float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
+                cv[s] = __fdiv_rn(sum, fmaxf((float)n, a.guard));
+                if (s == 0) {
+                    cv[1] = 0.0f;
+                    cv[2] = 0.0f;
+                }
+            }
+        }
+    }
+}
+
 uint32_t cm_grid(uint64_t items, uint64_t per_block, uint32_t n_cu)
 {
     const uint64_t want = (items + per_block - 1) / per_block;
@@ -237,9 +308,19 @@ hipError_t launch_cm_tile(const CmArgs &a, uint32_t n_cu, hipStream_t s)
     constexpr int F = 8;
     const uint64_t items = (a.n_frames + F - 1) / F * (uint64_t)a.T;
     if (items == 0) return hipSuccess;
-    const uint32_t grid = cm_grid(items, 1, n_cu);
-    for (int st = 0; st < a.stages; ++st)
-        hipLaunchKernelGGL(cm_tile_kernel<F>, dim3(grid), dim3(kCmThreads), 0, s, a, st);
+    // wide loads need every tile and frame on a 4-pixel (8-byte) boundary
+    const uint64_t hw = (uint64_t)a.H * a.W;
+    const bool wide = a.gain_mode == 0 && hw % 4 == 0 && ((uintptr_t)a.frames & 7u) == 0 &&
+                      ((uintptr_t)a.ped & 15u) == 0 && ((uintptr_t)a.k & 15u) == 0;
+    if (wide) {
+        const uint32_t grid = cm_grid(items, kCmThreads / 64, n_cu);
+        for (int st = 0; st < a.stages; ++st)
+            hipLaunchKernelGGL(cm_tile_wide_kernel<F>, dim3(grid), dim3(kCmThreads), 0, s, a, st);
+    } else {
+        const uint32_t grid = cm_grid(items, 1, n_cu);
+        for (int st = 0; st < a.stages; ++st)
+            hipLaunchKernelGGL(cm_tile_kernel<F>, dim3(grid), dim3(kCmThreads), 0, s, a, st);
+    }
     return hipGetLastError();
 }
 
