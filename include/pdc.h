@@ -252,6 +252,16 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
  * scatter).  Either pointer may be NULL. */
 pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms);
 
+/* Measurement aid: a plain streaming read of bytes (a nonzero multiple of 16)
+ * at the DEVICE pointer src_dev (16-byte aligned), each byte once, on
+ * hip_stream (NULL: the context's stream); *ms_out (may be NULL) receives its
+ * duration from HIP events around the kernel on that stream.  bytes / ms is
+ * the HBM read bandwidth a kernel can reach on this device, the reference
+ * beside the frame kernel's fraction of the published peak.  Synchronous;
+ * allocates 4 bytes and two events for the call.  EINVAL on a bad pointer or
+ * size. */
+pdc_status pdc_stream_read(pdc_ctx *ctx, const void *src_dev, uint64_t bytes, void *hip_stream, float *ms_out);
+
 /* HIP graph of one batch (the pipeline of the Fig. a chain, as
  * pdc_process_frames enqueues it), for loops that process the same number of
  * frames from the same device buffer over and over: the kernels are captured
@@ -432,6 +442,16 @@ typedef struct {
  * calls it makes are returned as they are.  summary may be NULL. */
 pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_streams,
                          const pdc_serve_config *cfg, pdc_serve_summary *summary);
+
+/* Test hook of the serving loop's batching (host only, no device work): the
+ * number of frames the loop launches next for a queue holding the stream
+ * frame indices pending[0..n_pending) (strictly increasing; gaps are frames
+ * that were dropped), i.e. the run of consecutive indices at the front, at
+ * most max_batch and not past the end of the device pool (pool frame
+ * pending[0] % pool_frames onwards).  0 when the queue is empty.  EINVAL on
+ * a NULL pointer or indices that do not increase. */
+pdc_status pdc_debug_serve_batch_len(const uint64_t *pending, uint64_t n_pending, uint64_t max_batch,
+                                     uint64_t pool_frames, uint64_t *n_out);
 
 /* ------------------------------------------------------------------------
  * Summaries (Summarization section: photon-counting maps and histograms

@@ -1125,6 +1125,32 @@ pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch)
     return PDC_OK;
 }
 
+pdc_status pdc_stream_read(pdc_ctx *ctx, const void *src_dev, uint64_t bytes, void *hip_stream, float *ms_out)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (!src_dev || bytes == 0 || bytes % 16 || ((uintptr_t)src_dev & 15))
+        return fail(ctx, PDC_EINVAL, "stream_read: src must be 16-byte aligned and bytes a nonzero multiple of 16");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    uint32_t *out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    pdc_status rc = PDC_OK;
+    if (hipMalloc((void **)&out, sizeof(uint32_t)) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+        hipEventCreate(&e1) != hipSuccess)
+        rc = fail(ctx, PDC_ENOMEM, "stream_read: no memory for its result or events");
+    if (rc == PDC_OK && (launch_fill_u32(out, 1, s) != hipSuccess || hipEventRecord(e0, s) != hipSuccess ||
+                         launch_stream_read(src_dev, bytes, out, (uint32_t)ctx->n_cu, s) != hipSuccess ||
+                         hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+        rc = fail(ctx, PDC_EDEVICE, "stream_read: launch failed");
+    float ms = 0;
+    if (rc == PDC_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = fail(ctx, PDC_EDEVICE, "stream_read: timing");
+    if (rc == PDC_OK && ms_out) *ms_out = ms;
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(out);
+    return rc;
+}
+
 pdc_status pdc_batch_timing(pdc_ctx *ctx, uint64_t batch, float *main_ms, float *total_ms)
 {
     if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");

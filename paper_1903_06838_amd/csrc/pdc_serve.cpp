@@ -43,9 +43,34 @@ struct StreamState {
     std::vector<uint64_t> fp;
 };
 
+// Frames of the next launch: the run of consecutive stream frames at the
+// front of the queue (a dropped arrival leaves a gap that ends it), at most
+// max_batch of them and contiguous in the device pool (frame i is pool frame
+// i mod pool_frames, so the run stops where the pool wraps).
+template <typename Seq>
+uint64_t next_batch_len(const Seq &pending, uint64_t n_pending, uint64_t max_batch, uint64_t pool_frames)
+{
+    if (n_pending == 0 || max_batch == 0 || pool_frames == 0) return 0;
+    const uint64_t first = pending[0];
+    const uint64_t lim = std::min<uint64_t>(std::min<uint64_t>(n_pending, max_batch), pool_frames - first % pool_frames);
+    uint64_t n = 1;
+    while (n < lim && pending[n] == first + n) ++n;
+    return n;
+}
+
 }  // namespace
 
 extern "C" {
+
+pdc_status pdc_debug_serve_batch_len(const uint64_t *pending, uint64_t n_pending, uint64_t max_batch,
+                                     uint64_t pool_frames, uint64_t *n_out)
+{
+    if (!n_out || (n_pending && !pending)) return PDC_EINVAL;
+    for (uint64_t i = 1; i < n_pending; ++i)
+        if (pending[i] <= pending[i - 1]) return PDC_EINVAL;
+    *n_out = next_batch_len(pending, n_pending, max_batch, pool_frames);
+    return PDC_OK;
+}
 
 pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_streams,
                          const pdc_serve_config *cfg, pdc_serve_summary *summary)
@@ -138,8 +163,7 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
             while (rc == PDC_OK && !st.pending.empty() && st.inflight.size() < (size_t)cfg->max_inflight) {
                 const uint64_t first = st.pending.front();
                 const uint64_t pool_i = first % d.pool_frames;
-                uint64_t n = std::min<uint64_t>(st.pending.size(), cfg->max_batch);
-                n = std::min<uint64_t>(n, d.pool_frames - pool_i);  // contiguous in the pool
+                const uint64_t n = next_batch_len(st.pending, st.pending.size(), cfg->max_batch, d.pool_frames);
                 const uint64_t hit_cap = std::max<uint64_t>(1024, (uint64_t)(d.hit_fraction * (double)(st.pixels * n)));
                 const uint64_t bytes = hit_cap * 16 + n * 64;
                 if (cfg->hbm_budget && held_bytes + bytes > cfg->hbm_budget && !st.inflight.empty()) break;

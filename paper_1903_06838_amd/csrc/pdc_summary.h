@@ -28,6 +28,9 @@ struct AccumulateArgs {
 };
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, hipStream_t s);
+// Read bytes (a multiple of 16, 16-byte aligned) from src once; *out receives
+// an XOR of everything read.
+hipError_t launch_stream_read(const void *src, uint64_t bytes, uint32_t *out, uint32_t n_cu, hipStream_t s);
 bool accumulate_uses_lds(const AccumulateArgs &a);
 hipError_t launch_accumulate_hits(const AccumulateArgs &a, uint32_t max_grid, hipStream_t s);
 hipError_t launch_histogram(const float *x, uint64_t n, float lo, float scale, uint32_t nbins, uint32_t *hist,

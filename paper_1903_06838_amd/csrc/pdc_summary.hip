@@ -227,6 +227,40 @@ uint32_t stride_grid(uint64_t items, uint32_t cap)
 
 }  // namespace
 
+// Plain streaming read of n16 16-byte words: four independent loads per
+// thread and step, grid-stride; each wave folds what it read into one XOR and
+// adds it to *out with one atomic, so no load can be dropped.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t fold4(u32x4 a) { return (a.x ^ a.y) ^ (a.z ^ a.w); }
+
+__global__ void __launch_bounds__(kThreads) stream_read_kernel(const u32x4 *src, uint64_t n16, uint32_t *out)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * kThreads;
+    uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+    uint32_t acc = 0;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(src + i);
+        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        acc ^= (fold4(a) ^ fold4(b)) ^ (fold4(c) ^ fold4(d));
+    }
+    for (; i < n16; i += stride) acc ^= fold4(__builtin_nontemporal_load(src + i));
+    for (int o = 32; o > 0; o >>= 1) acc ^= (uint32_t)__shfl_xor((int)acc, o);
+    if ((threadIdx.x & 63) == 0) atomicXor(out, acc);
+}
+
+hipError_t launch_stream_read(const void *src, uint64_t bytes, uint32_t *out, uint32_t n_cu, hipStream_t s)
+{
+    const uint64_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const uint32_t grid = stride_grid(n16, 16u * (n_cu ? n_cu : 256u));
+    hipLaunchKernelGGL(stream_read_kernel, dim3(grid), dim3(kThreads), 0, s, reinterpret_cast<const u32x4 *>(src),
+                       n16, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, hipStream_t s)
 {
     if (n == 0) return hipSuccess;

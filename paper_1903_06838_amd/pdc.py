@@ -104,6 +104,9 @@ _sig = {
     "pdc_graph_destroy": (_st, [_P]),
     "pdc_graph_create_mixed": (_st, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P)]),
     "pdc_graph_items": (ctypes.c_int32, [_P]),
+    "pdc_stream_read": (_st, [_P, _P, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_float)]),
+    "pdc_debug_serve_batch_len": (_st, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
 }
 for _name, (_res, _args) in _sig.items():
     _f = getattr(_lib, _name)
@@ -263,6 +266,22 @@ def debug_batch_path(ctx, batch: int) -> int:
     p = ctypes.c_int32(0)
     _check(_lib.pdc_debug_batch_path(ctx, batch, ctypes.byref(p)), ctx)
     return p.value
+
+
+def stream_read(ctx, src_dev, nbytes: int, stream=None) -> float:
+    """Milliseconds of a plain streaming read of nbytes of device memory."""
+    ms = ctypes.c_float(0)
+    _check(_lib.pdc_stream_read(ctx, _ptr(src_dev), nbytes, _stream(stream), ctypes.byref(ms)), ctx)
+    return ms.value
+
+
+def debug_serve_batch_len(pending, max_batch: int, pool_frames: int) -> int:
+    """Frames the serving loop would launch next for this queue (host only)."""
+    a = np.ascontiguousarray(pending, dtype=np.uint64)
+    n = ctypes.c_uint64(0)
+    _check(_lib.pdc_debug_serve_batch_len(a.ctypes.data if a.size else None, a.size, max_batch, pool_frames,
+                                          ctypes.byref(n)))
+    return n.value
 
 
 def release_batch(ctx, batch: int) -> None:

@@ -130,6 +130,7 @@ def test_null_context_paths(pdc):
     assert lib.pdc_graph_destroy(None) == pdc.OK
     assert lib.pdc_graph_create_mixed(None, None, 1, None) == pdc.EINVAL
     assert lib.pdc_graph_items(None) == 0
+    assert lib.pdc_stream_read(None, None, 16, None, None) == pdc.EINVAL
 
 
 def test_create_without_gpu_is_edevice(pdc):
@@ -140,3 +141,27 @@ def test_create_without_gpu_is_edevice(pdc):
     h = ctypes.c_void_p()
     assert pdc._lib.pdc_create(0, ctypes.byref(h)) == pdc.EDEVICE
     assert h.value is None
+
+
+@pytest.mark.parametrize("pending,max_batch,pool,want", [
+    ([], 8, 4, 0),
+    ([0, 1, 2], 8, 16, 3),
+    ([0, 1, 2], 2, 16, 2),            # at most max_batch
+    ([3, 5], 8, 3, 1),                # frame 4 was dropped: the gap ends the run
+    ([2, 3, 6, 7], 8, 16, 2),
+    ([3, 4, 5, 6], 8, 5, 2),          # pool frames 3, 4, then the pool wraps
+    ([5, 6, 7], 8, 5, 3),             # frame 5 is pool frame 0
+])
+def test_serve_batch_is_a_run_of_consecutive_frames(pdc, pending, max_batch, pool, want):
+    """The serving loop launches the consecutive frames at the front of its
+    queue: a frame dropped on arrival (queue full) leaves a gap that must end
+    the batch, or the dropped frame would be processed in place of the one
+    after the gap."""
+    assert pdc.debug_serve_batch_len(pending, max_batch, pool) == want
+
+
+def test_serve_batch_len_rejects_unordered(pdc):
+    with pytest.raises(pdc.PdcError):
+        pdc.debug_serve_batch_len([3, 3], 8, 16)
+    with pytest.raises(pdc.PdcError):
+        pdc.debug_serve_batch_len([4, 2], 8, 16)
