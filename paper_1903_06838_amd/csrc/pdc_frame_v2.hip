@@ -45,6 +45,17 @@ __device__ __forceinline__ float uniform_f(float x)
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x)));
 }
 
+// Workgroup barrier for LDS only: it waits for the wave's own LDS accesses,
+// while its global loads (the next frame's words) and stores stay in flight.
+// Nothing a wave writes to global memory inside the frame loop is read by
+// another wave of the workgroup.
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Inclusive prefix sum over the 64 lanes (DPP row shifts, then row
 // broadcasts); all lanes must be active.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
@@ -109,6 +120,88 @@ __device__ __forceinline__ bool done_single(float lo, float hi)
     return (uint32_t)(f2key(hi) - f2key(lo)) <= 1u;
 }
 
+// Rough location of an L-lane group's median: medians of three of each lane's
+// values (up to eight triples), averaged over the group.  Dense banks (no +inf
+// inside the first B columns) take the triples that every lane holds; with
+// invalid pixels (SPARSE) each lane takes the finite ones.  Only the work of
+// the searches below depends on it, never their result.
+template <int V, int L, bool SPARSE>
+__device__ __forceinline__ float group_estimate(const float (&x)[V], int B)
+{
+    static_assert(V >= 3, "the start estimate takes triples of values per lane");
+    constexpr int NT = V / 3 < 8 ? V / 3 : 8;
+    if (!SPARSE && B >= 3 * L * NT) {  // uniform: every lane's NT triples lie inside the bank
+        float s3 = 0.0f;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
+        return gsum_f<L>(s3) * (1.0f / (float)(NT * L));
+    }
+    float s3 = 0.0f;
+    int n3 = 0;
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+        const float a = x[3 * t];
+        const float b = x[3 * t + 1] < INFINITY ? x[3 * t + 1] : a;
+        const float c = x[3 * t + 2] < INFINITY ? x[3 * t + 2] : b;
+        if (a < INFINITY) {
+            s3 += __builtin_amdgcn_fmed3f(a, b, c);
+            ++n3;
+        }
+    }
+    const float ssum = gsum_f<L>(s3);
+    const int nl = gsum_i<L>(n3);
+    return nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
+}
+
+// Ascending bitonic sort of one value per lane over an aligned L-lane group,
+// then the value of lane r broadcast to the group.  Merges of size 2b start
+// with the mirror partner inside the block, then halve with xor partners; a
+// compare-exchange is one median of three: med3(y, partner, -inf) is the
+// smaller of the two (kept by the lower lane of the pair), med3(y, partner,
+// +inf) the larger (no NaN is present).  The pick is an OR over the group of
+// the chosen lane's bits and zeros elsewhere.  All lanes must be active.
+template <int L>
+__device__ __forceinline__ float group_sort_pick(float y, int r)
+{
+    const int gl = __lane_id() & (L - 1);
+    const float e1 = (gl & 1) ? INFINITY : -INFINITY;
+    const float e2 = (gl & 2) ? INFINITY : -INFINITY;
+    const float e4 = (gl & 4) ? INFINITY : -INFINITY;
+    const float e8 = (gl & 8) ? INFINITY : -INFINITY;
+#define PDC_CX(partner, e) y = __builtin_amdgcn_fmed3f(y, (partner), (e));
+#define PDC_DPP(ctrl) __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), ctrl, 0xF, 0xF, false))
+    PDC_CX(PDC_DPP(0xB1), e1)                      // merge 2: mirror (xor 1)
+    if (L >= 4) {
+        PDC_CX(PDC_DPP(0x1B), e2)                  // merge 4: mirror in 4
+        PDC_CX(PDC_DPP(0xB1), e1)
+    }
+    if (L >= 8) {
+        PDC_CX(PDC_DPP(0x141), e4)                 // merge 8: row_half_mirror
+        PDC_CX(PDC_DPP(0x4E), e2)                  // xor 2
+        PDC_CX(PDC_DPP(0xB1), e1)
+    }
+    if (L >= 16) {
+        PDC_CX(PDC_DPP(0x140), e8)                 // merge 16: row_mirror
+        {
+            const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x104, 0xF, 0xF, true));  // row_shl:4
+            const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x114, 0xF, 0xF, true));  // row_shr:4
+            PDC_CX((gl & 4) ? up : dn, e4)         // xor 4
+        }
+        PDC_CX(PDC_DPP(0x4E), e2)
+        PDC_CX(PDC_DPP(0xB1), e1)
+    }
+#undef PDC_DPP
+#undef PDC_CX
+    int rb = gl == r ? __float_as_int(y) : 0;
+#define PDC_GX(ctrl) rb |= __builtin_amdgcn_update_dpp(0, rb, ctrl, 0xF, 0xF, false);
+    PDC_GX(0xB1)
+    if (L >= 4) PDC_GX(0x4E)
+    if (L >= 8) PDC_GX(0x141)
+    if (L >= 16) PDC_GX(0x140)
+#undef PDC_GX
+    return __int_as_float(rb);
+}
+
 // Exact element of rank k (0-based, ascending) among the nval finite values
 // held by an L-lane group (V values per lane, absent values +inf); every
 // group of the wave searches its own bank at once.  Bracketing search on
@@ -123,36 +216,7 @@ __device__ __forceinline__ bool done_single(float lo, float hi)
 template <int V, int L, bool SPARSE>
 __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bool act, float *gsc, int B)
 {
-    static_assert(V >= 3, "the start estimate takes triples of values per lane");
-    // start: medians of three of each lane's values (up to eight triples),
-    // averaged over the group.  Dense banks (no +inf inside the first B
-    // columns) take the triples that every lane holds; with invalid pixels
-    // (SPARSE) each lane takes the finite ones.  Only the number of search
-    // steps depends on the start, never the result.
-    constexpr int NT = V / 3 < 8 ? V / 3 : 8;
-    float est;
-    if (!SPARSE && B >= 3 * L * NT) {  // uniform: every lane's NT triples lie inside the bank
-        float s3 = 0.0f;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
-        est = gsum_f<L>(s3) * (1.0f / (float)(NT * L));
-    } else {
-        float s3 = 0.0f;
-        int n3 = 0;
-#pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const float a = x[3 * t];
-            const float b = x[3 * t + 1] < INFINITY ? x[3 * t + 1] : a;
-            const float c = x[3 * t + 2] < INFINITY ? x[3 * t + 2] : b;
-            if (a < INFINITY) {
-                s3 += __builtin_amdgcn_fmed3f(a, b, c);
-                ++n3;
-            }
-        }
-        const float ssum = gsum_f<L>(s3);
-        const int nl = gsum_i<L>(n3);
-        est = nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
-    }
+    const float est = group_estimate<V, L, SPARSE>(x, B);
 
     const float w0 = 5.0f * rw;
     float lo = est - w0, hi = est + w0;
@@ -256,49 +320,30 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    // ascending bitonic sort over the group's lanes: merges of size 2b start
-    // with the mirror partner inside the block, then halve with xor partners.
-    // A compare-exchange is one median of three: med3(y, partner, -inf) is
-    // the smaller of the two (kept by the lower lane of the pair), med3(y,
-    // partner, +inf) the larger; no NaN is present.
-    const float e1 = (gl & 1) ? INFINITY : -INFINITY;
-    const float e2 = (gl & 2) ? INFINITY : -INFINITY;
-    const float e4 = (gl & 4) ? INFINITY : -INFINITY;
-    const float e8 = (gl & 8) ? INFINITY : -INFINITY;
-#define PDC_CX(partner, e) y = __builtin_amdgcn_fmed3f(y, (partner), (e));
-#define PDC_DPP(ctrl) __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), ctrl, 0xF, 0xF, false))
-    PDC_CX(PDC_DPP(0xB1), e1)                      // merge 2: mirror (xor 1)
-    if (L >= 4) {
-        PDC_CX(PDC_DPP(0x1B), e2)                  // merge 4: mirror in 4
-        PDC_CX(PDC_DPP(0xB1), e1)
-    }
-    if (L >= 8) {
-        PDC_CX(PDC_DPP(0x141), e4)                 // merge 8: row_half_mirror
-        PDC_CX(PDC_DPP(0x4E), e2)                  // xor 2
-        PDC_CX(PDC_DPP(0xB1), e1)
-    }
-    if (L >= 16) {
-        PDC_CX(PDC_DPP(0x140), e8)                 // merge 16: row_mirror
-        {
-            const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x104, 0xF, 0xF, true));  // row_shl:4
-            const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x114, 0xF, 0xF, true));  // row_shr:4
-            PDC_CX((gl & 4) ? up : dn, e4)         // xor 4
+    // exactly one lane of the group (k - clo < n <= L) holds the answer
+    const float pick = group_sort_pick<L>(y, k - clo);
+    return gather ? pick : lo;
+}
+
+// The L-lane group's values of a bank-row: lane gl takes src[L v] (src
+// points at its first column) for L v < lim = B - gl, else pad.  When
+// tail_only (wave-uniform: B > L (V - 1)) only the last slot can lie past
+// the bank, and the others are read without a test.
+template <int V, int L>
+__device__ __forceinline__ void read_group(float (&x)[V], const float *src, int lim, bool tail_only, float pad)
+{
+    if (tail_only) {
+#pragma unroll
+        for (int v = 0; v < V - 1; ++v) x[v] = src[L * v];
+        const float t = src[L * (V - 1)];
+        x[V - 1] = L * (V - 1) < lim ? t : pad;
+    } else {
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+            const float t = src[L * v];
+            x[v] = L * v < lim ? t : pad;
         }
-        PDC_CX(PDC_DPP(0x4E), e2)
-        PDC_CX(PDC_DPP(0xB1), e1)
     }
-#undef PDC_DPP
-#undef PDC_CX
-    // exactly one lane of the group (k - clo < n <= L) holds the answer: an
-    // OR over the group of its bits and zeros elsewhere broadcasts it
-    int rb = gl == k - clo ? __float_as_int(y) : 0;
-#define PDC_GX(ctrl) rb |= __builtin_amdgcn_update_dpp(0, rb, ctrl, 0xF, 0xF, false);
-    PDC_GX(0xB1)
-    if (L >= 4) PDC_GX(0x4E)
-    if (L >= 8) PDC_GX(0x141)
-    if (L >= 16) PDC_GX(0x140)
-#undef PDC_GX
-    return gather ? __int_as_float(rb) : lo;
 }
 
 // Smallest binary32 value th such that fl(th - m) > t (fl(x - m) is
@@ -322,8 +367,8 @@ struct V2Layout {
 // LDS of one workgroup (floats): u, med, bits, cnt, the seed lists and the
 // hit lists (key and charge of each local maximum, half a seed list long)
 // are double-buffered by frame parity, the seed counts kept for three frames
-// (frame f mod 3); pref is single.
-__device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
+// (frame f mod 3); pref and the median finish scratch gs are single.
+__device__ __host__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
 {
     V2Layout L;
     uint32_t o = 0;
@@ -354,9 +399,7 @@ __device__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap)
 {
-    size_t o = 2ull * rmax * W + 2ull * rmax * nb + 2ull * rmax * nb * 8 + 2ull * rmax * nb + 4ull * seed_cap + 1 +
-               3 + 2 + (size_t)rmax * nb + 1 + 1024;
-    return o * 4;
+    return (size_t)v2_layout(rmax, W, nb, seed_cap).total * 4;
 }
 
 // Item (frame group, strip) of block b among n: blocks are dealt to the 8 XCDs
@@ -377,9 +420,20 @@ __device__ __forceinline__ uint32_t seed_key(int row, int bank, int col)
     return ((uint32_t)row << 18) | ((uint32_t)bank << 11) | (uint32_t)col;
 }
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Pixels of a strip's loaded rows per thread in the flat correction pass:
+// CH chunks of 4 (a strip holds at most 16 waves x 4 x 64 / L bank-rows of
+// at most 256 / 128 pixels, i.e. 16384 pixels).
+constexpr int kFlatChunks = 4;
+
 template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG>
 __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 {
+    // Single-gain kernels correct the strip as one flat block of pixels
+    // (FLAT); auto-ranging kernels keep a wave per bank-row, whose lanes
+    // look up their pixels' range planes.
+    constexpr bool FLAT = !MG;
     extern __shared__ __align__(16) float lds[];
     __shared__ unsigned long long s_photons;
     __shared__ uint64_t s_base;
@@ -460,6 +514,20 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             }
         }
     }
+    // FLAT: the loaded rows are one contiguous block of R W words of each
+    // frame (W % 4 == 0), cut into 4-pixel chunks j = tid + 1024 c; each
+    // chunk's dark and 1/gain values stay in registers
+    const int nchunk = FLAT ? (R * W) >> 2 : 0;
+    float4 pdq[kFlatChunks], kkq[kFlatChunks];
+#pragma unroll
+    for (int c = 0; c < kFlatChunks; ++c) {
+        const int j = tid + kV2Threads * c;
+        pdq[c] = kkq[c] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (FLAT && j < nchunk) {
+            pdq[c] = *reinterpret_cast<const float4 *>(A.ped + row_base + 4u * j);
+            kkq[c] = *reinterpret_cast<const float4 *>(A.k + row_base + 4u * j);
+        }
+    }
     for (int x = tid; x < 2 * RN * 8; x += kV2Threads) s_bits[x] = 0;
     for (int x = tid; x < 2 * RN; x += kV2Threads) s_cnt[x] = 0;
     if (tid < 3) s_nseed[tid] = 0;
@@ -477,10 +545,28 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             const bool gv = g < ng;
 #pragma unroll
             for (int q = 0; q < NQ; ++q)
-                raw[g][q] = (gv && lok[q]) ? __builtin_nontemporal_load(fr + ((gb_[g] + 128 * q + lane_off) >> 1)) : 0u;
+                // gb_[g] is even (W and B are), so the word address is a
+                // wave-uniform base plus the lane
+                raw[g][q] = (gv && lok[q]) ? __builtin_nontemporal_load(fr + ((gb_[g] >> 1) + 64 * q) + lane) : 0u;
         }
     };
-    if (f_begin < f_end) load_raw(f_begin, lane_ok);
+    u32x2 rawq[kFlatChunks];
+#pragma unroll
+    for (int c = 0; c < kFlatChunks; ++c) rawq[c] = u32x2{0u, 0u};
+    auto load_raw_flat = [&](uint64_t f) {
+        const u32x2 *fr = reinterpret_cast<const u32x2 *>(A.frames + f * npix + row_base);
+#pragma unroll
+        for (int c = 0; c < kFlatChunks; ++c) {
+            const int j = tid + kV2Threads * c;
+            if (j < nchunk) rawq[c] = __builtin_nontemporal_load(fr + j);
+        }
+    };
+    if (f_begin < f_end) {
+        if constexpr (FLAT)
+            load_raw_flat(f_begin);
+        else
+            load_raw(f_begin, lane_ok);
+    }
     __syncthreads();
 
     // Seeds of a bank-row held by an L-lane group in phase B (lane gl holds
@@ -508,6 +594,36 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const int v = __ffs(sb) - 1;
                 sb &= sb - 1;
                 if (pos < (uint32_t)cap) s_seed[sbuf * cap + pos] = seed_key(row, bank, bank * B + L * v + gl);
+                ++pos;
+            }
+        }
+    };
+    // The same for the single-gain median kernels: values of the slots in
+    // vmask are finite (the others, past the bank, are dropped), the mask is
+    // built from the last value down, a sign bit per value.
+    auto append_seeds_dense = [&](const float(&xs)[V], float th, bool own, uint32_t vmask, int row, int bank, int gl,
+                                  int sbuf, int slot) {
+        // x >= th  <=>  x > tp, tp the float below th, <=>  fl(tp - x) < 0:
+        // a nonzero difference keeps its sign, x == tp gives +0 and
+        // x = -inf gives +inf, so the sign bit is the test (th finite)
+        const float tp = key2f(f2key(th) - 1);
+        uint32_t sb = 0;
+#pragma unroll
+        for (int v = V - 1; v >= 0; --v)
+            sb = __builtin_amdgcn_alignbit(sb, __float_as_uint(__fsub_rn(tp, xs[v])), 31);
+        sb = own ? sb & vmask : 0u;
+        const uint32_t ns = (uint32_t)__popc(sb);
+        const uint32_t incl = wave_incl_scan(ns);
+        const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        if (wtot) {
+            uint32_t base = 0;
+            if (lane == 0) base = atomicAdd(&s_nseed[slot], wtot);
+            uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
+            const uint32_t key0 = seed_key(row, bank, bank * B + gl);
+            while (sb) {
+                const int v = __ffs(sb) - 1;
+                sb &= sb - 1;
+                if (pos < (uint32_t)cap) s_seed[sbuf * cap + pos] = key0 + (uint32_t)(L * v);
                 ++pos;
             }
         }
@@ -550,7 +666,23 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         }
 
         // ================= A: 1a(f) | Frames2(f-1) | 3(f-2) =======================
-        if (cur_ok) {
+        if (FLAT && cur_ok) {
+            // frame f's words were loaded at the end of the previous A
+#pragma unroll
+            for (int c = 0; c < kFlatChunks; ++c) {
+                const int j = tid + kV2Threads * c;
+                if (j < nchunk) {
+                    const uint32_t w0 = rawq[c].x & 0x3FFF3FFFu, w1 = rawq[c].y & 0x3FFF3FFFu;
+                    float4 o;
+                    o.x = __fmul_rn(__fsub_rn((float)(w0 & 0xFFFFu), pdq[c].x), kkq[c].x);
+                    o.y = __fmul_rn(__fsub_rn((float)(w0 >> 16), pdq[c].y), kkq[c].y);
+                    o.z = __fmul_rn(__fsub_rn((float)(w1 & 0xFFFFu), pdq[c].z), kkq[c].z);
+                    o.w = __fmul_rn(__fsub_rn((float)(w1 >> 16), pdq[c].w), kkq[c].w);
+                    *reinterpret_cast<float4 *>(u_c + 4 * j) = o;
+                }
+            }
+        }
+        if (!FLAT && cur_ok) {
             uint32_t cur[GMAX][NQ];
 #pragma unroll
             for (int g = 0; g < GMAX; ++g)
@@ -610,8 +742,9 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             *s_p2next = 0;
             *s_p4next = 0;
         }
-        if (KEEP && p1_ok) {
-            // Frames2 of frame f-1 (its u and medians, parity pp, are intact)
+        if (KEEP && !FLAT && p1_ok) {
+            // Frames2 of frame f-1 (its u and medians, parity pp, are intact);
+            // the flat kernels write Frames2 in phase B
 #pragma unroll
             for (int g = 0; g < GMAX; ++g) {
                 if (g >= ng) break;
@@ -677,7 +810,11 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 s_chunk[1] = chunk_end;
             }
         }
-        __syncthreads();  // A -> B
+        // the loads of frame f + 1 go out last in A, into the registers frame
+        // f's words were in: they overlap phase B and the barriers, and no
+        // wait in A (the staging claim's atomics) waits for them
+        if (FLAT && f + 1 < f_end) load_raw_flat(f + 1);
+        lds_barrier();  // A -> B
 
         // ================= B: 1b(f) | 2(f-1) | 4(f-2) =============================
         if (CMM && cur_ok && A.cm_mode == 1) {
@@ -727,10 +864,17 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 for (int v = 0; v < V; ++v) x[v] = __fsub_rn(x[v], cm);
             }
             if (act) {
+                float *f2 = (KEEP && FLAT && row >= own_lo && row < own_hi)
+                                ? A.corrected + f * npix + row_base + row * W + bank * B
+                                : nullptr;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int c = L * v + gl;
-                    if (c < B) dst[c] = x[v] < INFINITY ? x[v] : 0.0f;  // invalid: v = 0
+                    if (c < B) {
+                        const float y = x[v] < INFINITY ? x[v] : 0.0f;  // invalid: v = 0
+                        dst[c] = y;
+                        if (f2) f2[c] = y;
+                    }
                 }
                 if (gl == 0) med_c[i] = 0.0f;
             }
@@ -754,6 +898,9 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const float *cv = A.cm + (f * A.cm_regions + reg) * 3;
                 const float c0 = cv[0], c1 = cv[1], c2 = cv[2];
                 float *dst = u_c + row * W + bank * B;
+                float *f2 = (KEEP && FLAT && row >= own_lo && row < own_hi)
+                                ? A.corrected + f * npix + row_base + row * W + bank * B
+                                : nullptr;
 #pragma unroll
                 for (int v = 0; v < V; ++v) {
                     const int c = L * v + gl;
@@ -763,13 +910,45 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                         const float y = __fsub_rn(__fsub_rn(__fsub_rn(u, c0), c1), c2);
                         x[v] = y;
                         dst[c] = (MG && !(u < INFINITY)) ? 0.0f : y;
+                        if (f2) f2[c] = y;
                     }
                 }
                 if (gl == 0) med_c[i] = 0.0f;
             }
             append_seeds(x, th0, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
-        if (!CMM && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
+        if (!CMM && FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
+            constexpr int G = 64 / L;
+            const int grp = lane / L, gl = lane - grp * L;
+            const int i = wave * G + grp;
+            const bool act = i < BR;
+            const int row = act ? i / nb : 0;
+            const int bank = act ? i - row * nb : 0;
+            const float *src = u_c + row * W + bank * B + gl;
+            // every lane reads (inside the u buffers or the LDS that follows
+            // them; an inactive group reads row 0) and columns past the bank
+            // become +inf; lim is opaque so that the compares stay at the
+            // reads rather than as loop-invariant masks
+            int lim = B - gl;
+            asm volatile("" : "+v"(lim));
+            const bool tail_only = B > L * (V - 1);
+            float x[V];
+            read_group<V, L>(x, src, lim, tail_only, INFINITY);
+            const float m = group_median<V, L, false>(x, B, kmed, A.rank_width, act, s_gs + tid, B);
+            if (act && gl == 0) med_c[i] = m;
+            const bool own = act && row >= own_lo && row < own_hi;
+            if (KEEP && own) {
+                float *f2 = A.corrected + f * npix + row_base + row * W + bank * B + gl;
+#pragma unroll
+                for (int v = 0; v < V; ++v)
+                    if (L * v < lim) f2[L * v] = __fsub_rn(x[v], m);
+            }
+            // slots past the bank (+inf) are no seeds
+            const uint32_t vmask = tail_only ? ((L * (V - 1) < lim) ? (1u << V) - 1u : (1u << (V - 1)) - 1u)
+                                             : (uint32_t)((1ull << min(V, max(0, (lim + L - 1) / L))) - 1ull);
+            append_seeds_dense(x, seed_threshold(m, A.t_seed), own, vmask, row, bank, gl, par, sc0);
+        }
+        if (!CMM && !FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
             constexpr int G = 64 / L;
             const int grp = lane / L, gl = lane - grp * L;
             const int i = wave * G + grp;
@@ -919,7 +1098,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 }
             }
         }
-        __syncthreads();  // B -> next A
+        lds_barrier();  // B -> next A
     }
 }
 

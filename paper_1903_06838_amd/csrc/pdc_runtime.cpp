@@ -304,6 +304,9 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     d.v2_ok = false;
     if ((g.cols & 1) || (g.bank_cols & 1) || g.bank_cols > 256 || g.bank_cols < 2)
         return false;
+    // single-gain kernels read each strip as a block of 4-pixel chunks
+    if (!g.gain_mode && (g.cols % 4))
+        return false;
     const int nb = g.cols / g.bank_cols;
     d.nq = g.bank_cols > 128 ? 2 : 1;
     d.gmax = d.nq == 2 ? 4 : 8;
