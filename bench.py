@@ -94,10 +94,11 @@ def run_steps(torch, pdc, ctx, det, frames, n_frames, hit_cap, steps, warmup):
         b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
         pdc.get_hits(ctx, b, n_frames, capacity=0)
         pdc.release_batch(ctx, b)
-    mains, totals = [], []
+    mains, totals, step_ms = [], [], []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
+        ts = time.perf_counter()
         b = pdc.process_frames(ctx, det, frames, n_frames, hit_cap, stream)
         # the step ends with the batch's final per-frame results: this also
         # runs any recomputation the batch needs (seed lists or staging full)
@@ -106,8 +107,10 @@ def run_steps(torch, pdc, ctx, det, frames, n_frames, hit_cap, steps, warmup):
         mains.append(m)
         totals.append(t)
         pdc.release_batch(ctx, b)
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    run_steps.step_ms = step_ms
     return (t1 - t0) * 1e3 / steps, mains, totals, total, (fh, fp), hit_cap
 
 
@@ -175,7 +178,44 @@ def cpu_baseline(pool, ped, gain, bank_cols, gpu_fh, gpu_fp, gpu_hits_fn):
                       % (passes, P, passes * P, wall)}, exact
 
 
-def latency(torch, pdc, ctx, det, frame, calls=300, use_graph=False):
+def stats_ms(xs):
+    import numpy as np
+
+    return {"mean": round(float(np.mean(xs)), 4), "median": round(float(np.median(xs)), 4),
+            "min": round(float(np.min(xs)), 4), "max": round(float(np.max(xs)), 4), "n": len(xs)}
+
+
+def pool_check(pool, ped, gain, bank_cols, gpu_fh, gpu_fp, gpu_hits_fn):
+    """The oracle on the distinct frames of a replicated batch: True when the
+    GPU's counts and photon totals of every batch frame, and its hit list of
+    the pool, equal the oracle's bit for bit."""
+    import numpy as np
+
+    from oracle import oracle
+
+    o = oracle.load()
+    P = pool.shape[0]
+    threads = min(16, os.cpu_count() or 1, P)
+    bounds = np.linspace(0, P, threads + 1).astype(int)
+    parts = [(bounds[i], bounds[i + 1]) for i in range(threads) if bounds[i + 1] > bounds[i]]
+    with cf.ThreadPoolExecutor(len(parts)) as ex:
+        outs = list(ex.map(lambda ab: o.process(pool[ab[0]:ab[1]], ped, gain, bank_cols), parts))
+    fh = np.concatenate([r["frame_hits"] for r in outs])
+    fp = np.concatenate([r["frame_photons"] for r in outs])
+    hits = []
+    for (a, _), r in zip(parts, outs):
+        h = r["hits"].copy()
+        h["frame"] += np.uint32(a)
+        hits.append(h)
+    hits = np.concatenate(hits)
+    idx = np.arange(len(gpu_fh)) % P
+    exact = bool(np.array_equal(gpu_fh, fh[idx]) and np.array_equal(gpu_fp, fp[idx]))
+    g = gpu_hits_fn(int(fh.sum()))
+    return exact and g is not None and np.array_equal(
+        np.ascontiguousarray(g).view(np.uint32), np.ascontiguousarray(hits).view(np.uint32))
+
+
+def latency(torch, pdc, ctx, det, frame, calls=10000, use_graph=False):
     """Small-batch process_frames (or a replay of its captured graph) + get_hits,
     host-observed and kernel-only."""
     import numpy as np
@@ -598,6 +638,7 @@ def main():
     log("autotune: frame groups x%d (frame kernel ms x1/x2/x4: %s)" % (tune_mult, [round(float(x), 3) for x in tune_ms]))
     ms, mains, totals, hits, (fh, fp), hit_cap = run_steps(
         torch, pdc, ctx, det, frames, N, est, args.steps, args.warmup)
+    step_ms = list(run_steps.step_ms)
     log("headline: %.3f ms/step, frame kernel %.3f ms, all kernels %.3f ms, %d hits"
         % (ms, sum(mains) / len(mains), sum(totals) / len(totals), hits))
 
@@ -625,7 +666,8 @@ def main():
                                                  "frame_kernel_ms_x1_x2_x4": [round(float(x), 3) for x in tune_ms]}},
            "roofline": roofline(N, npix, hits, mains),
            "hits_per_step": hits,
-           "all_kernels_ms": round(sum(totals) / len(totals), 4)}
+           "all_kernels_ms": round(sum(totals) / len(totals), 4),
+           "step_ms": stats_ms(step_ms), "frame_kernel_ms": stats_ms(mains)}
 
     # stream-copy context: achievable HBM bandwidth of a plain device copy
     src = torch.empty(COPY_BYTES // 2, dtype=torch.int16, device=dev)
@@ -638,6 +680,14 @@ def main():
     torch.cuda.synchronize()
     out["copy_GBps"] = round(5 * 2 * COPY_BYTES / (time.perf_counter() - t0) / 1e9, 1)
     del src, dst
+    # achievable HBM read bandwidth: a plain streaming read of the same batch
+    nbytes = N * npix * 2
+    pdc.stream_read(ctx, frames, nbytes, torch.cuda.current_stream())
+    rd = [pdc.stream_read(ctx, frames, nbytes, torch.cuda.current_stream()) for _ in range(3)]
+    rd_gbps = nbytes / (min(rd) / 1e3) / 1e9
+    out["stream_read"] = {"bytes": nbytes, "ms_min": round(min(rd), 4), "GBps": round(rd_gbps, 1),
+                          "frame_kernel_frac_of_stream_read": round(out["roofline"]["achieved"] / rd_gbps, 4)}
+    log("stream read: %s" % out["stream_read"])
 
     if not args.no_cpu:
         def gpu_pool_hits(n):
@@ -699,14 +749,25 @@ def main():
         sweep = [{"occupancy": 0.01, "Mpixel_s": out["value"], "frac": out["roofline"]["frac"],
                   "hits": hits}]
         del frames
+        if "bit_exact_vs_oracle" in out:
+            sweep[0]["bit_exact"] = out["bit_exact_vs_oracle"]
         for occ_id in (0, 2):
-            _, fr = make_batch(torch, synth, geom, ped, gain, occ_id, args.pool, N, dev)
+            pool2, fr = make_batch(torch, synth, geom, ped, gain, occ_id, args.pool, N, dev)
             occ = synth.CSPAD_OCCUPANCIES[occ_id]
-            ms2, m2, _, h2, _, _ = run_steps(torch, pdc, ctx, det, fr, N,
-                                             int(occ * 1.3 * npix * N) + 4096, max(2, args.steps // 3), 1)
+            ms2, m2, _, h2, (fh2, fp2), _ = run_steps(torch, pdc, ctx, det, fr, N,
+                                                      int(occ * 1.3 * npix * N) + 4096, max(2, args.steps // 3), 1)
             rf = roofline(N, npix, h2, m2)
-            sweep.append({"occupancy": occ, "Mpixel_s": round(N * npix / (ms2 / 1e3) / 1e6, 1),
-                          "frac": rf["frac"], "hits": h2, "ms_per_step": round(ms2, 4)})
+            ent = {"occupancy": occ, "Mpixel_s": round(N * npix / (ms2 / 1e3) / 1e6, 1),
+                   "frac": rf["frac"], "hits": h2, "ms_per_step": round(ms2, 4)}
+
+            def pool_hits(n, fr=fr):
+                b = pdc.process_frames(ctx, det, fr, args.pool, n + 1024, torch.cuda.current_stream())
+                h, total, _, _, _ = pdc.get_hits(ctx, b, args.pool)
+                pdc.release_batch(ctx, b)
+                return h if total == n else None
+            ent["bit_exact"] = pool_check(pool2, ped, gain, geom.bank_cols, fh2, fp2, pool_hits)
+            log("sweep: %s" % ent)
+            sweep.append(ent)
             del fr
         out["sweep"] = sorted(sweep, key=lambda s: s["occupancy"])
     pdc.destroy(ctx)

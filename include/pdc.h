@@ -172,7 +172,11 @@ pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pe
 /* Free a detector's planes after its pending batches complete. */
 pdc_status pdc_release_detector(pdc_ctx *ctx, int32_t det);
 
-/* Enqueue the whole pipeline on a batch of frames.
+/* Enqueue the whole pipeline on a batch of frames: the raw minibatch
+ * N x H x W x 1 of the Dark and Gain section goes through dark and gain
+ * (Fig. b), common mode (Fig. c) and photon finding, charge summing and
+ * counting (Fig. e, Photon Charge Summing section), and ends in the sparse
+ * photon lists of the Summarization section.
  * frames_dev: DEVICE pointer to uint16 [n_frames][n_tiles][rows][cols], raw
  *   ADC words (bits 14-15 ignored); borrowed, it must stay valid and unchanged
  *   until pdc_get_hits or pdc_release_batch of this batch returns.
@@ -221,15 +225,20 @@ pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t 
 pdc_status pdc_autotune(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
                         uint64_t hit_capacity, void *hip_stream, int32_t *mult_out, float *ms_out);
 
-/* Wait for the batch and copy its results, hits in (frame, pixel) order.
+/* Wait for the batch and copy its results (Summarization section: lists of
+ * sparse photons, each with its position, energy and photon count; per-frame
+ * photon-counting totals), hits in (frame, pixel) order.
  * dst: room for dst_capacity records, in host memory (dst_is_device = 0) or
  *   device memory of the context's device (dst_is_device = 1); may be NULL
  *   when dst_capacity is 0.  The first min(total, dst_capacity) hits are
  *   written; *n_hits_total (may be NULL) receives the true total.
  * per_frame_hits (uint32 [n_frames]) and per_frame_photons (uint64
  *   [n_frames]): host arrays or NULL.
- * Returns PDC_WARN_TRUNCATED when total > dst_capacity, else PDC_OK.  The batch
- * stays alive until pdc_release_batch.  ESTATE for an unknown batch. */
+ * Returns PDC_WARN_TRUNCATED when total > dst_capacity, else PDC_OK.  A
+ * batch whose hits outgrew the buffers sized from hit_capacity is recomputed
+ * here with exact sizes first, so the total and the lists are always
+ * complete.  The batch stays alive until pdc_release_batch (it can be read
+ * again, with other destinations).  ESTATE for an unknown batch. */
 pdc_status pdc_get_hits(pdc_ctx *ctx, uint64_t batch, pdc_hit *dst, uint64_t dst_capacity,
                         int32_t dst_is_device, uint64_t *n_hits_total, uint32_t *per_frame_hits,
                         uint64_t *per_frame_photons);

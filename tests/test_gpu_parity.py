@@ -192,12 +192,15 @@ def test_two_detectors_one_context(ctx):
     pdc.release_detector(ctx, d2)
 
 
-@pytest.mark.parametrize("occ_id", [1])
+@pytest.mark.parametrize("occ_id", [0, 1, 2], ids=lambda i: "occupancy_%g" % synth.CSPAD_OCCUPANCIES[i])
 def test_cspad_full_batch(ctx, occ_id):
     """CSPAD-like 32 x 185 x 388, 194-pixel banks, 10,000 frames in one batch
-    (64 distinct frames replicated on the device).  Every frame's counts and
-    photon totals, and every hit, against the oracle's result for its pool
-    frame."""
+    (64 distinct frames replicated on the device), at each occupancy the
+    benchmark sweeps (0.001, 0.01, 0.05 photons per pixel; at 0.05 about 920 M
+    hits).  Every frame's counts and photon totals, and every hit record of
+    every frame, against the oracle's result for its pool frame: the records
+    are written to device memory and compared there, one 64-frame replica of
+    the pool at a time."""
     import torch
 
     from paper_1903_06838_amd import pdc
@@ -205,6 +208,7 @@ def test_cspad_full_batch(ctx, occ_id):
     geom = synth.CSPAD
     occ = synth.CSPAD_OCCUPANCIES[occ_id]
     P, N = 64, 10000
+    print("full batch: occupancy %g, %d frames" % (occ, N), flush=True)
     ped, gain = synth.make_calibration(geom, 1)
     pool = synth.make_frames(geom, ped, gain, P, occ, 1, occ_id)
     want = oracle_threads(pool, ped, gain, geom.bank_cols)
@@ -215,22 +219,35 @@ def test_cspad_full_batch(ctx, occ_id):
         frames[i:i + n].copy_(dpool[:n])
     torch.cuda.synchronize()  # torch's copies run on its stream, the library on the context's
     del dpool
+    idx = np.arange(N) % P
+    total_want = int(want["frame_hits"][idx].sum())
     det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
-    b = pdc.process_frames(ctx, det, frames, N, int(want["total"] * (N / P) * 1.1) + 1, None)
-    hits, total, fh, fp, st = pdc.get_hits(ctx, b, N)
+    b = pdc.process_frames(ctx, det, frames, N, int(total_want * 1.05) + 1, None)
+    recs = torch.empty((total_want + 1, 4), dtype=torch.int32, device="cuda")
+    _, total, fh, fp, st = pdc.get_hits(ctx, b, N, capacity=total_want + 1, dst_dev=recs)
     pdc.release_batch(ctx, b)
     pdc.release_detector(ctx, det)
     del frames
-    idx = np.arange(N) % P
+    assert st == pdc.OK
     assert np.array_equal(fh, want["frame_hits"][idx])
     assert np.array_equal(fp, want["frame_photons"][idx])
-    assert total == int(want["frame_hits"][idx].sum())
-    # expected list: pool frame hits repeated with their batch frame index
-    starts = np.concatenate([[0], np.cumsum(want["frame_hits"])]).astype(np.int64)
-    sel = np.concatenate([np.arange(starts[j], starts[j + 1]) for j in idx])
-    exp = want["hits"][sel].copy()
-    exp["frame"] = np.repeat(np.arange(N, dtype=np.uint32), want["frame_hits"][idx])
-    assert np.array_equal(hits_u32(hits), hits_u32(exp))
+    assert total == total_want
+    # one replica of the pool: its hits with frame indices rebased, compared
+    # record by record on the device
+    ref = torch.from_numpy(hits_u32(want["hits"]).view(np.int32).copy()).cuda()
+    pool_frame = ref[:, 0].clone()
+    per = int(want["total"])
+    for r, f0 in enumerate(range(0, N, P)):
+        nf = min(P, N - f0)
+        nh = int(want["frame_hits"][:nf].sum())
+        got = recs[r * per:r * per + nh]
+        exp = ref[:nh].clone()
+        exp[:, 0] = pool_frame[:nh] + f0
+        if not torch.equal(got, exp):
+            bad = int(torch.nonzero(torch.any(got != exp, dim=1))[0, 0])
+            raise AssertionError("replica %d (frames %d..): record %d is %s, want %s" % (
+                r, f0, r * per + bad, got[bad].tolist(), exp[bad].tolist()))
+    del recs
 
 
 @pytest.fixture(scope="module")
