@@ -196,6 +196,37 @@ pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_
                               uint64_t n_frames, uint64_t hit_capacity, void *hip_stream,
                               uint64_t *batch_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * results of pdc_process_frames + pdc_get_hits (device destination) +
+ * pdc_release_batch in one synchronous call that allocates nothing.  Every
+ * intermediate buffer (batch state, per-unit and per-frame arrays, the
+ * common-mode values of the mean modes, the hit staging pool) lies in a
+ * static device array of PDC_STATIC_SCRATCH_BYTES that each GPU the library
+ * runs on holds until the process ends; its address is taken per device by
+ * pdc_create.  All calls on one GPU share that array and it keeps the last
+ * call's contents: calls that overlap on one GPU (from several threads or
+ * contexts, on any streams) race, so the caller serializes them.
+ * frames_dev: DEVICE uint16 [n_frames][n_tiles][rows][cols] as for
+ *   pdc_process_frames.
+ * hits_dev: DEVICE records, room for hits_capacity (the first
+ *   min(total, hits_capacity) hits in (frame, pixel) order are written).
+ * frame_hits_dev (uint32 [n_frames]) and frame_photons_dev (uint64
+ *   [n_frames]): DEVICE per-frame counts and photon totals.
+ * *n_hits_total (may be NULL): the true total.
+ * Work is enqueued on hip_stream (NULL: the context's stream) and the call
+ * returns when it has finished.  PDC_WARN_TRUNCATED when the total exceeds
+ * hits_capacity.  EINVAL when n_frames needs more per-unit arrays and
+ * staging room than the scratch holds (an ePix100 or CSPAD detector fits
+ * several hundred frames per call), or for a PDC_KEEP_CORRECTED detector
+ * (Frames2 needs a buffer of its own); ENOMEM when the batch's hits
+ * overflow the scratch's staging pool (the outputs are then unspecified);
+ * ESTATE for an unknown detector. */
+#define PDC_STATIC_SCRATCH_BYTES (64ull << 20)
+pdc_status pdc_process_frames_static(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                                     pdc_hit *hits_dev, uint64_t hits_capacity, uint32_t *frame_hits_dev,
+                                     uint64_t *frame_photons_dev, void *hip_stream, uint64_t *n_hits_total);
+
 /* Batches of several detectors (mixed geometries, gain modes and
  * common-mode settings) enqueued at once: item i becomes batch batch_out[i]
  * exactly as pdc_process_frames would make it, on one of up to 8 internal

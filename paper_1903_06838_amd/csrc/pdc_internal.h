@@ -147,6 +147,12 @@ struct HitRecord {
     float charge;
     uint32_t nphot;
 };
+// The staged runs straight into records at their raster positions (first
+// out_cap of them).
+hipError_t launch_scatter_records(const uint32_t *unit_count, const uint64_t *unit_base,
+                                  const uint32_t *unit_local, const unsigned long long *frame_offset,
+                                  const uint2 *pool, uint64_t n_units, int32_t units_per_frame, float photon_adu,
+                                  HitRecord *out, uint64_t out_cap, hipStream_t s);
 // Expand hits [first, first + n) of the raster-order list into records.
 hipError_t launch_format_hits(const uint2 *hits, const unsigned long long *frame_offset,
                               uint64_t n_frames, uint64_t first, uint64_t n, float photon_adu,

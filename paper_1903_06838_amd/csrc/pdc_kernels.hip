@@ -424,6 +424,46 @@ hipError_t launch_scatter(const uint32_t *unit_count, const uint64_t *unit_base,
     return hipGetLastError();
 }
 
+// Like scatter_kernel, but each hit goes straight to its 16-byte record
+// (frame, pixel, charge, photon count) at its raster position; records past
+// out_cap are not written (the caller's destination keeps the first ones).
+__global__ void __launch_bounds__(256)
+scatter_records_kernel(const uint32_t *unit_count, const uint64_t *unit_base, const uint32_t *unit_local,
+                       const unsigned long long *frame_offset, const uint2 *pool, uint64_t n_units, int32_t upf,
+                       float photon_adu, HitRecord *out, uint64_t out_cap)
+{
+    const uint64_t unit = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (unit >= n_units) return;
+    const uint32_t c = unit_count[unit];
+    const uint64_t b = unit_base[unit];
+    if (c == 0 || b == kNoBase) return;
+    const uint64_t f = unit / (uint64_t)upf;
+    const uint64_t dst = frame_offset[f] + unit_local[unit];
+    for (uint32_t i = lane; i < c && dst + i < out_cap; i += 64) {
+        const uint2 h = pool[b + i];
+        const float q = __uint_as_float(h.y);
+        HitRecord r;
+        r.frame = (uint32_t)f;
+        r.pixel = h.x;
+        r.charge = q;
+        r.nphot = photon_count(q, photon_adu);
+        out[dst + i] = r;
+    }
+}
+
+hipError_t launch_scatter_records(const uint32_t *unit_count, const uint64_t *unit_base,
+                                  const uint32_t *unit_local, const unsigned long long *frame_offset,
+                                  const uint2 *pool, uint64_t n_units, int32_t units_per_frame, float photon_adu,
+                                  HitRecord *out, uint64_t out_cap, hipStream_t s)
+{
+    if (n_units == 0) return hipSuccess;
+    uint64_t blocks = (n_units + 3) / 4;
+    hipLaunchKernelGGL(scatter_records_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, unit_count, unit_base,
+                       unit_local, frame_offset, pool, n_units, units_per_frame, photon_adu, out, out_cap);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256)
 format_hits_kernel(const uint2 *hits, const unsigned long long *frame_offset, uint64_t n_frames,
                    uint64_t first, uint64_t n, float photon_adu, HitRecord *out)

@@ -10,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <set>
 #include <string>
@@ -25,6 +26,17 @@ using namespace pdc;
 namespace {
 
 thread_local char g_thread_error[512] = "";
+
+// Device scratch of pdc_process_frames_static, for callers that cannot
+// allocate: a file-scope device array, one copy per GPU for as long as the
+// process lives.  Host code never uses the array's name as an address; its
+// address on each device comes from hipGetSymbolAddress, taken once per
+// device by pdc_create with that device current.
+constexpr uint64_t kStaticScratchBytes = PDC_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+unsigned char *g_scratch_ptr[kMaxDevices] = {};
 
 // LDS budget of the v1 frame kernel (bytes per workgroup).
 constexpr size_t kV1LdsBudget = 64 * 1024;
@@ -107,6 +119,8 @@ struct Batch {
     pdc_graph *graph = nullptr;  // launched from this graph, whose buffers it holds
     int gitem = 0;               // its item in that graph
     Buffers *buf = nullptr;
+    HitRecord *records = nullptr;  // pdc_process_frames_static: hits go straight to these records
+    uint64_t records_cap = 0;
 };
 
 void free_buffers(Buffers *b)
@@ -543,8 +557,13 @@ pdc_status enqueue_tail(pdc_ctx *ctx, Batch &bt)
     HIP_TRY(ctx, launch_frame_sums(b->unit_count, b->unit_photons, bt.n_frames, bt.upf,
                                    b->unit_local, b->frame_hits, b->frame_photons, s));
     HIP_TRY(ctx, launch_frame_scan(b->frame_hits, bt.n_frames, b->frame_offset, b->state, s));
-    HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
-                                bt.n_units, bt.upf, b->hits, b->cap_pool, s));
+    if (bt.records)
+        HIP_TRY(ctx, launch_scatter_records(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
+                                            bt.n_units, bt.upf, ctx->dets[bt.det].p.photon_adu, bt.records,
+                                            bt.records_cap, s));
+    else
+        HIP_TRY(ctx, launch_scatter(b->unit_count, b->unit_base, b->unit_local, b->frame_offset, b->pool,
+                                    bt.n_units, bt.upf, b->hits, b->cap_pool, s));
     if (bt.capture) return PDC_OK;
     return record_end(ctx, b, s);
 }
@@ -835,6 +854,15 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
         delete ctx;
         return fail(nullptr, PDC_EDEVICE, "stream creation failed");
     }
+    if (device < kMaxDevices) {
+        // the static scratch's address on this device (device current)
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[device]) {
+            void *p = nullptr;
+            if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+                g_scratch_ptr[device] = static_cast<unsigned char *>(p);
+        }
+    }
     *out = ctx;
     return PDC_OK;
 }
@@ -944,6 +972,101 @@ pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_
                               uint64_t hit_capacity, void *hip_stream, uint64_t *batch_out)
 {
     return process_batch(ctx, det, frames_dev, n_frames, hit_capacity, hip_stream, 1.0, batch_out);
+}
+
+pdc_status pdc_process_frames_static(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                                     pdc_hit *hits_dev, uint64_t hits_capacity, uint32_t *frame_hits_dev,
+                                     uint64_t *frame_photons_dev, void *hip_stream, uint64_t *n_hits_total)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    Detector &d = ctx->dets[det];
+    if (d.p.flags & PDC_KEEP_CORRECTED)
+        return fail(ctx, PDC_EINVAL, "static: a PDC_KEEP_CORRECTED detector needs pdc_process_frames (Frames2 buffer)");
+    if (n_frames == 0) {
+        if (n_hits_total) *n_hits_total = 0;
+        return PDC_OK;
+    }
+    if (!frames_dev || !frame_hits_dev || !frame_photons_dev || (hits_capacity > 0 && !hits_dev))
+        return fail(ctx, PDC_EINVAL, "static: frames_dev, frame_hits_dev, frame_photons_dev (and hits_dev) must be non-NULL");
+    if (n_frames > ((uint64_t)1 << 31)) return fail(ctx, PDC_EINVAL, "n_frames must be <= 2^31");
+    unsigned char *base = ctx->device < kMaxDevices ? g_scratch_ptr[ctx->device] : nullptr;
+    if (!base) return fail(ctx, PDC_EDEVICE, "static: no address of the static scratch on device %d", ctx->device);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Batch bt;
+    bt.det = det;
+    bt.frames = frames_dev;
+    bt.n_frames = n_frames;
+    set_path(d, bt, d.v2_ok ? 2 : 1);
+    bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    bt.capture = true;  // kernels only: no events, no copies to pinned memory
+    bt.records = reinterpret_cast<HitRecord *>(hits_dev);
+    bt.records_cap = hits_capacity;
+    // carve the scratch: batch state, per-unit and per-frame arrays, the
+    // common-mode values of the mean modes, then the staging pool
+    Buffers b;
+    uint64_t off = 0;
+    bool fits = true;
+    auto carve = [&](uint64_t bytes) -> unsigned char * {
+        off = (off + 255) & ~(uint64_t)255;
+        unsigned char *p = base + off;
+        if (bytes > kStaticScratchBytes - std::min(off, kStaticScratchBytes)) fits = false;
+        off += bytes;
+        return p;
+    };
+    const uint64_t U = n_frames * (uint64_t)std::max(d.units_per_frame, d.n_strips);  // either path
+    b.state = reinterpret_cast<BatchState *>(carve(sizeof(BatchState)));
+    b.unit_count = reinterpret_cast<uint32_t *>(carve(4 * U));
+    b.unit_photons = reinterpret_cast<unsigned long long *>(carve(8 * U));
+    b.unit_base = reinterpret_cast<uint64_t *>(carve(8 * U));
+    b.unit_local = reinterpret_cast<uint32_t *>(carve(4 * U));
+    b.fb_units = reinterpret_cast<uint64_t *>(carve(8 * U));
+    b.frame_offset = reinterpret_cast<unsigned long long *>(carve(8 * (n_frames + 1)));
+    b.invalid = reinterpret_cast<uint32_t *>(carve(4 * n_frames));
+    b.cm = reinterpret_cast<float *>(carve(4 * cm_floats(d, bt)));
+    b.frame_hits = frame_hits_dev;
+    b.frame_photons = reinterpret_cast<unsigned long long *>(frame_photons_dev);
+    off = (off + 255) & ~(uint64_t)255;
+    const uint64_t pool_bytes = fits && off < kStaticScratchBytes ? kStaticScratchBytes - off : 0;
+    b.pool = reinterpret_cast<uint2 *>(base + std::min(off, kStaticScratchBytes));
+    b.cap_pool = pool_bytes / sizeof(uint2);
+    bt.buf = &b;
+    // room for the staging chunks every workgroup may hold open
+    const uint64_t slack = pool_capacity(d, bt.path, 0, batch_grid(d, bt));
+    if (!fits || b.cap_pool <= slack)
+        return fail(ctx, PDC_EINVAL,
+                    "static: %llu frames need more than the %llu-byte static scratch (per-unit arrays and staging "
+                    "slack); process fewer frames per call",
+                    (unsigned long long)n_frames, (unsigned long long)kStaticScratchBytes);
+    bt.pool_cap = b.cap_pool;
+    BatchState st{};
+    auto wait_state = [&]() -> pdc_status {
+        HIP_TRY(ctx, hipMemcpyAsync(&st, b.state, sizeof st, hipMemcpyDeviceToHost, bt.stream));
+        HIP_TRY(ctx, hipStreamSynchronize(bt.stream));
+        return PDC_OK;
+    };
+    pdc_status rc = enqueue(ctx, bt);
+    if (rc == PDC_OK) rc = wait_state();
+    if (rc == PDC_OK && st.fallback && !st.overflow) {
+        if (bt.path == 2 && d.fb_ok) {
+            // strip-frames whose seeds overflowed the on-chip lists: the
+            // general kernel redoes them into the same staging pool
+            rc = enqueue_partial(ctx, bt, st.n_fallback);
+        } else {
+            set_path(d, bt, 1);
+            rc = enqueue(ctx, bt);
+        }
+        if (rc == PDC_OK) rc = wait_state();
+    }
+    if (rc != PDC_OK) return rc;
+    if (st.overflow)
+        return fail(ctx, PDC_ENOMEM,
+                    "static: the batch's hits overflow the staging pool of the static scratch (%llu entries); "
+                    "process fewer frames per call",
+                    (unsigned long long)bt.pool_cap);
+    if (n_hits_total) *n_hits_total = st.total;
+    return st.total > hits_capacity ? PDC_WARN_TRUNCATED : PDC_OK;
 }
 
 pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t n_items, void *hip_stream,

@@ -104,6 +104,8 @@ _sig = {
     "pdc_graph_destroy": (_st, [_P]),
     "pdc_graph_create_mixed": (_st, [_P, _P, ctypes.c_int32, ctypes.POINTER(_P)]),
     "pdc_graph_items": (ctypes.c_int32, [_P]),
+    "pdc_process_frames_static": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, _P, ctypes.c_uint64, _P, _P, _P,
+                                        ctypes.POINTER(ctypes.c_uint64)]),
     "pdc_stream_read": (_st, [_P, _P, ctypes.c_uint64, _P, ctypes.POINTER(ctypes.c_float)]),
     "pdc_debug_serve_batch_len": (_st, [_P, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                         ctypes.POINTER(ctypes.c_uint64)]),
@@ -266,6 +268,20 @@ def debug_batch_path(ctx, batch: int) -> int:
     p = ctypes.c_int32(0)
     _check(_lib.pdc_debug_batch_path(ctx, batch, ctypes.byref(p)), ctx)
     return p.value
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def process_frames_static(ctx, det: int, frames_dev, n_frames: int, hits_dev, hits_capacity: int,
+                          frame_hits_dev, frame_photons_dev, stream=None):
+    """pdc_process_frames_static: results in the caller's device tensors, no
+    allocation; returns (status, total hits)."""
+    total = ctypes.c_uint64(0)
+    st = _check(_lib.pdc_process_frames_static(ctx, det, _ptr(frames_dev), n_frames, _ptr(hits_dev), hits_capacity,
+                                               _ptr(frame_hits_dev), _ptr(frame_photons_dev), _stream(stream),
+                                               ctypes.byref(total)), ctx)
+    return st, total.value
 
 
 def stream_read(ctx, src_dev, nbytes: int, stream=None) -> float:
