@@ -15,15 +15,21 @@ the output of stage s - 1.
 
 Readings fixed here (the paper leaves them open):
 * binary32 throughout; Frames2 = fl(v - CM) at each stage;
-* the sum: pixel i of the region (raster order inside the region) goes to
-  partial sum i mod P, partials start at +0.0 and add their pixels in
-  increasing i; the P partials are then added in a balanced binary tree
-  (neighbours (0,1), (2,3), ... first).  P = 64 for a bank, 256 for a tile;
-* a pixel that is not below T adds nothing;
+* the sum has no order: it is the exact sum of the region's noise pixels
+  (a rational number), rounded once to the nearest binary32, ties to even;
+  a pixel that is not below T adds nothing;
 * N0 is converted to binary32, the guard is fl(sqrt(fl(region size))), and
   CM = fl(sum / max(N0, guard)).
+
+The exact sum is computed with integers: a binary32 x is M 2^(E - 150),
+M its 24-bit significand and E its exponent field (E = 1 and M the fraction
+for subnormals), so every value is an integer multiple of 2^-149; the
+multiples M are summed per exponent in int64 and the per-exponent sums are
+combined in Python's unbounded integers before the one rounding.
 """
 from __future__ import annotations
+
+import math
 
 import numpy as np
 
@@ -31,30 +37,55 @@ F32 = np.float32
 
 BANK = 1
 TILE = 2
-PARTIALS = {BANK: 64, TILE: 256}
 
 
-def tree_sum(parts):
-    """Balanced binary tree over the last axis (a power of two long)."""
-    p = np.asarray(parts, F32)
-    while p.shape[-1] > 1:
-        p = (p[..., 0::2] + p[..., 1::2]).astype(F32)
-    return p[..., 0]
+def round_to_f32(n):
+    """The binary32 nearest to n * 2^-149 (n a Python int), ties to even."""
+    if n == 0:
+        return F32(0.0)
+    neg = n < 0
+    a = -n if neg else n
+    if a < (1 << 24):  # subnormal or normal with the unit 2^-149: exact
+        r = math.ldexp(a, -149)
+    else:
+        sh = a.bit_length() - 24
+        q, rem = a >> sh, a & ((1 << sh) - 1)
+        half = 1 << (sh - 1)
+        if rem > half or (rem == half and q & 1):
+            q += 1
+        r = math.ldexp(q, sh - 149)  # q <= 2^24: exact in a double
+    r = F32(r)
+    assert np.isfinite(r), "sum beyond the binary32 range"
+    return F32(-r) if neg else r
 
 
-def region_cm(x, t_cm, n_partials):
-    """x float32 [regions, n] (each region's pixels in raster order); returns
-    (cm float32 [regions], n0 int64 [regions])."""
+def exact_sums(vals):
+    """vals float32 [R, n] -> float32 [R]: each row's exact sum rounded once
+    to binary32 (ties to even)."""
+    v = np.ascontiguousarray(vals, F32)
+    R, n = v.shape
+    b = v.view(np.uint32).astype(np.int64)
+    e = (b >> 23) & 0xFF
+    frac = b & 0x7FFFFF
+    m = np.where(e > 0, frac | (1 << 23), frac)
+    m = np.where(b >> 31 == 1, -m, m)
+    e = np.maximum(e, 1)
+    per = np.zeros((R, 256), np.int64)  # |sum| <= n 2^24 per exponent
+    np.add.at(per, (np.repeat(np.arange(R), n), e.ravel()), m.ravel())
+    out = np.zeros(R, F32)
+    for r in range(R):
+        nz = np.nonzero(per[r])[0]
+        out[r] = round_to_f32(sum(int(per[r, k]) << int(k - 1) for k in nz))
+    return out
+
+
+def region_cm(x, t_cm):
+    """x float32 [regions, n] (each region's pixels); returns (cm float32
+    [regions], n0 int64 [regions])."""
     x = np.asarray(x, F32)
     R, n = x.shape
     mask = x < F32(t_cm)
-    vals = np.where(mask, x, F32(0))
-    part = np.zeros((R, n_partials), F32)
-    for k0 in range(0, n, n_partials):
-        chunk = vals[:, k0:k0 + n_partials]
-        w = chunk.shape[1]
-        part[:, :w] = (part[:, :w] + chunk).astype(F32)
-    s = tree_sum(part)
+    s = exact_sums(np.where(mask, x, F32(0)))
     n0 = np.count_nonzero(mask, axis=1)
     guard = F32(np.sqrt(F32(n)))
     N = np.maximum(n0.astype(F32), guard)
@@ -80,7 +111,7 @@ def common_mode(frames1, region, bank_cols, stages, t_cm):
     x = _regions(v, region, bank_cols)
     cms = np.zeros((x.shape[0], 3), F32)
     for s in range(stages):
-        c, _ = region_cm(x, t_cm, PARTIALS[region])
+        c, _ = region_cm(x, t_cm)
         cms[:, s] = c
         x = (x - c[:, None]).astype(F32)
     return x.reshape(shape), cms

@@ -1,6 +1,11 @@
 """Pins for the thresholded-mean common-mode oracle (oracle/cm_mean.py): closed
-forms, the guard, the summation order worked by hand, stacked stages worked by
-hand, and the float64 mean within its rounding bound.  CPU only."""
+forms, the guard, exact sums worked by hand (where a left-to-right sum and a
+tree of partial sums both differ from the exactly rounded one), ties of the
+one rounding, order invariance, the integer method against Fractions with an
+independent nearest-float search, stacked stages worked by hand, and the
+float64 mean within two roundings.  CPU only."""
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -35,31 +40,64 @@ def test_guard_limits_few_noise_pixels():
     assert cms[0, 0] == 0.0
 
 
-def test_sum_order_interleaved_then_tree_bank():
-    # B = 4: partials hold one pixel each; the tree adds (p0 + p1) + (p2 + p3):
-    # fl(2^24 + 1) = 2^24 (tie to even), fl(1 - 2^24) = -(2^24 - 1), sum 1;
-    # left to right would give 0, the exact sum is 2.
+def test_exact_sum_by_hand():
+    # [2^24, 1, 1, -2^24]: the exact sum is 2 (a left-to-right binary32 sum
+    # gives 0, the tree (p0 + p1) + (p2 + p3) gives 1); CM = 2 / 4
     f1, B = _bank([BIG, 1.0, 1.0, -BIG])
     _, cms = M.common_mode(f1, M.BANK, B, 1, 2.0 ** 25)
-    assert cms[0, 0] == F32(1.0) / F32(4.0)
-    # B = 128: pixel i goes to partial i mod 64; partial 0 = fl(2^24 + 1) = 2^24,
-    # partial 1 = fl(1 - 2^24); sum 1, N = 128
-    v = np.zeros(128, F32)
-    v[0], v[64], v[1], v[65] = BIG, 1.0, 1.0, -BIG
-    _, cms = M.common_mode(v.reshape(1, 1, 128), M.BANK, 128, 1, 2.0 ** 25)
-    assert cms[0, 0] == F32(1.0 / 128)
+    assert cms[0, 0] == F32(0.5)
+    # [2^24, 1, 1/4, 1/4]: exact 2^24 + 1.5, rounded once to 2^24 + 2 (both
+    # orders above give 2^24); CM = (2^24 + 2) / 4 = 2^22 + 1/2
+    f1, B = _bank([BIG, 1.0, 0.25, 0.25])
+    _, cms = M.common_mode(f1, M.BANK, B, 1, 2.0 ** 25)
+    assert cms[0, 0] == F32(2.0 ** 22 + 0.5)
 
 
-def test_sum_order_tile_uses_256_partials():
-    # a 2 x 256 tile: pixel (r, c) goes to partial c; the same pixels in a bank
-    # region (one row each) give different sums
-    v = np.zeros((1, 2, 256), F32)
-    v[0, 0, 0], v[0, 1, 0], v[0, 0, 1], v[0, 1, 1] = BIG, 1.0, 1.0, -BIG
-    _, cms = M.common_mode(v, M.TILE, 256, 1, 2.0 ** 25)
-    assert cms[0, 0] == F32(1.0 / 512)
-    _, cb = M.common_mode(v, M.BANK, 256, 1, 2.0 ** 25)
-    # row 0: partial 0 = 2^24, partial 1 = 1 -> (2^24 + 1) = 2^24; row 1: 1 - 2^24
-    assert cb[0, 0] == BIG / F32(256) and cb[1, 0] == F32(1.0 - 2.0 ** 24) / F32(256)
+def test_one_rounding_ties_to_even():
+    # 2^24 + 1 lies halfway between 2^24 and 2^24 + 2: the even one is 2^24;
+    # 2^24 + 3 lies halfway between 2^24 + 2 and 2^24 + 4: the even one is 2^24 + 4
+    assert M.exact_sums(np.array([[BIG, 1.0, 0.0, 0.0]], F32))[0] == BIG
+    assert M.exact_sums(np.array([[BIG + F32(2.0), 1.0, 0.0, 0.0]], F32))[0] == F32(2.0 ** 24 + 4)
+    # the same below zero, and a sum that cancels to +0
+    assert M.exact_sums(np.array([[-BIG, -1.0]], F32))[0] == -BIG
+    z = M.exact_sums(np.array([[3.5, -3.5, 0.0]], F32))[0]
+    assert z == 0.0 and not np.signbit(z)
+
+
+def test_sum_has_no_order():
+    rng = np.random.default_rng(7)
+    x = (rng.normal(0.0, 1.0, size=(40, 194)) * np.exp2(rng.integers(-30, 30, size=(40, 194)))).astype(F32)
+    want = M.exact_sums(x)
+    for _ in range(5):
+        perm = rng.permutation(194)
+        assert np.array_equal(M.exact_sums(x[:, perm]).view(np.uint32), want.view(np.uint32))
+    # a tile's sum is the exact sum over all its rows, whatever the row split
+    v = x.reshape(1, 20, 388)
+    _, ct = M.common_mode(v, M.TILE, 194, 1, 1e30)
+    assert ct[0, 0] == F32(M.exact_sums(x.reshape(1, -1))[0] / F32(40 * 194))
+
+
+def _nearest_f32(q):
+    """Nearest binary32 to the Fraction q, ties to even, by searching the
+    neighbours of the double nearest to q (independent of the oracle)."""
+    d = np.float32(float(q))
+    cands = {d, np.nextafter(d, np.float32(np.inf)), np.nextafter(d, np.float32(-np.inf))}
+    best = sorted(cands, key=lambda f: (abs(Fraction(float(f)) - q), int(np.float32(f).view(np.uint32)) & 1))
+    return np.float32(best[0])
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_exact_sums_against_fractions(seed):
+    rng = np.random.default_rng(seed)
+    R, n = 30, 50
+    mag = np.exp2(rng.integers(-149, 60, size=(R, n)).astype(np.float64))
+    x = (rng.choice([-1.0, 1.0], size=(R, n)) * mag * rng.uniform(1.0, 2.0, size=(R, n))).astype(F32)
+    x[rng.random((R, n)) < 0.2] = 0.0
+    x[0, :] = np.float32(2.0 ** -149) * rng.integers(-5, 6, size=n).astype(F32)  # subnormals
+    got = M.exact_sums(x)
+    for r in range(R):
+        q = sum(Fraction(float(v)) for v in x[r])
+        assert got[r] == _nearest_f32(q), (r, got[r])
 
 
 def test_stacked_stages_by_hand():
@@ -93,10 +131,9 @@ def test_close_to_float64_mean(region, shape):
     m = x < t
     n0 = m.sum(axis=1)
     want = (x * m).sum(axis=1) / np.maximum(n0, np.sqrt(x.shape[1]))
-    # rounding bound of a sum of n terms: about n * eps * sum |x|
-    bound = x.shape[1] * 2.0 ** -23 * (np.abs(x) * m).sum(axis=1) / np.maximum(n0, 1) + 1e-6
-    assert np.all(np.abs(cms[:, 0] - want) <= bound)
-    assert np.max(np.abs(cms[:, 0] - want)) < 1e-4
+    # two roundings (the exact sum, then the quotient) and the float64 sum's
+    # own error, far smaller
+    assert np.all(np.abs(cms[:, 0] - want) <= 2.0 ** -22 * np.abs(want) + 1e-9)
 
 
 def test_process_reduces_to_find_hits():

@@ -106,7 +106,7 @@ def test_cm_mean_guard_at_high_occupancy(ctx):
     from oracle import oracle as C
 
     f1 = C.load().dark_gain(raw[0], ped, gain)
-    _, n0 = M.region_cm(M._regions(f1, M.BANK, 194), np.float32(9.0), 64)
+    _, n0 = M.region_cm(M._regions(f1, M.BANK, 194), np.float32(9.0))
     assert np.count_nonzero(n0 < np.sqrt(194)) > 5
     want = M.process(raw, ped, gain, 194, M.BANK, 3, keep_corrected=True)
     got = _run(ctx, raw, ped, gain, 194, M.BANK, 3)
