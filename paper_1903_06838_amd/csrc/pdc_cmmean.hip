@@ -4,17 +4,17 @@
 //   noise pixels: v < t_cm;  N0 = their number;  S = their sum;
 //   CM_s = S / max(N0, guard),  guard = sqrt(region size) in binary32;
 //   v <- v - CM_s  (the next stage segments the corrected values).
-// S is a binary32 sum in a fixed order: pixel i of the region (raster order)
-// is added to partial sum i mod P (P = 64 for a bank, 256 for a tile) in
-// increasing i from +0.0, then the partials are added in a balanced binary
-// tree.  A lane owns one partial; a butterfly over lanes xor 1, 2, 4, ...
-// forms the tree exactly, since each pair adds the same two values.
+// S is the exact sum of the noise values rounded once to binary32 (ties to
+// even), so no order of summation enters: each lane adds its values into
+// binary64 limbs exactly, and the lanes' limbs are put together in a
+// multiword integer (pdc_exact.h).
 // The frame kernels then subtract CM_1, CM_2, CM_3 in turn (zeros for unused
 // stages: x - 0 = x bit for bit).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include "pdc_device.h"
+#include "pdc_exact.h"
 #include "pdc_internal.h"
 
 #pragma clang fp contract(off)
@@ -24,13 +24,6 @@ namespace pdc {
 namespace {
 
 constexpr int kCmThreads = 256;
-
-__device__ __forceinline__ float tree64(float p)
-{
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) p = __fadd_rn(p, __shfl_xor(p, d, 64));
-    return p;
-}
 
 __device__ __forceinline__ uint32_t sum64(uint32_t n)
 {
@@ -74,7 +67,7 @@ __global__ __launch_bounds__(kCmThreads) void cm_bank_kernel(CmArgs a)
             const uint16_t *fr = a.frames + (f0 + j) * npix + p0;
 #pragma unroll
             for (int k = 0; k < KV; ++k) {
-                x[j][k] = 0.0f;
+                x[j][k] = __builtin_inff();  // absent column or frame: never noise
                 if (j < nf && ok[k]) {
                     const uint32_t w = fr[lane + 64 * k];
                     bool bad;
@@ -85,25 +78,24 @@ __global__ __launch_bounds__(kCmThreads) void cm_bank_kernel(CmArgs a)
             }
         }
         float cs[F][3];
+        SumWindow win[F];
 #pragma unroll
-        for (int j = 0; j < F; ++j) cs[j][0] = cs[j][1] = cs[j][2] = 0.0f;
+        for (int j = 0; j < F; ++j) {
+            cs[j][0] = cs[j][1] = cs[j][2] = 0.0f;
+            win[j] = {a.sum_lo, a.sum_hi};
+        }
 #pragma unroll
         for (int s = 0; s < 3; ++s) {
             if (s >= a.stages) break;
 #pragma unroll
             for (int j = 0; j < F; ++j) {
-                float part = 0.0f;
-                uint32_t n0 = 0;
-#pragma unroll
-                for (int k = 0; k < KV; ++k)
-                    if (ok[k] && x[j][k] < a.t_cm) {
-                        part = __fadd_rn(part, x[j][k]);
-                        ++n0;
-                    }
-                const float sum = tree64(part);
-                const uint32_t n = sum64(n0);
+                int n0;
+                bool fits;
+                const float sum = region_sum<64, KV>(x[j], a.t_cm, (uint32_t)a.B, win[j], n0, fits);
+                const uint32_t n = sum64((uint32_t)n0);
                 const float c = __fdiv_rn(sum, fmaxf((float)n, a.guard));
                 cs[j][s] = c;
+                win[j] = next_window(win[j], c);
 #pragma unroll
                 for (int k = 0; k < KV; ++k) x[j][k] = __fsub_rn(x[j][k], c);
             }
@@ -125,73 +117,151 @@ __global__ __launch_bounds__(kCmThreads) void cm_bank_kernel(CmArgs a)
     }
 }
 
+// Window of stage s of a tile item (F frames from f0, nf of them): the union
+// of the frames' windows.  Returns false when the two-limb way cannot hold
+// it with K-bit limbs.
+template <int F>
+__device__ __forceinline__ bool tile_window(const CmArgs &a, int s, uint64_t f0, uint32_t t, int nf, int K,
+                                            float (&c0)[F], float (&c1)[F], int &lo)
+{
+    int l = a.sum_lo, h = a.sum_hi;
+#pragma unroll
+    for (int j = 0; j < F; ++j) {
+        const float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
+        c0[j] = (s > 0 && j < nf) ? cv[0] : 0.0f;
+        c1[j] = (s > 1 && j < nf) ? cv[1] : 0.0f;
+        SumWindow w = next_window(next_window({a.sum_lo, a.sum_hi}, c0[j]), c1[j]);
+        l = w.lo < l ? w.lo : l;
+        h = w.hi > h ? w.hi : h;
+    }
+    lo = l;
+    return h - l <= 2 * K;
+}
+
+// One pixel of a tile at stage s: Frames1 less the earlier stages' values.
+__device__ __forceinline__ float tile_value(const CmArgs &a, int s, uint32_t w, float pp, float kp, uint64_t p,
+                                            uint64_t npix, float c0, float c1)
+{
+    bool bad;
+    // an invalid pixel is +inf: never below t_cm, and stays +inf
+    float y = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, pp, kp, a.ped, a.k, npix, p, bad) : dark_gain(w, pp, kp);
+    if (s > 0) y = __fsub_rn(y, c0);
+    if (s > 1) y = __fsub_rn(y, c1);
+    return y;
+}
+
+// General-way sum of stage s over one tile and frame f (values beyond the
+// two-limb window): the lanes of the workgroup (or wave, with nt = 64) add
+// pixels tid, tid + nt, ... in eight 28-bit limbs of unit 2^-149.
+__device__ __forceinline__ Wide<4> tile_sum_general(const CmArgs &a, int s, uint64_t f, uint32_t t, float c0, float c1,
+                                                    uint32_t tid, uint32_t nt, uint32_t &n0)
+{
+    constexpr int NL = kGenNL25, KG = kGenK25;
+    const uint32_t HW = (uint32_t)a.H * (uint32_t)a.W;
+    const uint64_t npix = (uint64_t)a.T * HW;
+    double pw[NL], ipw[NL], q[NL];
+#pragma unroll
+    for (int i = 0; i < NL; ++i) {
+        pw[i] = __builtin_ldexp(1.0, KG * i);
+        ipw[i] = __builtin_ldexp(1.0, -KG * i);
+        q[i] = 0.0;
+    }
+    const double sc = __builtin_ldexp(1.0, 149);
+    const uint16_t *fr = a.frames + f * npix + (uint64_t)t * HW;
+    const uint64_t pbase = (uint64_t)t * HW;
+    n0 = 0;
+    for (uint32_t p = tid; p < HW; p += nt) {
+        const float y = tile_value(a, s, fr[p], a.ped[pbase + p], a.k[pbase + p], pbase + p, npix, c0, c1);
+        const bool nz = y < a.t_cm;
+        n0 += nz;
+        limbs_add<NL>(q, nz ? y : 0.0f, sc, pw, ipw);
+    }
+    return wide_from_limbs<4>(q, KG);
+}
+
 // Stage s of the tile regions: one workgroup per (tile, group of F frames);
-// thread j owns partial j (pixels p = j + 256 k of the tile) of each frame;
-// waves hold partials 64w..64w+63.  Dark and 1/gain are read once per F frames.
+// thread j adds pixels j + 256 k of the tile in each frame; dark and 1/gain
+// are read once per F frames.
 template <int F>
 __global__ __launch_bounds__(kCmThreads) void cm_tile_kernel(CmArgs a, int s)
 {
-    __shared__ float s_part[kCmThreads / 64][F];
+    __shared__ Wide<4> s_part[kCmThreads / 64][F];
     __shared__ uint32_t s_cnt[kCmThreads / 64][F];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint64_t nfg = (a.n_frames + F - 1) / F;
     const uint64_t items = nfg * (uint64_t)a.T;
     const uint32_t HW = (uint32_t)a.H * (uint32_t)a.W;
     const uint64_t npix = (uint64_t)a.T * HW;
+    const int K = 53 - clog2((HW + kCmThreads - 1) / kCmThreads);  // values one thread adds per frame
     for (uint64_t it = blockIdx.x; it < items; it += gridDim.x) {
         const uint64_t fg = it / (uint64_t)a.T;
         const uint32_t t = (uint32_t)(it - fg * (uint64_t)a.T);
         const uint64_t f0 = fg * F;
         const int nf = (int)(a.n_frames - f0 < (uint64_t)F ? a.n_frames - f0 : (uint64_t)F);
-        float c0[F], c1[F], part[F];
+        float c0[F], c1[F];
+        int lo;
+        const bool fast = tile_window<F>(a, s, f0, t, nf, K, c0, c1, lo);
+        Wide<4> S[F];
         uint32_t n0[F];
-#pragma unroll
-        for (int j = 0; j < F; ++j) {
-            const float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
-            c0[j] = (s > 0 && j < nf) ? cv[0] : 0.0f;
-            c1[j] = (s > 1 && j < nf) ? cv[1] : 0.0f;
-            part[j] = 0.0f;
-            n0[j] = 0;
-        }
-        const uint16_t *fr = a.frames + f0 * npix + (uint64_t)t * HW;
-        const float *pd = a.ped + (uint64_t)t * HW;
-        const float *kk = a.k + (uint64_t)t * HW;
-#pragma unroll 4
-        for (uint32_t p = threadIdx.x; p < HW; p += kCmThreads) {
-            const float pp = pd[p], kp = kk[p];
+        if (fast) {
+            const double sc = __builtin_ldexp(1.0, -lo), sk = __builtin_ldexp(1.0, -lo - K),
+                         pk = __builtin_ldexp(1.0, K);
+            double q0[F], q1[F];
 #pragma unroll
             for (int j = 0; j < F; ++j) {
-                if (j >= nf) break;
-                const uint32_t w = fr[j * npix + p];
-                bool bad;
-                // an invalid pixel is +inf: never below t_cm, and stays +inf
-                float y = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, pp, kp, a.ped, a.k, npix,
-                                                         (uint64_t)t * HW + p, bad)
-                                      : dark_gain(w, pp, kp);
-                if (s > 0) y = __fsub_rn(y, c0[j]);
-                if (s > 1) y = __fsub_rn(y, c1[j]);
-                if (y < a.t_cm) {
-                    part[j] = __fadd_rn(part[j], y);
-                    ++n0[j];
+                q0[j] = q1[j] = 0.0;
+                n0[j] = 0;
+            }
+            const uint16_t *fr = a.frames + f0 * npix + (uint64_t)t * HW;
+            const float *pd = a.ped + (uint64_t)t * HW;
+            const float *kk = a.k + (uint64_t)t * HW;
+#pragma unroll 2
+            for (uint32_t p = threadIdx.x; p < HW; p += kCmThreads) {
+                const float pp = pd[p], kp = kk[p];
+#pragma unroll
+                for (int j = 0; j < F; ++j) {
+                    if (j >= nf) break;
+                    const float y = tile_value(a, s, fr[j * npix + p], pp, kp, (uint64_t)t * HW + p, npix, c0[j], c1[j]);
+                    const bool nz = y < a.t_cm;
+                    n0[j] += nz;
+                    limbs2_add(q0[j], q1[j], nz ? y : 0.0f, sc, sk, pk);
                 }
+            }
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                const double q[2] = {q0[j], q1[j]};
+                S[j] = wide_from_limbs<4>(q, K);
+            }
+        } else {
+            lo = -149;
+#pragma unroll
+            for (int j = 0; j < F; ++j) {
+                n0[j] = 0;
+                S[j] = Wide<4>{{0, 0, 0, 0}};
+                if (j < nf) S[j] = tile_sum_general(a, s, f0 + j, t, c0[j], c1[j], threadIdx.x, kCmThreads, n0[j]);
             }
         }
 #pragma unroll
         for (int j = 0; j < F; ++j) {
-            const float ps = tree64(part[j]);
+            wave_sum_wide(S[j]);
             const uint32_t ns = sum64(n0[j]);
             if (lane == 0) {
-                s_part[wave][j] = ps;
+                s_part[wave][j] = S[j];
                 s_cnt[wave][j] = ns;
             }
         }
         __syncthreads();
         if (threadIdx.x < nf) {
             const int j = threadIdx.x;
-            const float sum = __fadd_rn(__fadd_rn(s_part[0][j], s_part[1][j]), __fadd_rn(s_part[2][j], s_part[3][j]));
-            const uint32_t n = s_cnt[0][j] + s_cnt[1][j] + s_cnt[2][j] + s_cnt[3][j];
+            Wide<4> sum = s_part[0][j];
+            uint32_t n = s_cnt[0][j];
+#pragma unroll
+            for (int w = 1; w < kCmThreads / 64; ++w) {
+                wide_add(sum, s_part[w][j]);
+                n += s_cnt[w][j];
+            }
             float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
-            cv[s] = __fdiv_rn(sum, fmaxf((float)n, a.guard));
+            cv[s] = __fdiv_rn(wide_round(sum, lo), fmaxf((float)n, a.guard));
             if (s == 0) {
                 cv[1] = 0.0f;
                 cv[2] = 0.0f;
@@ -203,10 +273,8 @@ __global__ __launch_bounds__(kCmThreads) void cm_tile_kernel(CmArgs a, int s)
 
 // Stage s of the tile regions when every tile and frame starts on a 4-pixel
 // boundary (single gain range): one wave per (tile, group of F frames); lane
-// l owns partials 4l .. 4l + 3, that is pixels 256 k + 4 l + i, which it reads
-// as one 8-byte group of raw words and one 16-byte group of dark and 1/gain
-// values per k.  The partials' tree is the same balanced one: its first two
-// levels inside the lane, (q0 + q1) + (q2 + q3), the other six across lanes.
+// l adds pixels 256 k + 4 l + i, which it reads as one 8-byte group of raw
+// words and one 16-byte group of dark and 1/gain values per k.
 template <int F>
 __global__ __launch_bounds__(kCmThreads) void cm_tile_wide_kernel(CmArgs a, int s)
 {
@@ -216,56 +284,76 @@ __global__ __launch_bounds__(kCmThreads) void cm_tile_wide_kernel(CmArgs a, int 
     const uint32_t HW = (uint32_t)a.H * (uint32_t)a.W;
     const uint64_t npix = (uint64_t)a.T * HW;
     const uint64_t nwaves = ((uint64_t)gridDim.x * kCmThreads) >> 6;
+    const int K = 53 - clog2(4u * ((HW + 255u) / 256u));  // values one lane adds per frame
     for (uint64_t it = ((uint64_t)blockIdx.x * kCmThreads + threadIdx.x) >> 6; it < items; it += nwaves) {
         const uint64_t fg = it / (uint64_t)a.T;
         const uint32_t t = (uint32_t)(it - fg * (uint64_t)a.T);
         const uint64_t f0 = fg * F;
         const int nf = (int)(a.n_frames - f0 < (uint64_t)F ? a.n_frames - f0 : (uint64_t)F);
-        float c0[F], c1[F], part[F][4];
-        uint32_t n0[F];
-#pragma unroll
-        for (int j = 0; j < F; ++j) {
-            const float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
-            c0[j] = (s > 0 && j < nf) ? cv[0] : 0.0f;
-            c1[j] = (s > 1 && j < nf) ? cv[1] : 0.0f;
-            part[j][0] = part[j][1] = part[j][2] = part[j][3] = 0.0f;
-            n0[j] = 0;
-        }
-        const uint16_t *fr = a.frames + f0 * npix + (uint64_t)t * HW;
-        const float *pd = a.ped + (uint64_t)t * HW;
-        const float *kk = a.k + (uint64_t)t * HW;
-        for (uint32_t p = 4u * (uint32_t)lane; p < HW; p += 256u) {  // HW is a multiple of 4
-            const float4 pp = *reinterpret_cast<const float4 *>(pd + p);
-            const float4 kp = *reinterpret_cast<const float4 *>(kk + p);
-            const float pv[4] = {pp.x, pp.y, pp.z, pp.w}, kv[4] = {kp.x, kp.y, kp.z, kp.w};
+        float c0[F], c1[F];
+        int lo;
+        const bool fast = tile_window<F>(a, s, f0, t, nf, K, c0, c1, lo);
+        if (fast) {
+            const double sc = __builtin_ldexp(1.0, -lo), sk = __builtin_ldexp(1.0, -lo - K),
+                         pk = __builtin_ldexp(1.0, K);
+            double q0[F], q1[F];
+            uint32_t n0[F];
 #pragma unroll
             for (int j = 0; j < F; ++j) {
-                if (j >= nf) break;
-                const uint2 w = *reinterpret_cast<const uint2 *>(fr + (uint64_t)j * npix + p);
-                const uint32_t r[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+                q0[j] = q1[j] = 0.0;
+                n0[j] = 0;
+            }
+            const uint16_t *fr = a.frames + f0 * npix + (uint64_t)t * HW;
+            const float *pd = a.ped + (uint64_t)t * HW;
+            const float *kk = a.k + (uint64_t)t * HW;
+            for (uint32_t p = 4u * (uint32_t)lane; p < HW; p += 256u) {  // HW is a multiple of 4
+                const float4 pp = *reinterpret_cast<const float4 *>(pd + p);
+                const float4 kp = *reinterpret_cast<const float4 *>(kk + p);
+                const float pv[4] = {pp.x, pp.y, pp.z, pp.w}, kv[4] = {kp.x, kp.y, kp.z, kp.w};
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    float y = dark_gain(r[i], pv[i], kv[i]);
-                    if (s > 0) y = __fsub_rn(y, c0[j]);
-                    if (s > 1) y = __fsub_rn(y, c1[j]);
-                    if (y < a.t_cm) {
-                        part[j][i] = __fadd_rn(part[j][i], y);
-                        ++n0[j];
+                for (int j = 0; j < F; ++j) {
+                    if (j >= nf) break;
+                    const uint2 w = *reinterpret_cast<const uint2 *>(fr + (uint64_t)j * npix + p);
+                    const uint32_t r[4] = {w.x & 0xFFFFu, w.x >> 16, w.y & 0xFFFFu, w.y >> 16};
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        float y = dark_gain(r[i], pv[i], kv[i]);
+                        if (s > 0) y = __fsub_rn(y, c0[j]);
+                        if (s > 1) y = __fsub_rn(y, c1[j]);
+                        const bool nz = y < a.t_cm;
+                        n0[j] += nz;
+                        limbs2_add(q0[j], q1[j], nz ? y : 0.0f, sc, sk, pk);
                     }
                 }
             }
-        }
 #pragma unroll
-        for (int j = 0; j < F; ++j) {
-            const float q = __fadd_rn(__fadd_rn(part[j][0], part[j][1]), __fadd_rn(part[j][2], part[j][3]));
-            const float sum = tree64(q);
-            const uint32_t n = sum64(n0[j]);
-            if (lane == 0 && j < nf) {
-                float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
-                cv[s] = __fdiv_rn(sum, fmaxf((float)n, a.guard));
-                if (s == 0) {
-                    cv[1] = 0.0f;
-                    cv[2] = 0.0f;
+            for (int j = 0; j < F; ++j) {
+                const double q[2] = {q0[j], q1[j]};
+                Wide<2> S = wide_from_limbs<2>(q, K);
+                wave_sum_wide(S);
+                const uint32_t n = sum64(n0[j]);
+                if (lane == 0 && j < nf) {
+                    float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
+                    cv[s] = __fdiv_rn(wide_round(S, lo), fmaxf((float)n, a.guard));
+                    if (s == 0) {
+                        cv[1] = 0.0f;
+                        cv[2] = 0.0f;
+                    }
+                }
+            }
+        } else {
+            for (int j = 0; j < nf; ++j) {
+                uint32_t n0;
+                Wide<4> S = tile_sum_general(a, s, f0 + j, t, c0[j], c1[j], (uint32_t)lane, 64u, n0);
+                wave_sum_wide(S);
+                const uint32_t n = sum64(n0);
+                if (lane == 0) {
+                    float *cv = a.cm + ((f0 + j) * a.T + t) * 3;
+                    cv[s] = __fdiv_rn(wide_round(S, -149), fmaxf((float)n, a.guard));
+                    if (s == 0) {
+                        cv[1] = 0.0f;
+                        cv[2] = 0.0f;
+                    }
                 }
             }
         }

@@ -27,6 +27,7 @@
 #include <math.h>
 
 #include "pdc_device.h"
+#include "pdc_exact.h"
 #include "pdc_internal.h"
 
 #pragma clang fp contract(off)
@@ -818,14 +819,13 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
 
         // ================= B: 1b(f) | 2(f-1) | 4(f-2) =============================
         if (CMM && cur_ok && A.cm_mode == 1) {
-            // thresholded mean of each bank-row (Fig. c), stacked stages: lane j
-            // of the group holds partial sums j + L q (q < 64 / L) of the
-            // bank's 64 interleaved partials (column c goes to partial c mod 64,
-            // in increasing c); the group's DPP tree adds partials of equal q in
-            // lane order, the lane then adds its Q results in a balanced tree,
-            // which is the balanced tree over all 64.  v replaces u in place
-            // and the median slot holds 0.
-            constexpr int G = 64 / L, Q = 64 / L;
+            // thresholded mean of each bank-row (Fig. c), stacked stages: the sum
+            // of the noise values is exact, rounded once (the group's lanes add
+            // two binary64 limbs); v replaces u in place and the median slot
+            // holds 0.  A bank-row whose values span more than two limbs hold
+            // marks the frame's seed list full, so that the general kernel
+            // redoes the unit from the separately computed stage values.
+            constexpr int G = 64 / L;
             const int grp = lane / L, gl = lane - grp * L;
             const int i = wave * G + grp;
             const bool act = i < BR;
@@ -838,31 +838,22 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 const int c = L * v + gl;
                 x[v] = (act && c < B) ? dst[c] : INFINITY;  // +inf: absent or invalid, never noise
             }
+            SumWindow win = {A.sum_lo, A.sum_hi};
+            bool wide = false;
 #pragma unroll
             for (int s = 0; s < 3; ++s) {
                 if (s >= A.cm_stages) break;
-                float P[Q];
-                int n = 0;
-#pragma unroll
-                for (int q = 0; q < Q; ++q) P[q] = 0.0f;
-#pragma unroll
-                for (int v = 0; v < V; ++v)
-                    if (x[v] < A.t_cm) {
-                        P[v % Q] = __fadd_rn(P[v % Q], x[v]);
-                        ++n;
-                    }
-                float T[Q];
-#pragma unroll
-                for (int q = 0; q < Q; ++q) T[q] = gsum_f<L>(P[q]);
-#pragma unroll
-                for (int w = 1; w < Q; w *= 2)
-#pragma unroll
-                    for (int q = 0; q + w < Q; q += 2 * w) T[q] = __fadd_rn(T[q], T[q + w]);
+                int n;
+                bool fits;
+                const float sum = region_sum<L, V, false>(x, A.t_cm, (uint32_t)B, win, n, fits);
+                wide |= !fits;
                 const int n0 = gsum_i<L>(n);
-                const float cm = __fdiv_rn(T[0], fmaxf((float)n0, A.cm_guard));
+                const float cm = __fdiv_rn(sum, fmaxf((float)n0, A.cm_guard));
+                win = next_window(win, cm);
 #pragma unroll
                 for (int v = 0; v < V; ++v) x[v] = __fsub_rn(x[v], cm);
             }
+            if (act && wide && gl == 0) atomicAdd(&s_nseed[sc0], (uint32_t)cap + 1u);
             if (act) {
                 float *f2 = (KEEP && FLAT && row >= own_lo && row < own_hi)
                                 ? A.corrected + f * npix + row_base + row * W + bank * B

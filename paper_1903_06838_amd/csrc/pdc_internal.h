@@ -94,6 +94,7 @@ struct V2Args {
                                   // 2 thresholded-mean stage values read from cm
     int32_t cm_stages;            // cm_mode 1: stages, noise threshold and guard
     float t_cm, cm_guard;
+    int32_t sum_lo, sum_hi;       // cm_mode 1: Frames1 values are multiples of 2^sum_lo below 2^sum_hi
     int32_t gain_mode;
     uint32_t *invalid;
 };
@@ -104,9 +105,8 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
                                   hipStream_t s);
 
 // Thresholded-mean common mode (Fig. c), computed ahead of the frame kernels:
-// cm[f][region][s] for stages s < stages, zeros after.  Bank regions take 64
-// interleaved partial sums per region, tile regions 256, each partial adding
-// its pixels in raster order from +0, then a balanced tree over the partials.
+// cm[f][region][s] for stages s < stages, zeros after.  A region's sum is the
+// exact sum of its noise pixels rounded once to binary32.
 struct CmArgs {
     const uint16_t *frames;       // [n_frames][T][H][W]
     const float *ped, *k;         // [T][H][W]
@@ -115,6 +115,7 @@ struct CmArgs {
     int32_t stages;               // 1..3
     float t_cm;                   // pixels below it are noise
     float guard;                  // fl(sqrt(fl(region size)))
+    int32_t sum_lo, sum_hi;       // Frames1 values are multiples of 2^sum_lo below 2^sum_hi
     int32_t gain_mode;            // as in FrameKernelArgs
     float *cm;
 };

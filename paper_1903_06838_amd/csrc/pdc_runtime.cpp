@@ -49,6 +49,7 @@ struct Detector {
     float t_seed = 0, t_nb = 0;
     float t_cm = 0, cm_guard = 0;         // thresholded-mean common mode (cm_mode 1 or 2)
     uint32_t cm_regions = 0;              // regions per frame
+    int32_t sum_lo = 0, sum_hi = 0;       // window of Frames1: multiples of 2^sum_lo below 2^sum_hi
     float *d_ped = nullptr;
     float *d_k = nullptr;
     // derived launch shape of the general kernel (v1)
@@ -259,6 +260,45 @@ pdc_status check_params(const pdc_params *p, float *t_seed, float *t_nb)
 }
 
 int n_ranges(const pdc_geometry &g) { return g.gain_mode ? 3 : 1; }
+
+// Lowest set bit of a nonzero finite binary32 (c is an odd multiple of 2^lsb)
+// and the smallest h with |c| < 2^h (zero: -149).
+int f32_lsb_host(float c)
+{
+    uint32_t b;
+    std::memcpy(&b, &c, 4);
+    const int E = (int)((b >> 23) & 0xFFu);
+    const uint32_t M = E ? ((b & 0x7FFFFFu) | 0x800000u) : (b & 0x7FFFFFu);
+    return (E ? E : 1) - 150 + __builtin_ctz(M);
+}
+int f32_hi_host(float c)
+{
+    uint32_t b;
+    std::memcpy(&b, &c, 4);
+    b &= 0x7FFFFFFFu;
+    if (!b) return -149;
+    const int E = (int)(b >> 23);
+    return E ? E - 126 : -149 + (32 - __builtin_clz(b));
+}
+
+// Window of every Frames1 value fl(fl(adc - dark) * k), adc in [0, 16383]: a
+// multiple of 2^(min(0, lsb(dark)) + lsb(k)) (adc is an integer; a rounding to
+// binary32 keeps such a multiple), at most the larger of |x(0)| and |x(16383)|
+// in magnitude (x is monotone in adc).  The exact thresholded sums size their
+// accumulators from it.
+void frames1_window(const float *ped, const float *k, size_t n, int32_t *lo, int32_t *hi)
+{
+    int l = 0, h = -149;
+    for (size_t i = 0; i < n; ++i) {
+        const int lp = ped[i] == 0.0f ? 0 : std::min(0, f32_lsb_host(ped[i]));
+        l = std::min(l, lp + f32_lsb_host(k[i]));
+        volatile float a0 = 0.0f - ped[i], a1 = 16383.0f - ped[i];  // binary32
+        volatile float x0 = a0 * k[i], x1 = a1 * k[i];
+        h = std::max(h, std::max(f32_hi_host(x0), f32_hi_host(x1)));
+    }
+    *lo = l;
+    *hi = h;
+}
 
 pdc_status check_planes(const pdc_geometry *g, const float *ped, const float *gain)
 {
@@ -496,6 +536,8 @@ hipError_t launch_cm_pass(pdc_ctx *ctx, const Detector &d, const Batch &bt)
     c.stages = d.p.cm_stages;
     c.t_cm = d.t_cm;
     c.guard = d.cm_guard;
+    c.sum_lo = d.sum_lo;
+    c.sum_hi = d.sum_hi;
     c.gain_mode = d.g.gain_mode;
     c.cm = bt.buf->cm;
     if (d.p.cm_mode == PDC_CM_BANK_MEAN) return launch_cm_bank(c, (uint32_t)ctx->n_cu, bt.stream);
@@ -615,6 +657,8 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.cm_stages = d.p.cm_stages;
         a.t_cm = d.t_cm;
         a.cm_guard = d.cm_guard;
+        a.sum_lo = d.sum_lo;
+        a.sum_hi = d.sum_hi;
         a.gain_mode = d.g.gain_mode;
         a.invalid = b->invalid;
         HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
@@ -937,6 +981,7 @@ pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pe
         volatile float r = 1.0f / gain[i];  // binary32 division
         k[i] = r;
     }
+    if (params->cm_mode != PDC_CM_MEDIAN) frames1_window(pedestal, k.data(), n, &d.sum_lo, &d.sum_hi);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipMalloc((void **)&d.d_ped, n * sizeof(float)));
     HIP_TRY(ctx, hipMalloc((void **)&d.d_k, n * sizeof(float)));

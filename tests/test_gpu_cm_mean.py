@@ -1,7 +1,9 @@
 """Thresholded-mean common mode (Fig. c, stacked stages) on the GPU through the
 C ABI against oracle/cm_mean.py, bit for bit: hit lists, per-frame counts and
 photon totals, and Frames2, for bank and tile regions, 1 to 3 stages, on the
-persistent kernel (both lane layouts) and the general kernel."""
+persistent kernel (both lane layouts) and the general kernel.  The oracle's
+sum is the exact sum rounded once, so these also check that no order of
+summation shows through."""
 import os
 
 import numpy as np
@@ -94,6 +96,28 @@ def test_tile_mean_overflow_redoes_units(ctx):
     want = M.process(raw, ped, gain, 194, M.TILE, 2, keep_corrected=True)
     got = _run(ctx, raw, ped, gain, 194, M.TILE, 2)
     assert got["path"] == 3
+    assert_same(got, want, corrected=True)
+
+
+@pytest.mark.parametrize("region", [M.BANK, M.TILE])
+def test_cm_mean_wide_window(ctx, region):
+    """One pixel's dark of 2^-60 gives its Frames1 bits far below the ADC's
+    unit (raw 0 there makes a tiny negative noise value), which widens every
+    sum's window past two binary64 limbs: the separate pass takes the general
+    way (unit 2^-149), and with bank regions the persistent kernel hands its
+    units to the general kernel, which reads the pass's values."""
+    geom = synth.Geometry(2, 40, 388, 194)
+    ped, gain = synth.make_calibration(geom, 26)
+    ped[0, 3, 5] = 2.0 ** -60
+    ped[1, 30, 200] = -(2.0 ** -40)
+    sim = synth.SimParams(cm_sigma=1.0) if region == M.TILE else synth.SimParams()
+    raw = synth.make_frames(geom, ped, gain, 3, 0.02, 26, sim=sim)
+    raw[1, 0, 3, 5] = 0
+    raw[2, 1, 30, 200] = 0
+    want = M.process(raw, ped, gain, 194, region, 3, keep_corrected=True)
+    got = _run(ctx, raw, ped, gain, 194, region, 3)
+    if region == M.BANK:
+        assert got["path"] == 3  # every unit redone by the general kernel
     assert_same(got, want, corrected=True)
 
 
