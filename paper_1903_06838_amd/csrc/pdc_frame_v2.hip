@@ -96,23 +96,20 @@ __device__ __forceinline__ float gsum_f(float x)
     return x;
 }
 
-// Number of the lane's values below p.  For finite p, x < p exactly when
-// fl(x - p) has its sign bit set (a nonzero difference never rounds to +0,
-// x == p gives +0, x = +inf gives +inf); p is clamped to the finite range,
-// which changes no count because the values are bounded far below FLT_MAX.
-// The sign bits are summed in a tree, so the count is no serial chain.
+// Mask of the lane's values below p: bit v is set when x[v] < p.  For finite
+// p, x < p exactly when fl(x - p) has its sign bit set (a nonzero difference
+// never rounds to +0, x == p gives +0, x = +inf gives +inf); p is clamped to
+// the finite range, which changes no answer because the values are bounded far
+// below FLT_MAX.  Each value costs a subtraction and an alignbit that shifts
+// its sign bit in; the count is one popcount of the mask.
 template <int V>
-__device__ __forceinline__ int lane_count(const float (&x)[V], float p)
+__device__ __forceinline__ uint32_t lane_mask(const float (&x)[V], float p)
 {
     const float pc = __builtin_amdgcn_fmed3f(p, -3.40282347e38f, 3.40282347e38f);
-    uint32_t t[V];
+    uint32_t m = 0;
 #pragma unroll
-    for (int v = 0; v < V; ++v) t[v] = __float_as_uint(__fsub_rn(x[v], pc)) >> 31;
-#pragma unroll
-    for (int w = 1; w < V; w *= 2)
-#pragma unroll
-        for (int v = 0; v + w < V; v += 2 * w) t[v] += t[v + w];
-    return (int)t[0];
+    for (int v = V - 1; v >= 0; --v) m = __builtin_amdgcn_alignbit(m, __float_as_uint(__fsub_rn(x[v], pc)), 31);
+    return m;
 }
 
 // [lo, hi) holds a single float (adjacent keys, both bounds finite or not).
@@ -204,26 +201,30 @@ __device__ __forceinline__ float group_sort_pick(float y, int r)
 }
 
 // Exact element of rank k (0-based, ascending) among the nval finite values
-// held by an L-lane group (V values per lane, absent values +inf); every
-// group of the wave searches its own bank at once.  Bracketing search on
-// counts, count(x < lo) <= k < count(x < hi) throughout: the first step tests
+// held by an L-lane group (V values per lane, absent values +inf, lane value
+// v also at src[L v] in LDS); every group of the wave searches its own bank
+// at once.  Bracketing search on counts, count(x < lo) <= k < count(x < hi)
+// throughout, with the lane masks of both bounds kept: the first step tests
 // est -/+ 5 rank widths rw together (widening until they bracket), later steps
 // interpolate the pivot from the bracket counts and bisect in key space when
 // the interpolated pivot is not strictly inside or the bracket stopped
-// halving.  Once at most L values remain in [lo, hi) they are sorted across
-// the group's lanes and the answer is read off; a bracket that holds a single
-// float (possibly many copies of it) gives that float.  Groups with act false
-// return an unspecified value.
+// halving.  Once at most L values remain in [lo, hi) (the lane's are the bits
+// of mhi & ~mlo) they are gathered from LDS into the group's lanes, sorted
+// across them, and the answer is read off; a bracket that holds a single float
+// (possibly many copies of it) gives that float.  Groups with act false return
+// an unspecified value.
 template <int V, int L, bool SPARSE>
-__device__ float group_median(const float (&x)[V], int nval, int k, float rw, bool act, float *gsc, int B)
+__device__ float group_median(const float (&x)[V], const float *src, int nval, int k, float rw, bool act,
+                              float *gsc, int B)
 {
     const float est = group_estimate<V, L, SPARSE>(x, B);
 
     const float w0 = 5.0f * rw;
     float lo = est - w0, hi = est + w0;
+    uint32_t mlo = lane_mask<V>(x, lo), mhi = lane_mask<V>(x, hi);
     int clo, chi;
     {
-        const int pk = gsum_i<L>(lane_count<V>(x, lo) | (lane_count<V>(x, hi) << 16));
+        const int pk = gsum_i<L>(__popc(mlo) | (__popc(mhi) << 16));
         clo = pk & 0xFFFF;
         chi = pk >> 16;
     }
@@ -237,18 +238,23 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
         const float d = (float)((down ? clo - k : k + 1 - chi) + 3) * sc;
         sc = sc + sc;
         const float p = it < 38 ? (down ? lo - d : hi + d) : (down ? -INFINITY : INFINITY);
-        const int cp = gsum_i<L>(lane_count<V>(x, p));
+        const uint32_t mp = lane_mask<V>(x, p);
+        const int cp = gsum_i<L>(__popc(mp));
         if (!ok) {
             if (down) {
                 hi = lo;
                 chi = clo;
+                mhi = mlo;
                 lo = p;
                 clo = cp;
+                mlo = mp;
             } else {
                 lo = hi;
                 clo = chi;
+                mlo = mhi;
                 hi = p;
                 chi = cp;
+                mhi = mp;
             }
             ok = clo <= k && k < chi;
         }
@@ -273,25 +279,27 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
         done = done || n <= L || single;
         if (__ballot(!done) == 0) break;
         last_n = interp ? n : 4 * nval;
-        const int cq = gsum_i<L>(lane_count<V>(x, q));
+        const uint32_t mq = lane_mask<V>(x, q);
+        const int cq = gsum_i<L>(__popc(mq));
         if (!done) {
             if (cq <= k) {
                 lo = q;
                 clo = cq;
+                mlo = mq;
             } else {
                 hi = q;
                 chi = cq;
+                mhi = mq;
             }
         }
     }
-    // Finish: the n <= L values in [lo, hi) are compacted into the group's
-    // lanes through LDS (gsc: L floats per group, in lane order), sorted
-    // across the lanes, and lane k - clo holds the answer.  A bracket that
-    // holds a single float (n > L possible) has the answer lo.
+    // Finish: the n <= L values in [lo, hi) are gathered from LDS into the
+    // group's lanes (gsc: L floats per group, in lane order), sorted across the
+    // lanes, and lane k - clo holds the answer.  A bracket that holds a single
+    // float (n > L possible) has the answer lo.
     const int gl = __lane_id() & (L - 1);
-    uint32_t cm = 0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) cm |= (uint32_t)(x[v] >= lo && x[v] < hi) << v;
+    const bool gather = !done_single(lo, hi);
+    uint32_t cm = gather ? mhi & ~mlo : 0u;
     const int c = __popc(cm);
     int incl = c;
 #define PDC_SCAN(ctrl, sh)                                                                       \
@@ -304,15 +312,14 @@ __device__ float group_median(const float (&x)[V], int nval, int k, float rw, bo
     if (L >= 8) PDC_SCAN(0x114, 4)
     if (L >= 16) PDC_SCAN(0x118, 8)
 #undef PDC_SCAN
-    const bool gather = !done_single(lo, hi);
     float *gb = gsc - gl;  // the group's L slots
     int pos = incl - c;
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-        if ((cm >> v) & 1u) {
-            if (gather && pos < L) gb[pos] = x[v];
-            ++pos;
-        }
+    while (cm) {
+        const int v = __builtin_ctz(cm);
+        cm &= cm - 1u;
+        if (pos < L) gb[pos] = src[L * v];
+        ++pos;
+    }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
@@ -925,7 +932,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             const bool tail_only = B > L * (V - 1);
             float x[V];
             read_group<V, L>(x, src, lim, tail_only, INFINITY);
-            const float m = group_median<V, L, false>(x, B, kmed, A.rank_width, act, s_gs + tid, B);
+            const float m = group_median<V, L, false>(x, src, B, kmed, A.rank_width, act, s_gs + tid, B);
             if (act && gl == 0) med_c[i] = m;
             const bool own = act && row >= own_lo && row < own_hi;
             if (KEEP && own) {
@@ -970,7 +977,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 kq = nv > 0 ? (nv - 1) / 2 : 0;
                 actv = act && nv > 0;
             }
-            float m = group_median<V, L, MG>(x, nv, kq, A.rank_width, actv, s_gs + tid, B);
+            float m = group_median<V, L, MG>(x, src + gl, nv, kq, A.rank_width, actv, s_gs + tid, B);
             if constexpr (MG) {
                 if (!actv) m = 0.0f;
                 // invalid pixels take the median: v = fl(m - m) = +0
