@@ -379,7 +379,10 @@ struct V2Layout {
 __device__ __host__ __forceinline__ V2Layout v2_layout(int rmax, int W, int nb, int seed_cap)
 {
     V2Layout L;
-    uint32_t o = 0;
+    // W + 1 floats before u: phase 2 reads a seed's neighbours at fixed
+    // offsets from the row above, column left, without clamping (what lies
+    // outside the rows or the tile is read and then masked)
+    uint32_t o = ((uint32_t)W + 4u) & ~3u;
     L.u = o;
     o += 2u * rmax * W;
     L.med = o;
@@ -1007,57 +1010,41 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                     const uint32_t key = s_seed[pp * cap + j];
                     const int row = (int)(key >> 18), bank = (int)((key >> 11) & 127u), col = (int)(key & 2047u);
                     const int i = row * nb + bank;
-                    // addresses first, then all 18 reads, then the arithmetic
-                    int ua[3][3], ma[3][3];
-                    bool ex[3][3];
-#pragma unroll
-                    for (int dr = 0; dr < 3; ++dr) {
-                        const int rr = row + dr - 1;
-                        const int rc = min(max(rr, 0), R - 1);
-                        // in the loaded rows and in the seed's tile
-                        const bool rin = rr >= 0 && rr < R && ((rr >= bnd) == (row >= bnd));
-#pragma unroll
-                        for (int dc = 0; dc < 3; ++dc) {
-                            const int cc = col + dc - 1;
-                            ex[dr][dc] = rin && cc >= 0 && cc < W;
-                            const int ccl = min(max(cc, 0), W - 1);
-                            const int bk = ccl >= (bank + 1) * B ? bank + 1 : (ccl < bank * B ? bank - 1 : bank);
-                            ua[dr][dc] = rc * W + ccl;
-                            ma[dr][dc] = rc * nb + bk;
-                        }
-                    }
-                    float uv[3][3], mv[3][3];
-#pragma unroll
-                    for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                        for (int dc = 0; dc < 3; ++dc) {
-                            uv[dr][dc] = u_p[ua[dr][dc]];
-                            mv[dr][dc] = med_p[ma[dr][dc]];
-                        }
+                    const int cb = col - bank * B;
+                    // the 3x3 neighbourhood from the row above and the column
+                    // left; the left and right columns take the next bank's
+                    // median at a bank edge.  Neighbours outside the loaded
+                    // rows, across a tile edge or outside the row are -inf:
+                    // never above the seed nor above t_nb.
+                    const float *up = u_p + (row - 1) * W + (col - 1);
+                    const float *mp = med_p + (row - 1) * nb + bank;
+                    const int ml = cb == 0 ? -1 : 0, mr = cb == B - 1 ? 1 : 0;
+                    const bool r0 = row >= 1 && row != bnd, r2 = row + 1 < R && row + 1 != bnd;
+                    const bool c0 = col >= 1, c2 = col + 1 < W;
                     float nv[3][3];
 #pragma unroll
-                    for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                        for (int dc = 0; dc < 3; ++dc) nv[dr][dc] = __fsub_rn(uv[dr][dc], mv[dr][dc]);
+                    for (int dr = 0; dr < 3; ++dr) {
+                        const float m0 = mp[dr * nb + ml], m1 = mp[dr * nb], m2 = mp[dr * nb + mr];
+                        const bool rin = dr == 1 || (dr == 0 ? r0 : r2);
+                        const float a = __fsub_rn(up[dr * W], m0), b = __fsub_rn(up[dr * W + 1], m1),
+                                    c = __fsub_rn(up[dr * W + 2], m2);
+                        nv[dr][0] = rin && c0 ? a : -INFINITY;
+                        nv[dr][1] = rin ? b : -INFINITY;
+                        nv[dr][2] = rin && c2 ? c : -INFINITY;
+                    }
                     const float vp = nv[1][1];
-                    bool is_max = true;
-#pragma unroll
-                    for (int dr = 0; dr < 3; ++dr)
-#pragma unroll
-                        for (int dc = 0; dc < 3; ++dc) {
-                            if (dr == 1 && dc == 1) continue;
-                            const bool later = dr > 1 || (dr == 1 && dc > 1);
-                            const float vq = nv[dr][dc];
-                            if (ex[dr][dc] && !(vp > vq || (vp == vq && later))) is_max = false;
-                        }
+                    // strictly above the neighbours before it in raster order,
+                    // at least the ones after it (ties go to the first)
+                    const float me = fmaxf(fmaxf(nv[0][0], nv[0][1]), fmaxf(nv[0][2], nv[1][0]));
+                    const float ml2 = fmaxf(fmaxf(nv[1][2], nv[2][0]), fmaxf(nv[2][1], nv[2][2]));
+                    const bool is_max = vp > me && vp >= ml2;
                     if (is_max) {
                         float qsum = 0.0f;
 #pragma unroll
                         for (int dr = 0; dr < 3; ++dr)
 #pragma unroll
                             for (int dc = 0; dc < 3; ++dc)
-                                qsum = __fadd_rn(qsum, (ex[dr][dc] && nv[dr][dc] > A.t_nb) ? nv[dr][dc] : 0.0f);
-                        const int cb = col - bank * B;
+                                qsum = __fadd_rn(qsum, nv[dr][dc] > A.t_nb ? nv[dr][dc] : 0.0f);
                         atomicOr(&s_bits[(pp * RN + i) * 8 + (cb >> 5)], 1u << (cb & 31));
                         atomicAdd(&s_cnt[pp * RN + i], 1u);
                         my_ph += photon_count(qsum, A.photon_adu);
