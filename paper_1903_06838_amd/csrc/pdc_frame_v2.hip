@@ -610,18 +610,16 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
         }
     };
     // The same for the single-gain median kernels: values of the slots in
-    // vmask are finite (the others, past the bank, are dropped), the mask is
-    // built from the last value down, a sign bit per value.
-    auto append_seeds_dense = [&](const float(&xs)[V], float th, bool own, uint32_t vmask, int row, int bank, int gl,
-                                  int sbuf, int slot) {
-        // x >= th  <=>  x > tp, tp the float below th, <=>  fl(tp - x) < 0:
-        // a nonzero difference keeps its sign, x == tp gives +0 and
-        // x = -inf gives +inf, so the sign bit is the test (th finite)
-        const float tp = key2f(f2key(th) - 1);
+    // vmask are finite (the others, past the bank, are dropped); a value is a
+    // seed when fl(x - m) > t, that is when fl(t - fl(x - m)) < 0 (exact
+    // difference of two finite values: its sign is the test, equality gives
+    // +0), one sign bit per value shifted in from the last value down.
+    auto append_seeds_dense = [&](const float(&xs)[V], float m, float t, bool own, uint32_t vmask, int row, int bank,
+                                  int gl, int sbuf, int slot) {
         uint32_t sb = 0;
 #pragma unroll
         for (int v = V - 1; v >= 0; --v)
-            sb = __builtin_amdgcn_alignbit(sb, __float_as_uint(__fsub_rn(tp, xs[v])), 31);
+            sb = __builtin_amdgcn_alignbit(sb, __float_as_uint(__fsub_rn(t, __fsub_rn(xs[v], m))), 31);
         sb = own ? sb & vmask : 0u;
         const uint32_t ns = (uint32_t)__popc(sb);
         const uint32_t incl = wave_incl_scan(ns);
@@ -947,7 +945,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
             // slots past the bank (+inf) are no seeds
             const uint32_t vmask = tail_only ? ((L * (V - 1) < lim) ? (1u << V) - 1u : (1u << (V - 1)) - 1u)
                                              : (uint32_t)((1ull << min(V, max(0, (lim + L - 1) / L))) - 1ull);
-            append_seeds_dense(x, seed_threshold(m, A.t_seed), own, vmask, row, bank, gl, par, sc0);
+            append_seeds_dense(x, m, A.t_seed, own, vmask, row, bank, gl, par, sc0);
         }
         if (!CMM && !FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
             constexpr int G = 64 / L;
