@@ -354,20 +354,6 @@ __device__ __forceinline__ void read_group(float (&x)[V], const float *src, int 
     }
 }
 
-// Smallest binary32 value th such that fl(th - m) > t (fl(x - m) is
-// monotone in x, so fl(u - m) > t  <=>  u >= th).  Per lane.
-__device__ __forceinline__ float seed_threshold(float m, float t)
-{
-    float th = __fadd_rn(m, t);
-    for (int i = 0; i < 64 && !(__fsub_rn(th, m) > t); ++i) th = key2f(f2key(th) + 1);
-    for (int i = 0; i < 64; ++i) {
-        const float d = key2f(f2key(th) - 1);
-        if (__fsub_rn(d, m) > t) th = d;
-        else break;
-    }
-    return th;
-}
-
 struct V2Layout {
     uint32_t u, med, bits, cnt, seed, hl, nseed, hcnt, pref, gs, total;  // float offsets
 };
@@ -581,19 +567,22 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
     __syncthreads();
 
     // Seeds of a bank-row held by an L-lane group in phase B (lane gl holds
-    // columns L v + gl in xs, +inf where absent or invalid): u >= th, own rows
-    // only, appended to the pooled list sbuf (frame parity; order is free,
-    // phase 4 restores raster order) counted in slot (frame mod 3), with a
-    // DPP prefix of the lanes' counts and one LDS atomic per wave.  All lanes
-    // of the wave must call it.
-    const float th0 = seed_threshold(0.0f, A.t_seed);
-    auto append_seeds = [&](const float(&xs)[V], float th, bool own, int row, int bank, int gl, int sbuf, int slot) {
-        uint32_t sb = 0;
-        if (own) {
+    // columns L v + gl in xs, +inf where absent or invalid): fl(x - m) > t,
+    // own rows only, appended to the pooled list sbuf (frame parity; order is
+    // free, phase 4 restores raster order) counted in slot (frame mod 3), with
+    // a DPP prefix of the lanes' counts and one LDS atomic per wave.  The test
+    // is the sign of fl(t - fl(x - m)) (see append_seeds_dense), and +inf is
+    // dropped by the sign of x - 2^100 (set for every finite value, which is
+    // far below 2^100).  All lanes of the wave must call it.
+    auto append_seeds = [&](const float(&xs)[V], float m, float t, bool own, int row, int bank, int gl, int sbuf,
+                            int slot) {
+        uint32_t sb = 0, fin = 0;
 #pragma unroll
-            for (int v = 0; v < V; ++v)
-                if (xs[v] < INFINITY && xs[v] >= th) sb |= 1u << v;  // columns past the bank hold +inf
+        for (int v = V - 1; v >= 0; --v) {
+            sb = __builtin_amdgcn_alignbit(sb, __float_as_uint(__fsub_rn(t, __fsub_rn(xs[v], m))), 31);
+            fin = __builtin_amdgcn_alignbit(fin, __float_as_uint(__fsub_rn(xs[v], 0x1p100f)), 31);
         }
+        sb = own ? sb & fin : 0u;
         const uint32_t ns = (uint32_t)__popc(sb);
         const uint32_t incl = wave_incl_scan(ns);
         const uint32_t wtot = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
@@ -877,7 +866,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 }
                 if (gl == 0) med_c[i] = 0.0f;
             }
-            append_seeds(x, th0, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
+            append_seeds(x, 0.0f, A.t_seed, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (CMM && cur_ok && A.cm_mode == 2) {
             // thresholded-mean common mode, computed ahead: v = ((u - c1) - c2) - c3
@@ -914,7 +903,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 }
                 if (gl == 0) med_c[i] = 0.0f;
             }
-            append_seeds(x, th0, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
+            append_seeds(x, 0.0f, A.t_seed, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (!CMM && FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
             constexpr int G = 64 / L;
@@ -992,7 +981,7 @@ __global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
                 }
             }
             if (act && gl == 0) med_c[i] = m;
-            append_seeds(x, seed_threshold(m, A.t_seed), act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
+            append_seeds(x, m, A.t_seed, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (p1_ok && !ovf_1) {
             // frame f-1's seeds in chunks of 64, claimed by whole waves as they
