@@ -34,8 +34,6 @@
 
 namespace pdc {
 
-constexpr int kV2Waves = 16;
-constexpr int kV2Threads = kV2Waves * 64;
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
@@ -425,7 +423,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 constexpr int kFlatChunks = 4;
 
 template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG>
-__global__ void __launch_bounds__(kV2Threads) frame_kernel_v2(V2Args A)
+__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(4, 4))) frame_kernel_v2(V2Args A)
 {
     // Single-gain kernels correct the strip as one flat block of pixels
     // (FLAT); auto-ranging kernels keep a wave per bank-row, whose lanes

@@ -9,6 +9,15 @@ namespace pdc {
 
 // Sentinel for "this unit's hits could not be staged" (staging pool full).
 constexpr uint64_t kNoBase = ~0ull;
+
+// Waves per workgroup of the persistent kernel; 16 / kV2Waves workgroups
+// share a compute unit (its LDS split between them, four waves per SIMD).
+#ifndef PDC_V2_WAVES
+#define PDC_V2_WAVES 16
+#endif
+constexpr int kV2Waves = PDC_V2_WAVES;
+constexpr int kV2Threads = kV2Waves * 64;
+constexpr int kV2GroupsPerCu = 16 / kV2Waves;
 // Staging chunk claimed by one workgroup from the batch-wide pool cursor.
 constexpr uint64_t kChunkHits = 8192;
 

@@ -364,7 +364,7 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     const int nb = g.cols / g.bank_cols;
     d.nq = g.bank_cols > 128 ? 2 : 1;
     d.gmax = d.nq == 2 ? 4 : 8;
-    const int max_bank_rows = 16 * d.gmax;  // 16 waves per workgroup
+    const int max_bank_rows = kV2Waves * d.gmax;  // a bank-row group per wave and slot
     const int rmax_lim = max_bank_rows / nb;
     if (rmax_lim < 3) return false;
     const int own_max = rmax_lim - 2;
@@ -408,7 +408,8 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     // seed lists: as large as the workgroup's LDS allows (the kernel's
     // registers admit one workgroup per compute unit anyway), at least 1024
     // entries; 256 bytes stay free for the kernel's static LDS
-    const size_t lds_cap = (size_t)ctx->max_lds > 256 ? (size_t)ctx->max_lds - 256 : 0;
+    const size_t lds_wg = (size_t)ctx->max_lds / kV2GroupsPerCu;
+    const size_t lds_cap = lds_wg > 256 ? lds_wg - 256 : 0;
     size_t base = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, 0);
     if (base + 4 * 4 * 1024 > lds_cap) return false;
     d.seed_cap = (int)std::min<size_t>((lds_cap - base) / 16, 16384);
@@ -722,7 +723,7 @@ void set_path(const Detector &d, Batch &bt, int path)
 {
     bt.path = path;
     if (path == 2) {
-        const int fgb = frame_groups(d.n_cu, d.n_strips, bt.n_frames, d.fg_mult);
+        const int fgb = frame_groups(d.n_cu * kV2GroupsPerCu, d.n_strips, bt.n_frames, d.fg_mult);
         const uint64_t fg = (uint64_t)std::max(1.0, std::floor((double)fgb * bt.share));
         bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(fg, bt.n_frames));
         bt.upf = d.n_strips;
