@@ -56,6 +56,11 @@ typedef int32_t pdc_status;
 
 /* Keep Frames2 (float32 [N][T][H][W]) of a batch for pdc_get_corrected. */
 #define PDC_KEEP_CORRECTED 1u
+/* Keep each frame's common-mode values of a batch (the bank medians, or the
+ * thresholded mean's stage values): pdc_capture_patches then forms patches
+ * from the frames without Frames2.  They take
+ * n_frames * n_tiles * rows * (cols / bank_cols) floats of device memory. */
+#define PDC_KEEP_MEDIANS 2u
 
 typedef struct pdc_ctx pdc_ctx;
 typedef struct pdc_graph pdc_graph;
@@ -357,10 +362,15 @@ int32_t pdc_graph_items(const pdc_graph *graph);
  * scalar.
  * ------------------------------------------------------------------------ */
 
-/* Patches of the first min(total, capacity) hits of a batch processed with
- * PDC_KEEP_CORRECTED, in hit-list order, into patches_dev float32
- * [capacity][25]; *n_out (may be NULL) receives the number written.
- * Synchronous.  ESTATE for an unknown batch or one without the flag. */
+/* Patches of the first min(total, capacity) hits of a batch, in hit-list
+ * order, into patches_dev float32 [capacity][25]; *n_out (may be NULL)
+ * receives the number written.  The batch was processed with
+ * PDC_KEEP_CORRECTED (the patch is copied from Frames2) or with
+ * PDC_KEEP_MEDIANS, and then the frames given to pdc_process_frames must
+ * still hold the batch's frames: each patch value is formed from the raw
+ * word, the calibration and the kept common-mode values by the operations
+ * of Frames2, so it is the same binary32 value.  Synchronous.  ESTATE for an
+ * unknown batch or one with neither flag. */
 pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev, uint64_t capacity,
                                uint64_t *n_out);
 

@@ -921,7 +921,12 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
             float x[V];
             read_group<V, L>(x, src, lim, tail_only, INFINITY);
             const float m = group_median<V, L, false>(x, src, B, kmed, A.rank_width, act, s_gs + tid, B);
-            if (act && gl == 0) med_c[i] = m;
+            if (act && gl == 0) {
+                med_c[i] = m;
+                // kept for patches: the own rows' medians (each row has one owner)
+                if (A.meds && row >= own_lo && row < own_hi)
+                    A.meds[f * ((uint64_t)A.T * A.H * nb) + (uint64_t)(lr0 + row) * nb + bank] = m;
+            }
             const bool own = act && row >= own_lo && row < own_hi;
             if (KEEP && own) {
                 float *f2 = A.corrected + f * npix + row_base + row * W + bank * B + gl;
@@ -978,7 +983,12 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
                     }
                 }
             }
-            if (act && gl == 0) med_c[i] = m;
+            if (act && gl == 0) {
+                med_c[i] = m;
+                // kept for patches: the own rows' medians (each row has one owner)
+                if (A.meds && row >= own_lo && row < own_hi)
+                    A.meds[f * ((uint64_t)A.T * A.H * nb) + (uint64_t)(lr0 + row) * nb + bank] = m;
+            }
             append_seeds(x, m, A.t_seed, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (p1_ok && !ovf_1) {

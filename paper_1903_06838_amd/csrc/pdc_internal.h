@@ -73,6 +73,7 @@ struct FrameKernelArgs {
     int32_t cm_tile;              // 1: a region is a tile, 0: a bank
     int32_t gain_mode;            // 0 single range; 1, 2 auto-ranging (ped, k hold 3 planes)
     uint32_t *invalid;            // [n_frames] invalid-code pixels, cleared before the launch
+    float *meds;                  // [n_frames][T*H*nb] bank medians of the own rows, or nullptr
 };
 
 struct V2Args {
@@ -106,6 +107,7 @@ struct V2Args {
     int32_t sum_lo, sum_hi;       // cm_mode 1: Frames1 values are multiples of 2^sum_lo below 2^sum_hi
     int32_t gain_mode;
     uint32_t *invalid;
+    float *meds;                  // as in FrameKernelArgs (median mode)
 };
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);

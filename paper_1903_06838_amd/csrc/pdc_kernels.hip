@@ -178,6 +178,10 @@ __global__ void __launch_bounds__(kV1Threads) frame_kernel_v1(FrameKernelArgs A)
                 float u = s_v[(g0 + row) * W + c];
                 if (!(u < INFINITY)) u = m;  // invalid: v = fl(m - m) = +0
                 s_v[(g0 + row) * W + c] = __fsub_rn(u, m);
+                // kept for patches: the own rows' medians, once per bank
+                const int rl = lr0 + g0 + row;  // row in the tile
+                if (A.meds && rl >= r0 && rl < r1 && c % B == 0)
+                    A.meds[f * ((uint64_t)A.T * H * nb) + ((uint64_t)t * H + rl) * nb + c / B] = m;
             }
             __syncthreads();
         }

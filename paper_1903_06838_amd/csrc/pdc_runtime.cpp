@@ -88,6 +88,8 @@ struct Buffers {
     float *corrected = nullptr;
     float *cm = nullptr;               // [n_frames][regions][3] common-mode values
     uint64_t cap_cm = 0;
+    float *meds = nullptr;             // [n_frames][bank-rows] medians (PDC_KEEP_MEDIANS)
+    uint64_t cap_meds = 0;
     uint32_t *invalid = nullptr;       // [n_frames] pixels with an invalid gain code
     uint64_t cap_inv = 0;
     uint64_t *fb_units = nullptr;      // [n_units] units left to the general kernel
@@ -114,6 +116,7 @@ struct Batch {
     uint64_t pool_cap = 0;
     hipStream_t stream = nullptr;
     bool keep = false;
+    bool meds = false;       // PDC_KEEP_MEDIANS: common-mode values kept for patches
     bool checked = false;  // overflow handled, totals final
     int fb = 0;            // 1: overflowing units recomputed by the general kernel, 2: whole batch
     bool capture = false;  // being captured into a graph: kernels only, no events or copies
@@ -138,6 +141,7 @@ void free_buffers(Buffers *b)
     hipFree(b->hits);
     hipFree(b->corrected);
     hipFree(b->cm);
+    hipFree(b->meds);
     hipFree(b->invalid);
     hipFree(b->fb_units);
     hipFree(b->state);
@@ -245,7 +249,8 @@ pdc_status check_params(const pdc_params *p, float *t_seed, float *t_nb)
     if (!(tn <= ts)) return fail(nullptr, PDC_EINVAL, "n_nb*sigma must be <= n_seed*sigma");
     if (!finite_in(p->photon_adu, 0x1p-24f, 0x1p24f))
         return fail(nullptr, PDC_EINVAL, "photon_adu must be in [2^-24, 2^24]");
-    if (p->flags & ~PDC_KEEP_CORRECTED) return fail(nullptr, PDC_EINVAL, "unknown flag bits 0x%x", p->flags);
+    if (p->flags & ~(PDC_KEEP_CORRECTED | PDC_KEEP_MEDIANS))
+        return fail(nullptr, PDC_EINVAL, "unknown flag bits 0x%x", p->flags);
     if (p->cm_mode != PDC_CM_MEDIAN && p->cm_mode != PDC_CM_BANK_MEAN && p->cm_mode != PDC_CM_TILE_MEAN)
         return fail(nullptr, PDC_EINVAL, "unknown cm_mode %d", p->cm_mode);
     if (p->cm_mode != PDC_CM_MEDIAN) {
@@ -452,7 +457,7 @@ hipError_t grow(T **ptr, uint64_t &cap, uint64_t need)
 }
 
 pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n_frames,
-                          uint64_t pool_cap, uint64_t corr_floats, uint64_t cm_floats = 0)
+                          uint64_t pool_cap, uint64_t corr_floats, uint64_t cm_floats = 0, uint64_t meds_floats = 0)
 {
     if (!b->state) {
         HIP_TRY(ctx, hipMalloc((void **)&b->state, sizeof(BatchState)));
@@ -490,6 +495,9 @@ pdc_status ensure_buffers(pdc_ctx *ctx, Buffers *b, uint64_t n_units, uint64_t n
     }
     if (cm_floats > b->cap_cm) {
         HIP_TRY(ctx, grow(&b->cm, b->cap_cm, cm_floats));
+    }
+    if (meds_floats > b->cap_meds) {
+        HIP_TRY(ctx, grow(&b->meds, b->cap_meds, meds_floats));
     }
     if (n_frames > b->cap_inv || !b->invalid) {
         HIP_TRY(ctx, grow(&b->invalid, b->cap_inv, n_frames));
@@ -580,6 +588,7 @@ void fill_v1_args(const Detector &d, const Batch &bt, FrameKernelArgs &a)
     a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
     a.gain_mode = d.g.gain_mode;
     a.invalid = b->invalid;
+    a.meds = bt.meds && !d.p.cm_mode ? b->meds : nullptr;
 }
 
 // End of a batch's work on its stream: the timing event, then the state copy
@@ -620,7 +629,9 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
     if (d.g.gain_mode) HIP_TRY(ctx, launch_fill_u32(b->invalid, bt.n_frames, s));
     // the persistent kernel computes a bank's thresholded mean itself
-    const bool cm_inline = d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2;
+    // the persistent kernel computes a bank's thresholded mean itself unless
+    // the stage values are kept for patches
+    const bool cm_inline = d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2 && !bt.meds;
     if (d.p.cm_mode && !cm_inline) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));
     if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_cm, s));
     if (bt.n_units > 0 && bt.path == 2) {
@@ -662,6 +673,7 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
         a.sum_hi = d.sum_hi;
         a.gain_mode = d.g.gain_mode;
         a.invalid = b->invalid;
+        a.meds = bt.meds && !d.p.cm_mode ? b->meds : nullptr;
         HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
     } else if (bt.n_units > 0) {
         FrameKernelArgs a{};
@@ -679,7 +691,8 @@ pdc_status enqueue_partial(pdc_ctx *ctx, Batch &bt, uint64_t n_list)
     Detector &d = ctx->dets[bt.det];
     Buffers *b = bt.buf;
     hipStream_t s = bt.stream;
-    if (d.p.cm_mode == PDC_CM_BANK_MEAN) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));  // the kernel computed it inline
+    if (d.p.cm_mode == PDC_CM_BANK_MEAN && !bt.meds)
+        HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));  // the kernel computed it inline
     FrameKernelArgs a{};
     fill_v1_args(d, bt, a);
     a.n_units = bt.n_units;
@@ -748,6 +761,13 @@ uint64_t corr_floats(const Detector &d, const Batch &bt)
 uint64_t cm_floats(const Detector &d, const Batch &bt)
 {
     return d.p.cm_mode ? bt.n_frames * (uint64_t)d.cm_regions * 3 : 0;
+}
+
+// Bank medians kept for patches (the thresholded mean keeps its stage values
+// in cm anyway).
+uint64_t meds_floats(const Detector &d, const Batch &bt)
+{
+    return bt.meds && !d.p.cm_mode ? bt.n_frames * (uint64_t)d.g.n_tiles * d.g.rows * (d.g.cols / d.g.bank_cols) : 0;
 }
 
 Buffers *take_buffers(pdc_ctx *ctx)
@@ -1028,8 +1048,9 @@ pdc_status pdc_process_frames_static(pdc_ctx *ctx, int32_t det, const uint16_t *
     if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
         return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
     Detector &d = ctx->dets[det];
-    if (d.p.flags & PDC_KEEP_CORRECTED)
-        return fail(ctx, PDC_EINVAL, "static: a PDC_KEEP_CORRECTED detector needs pdc_process_frames (Frames2 buffer)");
+    if (d.p.flags & (PDC_KEEP_CORRECTED | PDC_KEEP_MEDIANS))
+        return fail(ctx, PDC_EINVAL,
+                    "static: a PDC_KEEP_CORRECTED or PDC_KEEP_MEDIANS detector needs pdc_process_frames (kept buffers)");
     if (n_frames == 0) {
         if (n_hits_total) *n_hits_total = 0;
         return PDC_OK;
@@ -1188,10 +1209,12 @@ pdc_status process_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, 
     set_path(d, bt, d.v2_ok ? 2 : 1);
     bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+    bt.meds = (d.p.flags & PDC_KEEP_MEDIANS) != 0;
     bt.pool_cap = ctx->tight_pool ? hit_capacity : pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
     Buffers *b = take_buffers(ctx);
     if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
-    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt));
+    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt),
+                                   meds_floats(d, bt));
     if (rc != PDC_OK) {
         ctx->spare.push_back(b);
         return rc;
@@ -1394,6 +1417,7 @@ static pdc_status graph_capture(pdc_ctx *ctx, const pdc_mixed_item *items, int32
         bt.share = n_items > 1 && ctx->mix_share && work > 0.0 ? std::min(1.0, px / work) : 1.0;
         set_path(d, bt, d.v2_ok ? 2 : 1);
         bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+        bt.meds = (d.p.flags & PDC_KEEP_MEDIANS) != 0;
         const uint64_t hc = items[i].hit_capacity;
         bt.pool_cap = ctx->tight_pool ? hc : pool_capacity(d, bt.path, hc, batch_grid(d, bt));
         g->buf[i] = new (std::nothrow) Buffers;
@@ -1402,7 +1426,7 @@ static pdc_status graph_capture(pdc_ctx *ctx, const pdc_mixed_item *items, int32
             return fail(ctx, PDC_ENOMEM, "host allocation failed");
         }
         pdc_status rc = ensure_buffers(ctx, g->buf[i], bt.n_units, bt.n_frames, bt.pool_cap, corr_floats(d, bt),
-                                       cm_floats(d, bt));
+                                       cm_floats(d, bt), meds_floats(d, bt));
         if (rc != PDC_OK) {
             drop();
             return rc;
@@ -1540,7 +1564,8 @@ pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev,
     if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
     Batch *bt = find_batch(ctx, batch);
     if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
-    if (!bt->keep) return fail(ctx, PDC_ESTATE, "batch was not processed with PDC_KEEP_CORRECTED");
+    if (!bt->keep && !bt->meds)
+        return fail(ctx, PDC_ESTATE, "batch was processed with neither PDC_KEEP_CORRECTED nor PDC_KEEP_MEDIANS");
     if (capacity > 0 && !patches_dev) return fail(ctx, PDC_EINVAL, "patches_dev is NULL with capacity > 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     pdc_status rc = finish_batch(ctx, *bt);
@@ -1550,8 +1575,26 @@ pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev,
     hipStream_t cs = ctx->copy_stream;
     HIP_TRY(ctx, hipStreamWaitEvent(cs, b->ev_end, 0));
     const uint64_t n = std::min<uint64_t>(b->host_state->total, capacity);
-    HIP_TRY(ctx, launch_capture_patches(b->corrected, b->hits, b->frame_offset, bt->n_frames, n, d.g.n_tiles,
-                                        d.g.rows, d.g.cols, patches_dev, cs));
+    if (bt->keep) {
+        HIP_TRY(ctx, launch_capture_patches(b->corrected, b->hits, b->frame_offset, bt->n_frames, n, d.g.n_tiles,
+                                            d.g.rows, d.g.cols, patches_dev, cs));
+    } else {
+        PatchSrc ps{};
+        ps.frames = bt->frames;
+        ps.ped = d.d_ped;
+        ps.k = d.d_k;
+        ps.T = d.g.n_tiles;
+        ps.H = d.g.rows;
+        ps.W = d.g.cols;
+        ps.B = d.g.bank_cols;
+        ps.nb = d.g.cols / d.g.bank_cols;
+        ps.gain_mode = d.g.gain_mode;
+        ps.meds = d.p.cm_mode ? nullptr : b->meds;
+        ps.cm = d.p.cm_mode ? b->cm : nullptr;
+        ps.cm_regions = d.cm_regions;
+        ps.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+        HIP_TRY(ctx, launch_patches_from_frames(ps, b->hits, b->frame_offset, bt->n_frames, n, patches_dev, cs));
+    }
     HIP_TRY(ctx, hipStreamSynchronize(cs));
     if (n_out) *n_out = n;
     return PDC_OK;

@@ -42,6 +42,21 @@ hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, floa
 hipError_t launch_capture_patches(const float *corrected, const uint2 *hits,
                                   const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, int T,
                                   int H, int W, float *patches, hipStream_t s);
+// Patches rebuilt from the frames: Frames2 of each window pixel from its raw
+// word, the calibration and the frame's kept common-mode values (meds: bank
+// medians [n_frames][T*H*nb]; or, with meds null, the thresholded mean's
+// stage values cm [n_frames][cm_regions][3]).
+struct PatchSrc {
+    const uint16_t *frames;
+    const float *ped, *k;
+    int32_t T, H, W, B, nb, gain_mode;
+    const float *meds;
+    const float *cm;
+    uint32_t cm_regions;
+    int32_t cm_tile;
+};
+hipError_t launch_patches_from_frames(const PatchSrc &a, const uint2 *hits, const unsigned long long *frame_offset,
+                                      uint64_t n_frames, uint64_t n, float *patches, hipStream_t s);
 hipError_t launch_mfma_probe(const uint16_t *A, const uint16_t *B, float *D, hipStream_t s);
 
 }  // namespace pdc

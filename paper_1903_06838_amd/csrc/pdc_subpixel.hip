@@ -12,6 +12,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "pdc_device.h"
 #include "pdc_subpixel.h"
 
 #pragma clang fp contract(off)
@@ -618,6 +619,63 @@ hipError_t launch_capture_patches(const float *corrected, const uint2 *hits, con
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(capture_patches_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, corrected, hits,
                        frame_offset, n_frames, n, T, H, W, patches);
+    return hipGetLastError();
+}
+
+// The same patches without Frames2: each window pixel's Frames2 value formed
+// again from its raw word, the calibration and the kept common-mode values,
+// by the frame kernels' operations (invalid gain codes give +0).
+__global__ void patches_from_frames_kernel(PatchSrc a, const uint2 *hits, const unsigned long long *frame_offset,
+                                           uint64_t n_frames, uint64_t n, float *patches)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t lo = 0, hi = n_frames;
+    while (hi - lo > 1) {
+        const uint64_t mid = (lo + hi) / 2;
+        if (frame_offset[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    const int H = a.H, W = a.W;
+    const uint64_t HW = (uint64_t)H * W, npix = (uint64_t)a.T * HW;
+    const uint32_t p = hits[i].x;
+    const int c = (int)(p % (uint32_t)W);
+    const int rt = (int)(p / (uint32_t)W);
+    const int t = rt / H, r = rt - t * H;
+    const uint16_t *fr = a.frames + lo * npix;
+    float *dst = patches + i * 25;
+#pragma unroll
+    for (int dr = -2; dr <= 2; ++dr)
+#pragma unroll
+        for (int dc = -2; dc <= 2; ++dc) {
+            const int rr = r + dr, cc = c + dc;
+            float v = 0.0f;
+            if (rr >= 0 && rr < H && cc >= 0 && cc < W) {
+                const uint64_t q = (uint64_t)t * HW + (uint64_t)rr * W + cc;
+                const uint32_t w = fr[q];
+                bool bad = false;
+                const float u = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, a.ped[q], a.k[q], a.ped, a.k, npix, q, bad)
+                                            : dark_gain(w, a.ped[q], a.k[q]);
+                const uint32_t grow = (uint32_t)(t * H + rr);
+                if (a.meds) {
+                    const float m = a.meds[lo * (uint64_t)a.T * H * a.nb + (uint64_t)grow * a.nb + cc / a.B];
+                    v = bad ? 0.0f : __fsub_rn(u, m);  // invalid: fl(m - m) = +0
+                } else {
+                    const uint32_t reg = a.cm_tile ? (uint32_t)t : grow * (uint32_t)a.nb + (uint32_t)(cc / a.B);
+                    const float *cv = a.cm + (lo * a.cm_regions + reg) * 3;
+                    v = bad ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, cv[0]), cv[1]), cv[2]);
+                }
+            }
+            dst[(dr + 2) * 5 + dc + 2] = v;
+        }
+}
+
+hipError_t launch_patches_from_frames(const PatchSrc &a, const uint2 *hits, const unsigned long long *frame_offset,
+                                      uint64_t n_frames, uint64_t n, float *patches, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(patches_from_frames_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, a, hits,
+                       frame_offset, n_frames, n, patches);
     return hipGetLastError();
 }
 

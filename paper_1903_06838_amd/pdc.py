@@ -29,6 +29,7 @@ ENOMEM = -2
 EDEVICE = -3
 ESTATE = -4
 KEEP_CORRECTED = 1
+KEEP_MEDIANS = 2
 
 HIT_DTYPE = np.dtype([("frame", "<u4"), ("pixel", "<u4"), ("charge", "<f4"), ("nphot", "<u4")])
 

@@ -52,6 +52,9 @@ def test_check_calibration_accepts_valid(pdc):
     g, ped, gain = _valid()
     assert pdc.check_calibration(pdc.geometry(*g), ped, gain, pdc.params()) == pdc.OK
     assert pdc.check_calibration(pdc.geometry(*g), ped, gain, pdc.params(flags=pdc.KEEP_CORRECTED)) == pdc.OK
+    assert pdc.check_calibration(pdc.geometry(*g), ped, gain, pdc.params(flags=pdc.KEEP_MEDIANS)) == pdc.OK
+    assert pdc.check_calibration(pdc.geometry(*g), ped, gain,
+                                 pdc.params(flags=pdc.KEEP_CORRECTED | pdc.KEEP_MEDIANS)) == pdc.OK
     # edges of the documented ranges
     ped2 = ped.copy()
     ped2[0, 0, 0] = 0.0
@@ -87,7 +90,7 @@ def test_check_calibration_rejects_gain_mode(pdc):
 BAD_PARAMS = [dict(sigma=0.0), dict(sigma=-1.0), dict(sigma=math.nan), dict(sigma=math.inf),
               dict(n_seed=-1.0), dict(n_nb=math.nan), dict(n_seed=3.0, n_nb=5.0),
               dict(photon_adu=0.0), dict(photon_adu=2.0 ** 25), dict(photon_adu=math.nan),
-              dict(flags=2), dict(sigma=3e38, n_seed=5.0)]
+              dict(flags=4), dict(flags=8), dict(sigma=3e38, n_seed=5.0)]
 
 
 @pytest.mark.parametrize("kw", BAD_PARAMS, ids=lambda k: str(k))

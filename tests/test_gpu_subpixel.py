@@ -323,3 +323,86 @@ def test_capture_patches_from_frames2(ctx):
     assert np.array_equal(_bits(got[:n]), _bits(exp))
     assert np.all(got[n:] == -1.0)
     assert np.array_equal(_bits(small.cpu().numpy()), _bits(exp[:7]))
+
+
+MED_CASES = [
+    # geometry, gain mode, cm mode, stages, occupancy, frames, force the general kernel
+    (synth.Geometry(2, 40, 388, 194), 0, 0, 1, 0.02, 3, False),   # persistent kernel, 16 lanes per bank
+    (synth.Geometry(1, 64, 768, 96), 0, 0, 1, 0.03, 3, False),    # 8 lanes per bank
+    (synth.Geometry(3, 37, 96, 48), 0, 0, 1, 0.02, 4, True),      # general kernel
+    (synth.Geometry(1, 48, 1024, 256), 2, 0, 1, 0.02, 2, False),  # Jungfrau-like gain ranges, invalid codes
+    (synth.Geometry(2, 40, 388, 194), 0, 1, 3, 0.02, 3, False),   # bank thresholded mean, 3 stages
+    (synth.Geometry(2, 40, 388, 194), 0, 2, 2, 0.02, 2, False),   # tile thresholded mean
+]
+
+
+@pytest.mark.parametrize("geom,gm,cm,stages,occ,n,general", MED_CASES, ids=lambda x: str(x))
+def test_capture_patches_from_kept_medians(ctx, geom, gm, cm, stages, occ, n, general):
+    """Patches of a batch that kept only its common-mode values (no Frames2),
+    formed from the frames, the calibration and those values, equal the
+    patches cut from Frames2 of the same frames bit for bit, and the hit
+    lists of the two batches are equal."""
+    import os
+
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    if gm:
+        ped, gain = synth.make_calibration_multigain(geom, 31)
+        raw = synth.make_frames_multigain(geom, ped, gain, n, occ, 31, gm)
+    else:
+        ped, gain = synth.make_calibration(geom, 31)
+        sim = synth.SimParams(cm_sigma=1.0) if cm == 2 else synth.SimParams()
+        raw = synth.make_frames(geom, ped, gain, n, occ, 31, sim=sim)
+    if general:
+        os.environ["PDC_FORCE_GENERAL"] = "1"
+        try:
+            c = pdc.create(0)
+        finally:
+            del os.environ["PDC_FORCE_GENERAL"]
+    else:
+        c = ctx
+    out = {}
+    try:
+        for flag in (pdc.KEEP_CORRECTED, pdc.KEEP_MEDIANS):
+            det = pdc.calibrate(c, pdc.geometry(*geom.shape, geom.bank_cols, gain_mode=gm), ped, gain,
+                                pdc.params(3.0, 5.0, 3.0, ADU, flag, cm_mode=cm, cm_stages=stages))
+            try:
+                frames = _dev(raw)
+                b = pdc.process_frames(c, det, frames, n, 200000)
+                hits, total, _, _, _ = pdc.get_hits(c, b, n)
+                pt = torch.full((total + 3, 25), -1.0, dtype=torch.float32, device="cuda")
+                torch.cuda.synchronize()
+                m = pdc.capture_patches(c, b, pt, total + 3)
+                path = pdc.debug_batch_path(c, b)
+                pdc.release_batch(c, b)
+            finally:
+                pdc.release_detector(c, det)
+            out[flag] = (hits, m, pt.cpu().numpy(), path)
+    finally:
+        if general:
+            pdc.destroy(c)
+    (h1, n1, p1, path1), (h2, n2, p2, path2) = out[pdc.KEEP_CORRECTED], out[pdc.KEEP_MEDIANS]
+    assert n1 == n2 == len(h1) > 20
+    assert path1 == path2 == (1 if general else 2)
+    assert np.array_equal(h1.view(np.uint32), h2.view(np.uint32))
+    assert np.array_equal(_bits(p1), _bits(p2))
+    assert np.all(p2[n2:] == -1.0)
+
+
+def test_capture_patches_needs_a_kept_buffer(ctx):
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(1, 16, 96, 48)
+    ped, gain = synth.make_calibration(geom, 33)
+    raw = synth.make_frames(geom, ped, gain, 1, 0.02, 33)
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params())
+    try:
+        b = pdc.process_frames(ctx, det, _dev(raw), 1, 10000)
+        with pytest.raises(pdc.PdcError) as e:
+            pdc.capture_patches(ctx, b, None, 0)
+        assert e.value.status == pdc.ESTATE
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
