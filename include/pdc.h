@@ -291,6 +291,16 @@ pdc_status pdc_get_invalid_counts(pdc_ctx *ctx, uint64_t batch, uint32_t *per_fr
 /* Wait for the batch and return its buffers to the context for reuse. */
 pdc_status pdc_release_batch(pdc_ctx *ctx, uint64_t batch);
 
+/* Device memory, in bytes, of the buffers pdc_process_frames uses for a batch
+ * of n_frames frames with this hit_capacity on detector det (staging pool,
+ * hit list, per-unit and per-frame records, and Frames2 or the kept
+ * common-mode values when the detector's flags ask for them).  Buffers are
+ * reused from batch to batch, so this is what a batch needs, not what a call
+ * allocates.  Admission control of a serving loop charges it.  ESTATE for an
+ * unknown detector; EINVAL for n_frames > 2^31 or a NULL pointer. */
+pdc_status pdc_batch_bytes(pdc_ctx *ctx, int32_t det, uint64_t n_frames, uint64_t hit_capacity,
+                           uint64_t *bytes);
+
 /* Timing of a finished batch from HIP events recorded on its stream:
  * *main_ms = the fused frame kernel alone, *total_ms = every kernel of the
  * batch (common-mode pass of the mean modes, frame kernel, scans, hit
@@ -458,6 +468,13 @@ typedef struct {
     int32_t reserved;
 } pdc_serve_frame;
 
+/* Subpixel stage of a served stream (Photon Subpixel Resolution section):
+ * positions of every hit, from the batch's patches (the detector must keep
+ * PDC_KEEP_CORRECTED or PDC_KEEP_MEDIANS). */
+#define PDC_SERVE_SUBPIXEL_NONE 0
+#define PDC_SERVE_SUBPIXEL_MLP 1       /* pdc_mlp_infer with the config's network */
+#define PDC_SERVE_SUBPIXEL_CENTROID 2  /* pdc_centroid, eta-corrected when the config has a table */
+
 typedef struct {
     int32_t det;                 /* detector id from pdc_calibrate */
     uint32_t pool_frames;        /* frames in pool_dev (>= 1 when n_frames > 0) */
@@ -473,23 +490,35 @@ typedef struct {
                                     frame = stream frame index, or NULL */
     uint64_t hits_capacity;      /* records the hits array holds (excess hits are not kept) */
     uint64_t hits_kept;          /* out: records written */
+    int32_t subpixel;            /* PDC_SERVE_SUBPIXEL_* */
+    float photon_adu;            /* the detector's single-photon signal (the network's input scale) */
+    float t_nb;                  /* the detector's neighbour threshold n_nb * sigma (centroid mask) */
+    float *positions;            /* host [hits_capacity][2] (dy, dx) of the kept hits, or NULL */
 } pdc_serve_stream;
 
 typedef struct {
     uint32_t max_batch;          /* frames per launch, >= 1 */
     uint32_t max_inflight;       /* batches in flight per stream, 1..64 */
     uint64_t max_queue;          /* waiting frames per stream before arrivals are dropped (0: none) */
-    uint64_t hbm_budget;         /* bytes of in-flight batch buffers over all streams (0: none);
+    uint64_t hbm_budget;         /* bytes of in-flight batches over all streams (0: none), each
+                                    charged pdc_batch_bytes plus its patches and positions;
                                     a stream with nothing in flight may always launch */
+    pdc_mlp *net;                /* network of PDC_SERVE_SUBPIXEL_MLP streams, or NULL */
+    const float *eta_dev;        /* eta table of PDC_SERVE_SUBPIXEL_CENTROID streams (float32
+                                    [2][eta_bins + 1] from pdc_eta_table), or NULL: plain centroid */
+    int32_t eta_bins;
 } pdc_serve_config;
 
 typedef struct {
     uint64_t frames_done, frames_dropped, batches, peak_bytes, wall_ns;
 } pdc_serve_summary;
 
-/* Run the serving loop over n_streams (1..64) streams.  EINVAL on a bad
- * argument (NULL arrays, decreasing arrival times, zero sizes); errors of the
- * calls it makes are returned as they are.  summary may be NULL. */
+/* Run the serving loop over n_streams (1..64) streams.  A frame is done once
+ * its hits, counts and (with a subpixel stage) positions are on the host; a
+ * subpixel stage runs when its batch completes, before the frame's done
+ * time.  EINVAL on a bad argument (NULL arrays, decreasing arrival times,
+ * zero sizes, an MLP stage without a network); errors of the calls it makes
+ * are returned as they are.  summary may be NULL. */
 pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_streams,
                          const pdc_serve_config *cfg, pdc_serve_summary *summary);
 

@@ -1034,6 +1034,29 @@ pdc_status pdc_release_detector(pdc_ctx *ctx, int32_t det)
 pdc_status process_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
                          uint64_t hit_capacity, void *hip_stream, double share, uint64_t *batch_out);
 
+pdc_status pdc_batch_bytes(pdc_ctx *ctx, int32_t det, uint64_t n_frames, uint64_t hit_capacity, uint64_t *bytes)
+{
+    if (!ctx || !bytes) return fail(ctx, PDC_EINVAL, "ctx and bytes must be non-NULL");
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    if (n_frames > ((uint64_t)1 << 31)) return fail(ctx, PDC_EINVAL, "n_frames must be <= 2^31");
+    const Detector &d = ctx->dets[det];
+    Batch bt;
+    bt.det = det;
+    bt.n_frames = n_frames;
+    set_path(d, bt, d.v2_ok ? 2 : 1);
+    bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+    bt.meds = (d.p.flags & PDC_KEEP_MEDIANS) != 0;
+    const uint64_t pool = pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
+    uint64_t b = bt.n_units * (sizeof(uint32_t) + sizeof(unsigned long long) + sizeof(uint64_t) + sizeof(uint32_t));
+    b += n_frames * (sizeof(uint32_t) + sizeof(unsigned long long)) + (n_frames + 1) * sizeof(unsigned long long);
+    b += pool * 2 * sizeof(uint2);
+    b += 4 * (corr_floats(d, bt) + cm_floats(d, bt) + meds_floats(d, bt));
+    b += n_frames * sizeof(uint32_t) + bt.n_units * sizeof(uint64_t) + sizeof(BatchState);
+    *bytes = b;
+    return PDC_OK;
+}
+
 pdc_status pdc_process_frames(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
                               uint64_t hit_capacity, void *hip_stream, uint64_t *batch_out)
 {

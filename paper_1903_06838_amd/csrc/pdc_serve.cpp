@@ -1,8 +1,9 @@
 // Serving loop: several detectors' frame streams arriving at their own times,
 // processed with continuous batching on one GPU (one HIP stream per detector,
 // so batches of different detectors overlap on the device), with admission
-// control by a device-memory budget and per-frame latency records.  Built on
-// the public C ABI of pdc.h only.
+// control by a device-memory budget (each batch charged what the library
+// reports for it), an optional subpixel stage on every hit, and per-frame
+// latency records.  Built on the public C ABI of pdc.h only.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +35,10 @@ struct InFlight {
 struct StreamState {
     pdc_serve_stream *d = nullptr;
     hipStream_t hs = nullptr;
+    hipStream_t ss = nullptr;    // subpixel work of completed batches
+    float *patches = nullptr;    // device [cap][25]
+    float *pos = nullptr;        // device [cap][2]
+    uint64_t cap = 0;
     uint64_t next_arrival = 0;   // next frame index not yet arrived
     std::deque<uint64_t> pending;  // arrived, not launched
     std::deque<InFlight> inflight;
@@ -85,6 +90,8 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
         pdc_serve_stream &d = streams[s];
         if (d.n_frames > 0 && (!d.pool_dev || d.pool_frames == 0 || !d.arrival_ns || !d.results)) return PDC_EINVAL;
         if (d.pixels_per_frame == 0) return PDC_EINVAL;
+        if (d.subpixel < PDC_SERVE_SUBPIXEL_NONE || d.subpixel > PDC_SERVE_SUBPIXEL_CENTROID) return PDC_EINVAL;
+        if (d.subpixel == PDC_SERVE_SUBPIXEL_MLP && !cfg->net) return PDC_EINVAL;
         for (uint64_t i = 1; i < d.n_frames; ++i)
             if (d.arrival_ns[i] < d.arrival_ns[i - 1]) return PDC_EINVAL;
         S[s].d = &d;
@@ -99,8 +106,12 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
         }
     }
     pdc_status rc = PDC_OK;
-    for (int s = 0; s < n_streams && rc == PDC_OK; ++s)
+    for (int s = 0; s < n_streams && rc == PDC_OK; ++s) {
         if (hipStreamCreateWithFlags(&S[s].hs, hipStreamNonBlocking) != hipSuccess) rc = PDC_EDEVICE;
+        if (rc == PDC_OK && streams[s].subpixel &&
+            hipStreamCreateWithFlags(&S[s].ss, hipStreamNonBlocking) != hipSuccess)
+            rc = PDC_EDEVICE;
+    }
 
     uint64_t done_frames = 0, dropped = 0, launched_batches = 0, held_bytes = 0, peak_bytes = 0;
     const Clock::time_point t0 = Clock::now();
@@ -117,6 +128,31 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
         const uint64_t tdone = ns_since(t0);
         const uint64_t kept = std::min(total, cap);
         for (uint64_t j = 0; j < kept; ++j) dst[j].frame += (uint32_t)b.first;  // stream frame index
+        if (st.d->subpixel && total > 0) {
+            // positions of all the batch's hits; those of the kept hits are copied out
+            if (total > st.cap) {
+                hipFree(st.patches);
+                hipFree(st.pos);
+                st.patches = st.pos = nullptr;
+                st.cap = 0;
+                if (hipMalloc((void **)&st.patches, total * 25 * sizeof(float)) != hipSuccess ||
+                    hipMalloc((void **)&st.pos, total * 2 * sizeof(float)) != hipSuccess)
+                    return PDC_ENOMEM;
+                st.cap = total;
+            }
+            uint64_t np = 0;
+            r = pdc_capture_patches(ctx, b.batch, st.patches, total, &np);
+            if (r < 0) return r;
+            r = st.d->subpixel == PDC_SERVE_SUBPIXEL_MLP
+                    ? pdc_mlp_infer(cfg->net, st.patches, np, st.d->photon_adu, st.pos, st.ss)
+                    : pdc_centroid(ctx, st.patches, np, st.d->t_nb, cfg->eta_dev, cfg->eta_bins, st.pos, st.ss);
+            if (r < 0) return r;
+            if (st.d->positions && kept > 0 &&
+                hipMemcpyAsync(st.d->positions + 2 * st.hits_written, st.pos, kept * 2 * sizeof(float),
+                               hipMemcpyDeviceToHost, st.ss) != hipSuccess)
+                return PDC_EDEVICE;
+            if (hipStreamSynchronize(st.ss) != hipSuccess) return PDC_EDEVICE;
+        }
         st.hits_written += kept;
         for (uint64_t j = 0; j < b.n; ++j) {
             pdc_serve_frame &fr = st.d->results[b.first + j];
@@ -165,7 +201,10 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
                 const uint64_t pool_i = first % d.pool_frames;
                 const uint64_t n = next_batch_len(st.pending, st.pending.size(), cfg->max_batch, d.pool_frames);
                 const uint64_t hit_cap = std::max<uint64_t>(1024, (uint64_t)(d.hit_fraction * (double)(st.pixels * n)));
-                const uint64_t bytes = hit_cap * 16 + n * 64;
+                uint64_t bytes = 0;
+                rc = pdc_batch_bytes(ctx, d.det, n, hit_cap, &bytes);
+                if (rc != PDC_OK) break;
+                if (d.subpixel) bytes += hit_cap * 27 * sizeof(float);  // patches and positions
                 if (cfg->hbm_budget && held_bytes + bytes > cfg->hbm_budget && !st.inflight.empty()) break;
                 InFlight b;
                 b.first = first;
@@ -204,6 +243,12 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
             hipStreamSynchronize(S[s].hs);
             hipStreamDestroy(S[s].hs);
         }
+        if (S[s].ss) {
+            hipStreamSynchronize(S[s].ss);
+            hipStreamDestroy(S[s].ss);
+        }
+        hipFree(S[s].patches);
+        hipFree(S[s].pos);
     }
     for (int s = 0; s < n_streams; ++s) streams[s].hits_kept = S[s].hits_written;
     if (summary) {

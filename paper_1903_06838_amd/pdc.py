@@ -73,6 +73,7 @@ _sig = {
                            ctypes.POINTER(ctypes.c_uint64), _P, _P]),
     "pdc_get_corrected": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_int32]),
     "pdc_release_batch": (_st, [_P, ctypes.c_uint64]),
+    "pdc_batch_bytes": (_st, [_P, ctypes.c_int32, ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
     "pdc_batch_timing": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
                                ctypes.POINTER(ctypes.c_float)]),
     "pdc_capture_patches": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
@@ -305,6 +306,13 @@ def release_batch(ctx, batch: int) -> None:
     _check(_lib.pdc_release_batch(ctx, batch), ctx)
 
 
+def batch_bytes(ctx, det: int, n_frames: int, hit_capacity: int) -> int:
+    """Device bytes of a batch of this shape on detector det."""
+    b = ctypes.c_uint64(0)
+    _check(_lib.pdc_batch_bytes(ctx, det, n_frames, hit_capacity, ctypes.byref(b)), ctx)
+    return b.value
+
+
 def graph_create(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int):
     """Capture a batch of n_frames frames read from frames_dev (device tensor or
     address) into a HIP graph; returns the graph handle."""
@@ -442,12 +450,13 @@ class ServeStream(ctypes.Structure):
     _fields_ = [("det", ctypes.c_int32), ("pool_frames", ctypes.c_uint32), ("pool_dev", _P),
                 ("pixels_per_frame", ctypes.c_uint64), ("n_frames", ctypes.c_uint64), ("arrival_ns", _P),
                 ("hit_fraction", ctypes.c_double), ("results", _P), ("hits", _P),
-                ("hits_capacity", ctypes.c_uint64), ("hits_kept", ctypes.c_uint64)]
+                ("hits_capacity", ctypes.c_uint64), ("hits_kept", ctypes.c_uint64), ("subpixel", ctypes.c_int32),
+                ("photon_adu", ctypes.c_float), ("t_nb", ctypes.c_float), ("positions", _P)]
 
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32), ("max_queue", ctypes.c_uint64),
-                ("hbm_budget", ctypes.c_uint64)]
+                ("hbm_budget", ctypes.c_uint64), ("net", _P), ("eta_dev", _P), ("eta_bins", ctypes.c_int32)]
 
 
 class ServeSummary(ctypes.Structure):
@@ -455,10 +464,16 @@ class ServeSummary(ctypes.Structure):
                 ("peak_bytes", ctypes.c_uint64), ("wall_ns", ctypes.c_uint64)]
 
 
-def serve_run(ctx, streams, max_batch=64, max_inflight=2, max_queue=0, hbm_budget=0):
+SERVE_SUBPIXEL_NONE, SERVE_SUBPIXEL_MLP, SERVE_SUBPIXEL_CENTROID = 0, 1, 2
+
+
+def serve_run(ctx, streams, max_batch=64, max_inflight=2, max_queue=0, hbm_budget=0, net=None, eta_dev=None,
+              eta_bins=0, return_positions=False):
     """streams: list of dicts with det, pool (device uint16 tensor [P, T, H, W]), arrival_ns (host
-    uint64 array), hit_fraction, keep_hits (capacity or 0).  Returns (results, hits, summary):
-    per stream a SERVE_FRAME_DTYPE array and a HIT_DTYPE array (or None)."""
+    uint64 array), hit_fraction, keep_hits (capacity or 0), and for a subpixel stage subpixel
+    (SERVE_SUBPIXEL_*), photon_adu and t_nb.  Returns (results, hits, summary): per stream a
+    SERVE_FRAME_DTYPE array and a HIT_DTYPE array (or None); with return_positions, a fourth
+    item: per stream float32 [hits_kept, 2] positions of the kept hits (or None)."""
     descs = (ServeStream * len(streams))()
     keep = []
     for d, st in zip(descs, streams):
@@ -477,13 +492,21 @@ def serve_run(ctx, streams, max_batch=64, max_inflight=2, max_queue=0, hbm_budge
         d.results = res.ctypes.data
         d.hits = hits.ctypes.data if cap else None
         d.hits_capacity = cap
-        keep.append((arr, res, hits))
-    cfg = ServeConfig(max_batch, max_inflight, max_queue, hbm_budget)
+        d.subpixel = int(st.get("subpixel", SERVE_SUBPIXEL_NONE))
+        d.photon_adu = float(st.get("photon_adu", 150.0))
+        d.t_nb = float(st.get("t_nb", 9.0))
+        pos = np.zeros((cap, 2), np.float32) if (cap and d.subpixel) else None
+        d.positions = pos.ctypes.data if pos is not None else None
+        keep.append((arr, res, hits, pos))
+    cfg = ServeConfig(max_batch, max_inflight, max_queue, hbm_budget, net, _ptr(eta_dev), eta_bins)
     summ = ServeSummary()
     _check(_lib.pdc_serve_run(ctx, descs, len(streams), ctypes.byref(cfg), ctypes.byref(summ)), ctx)
-    out_hits = [h[:d.hits_kept] if h is not None else None for (_, _, h), d in zip(keep, descs)]
+    out_hits = [h[:d.hits_kept] if h is not None else None for (_, _, h, _), d in zip(keep, descs)]
     summary = {f: getattr(summ, f) for f, _ in ServeSummary._fields_}
-    return [r for _, r, _ in keep], out_hits, summary
+    if return_positions:
+        out_pos = [p[:d.hits_kept] if p is not None else None for (_, _, _, p), d in zip(keep, descs)]
+        return [r for _, r, _, _ in keep], out_hits, summary, out_pos
+    return [r for _, r, _, _ in keep], out_hits, summary
 
 
 # ---------------------------------------------------------------------------

@@ -1,15 +1,26 @@
 """Serving loop (pdc_serve_run) on the GPU: several detectors' streams with
-Poisson arrivals, continuous batching and admission control.  Every frame's
-hits, counts and photon totals in the mix equal those of the frame processed
-alone, bit for bit; drops happen only through the admission limits."""
+Poisson arrivals, continuous batching and admission control.  Every served
+frame's hit records, count and photon total equal the oracle's for that frame,
+bit for bit, whatever batch it was served in; drops happen only through the
+admission limits.  With a subpixel stage, each kept hit's position equals the
+oracle's centroid (bit for bit) or the learned estimator on the same patches
+(bit for bit against pdc_mlp_infer, within the network's bfloat16 tolerance
+against the oracle's forward pass)."""
 import numpy as np
 import pytest
 
+from oracle import multigain as G
+from oracle import subpixel as S
 from paper_1903_06838_amd import synth
+from tests.helpers import oracle_threads
 
 pytestmark = pytest.mark.gpu
 
-GEOMS = [synth.Geometry(2, 40, 388, 194), synth.Geometry(1, 64, 768, 96), synth.Geometry(1, 48, 1024, 256)]
+ADU = 150.0
+T_NB = 9.0
+# geometry, gain mode (0 single; 2 Jungfrau-like ranges with invalid codes), pool frames
+DETS = [(synth.Geometry(2, 40, 388, 194), 0, 7), (synth.Geometry(1, 64, 768, 96), 0, 5),
+        (synth.Geometry(1, 48, 1024, 256), 0, 6), (synth.Geometry(1, 48, 1024, 256), 2, 4)]
 
 
 @pytest.fixture(scope="module")
@@ -24,27 +35,41 @@ def ctx():
     pdc.destroy(c)
 
 
+def _patches(corr, hits, H, W):
+    """Oracle 5x5 windows of Frames2 at the oracle's hits (zero outside the tile)."""
+    pad = np.pad(corr, ((0, 0), (0, 0), (2, 2), (2, 2)))
+    t, rc = np.divmod(hits["pixel"].astype(np.int64), H * W)
+    r, c = np.divmod(rc, W)
+    return np.stack([pad[hits["frame"][i], t[i], r[i]:r[i] + 5, c[i]:c[i] + 5].reshape(25)
+                     for i in range(len(hits))]).astype(np.float32) if len(hits) else np.zeros((0, 25), np.float32)
+
+
 @pytest.fixture(scope="module")
 def detectors(ctx):
-    """Calibrated detectors with device frame pools and each pool frame's
-    results processed alone."""
+    """Calibrated detectors (keeping their bank medians, for patches) with
+    device frame pools and the oracle's results for each pool frame."""
     import torch
 
     from paper_1903_06838_amd import pdc
 
     out = []
-    for j, (g, P) in enumerate(zip(GEOMS, (7, 5, 6))):
-        ped, gain = synth.make_calibration(g, 40 + j)
-        raw = synth.make_frames(g, ped, gain, P, 0.02, 40 + j)
-        det = pdc.calibrate(ctx, pdc.geometry(*g.shape, g.bank_cols), ped, gain, pdc.params())
-        pool = torch.from_numpy(raw).cuda()
-        alone = []
-        for i in range(P):
-            b = pdc.process_frames(ctx, det, pool[i:i + 1], 1, 1 << 16)
-            h, total, fh, fp, _ = pdc.get_hits(ctx, b, 1)
-            pdc.release_batch(ctx, b)
-            alone.append((h, int(fh[0]), int(fp[0])))
-        out.append(dict(det=det, pool=pool, alone=alone, geom=g))
+    for j, (g, gm, P) in enumerate(DETS):
+        if gm:
+            ped, gain = synth.make_calibration_multigain(g, 40 + j)
+            raw = synth.make_frames_multigain(g, ped, gain, P, 0.02, 40 + j, gm)
+            want = G.process(raw, ped, gain, g.bank_cols, gm, keep_corrected=True)
+        else:
+            ped, gain = synth.make_calibration(g, 40 + j)
+            raw = synth.make_frames(g, ped, gain, P, 0.02, 40 + j)
+            want = oracle_threads(raw, ped, gain, g.bank_cols, keep_corrected=True)
+        det = pdc.calibrate(ctx, pdc.geometry(*g.shape, g.bank_cols, gain_mode=gm), ped, gain,
+                            pdc.params(3.0, 5.0, 3.0, ADU, pdc.KEEP_MEDIANS))
+        h = want["hits"]
+        per = [h[h["frame"] == f] for f in range(P)]
+        T, H, W = g.shape
+        patches = [_patches(want["corrected"], p, H, W) for p in per]
+        out.append(dict(det=det, pool=torch.from_numpy(raw).cuda(), geom=g, per=per, patches=patches,
+                        fh=np.asarray(want["frame_hits"]), fp=np.asarray(want["frame_photons"])))
     yield out
     for d in out:
         pdc.release_detector(ctx, d["det"])
@@ -55,57 +80,120 @@ def _arrivals(n, rate_hz, seed):
     return np.cumsum(rng.exponential(1e9 / rate_hz, size=n)).astype(np.uint64)
 
 
-def _check_stream(res, hits, d, n):
+def _check_stream(res, hits, d):
+    """Each done frame against the oracle's results for its pool frame."""
     P = d["pool"].shape[0]
     done = np.nonzero(res["status"] == 1)[0]
     assert np.all(res["arrival_ns"][done] <= res["launch_ns"][done])
     assert np.all(res["launch_ns"][done] <= res["done_ns"][done])
-    per = {} if hits is None else {int(f): hits[hits["frame"] == f] for f in np.unique(hits["frame"])}
+    got = {} if hits is None else {int(f): hits[hits["frame"] == f] for f in np.unique(hits["frame"])}
     for i in done:
-        h, nh, nph = d["alone"][i % P]
-        assert res["hits"][i] == nh and res["photons"][i] == nph, (i, res["hits"][i], nh)
+        pf = int(i) % P
+        assert res["hits"][i] == d["fh"][pf] and res["photons"][i] == d["fp"][pf], (i, res["hits"][i], d["fh"][pf])
         if hits is not None:
-            got = per.get(int(i), np.zeros(0, hits.dtype)).copy()
-            want = h.copy()
-            want["frame"] = i
-            assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), i
+            g = got.get(int(i), np.zeros(0, hits.dtype)).copy()
+            w = d["per"][pf].copy()
+            w["frame"] = i
+            assert np.array_equal(g.view(np.uint32), w.view(np.uint32)), i
 
 
-def test_mix_equals_alone(ctx, detectors):
+def test_mix_equals_oracle(ctx, detectors):
     from paper_1903_06838_amd import pdc
 
-    ns = (60, 50, 40)
+    ns = (60, 50, 40, 30)
     streams = [dict(det=d["det"], pool=d["pool"], arrival_ns=_arrivals(n, 20000.0, 7 + j), hit_fraction=0.05,
                     keep_hits=200000) for j, (d, n) in enumerate(zip(detectors, ns))]
     res, hits, summ = pdc.serve_run(ctx, streams, max_batch=8, max_inflight=2)
     assert summ["frames_done"] == sum(ns) and summ["frames_dropped"] == 0
     assert summ["batches"] < sum(ns)  # some frames were batched together
-    for r, h, d, n in zip(res, hits, detectors, ns):
+    for r, h, d in zip(res, hits, detectors):
         assert np.all(r["status"] == 1)
         assert len(h) == int(r["hits"].sum())
-        _check_stream(r, h, d, n)
+        _check_stream(r, h, d)
 
 
 def test_admission_drops_and_budget(ctx, detectors):
     from paper_1903_06838_amd import pdc
 
     # a burst of 40 frames at t = 0 on one stream with room for 3 waiting
-    # frames, and a tight device-memory budget on the others
-    d0, d1, d2 = detectors
+    # frames, and a device-memory budget of about one batch on the others
+    d0, d1, d2, d3 = detectors
+    one = pdc.batch_bytes(ctx, d1["det"], 4, 1024)
+    assert one > 4 * 64
     streams = [dict(det=d0["det"], pool=d0["pool"], arrival_ns=np.zeros(40, np.uint64), hit_fraction=0.05,
                     keep_hits=200000),
                dict(det=d1["det"], pool=d1["pool"], arrival_ns=_arrivals(30, 5000.0, 3), hit_fraction=0.05,
                     keep_hits=200000),
-               dict(det=d2["det"], pool=d2["pool"], arrival_ns=_arrivals(30, 5000.0, 4), hit_fraction=0.05)]
-    res, hits, summ = pdc.serve_run(ctx, streams, max_batch=4, max_inflight=1, max_queue=3, hbm_budget=1 << 18)
-    assert summ["frames_done"] + summ["frames_dropped"] == 100
+               dict(det=d2["det"], pool=d2["pool"], arrival_ns=_arrivals(30, 5000.0, 4), hit_fraction=0.05),
+               dict(det=d3["det"], pool=d3["pool"], arrival_ns=_arrivals(20, 5000.0, 5), hit_fraction=0.05,
+                    keep_hits=200000)]
+    res, hits, summ = pdc.serve_run(ctx, streams, max_batch=4, max_inflight=1, max_queue=3, hbm_budget=one)
+    assert summ["frames_done"] + summ["frames_dropped"] == 120
     assert summ["frames_dropped"] == sum(int(np.count_nonzero(r["status"] == 2)) for r in res)
     # the burst: 4 frames launch at once, 3 wait, the rest are dropped
     assert np.count_nonzero(res[0]["status"] == 2) >= 40 - 4 - 3 - 4
     assert np.all(res[0]["batch_frames"][res[0]["status"] == 1] <= 4)
     for r, h, d in zip(res, hits, detectors):
         assert np.all((r["status"] == 1) | (r["status"] == 2))
-        _check_stream(r, h, d, len(r))
+        _check_stream(r, h, d)
+
+
+def test_batch_bytes_counts_the_kept_buffers(ctx, detectors):
+    from paper_1903_06838_amd import pdc
+
+    d = detectors[0]
+    T, H, W = d["geom"].shape
+    b1 = pdc.batch_bytes(ctx, d["det"], 1, 1000)
+    b8 = pdc.batch_bytes(ctx, d["det"], 8, 1000)
+    bh = pdc.batch_bytes(ctx, d["det"], 8, 100000)
+    # kept medians: T*H*nb floats per frame; staging and hit list: 16 bytes per hit at least
+    assert b8 - b1 >= 7 * T * H * (W // d["geom"].bank_cols) * 4
+    assert bh - b8 >= (100000 - 1000) * 16
+    with pytest.raises(pdc.PdcError):
+        pdc.batch_bytes(ctx, 9999, 1, 10)
+
+
+@pytest.mark.parametrize("stage", ["centroid", "mlp"])
+def test_subpixel_stage(ctx, detectors, stage):
+    """Every kept hit of every served frame gets its position: the masked
+    centroid equals the oracle's on the oracle's patches bit for bit; the
+    learned estimator equals pdc_mlp_infer on the oracle's patches bit for
+    bit (the same patches, hence the same bfloat16 products)."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    theta = S.init_params(5)
+    net = pdc.mlp_create(ctx, theta) if stage == "mlp" else None
+    sp = pdc.SERVE_SUBPIXEL_MLP if stage == "mlp" else pdc.SERVE_SUBPIXEL_CENTROID
+    try:
+        ns = (25, 20, 15, 12)
+        streams = [dict(det=d["det"], pool=d["pool"], arrival_ns=_arrivals(n, 10000.0, 11 + j), hit_fraction=0.05,
+                        keep_hits=200000, subpixel=sp, photon_adu=ADU, t_nb=T_NB)
+                   for j, (d, n) in enumerate(zip(detectors, ns))]
+        res, hits, summ, pos = pdc.serve_run(ctx, streams, max_batch=4, max_inflight=2, net=net,
+                                             return_positions=True)
+        assert summ["frames_done"] == sum(ns)
+        for r, h, p, d in zip(res, hits, pos, detectors):
+            _check_stream(r, h, d)
+            P = d["pool"].shape[0]
+            want_p = np.concatenate([d["patches"][int(f) % P] for f in np.unique(h["frame"])])
+            assert len(want_p) == len(h) == len(p) > 0
+            if stage == "centroid":
+                want = S.centroid(want_p.reshape(-1, 5, 5), T_NB)
+            else:
+                out = torch.empty((len(want_p), 2), dtype=torch.float32, device="cuda")
+                pd = torch.from_numpy(want_p).cuda()
+                torch.cuda.synchronize()  # torch copies on its stream, the library runs on its own
+                pdc.mlp_infer(net, pd, len(want_p), ADU, out)
+                torch.cuda.synchronize()
+                want = out.cpu().numpy()
+                ref, _ = S.mlp_forward(theta, want_p, ADU, bf16_ops=True)
+                assert np.abs(p - ref).max() <= 2e-2
+            assert np.array_equal(p.view(np.uint32), np.asarray(want, np.float32).view(np.uint32))
+    finally:
+        if net is not None:
+            pdc.mlp_destroy(net)
 
 
 def test_invalid_arguments(ctx, detectors):
@@ -117,3 +205,6 @@ def test_invalid_arguments(ctx, detectors):
         pdc.serve_run(ctx, bad)
     with pytest.raises(pdc.PdcError):
         pdc.serve_run(ctx, [dict(det=d["det"], pool=d["pool"], arrival_ns=np.zeros(2, np.uint64))], max_batch=0)
+    with pytest.raises(pdc.PdcError):  # a learned stage needs a network
+        pdc.serve_run(ctx, [dict(det=d["det"], pool=d["pool"], arrival_ns=np.zeros(2, np.uint64),
+                                 subpixel=pdc.SERVE_SUBPIXEL_MLP)])
