@@ -410,7 +410,9 @@ pdc_status pdc_eta_table(pdc_ctx *ctx, const float *patches_dev, uint64_t n, flo
  * accumulation (MFMA); parameters, biases and Adam state are float32.
  * theta layout, float32 [PDC_MLP_PARAMS]: W1[25][64], b1[64], W2[64][64],
  * b2[64], W3[64][2], b3[2] (row-major, W[in][out]).
- * Calls on one network are ordered: use one stream, or synchronize. */
+ * Calls on one network are ordered: use one stream, or synchronize.  The
+ * synchronous calls below wait for the network's own last enqueued work (on
+ * whatever stream it went), not for the whole device. */
 #define PDC_MLP_PARAMS 5954
 typedef struct pdc_mlp pdc_mlp;
 

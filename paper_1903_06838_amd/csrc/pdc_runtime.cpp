@@ -1663,6 +1663,7 @@ struct pdc_mlp {
     uint32_t max_grid = 0;
     int64_t step = 0;
     uint64_t last_n = 0;
+    hipEvent_t done = nullptr;  // after the network's last enqueued work (calls on it are ordered)
 };
 
 namespace {
@@ -1682,6 +1683,7 @@ void mlp_free(pdc_mlp *net)
     hipFree(net->grad);
     hipFree(net->slots);
     hipFree(net->packed);
+    if (net->done) hipEventDestroy(net->done);
     delete net;
 }
 
@@ -1718,6 +1720,7 @@ pdc_status pdc_mlp_create(pdc_ctx *ctx, const float *theta_host, pdc_mlp **out)
     if (e == hipSuccess) e = hipMalloc((void **)&net->grad, pbytes + sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void **)&net->slots, sizeof(float) * kMlpSlotStride * 4 * (size_t)net->max_grid);
     if (e == hipSuccess) e = hipMalloc((void **)&net->packed, sizeof(uint16_t) * kPackElems);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&net->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         mlp_free(net);
         return fail(ctx, e == hipErrorOutOfMemory ? PDC_ENOMEM : PDC_EDEVICE, "device allocation failed: %s",
@@ -1736,7 +1739,7 @@ pdc_status pdc_mlp_destroy(pdc_mlp *net)
 {
     if (!net) return PDC_OK;
     hipSetDevice(net->ctx->device);
-    hipDeviceSynchronize();
+    hipEventSynchronize(net->done);
     mlp_free(net);
     return PDC_OK;
 }
@@ -1748,11 +1751,12 @@ pdc_status pdc_mlp_set_params(pdc_mlp *net, const float *theta_host)
     if (!mlp_theta_ok(theta_host)) return fail(ctx, PDC_EINVAL, "theta has a non-finite value");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = ctx->stream;
-    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipEventSynchronize(net->done));  // the network's earlier work, on whatever stream
     HIP_TRY(ctx, hipMemcpyAsync(net->theta, theta_host, sizeof(float) * kMlpParams, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, launch_fill_zero(net->m, kMlpParams, s));
     HIP_TRY(ctx, launch_fill_zero(net->v, kMlpParams, s));
     HIP_TRY(ctx, launch_mlp_pack(net->theta, net->packed, s));
+    HIP_TRY(ctx, hipEventRecord(net->done, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     net->step = 0;
     net->last_n = 0;
@@ -1764,7 +1768,7 @@ pdc_status pdc_mlp_get_params(pdc_mlp *net, float *theta_host)
     if (!net || !theta_host) return fail(net ? net->ctx : nullptr, PDC_EINVAL, "net and theta_host must be non-NULL");
     pdc_ctx *ctx = net->ctx;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipEventSynchronize(net->done));
     HIP_TRY(ctx, hipMemcpy(theta_host, net->theta, sizeof(float) * kMlpParams, hipMemcpyDeviceToHost));
     return PDC_OK;
 }
@@ -1781,6 +1785,7 @@ pdc_status pdc_mlp_infer(pdc_mlp *net, const float *patches_dev, uint64_t n, flo
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     HIP_TRY(ctx, launch_mlp_infer(patches_dev, n, inv_adu_of(photon_adu), net->theta, net->packed, out_dev,
                                   8u * (uint32_t)ctx->n_cu, s));
+    HIP_TRY(ctx, hipEventRecord(net->done, s));
     return PDC_OK;
 }
 
@@ -1798,6 +1803,7 @@ pdc_status pdc_mlp_gradient(pdc_mlp *net, const float *patches_dev, const float 
                                  net->grad, net->slots, net->max_grid, s));
     std::vector<float> h(kMlpParams + 1);
     HIP_TRY(ctx, hipMemcpyAsync(h.data(), net->grad, sizeof(float) * h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipEventRecord(net->done, s));
     HIP_TRY(ctx, hipStreamSynchronize(s));
     if (grad_host) std::memcpy(grad_host, h.data(), sizeof(float) * kMlpParams);
     if (loss_host) *loss_host = (double)h[kMlpParams] / (2.0 * (double)n);
@@ -1819,6 +1825,7 @@ pdc_status pdc_mlp_train_step(pdc_mlp *net, const float *patches_dev, const floa
                                  net->grad, net->slots, net->max_grid, s));
     HIP_TRY(ctx, launch_adam(net->theta, net->m, net->v, net->grad, lr, net->step + 1, s));
     HIP_TRY(ctx, launch_mlp_pack(net->theta, net->packed, s));
+    HIP_TRY(ctx, hipEventRecord(net->done, s));
     net->step += 1;
     net->last_n = n;
     return PDC_OK;
@@ -1830,7 +1837,7 @@ pdc_status pdc_mlp_last_loss(pdc_mlp *net, double *loss)
     pdc_ctx *ctx = net->ctx;
     if (net->last_n == 0) return fail(ctx, PDC_ESTATE, "no training step yet");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipEventSynchronize(net->done));
     float l = 0.0f;
     HIP_TRY(ctx, hipMemcpy(&l, net->grad + kMlpParams, sizeof(float), hipMemcpyDeviceToHost));
     *loss = (double)l / (2.0 * (double)net->last_n);

@@ -65,6 +65,7 @@ CASES = [
     (synth.Geometry(1, 1, 1, 1), 0.5, 3, M.TILE, 3),
     (synth.Geometry(2, 12, 96, 48), 0.03, 37, M.BANK, 3),    # several frame groups and a ragged one
     (synth.Geometry(2, 12, 96, 48), 0.03, 19, M.TILE, 2),
+    (synth.Geometry(1, 200, 512, 128), 0.02, 2, M.TILE, 3),  # a tile beyond one workgroup's LDS: a pass per stage
 ]
 
 
