@@ -651,6 +651,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-summaries", action="store_true")
     ap.add_argument("--no-cm-mean", action="store_true")
+    ap.add_argument("--phase-timers", action="store_true",
+                    help="with the tracing build (PDC_LIB=.../libpdc_phase.so): per-phase cycles of the frame kernel")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="seconds of Poisson arrivals per serving rate (the workload's own figure is 60)")
     ap.add_argument("--no-mixed", action="store_true")
@@ -684,11 +686,39 @@ def main():
     # tile shape: the frame-group count of the persistent launch, tuned on this batch
     tune_mult, tune_ms = pdc.autotune(ctx, det, frames, N, est, torch.cuda.current_stream())
     log("autotune: frame groups x%d (frame kernel ms x1/x2/x4: %s)" % (tune_mult, [round(float(x), 3) for x in tune_ms]))
+    phase_fn = None
+    if args.phase_timers:
+        import ctypes
+
+        phase_fn = getattr(pdc._lib, "pdc_debug_phase_cycles", None)
+        if phase_fn is None:
+            sys.exit("--phase-timers needs the tracing build: PDC_PHASE_TIMERS=1 python -m paper_1903_06838_amd.build, "
+                     "then PDC_LIB=paper_1903_06838_amd/libpdc_phase.so")
+        phase_buf = (ctypes.c_ulonglong * (16 * 8))()
+        phase_fn(phase_buf)  # clear what earlier launches left
     ms, mains, totals, hits, (fh, fp), hit_cap = run_steps(
         torch, pdc, ctx, det, frames, N, est, args.steps, args.warmup)
     step_ms = list(run_steps.step_ms)
     log("headline: %.3f ms/step, frame kernel %.3f ms, all kernels %.3f ms, %d hits"
         % (ms, sum(mains) / len(mains), sum(totals) / len(totals), hits))
+    if phase_fn is not None:
+        phase_fn(phase_buf)
+        # each launch runs every strip-frame once on each wave index: CSPAD's
+        # 5,920 rows make 198 strips of at most 30 own rows
+        n_strips = -(-geom.n_tiles * geom.rows // 30)
+        launches = args.steps + args.warmup
+        names = ["A", "bar_AB", "medians", "seeds", "local_max", "hit_writes", "bar_BA"]
+        rows = [[phase_buf[w * 8 + p] / (launches * N * n_strips) for p in range(7)] for w in range(16)]
+        log("phase cycles per strip-frame per wave (s_memtime), %d launches of %d frames, %d strips:" % (
+            launches, N, n_strips))
+        log("wave " + " ".join("%10s" % n for n in names) + "      total")
+        for w, r in enumerate(rows):
+            log("%4d " % w + " ".join("%10.0f" % x for x in r) + " %10.0f" % sum(r))
+        mean = [sum(r[p] for r in rows) / 16 for p in range(7)]
+        log("mean " + " ".join("%10.0f" % x for x in mean) + " %10.0f" % sum(mean))
+        print(json.dumps({"phase_timers": True, "frame_kernel_ms": sum(mains) / len(mains), "phases": names,
+                          "cycles_per_strip_frame_per_wave": [[round(x, 1) for x in r] for r in rows]}))
+        return
 
     if args.profile:
         src = torch.empty(COPY_BYTES // 2, dtype=torch.int16, device=dev)

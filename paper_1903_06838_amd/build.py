@@ -22,6 +22,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libpdc.so")
+# PDC_PHASE_TIMERS=1: the tracing build, with per-phase cycle counters in the
+# persistent kernel (same results), as libpdc_phase.so beside the product library
+PHASE_LIB = os.path.join(PKG, "libpdc_phase.so")
 
 SOURCES = ["pdc_kernels.hip", "pdc_frame_v2.hip", "pdc_subpixel.hip", "pdc_summary.hip", "pdc_cmmean.hip", "pdc_runtime.cpp", "pdc_serve.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -35,19 +38,20 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, phase_timers: bool = False) -> str:
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-o", tmp, *srcs]
+    out = PHASE_LIB if phase_timers else LIB
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, *FLAGS, *(["-DPDC_PHASE_TIMERS"] if phase_timers else []), "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
         raise RuntimeError("hipcc failed building libpdc.so")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, phase_timers=os.environ.get("PDC_PHASE_TIMERS") == "1"))

@@ -34,6 +34,14 @@
 
 namespace pdc {
 
+#ifdef PDC_PHASE_TIMERS
+// Tracing build only (PDC_PHASE_TIMERS): shader-clock cycles each wave spends
+// in each phase of the persistent kernel's frame loop, summed over the launch:
+// [wave][0 A, 1 A->B barrier, 2 medians, 3 seeds, 4 local maxima, 5 hit
+// writes, 6 B->A barrier, 7 unused].
+__device__ unsigned long long g_phase_cycles[kV2Waves * 8];
+#endif
+
 
 __device__ __forceinline__ uint32_t popc64(uint64_t m) { return (uint32_t)__popcll(m); }
 
@@ -430,6 +438,10 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
     // look up their pixels' range planes.
     constexpr bool FLAT = !MG;
     extern __shared__ __align__(16) float lds[];
+#ifdef PDC_PHASE_TIMERS
+    __shared__ unsigned long long s_tm[kV2Waves * 8];
+    if (threadIdx.x < kV2Waves * 8) s_tm[threadIdx.x] = 0;
+#endif
     __shared__ unsigned long long s_photons;
     __shared__ uint64_t s_base;
     __shared__ uint64_t s_chunk[2];  // staging chunk in use: next free entry, end
@@ -634,6 +646,17 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
     // Two more iterations drain it.  u, medians, seed lists, hit lists, hit
     // bitmaps and counts are double-buffered by frame parity (par for f and
     // f-2, pp for f-1); the seed counts are kept for three frames (f mod 3).
+#ifdef PDC_PHASE_TIMERS
+    unsigned long long tm_prev = __builtin_amdgcn_s_memtime();
+#define PDC_PHASE(ph)                                                                     \
+    {                                                                                     \
+        const unsigned long long t_ = __builtin_amdgcn_s_memtime();                       \
+        if ((threadIdx.x & 63) == 0) atomicAdd(&s_tm[(threadIdx.x >> 6) * 8 + (ph)], t_ - tm_prev); \
+        tm_prev = t_;                                                                     \
+    }
+#else
+#define PDC_PHASE(ph)
+#endif
     for (uint64_t f = f_begin; f < f_end + 2; ++f) {
         const bool cur_ok = f < f_end;
         const bool p1_ok = f >= f_begin + 1 && f - 1 < f_end;
@@ -810,7 +833,9 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
         // f's words were in: they overlap phase B and the barriers, and no
         // wait in A (the staging claim's atomics) waits for them
         if (FLAT && f + 1 < f_end) load_raw_flat(f + 1);
+        PDC_PHASE(0);
         lds_barrier();  // A -> B
+        PDC_PHASE(1);
 
         // ================= B: 1b(f) | 2(f-1) | 4(f-2) =============================
         if (CMM && cur_ok && A.cm_mode == 1) {
@@ -937,6 +962,7 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
             // slots past the bank (+inf) are no seeds
             const uint32_t vmask = tail_only ? ((L * (V - 1) < lim) ? (1u << V) - 1u : (1u << (V - 1)) - 1u)
                                              : (uint32_t)((1ull << min(V, max(0, (lim + L - 1) / L))) - 1ull);
+            PDC_PHASE(2);
             append_seeds_dense(x, m, A.t_seed, own, vmask, row, bank, gl, par, sc0);
         }
         if (!CMM && !FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
@@ -991,6 +1017,7 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
             }
             append_seeds(x, m, A.t_seed, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
+        PDC_PHASE(3);
         if (p1_ok && !ovf_1) {
             // frame f-1's seeds in chunks of 64, claimed by whole waves as they
             // finish their median groups (waves without groups start at once)
@@ -1051,6 +1078,7 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
             }
             if (my_ph) atomicAdd(&s_photons, my_ph);
         }
+        PDC_PHASE(4);
         if (p2_ok && !ovf_2) {
             // frame f-2's hits in raster position (bank-row prefix + hits left
             // of the hit in its bank-row), claimed in chunks of 64 like phase 2
@@ -1078,8 +1106,15 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
                 }
             }
         }
+        PDC_PHASE(5);
         lds_barrier();  // B -> next A
+        PDC_PHASE(6);
     }
+#ifdef PDC_PHASE_TIMERS
+    __syncthreads();
+    if (threadIdx.x < kV2Waves * 8) atomicAdd(&g_phase_cycles[threadIdx.x], s_tm[threadIdx.x]);
+#endif
+#undef PDC_PHASE
 }
 
 template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG = false>
@@ -1152,3 +1187,19 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
 }
 
 }  // namespace pdc
+
+#ifdef PDC_PHASE_TIMERS
+// Tracing build only: copy the phase cycles of every launch since the last
+// call to out[kV2Waves * 8] and clear them (synchronous).
+extern "C" int pdc_debug_phase_cycles(unsigned long long *out)
+{
+    if (!out) return -1;
+    if (hipDeviceSynchronize() != hipSuccess) return -3;
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(pdc::g_phase_cycles), sizeof(unsigned long long) * pdc::kV2Waves * 8) !=
+        hipSuccess)
+        return -3;
+    static unsigned long long z[pdc::kV2Waves * 8];
+    if (hipMemcpyToSymbol(HIP_SYMBOL(pdc::g_phase_cycles), z, sizeof z) != hipSuccess) return -3;
+    return 0;
+}
+#endif

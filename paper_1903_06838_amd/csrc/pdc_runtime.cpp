@@ -414,7 +414,12 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     // registers admit one workgroup per compute unit anyway), at least 1024
     // entries; 256 bytes stay free for the kernel's static LDS
     const size_t lds_wg = (size_t)ctx->max_lds / kV2GroupsPerCu;
-    const size_t lds_cap = lds_wg > 256 ? lds_wg - 256 : 0;
+#ifdef PDC_PHASE_TIMERS
+    const size_t static_lds = 2048;  // the tracing build's per-wave counters
+#else
+    const size_t static_lds = 256;
+#endif
+    const size_t lds_cap = lds_wg > static_lds ? lds_wg - static_lds : 0;
     size_t base = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, 0);
     if (base + 4 * 4 * 1024 > lds_cap) return false;
     d.seed_cap = (int)std::min<size_t>((lds_cap - base) / 16, 16384);

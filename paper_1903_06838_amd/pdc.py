@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpdc.so")
+# PDC_LIB selects another build of the library (the tracing build, libpdc_phase.so)
+LIB_PATH = os.environ.get("PDC_LIB") or os.path.join(_HERE, "libpdc.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError("libpdc.so is not built (run `python -m paper_1903_06838_amd.build` or "
