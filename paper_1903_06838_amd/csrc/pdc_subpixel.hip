@@ -326,23 +326,115 @@ __device__ __forceinline__ void tile_forward(const float *patches, uint64_t n, u
 }
 
 // Inference: out[2h], out[2h + 1] = (dy, dx) of hit h.  Waves take 32-hit
-// tiles in a grid-stride loop.
-__global__ void __launch_bounds__(256) mlp_infer_kernel(const float *patches, uint64_t n, float inv_adu,
-                                                        const float *theta, const uint16_t *packed, float *out)
+// tiles in a grid-stride loop.  The first layer's A fragments come straight
+// from the patches into registers (lane (l, kq) takes row 16 rt + l, columns
+// kq .. kq + 7), the next tile's values loaded while the current one is in
+// the MFMAs; one 32 x 64 bf16 LDS buffer per wave holds H1, then H2 (its H1
+// fragments are read into registers before H2 is written over them).  The
+// operands and the order of the products are those of the training forward
+// pass, so the outputs are the same.
+constexpr int kInferWaves = 8;
+struct InferLds {
+    uint16_t H[kTile * 64];
+};
+
+__device__ __forceinline__ void load_x_tile(const float *patches, uint64_t n, uint64_t h0, int lane, float (&xv)[2][8])
+{
+    const int lo = lane & 15, kq = 8 * (lane >> 4);
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const uint64_t h = h0 + 16 * rt + lo;
+        const float *src = patches + h * 25 + kq;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) xv[rt][j] = (h < n && kq + j < 25) ? src[j] : 0.0f;
+    }
+}
+
+__device__ __forceinline__ void tile_forward_infer(const float (&xv)[2][8], float inv_adu, const WeightLds &W,
+                                                   InferLds &F, int lane, f32x4 (&y)[2])
+{
+    const int lo = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
+    // layer 1: X[32 x 32] W1[32 x 64]
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        bf16x8 a;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) a[j] = __builtin_bit_cast(__bf16, f2bf(xv[rt][j] * inv_adu));
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            const f32x4 acc = mfma(a, frag<32, 1>(W.w + kPackW1t, 16 * nt + lo, kq), zero4());
+            const int col = 16 * nt + lo;
+            const float bias = W.b1[col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[i] + bias;
+                F.H[(16 * rt + rq + i) * 64 + col] = f2bf(z > 0.0f ? z : 0.0f);
+            }
+        }
+    }
+    wave_lds_sync();
+    // layer 2: H1[32 x 64] W2[64 x 64], H1 read whole before H2 replaces it
+    bf16x8 a[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        a[rt][0] = frag<64, 1>(F.H, 16 * rt + lo, kq);
+        a[rt][1] = frag<64, 1>(F.H, 16 * rt + lo, 32 + kq);
+    }
+    wave_lds_sync();
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+            f32x4 acc = mfma(a[rt][0], frag<64, 1>(W.w + kPackW2t, 16 * nt + lo, kq), zero4());
+            acc = mfma(a[rt][1], frag<64, 1>(W.w + kPackW2t, 16 * nt + lo, 32 + kq), acc);
+            const int col = 16 * nt + lo;
+            const float bias = W.b2[col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float z = acc[i] + bias;
+                F.H[(16 * rt + rq + i) * 64 + col] = f2bf(z > 0.0f ? z : 0.0f);
+            }
+        }
+    }
+    wave_lds_sync();
+    // layer 3: H2[32 x 64] W3[64 x 16] (output columns 2..15 zero)
+    const float b3 = W.b3[lo < 2 ? lo : 3];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        f32x4 acc = mfma(frag<64, 1>(F.H, 16 * rt + lo, kq), frag<64, 1>(W.w + kPackW3t, lo, kq), zero4());
+        acc = mfma(frag<64, 1>(F.H, 16 * rt + lo, 32 + kq), frag<64, 1>(W.w + kPackW3t, lo, 32 + kq), acc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) acc[i] = acc[i] + b3;
+        y[rt] = acc;
+    }
+}
+
+__global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float *patches, uint64_t n, float inv_adu,
+                                                                     const float *theta, const uint16_t *packed,
+                                                                     float *out)
 {
     __shared__ WeightLds W;
-    __shared__ FwdLds F[kWaves];
+    __shared__ InferLds F[kInferWaves];
     stage_weights(W, theta, packed);
     __syncthreads();
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tiles = (n + kTile - 1) / kTile;
+    const uint64_t stride = (uint64_t)gridDim.x * kInferWaves;
     const int lo = lane & 15, rq = 4 * (lane >> 4);
-    for (uint64_t t = (uint64_t)blockIdx.x * kWaves + wv; t < tiles; t += (uint64_t)gridDim.x * kWaves) {
+    uint64_t t = (uint64_t)blockIdx.x * kInferWaves + wv;
+    float xv[2][8];
+    if (t < tiles) load_x_tile(patches, n, t * kTile, lane, xv);
+    for (; t < tiles; t += stride) {
+        float cur[2][8];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+            for (int j = 0; j < 8; ++j) cur[rt][j] = xv[rt][j];
+        if (t + stride < tiles) load_x_tile(patches, n, (t + stride) * kTile, lane, xv);
         const uint64_t h0 = t * kTile;
         f32x4 y[2];
-        uint32_t p1[2][4], p2[2][4];
-        tile_forward(patches, n, h0, inv_adu, W, F[wv], lane, y, p1, p2);
+        tile_forward_infer(cur, inv_adu, W, F[wv], lane, y);
         if (lo < 2)
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt)
@@ -360,10 +452,10 @@ hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, con
 {
     if (n == 0) return hipSuccess;
     const uint64_t tiles = (n + kTile - 1) / kTile;
-    uint64_t grid = (tiles + kWaves - 1) / kWaves;
+    uint64_t grid = (tiles + kInferWaves - 1) / kInferWaves;
     if (grid > max_grid) grid = max_grid;
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3((uint32_t)grid), dim3(64 * kWaves), 0, s, patches, n, inv_adu, theta,
-                       packed, out);
+    hipLaunchKernelGGL(mlp_infer_kernel, dim3((uint32_t)grid), dim3(64 * kInferWaves), 0, s, patches, n, inv_adu,
+                       theta, packed, out);
     return hipGetLastError();
 }
 
