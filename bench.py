@@ -50,7 +50,7 @@ HBM_PEAK_GBPS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "frame_kernel_cspad_traffic.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1903_06838_amd", "csrc", f)
                   for f in ("pdc_frame_v2.hip", "pdc_kernels.hip", "pdc_runtime.cpp", "pdc_internal.h",
-                            "pdc_device.h")]
+                            "pdc_device.h", "pdc_exact.h")]
 MAIN_KERNEL_PREFIX = "frame_kernel"
 COPY_BYTES = 2 << 30
 
