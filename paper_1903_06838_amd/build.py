@@ -10,6 +10,9 @@ Flags:
                                 IEEE division for the photon count
   -Xclang -target-feature -Xclang -packed-fp32-ops
                                 no packed FP32 instructions are generated
+  -mllvm -amdgpu-mfma-vgpr-form MFMA results in ordinary VGPRs, so that the
+                                network kernels feed one layer's results to
+                                the next without copies out of AGPRs
 """
 from __future__ import annotations
 
@@ -33,6 +36,7 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function",
     "-I", INCLUDE, "-I", CSRC,
 ]

@@ -12,6 +12,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "pdc_device.h"
 #include "pdc_subpixel.h"
 
@@ -20,8 +22,11 @@
 namespace pdc {
 
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2;
+typedef __attribute__((ext_vector_type(2))) float f32x2;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 typedef __attribute__((ext_vector_type(4))) unsigned int u32x4;
+typedef __attribute__((ext_vector_type(8))) short i16x8;
 
 namespace {
 
@@ -31,6 +36,13 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     uint32_t b = __float_as_uint(f);
     b += 0x7FFFu + ((b >> 16) & 1u);
     return (uint16_t)(b >> 16);
+}
+
+// Two float32 -> bfloat16 (a in the low half), round to nearest even: one
+// v_cvt_pk_bf16_f32, the same values as f2bf for finite inputs.
+__device__ __forceinline__ uint32_t pk_bf16(float a, float b)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{a, b}, bf16x2));
 }
 
 // Operand fragment: 8 bf16 values base[o * SO + (k + j) * SK], j = 0..7.
@@ -62,6 +74,10 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
+
+// The same for a wave whose global loads must stay in flight: waits for its
+// LDS accesses only (a workgroup fence would also wait for the loads).
+__device__ __forceinline__ void wave_lds_wait() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 }  // namespace
 
@@ -325,125 +341,144 @@ __device__ __forceinline__ void tile_forward(const float *patches, uint64_t n, u
     }
 }
 
-// Inference: out[2h], out[2h + 1] = (dy, dx) of hit h.  Waves take 32-hit
-// tiles in a grid-stride loop.  The first layer's A fragments come straight
-// from the patches into registers (lane (l, kq) takes row 16 rt + l, columns
-// kq .. kq + 7), the next tile's values loaded while the current one is in
-// the MFMAs; one 32 x 64 bf16 LDS buffer per wave holds H1, then H2 (its H1
-// fragments are read into registers before H2 is written over them).  The
-// operands and the order of the products are those of the training forward
-// pass, so the outputs are the same.
-constexpr int kInferWaves = 8;
-struct InferLds {
-    uint16_t H[kTile * 64];
-};
+// Inference: out[2h], out[2h + 1] = (dy, dx) of hit h, with every activation
+// kept in registers.  Each layer is computed transposed, Z^T = W^T H^T: the
+// weights are the A operand (rows = output units) and a 16-hit tile the B
+// operand (columns = hits), so the result fragment of lane (n, g) holds units
+// 16 m + 4 g + i of hit n.  After bias, ReLU and rounding to bf16 those values
+// are the next layer's B operand as they stand, once the contraction index is
+// permuted: slot (g, j) of K-chunk c stands for unit 16 (2 c + j / 4) + 4 g +
+// j % 4, which lane group g holds, and the weight fragments are loaded in the
+// same order.  The first layer's B operand comes straight from the patches
+// (lane (n, g) takes inputs 8 g .. 8 g + 7 of hit n), the next tile's values
+// loaded while the current one is in the MFMAs.  The weights (the bf16 copies training uses)
+// and biases stay in registers for the whole run.
+// Products use the training forward pass's bf16 operands; the float32 sums
+// differ from it in order only (the bias starts the accumulator here, where
+// training adds it to the finished sum).
+constexpr int kInferWaves = 4;
 
-__device__ __forceinline__ void load_x_tile(const float *patches, uint64_t n, uint64_t h0, int lane, float (&xv)[2][8])
+// The 32-hit tile's 800 patch words as 200 16-byte groups, lane l taking
+// groups l + 64 k, through a buffer resource that covers the tile's own hits
+// only, so that groups past the tile read as 0.  A partial last tile is read
+// word by word, each word range-checked on its own.
+constexpr int kXWords = kTile * 25, kXGroups = kXWords / 4;
+__device__ __forceinline__ void load_x_tile(const float *patches, uint64_t n, uint64_t h0, int lane, u32x4 (&xv)[4])
 {
-    const int lo = lane & 15, kq = 8 * (lane >> 4);
+    const uint64_t nv = n - h0 < (uint64_t)kTile ? n - h0 : (uint64_t)kTile;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(patches + h0 * 25), 0, (int)(nv * 100), 0x00020000);
+    if (nv == (uint64_t)kTile) {
 #pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        const uint64_t h = h0 + 16 * rt + lo;
-        const float *src = patches + h * 25 + kq;
+        for (int k = 0; k < 4; ++k)
+            xv[k] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (lane + 64 * k), 0, 0));
+    } else {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) xv[rt][j] = (h < n && kq + j < 25) ? src[j] : 0.0f;
+        for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) xv[k][i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 16 * (lane + 64 * k) + 4 * i, 0, 0);
     }
 }
 
-__device__ __forceinline__ void tile_forward_infer(const float (&xv)[2][8], float inv_adu, const WeightLds &W,
-                                                   InferLds &F, int lane, f32x4 (&y)[2])
+// ReLU and bf16 of the result fragments d[2c], d[2c + 1] (bias included):
+// K-chunk c.  Rounding keeps the sign, so ReLU is applied to the bf16 values,
+// two per instruction, as a signed 16-bit max with 0 (negative values and -0
+// have the sign bit set).
+__device__ __forceinline__ bf16x8 relu_chunk(const f32x4 &d0, const f32x4 &d1)
 {
-    const int lo = lane & 15, kq = 8 * (lane >> 4), rq = 4 * (lane >> 4);
-    // layer 1: X[32 x 32] W1[32 x 64]
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        bf16x8 a;
-#pragma unroll
-        for (int j = 0; j < 8; ++j) a[j] = __builtin_bit_cast(__bf16, f2bf(xv[rt][j] * inv_adu));
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            const f32x4 acc = mfma(a, frag<32, 1>(W.w + kPackW1t, 16 * nt + lo, kq), zero4());
-            const int col = 16 * nt + lo;
-            const float bias = W.b1[col];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float z = acc[i] + bias;
-                F.H[(16 * rt + rq + i) * 64 + col] = f2bf(z > 0.0f ? z : 0.0f);
-            }
-        }
-    }
-    wave_lds_sync();
-    // layer 2: H1[32 x 64] W2[64 x 64], H1 read whole before H2 replaces it
-    bf16x8 a[2][2];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        a[rt][0] = frag<64, 1>(F.H, 16 * rt + lo, kq);
-        a[rt][1] = frag<64, 1>(F.H, 16 * rt + lo, 32 + kq);
-    }
-    wave_lds_sync();
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-#pragma unroll
-        for (int nt = 0; nt < 4; ++nt) {
-            f32x4 acc = mfma(a[rt][0], frag<64, 1>(W.w + kPackW2t, 16 * nt + lo, kq), zero4());
-            acc = mfma(a[rt][1], frag<64, 1>(W.w + kPackW2t, 16 * nt + lo, 32 + kq), acc);
-            const int col = 16 * nt + lo;
-            const float bias = W.b2[col];
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const float z = acc[i] + bias;
-                F.H[(16 * rt + rq + i) * 64 + col] = f2bf(z > 0.0f ? z : 0.0f);
-            }
-        }
-    }
-    wave_lds_sync();
-    // layer 3: H2[32 x 64] W3[64 x 16] (output columns 2..15 zero)
-    const float b3 = W.b3[lo < 2 ? lo : 3];
-#pragma unroll
-    for (int rt = 0; rt < 2; ++rt) {
-        f32x4 acc = mfma(frag<64, 1>(F.H, 16 * rt + lo, kq), frag<64, 1>(W.w + kPackW3t, lo, kq), zero4());
-        acc = mfma(frag<64, 1>(F.H, 16 * rt + lo, 32 + kq), frag<64, 1>(W.w + kPackW3t, lo, 32 + kq), acc);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) acc[i] = acc[i] + b3;
-        y[rt] = acc;
-    }
+    const u32x4 w = {pk_bf16(d0[0], d0[1]), pk_bf16(d0[2], d0[3]), pk_bf16(d1[0], d1[1]), pk_bf16(d1[2], d1[3])};
+    const i16x8 v = __builtin_elementwise_max(__builtin_bit_cast(i16x8, w), i16x8{0, 0, 0, 0, 0, 0, 0, 0});
+    return __builtin_bit_cast(bf16x8, v);
 }
 
 __global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float *patches, uint64_t n, float inv_adu,
                                                                      const float *theta, const uint16_t *packed,
                                                                      float *out)
 {
-    __shared__ WeightLds W;
-    __shared__ InferLds F[kInferWaves];
-    stage_weights(W, theta, packed);
-    __syncthreads();
     const int lane = threadIdx.x & 63;
+    const int r = lane & 15, g = lane >> 4;
+    // weight fragments from the packed bf16 copies: lane (r, g) takes row
+    // 16 m + r of w1t (columns 8 g .. 8 g + 7) and of w2t, and row r of w3t,
+    // the latter two at the permuted columns (two runs of 4)
+    bf16x8 w1[4], w2[4][2], w3[2];
+    f32x4 b1[4], b2[4];  // accumulator start: the bias of units 16 m + 4 g + i
+    float b3[2];
+    typedef __attribute__((ext_vector_type(2))) unsigned int u32x2v;
+    auto runs = [&](const uint16_t *row, int c) {
+        const u32x2v p0 = *reinterpret_cast<const u32x2v *>(row + 32 * c + 4 * g);
+        const u32x2v p1 = *reinterpret_cast<const u32x2v *>(row + 32 * c + 16 + 4 * g);
+        return __builtin_bit_cast(bf16x8, u32x4{p0[0], p0[1], p1[0], p1[1]});
+    };
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        w1[m] = frag<32, 1>(packed + kPackW1t, 16 * m + r, 8 * g);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) w2[m][c] = runs(packed + kPackW2t + (16 * m + r) * 64, c);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            b1[m][i] = theta[kOffB1 + 16 * m + 4 * g + i];
+            b2[m][i] = theta[kOffB2 + 16 * m + 4 * g + i];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) w3[c] = runs(packed + kPackW3t + r * 64, c);
+    b3[0] = theta[kOffB3];
+    b3[1] = theta[kOffB3 + 1];
+    // wait for these loads here: a first use inside the loop below would wait
+    // for every load in flight there, the next tile's included (vmcnt 0)
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+
+    // inputs 25..31 (lane group 3, slots 1..7) are zero
+    const u32x4 xmask = g < 3 ? u32x4{~0u, ~0u, ~0u, ~0u} : u32x4{0xFFFFu, 0u, 0u, 0u};
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tiles = (n + kTile - 1) / kTile;
     const uint64_t stride = (uint64_t)gridDim.x * kInferWaves;
-    const int lo = lane & 15, rq = 4 * (lane >> 4);
     uint64_t t = (uint64_t)blockIdx.x * kInferWaves + wv;
-    float xv[2][8];
+    // the wave's tile, staged in LDS so that the loads above stay coalesced;
+    // lane (n, g) then reads inputs 8 g .. 8 g + 7 of hits n and 16 + n (lane
+    // group 3 also reads the words after input 24, which the mask clears)
+    __shared__ float s_x[kInferWaves][kXWords + 32];
+    float *xs = s_x[wv];
+    u32x4 xv[4];
     if (t < tiles) load_x_tile(patches, n, t * kTile, lane, xv);
     for (; t < tiles; t += stride) {
-        float cur[2][8];
 #pragma unroll
-        for (int rt = 0; rt < 2; ++rt)
-#pragma unroll
-            for (int j = 0; j < 8; ++j) cur[rt][j] = xv[rt][j];
+        for (int k = 0; k < 4; ++k)
+            if (lane + 64 * k < kXGroups) *reinterpret_cast<u32x4 *>(xs + 4 * (lane + 64 * k)) = xv[k];
+        wave_lds_wait();
         if (t + stride < tiles) load_x_tile(patches, n, (t + stride) * kTile, lane, xv);
-        const uint64_t h0 = t * kTile;
+        bf16x8 x[2];
+#pragma unroll
+        for (int rt = 0; rt < 2; ++rt) {
+            const float *src = xs + (16 * rt + r) * 25 + 8 * g;
+            u32x4 xw;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) xw[j] = pk_bf16(src[2 * j] * inv_adu, src[2 * j + 1] * inv_adu);
+            xw &= xmask;
+            x[rt] = __builtin_bit_cast(bf16x8, xw);
+        }
+        wave_lds_wait();
         f32x4 y[2];
-        tile_forward_infer(cur, inv_adu, W, F[wv], lane, y);
-        if (lo < 2)
 #pragma unroll
-            for (int rt = 0; rt < 2; ++rt)
+        for (int rt = 0; rt < 2; ++rt) {
+            f32x4 d[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const uint64_t h = h0 + 16 * rt + rq + i;
-                    if (h < n) out[2 * h + lo] = y[rt][i];
-                }
-        wave_lds_sync();
+            for (int m = 0; m < 4; ++m) d[m] = mfma(w1[m], x[rt], b1[m]);
+            const bf16x8 h1a = relu_chunk(d[0], d[1]), h1b = relu_chunk(d[2], d[3]);
+#pragma unroll
+            for (int m = 0; m < 4; ++m) d[m] = mfma(w2[m][1], h1b, mfma(w2[m][0], h1a, b2[m]));
+            const bf16x8 h2a = relu_chunk(d[0], d[1]), h2b = relu_chunk(d[2], d[3]);
+            y[rt] = mfma(w3[1], h2b, mfma(w3[0], h2a, zero4()));
+        }
+        if (g == 0) {
+            const uint64_t h0 = t * kTile;
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                const uint64_t h = h0 + 16 * rt + r;
+                if (h < n)
+                    *reinterpret_cast<float2 *>(out + 2 * h) = make_float2(y[rt][0] + b3[0], y[rt][1] + b3[1]);
+            }
+        }
     }
 }
 
@@ -451,9 +486,27 @@ hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, con
                             const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
+    // at most the workgroups that are resident at once: every wave loads the
+    // weights once and then takes tiles until none are left
+    static std::atomic<int> resident[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    int res = dev < 64 ? resident[dev].load(std::memory_order_relaxed) : 0;
+    if (res <= 0) {
+        int per_cu = 0, n_cu = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(mlp_infer_kernel),
+                                                         64 * kInferWaves, 0);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        res = (per_cu > 0 ? per_cu : 1) * (n_cu > 0 ? n_cu : 1);
+        if (dev < 64) resident[dev].store(res, std::memory_order_relaxed);
+    }
     const uint64_t tiles = (n + kTile - 1) / kTile;
     uint64_t grid = (tiles + kInferWaves - 1) / kInferWaves;
     if (grid > max_grid) grid = max_grid;
+    if (grid > (uint64_t)res) grid = (uint64_t)res;
     hipLaunchKernelGGL(mlp_infer_kernel, dim3((uint32_t)grid), dim3(64 * kInferWaves), 0, s, patches, n, inv_adu,
                        theta, packed, out);
     return hipGetLastError();
