@@ -535,6 +535,10 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
             kkq[c] = *reinterpret_cast<const float4 *>(A.k + row_base + 4u * j);
         }
     }
+    // the calibration loads complete here (vmcnt 0): left pending, their first
+    // use inside the frame loop would make the compiler wait there for every
+    // load in flight, the next frame's prefetch included
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     for (int x = tid; x < 2 * RN * 8; x += kV2Threads) s_bits[x] = 0;
     for (int x = tid; x < 2 * RN; x += kV2Threads) s_cnt[x] = 0;
     if (tid < 3) s_nseed[tid] = 0;
