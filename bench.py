@@ -307,7 +307,19 @@ def subpixel(torch, pdc, ctx, n_total=10_000_000, steps=4000, bs=2048, lr=2e-3, 
         e1.record()
         torch.cuda.synchronize()
         ms_inf = e0.elapsed_time(e1) / 5
-        del y_all
+        # the same positions from the 64-byte network inputs
+        x_all = torch.empty((n_total, pdc.MLP_INPUT_WORDS), dtype=torch.int16, device=dev)
+        pdc.mlp_make_inputs(ctx, dP, n_total, photon_adu, x_all, stream)
+        y_in = torch.empty((n_total, 2), dtype=torch.float32, device=dev)
+        pdc.mlp_infer_inputs(net, x_all, n_total, y_in, stream)
+        e0.record()
+        for _ in range(5):
+            pdc.mlp_infer_inputs(net, x_all, n_total, y_in, stream)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_inf16 = e0.elapsed_time(e1) / 5
+        same_inputs = bool(torch.equal(y_in, y_all))
+        del y_all, x_all, y_in
     finally:
         pdc.mlp_destroy(net)
     torch.cuda.set_stream(torch.cuda.default_stream())
@@ -320,6 +332,9 @@ def subpixel(torch, pdc, ctx, n_total=10_000_000, steps=4000, bs=2048, lr=2e-3, 
             "mlp_infer_hits_per_s": round(n_total / (ms_inf / 1e3), 1),
             "mlp_infer_GBps": round(inf_bytes / (ms_inf / 1e3) / 1e9, 1),
             "mlp_infer_TFLOPs_bf16": round(inf_flop / (ms_inf / 1e3) / 1e12, 2),
+            "mlp_infer_inputs_hits_per_s": round(n_total / (ms_inf16 / 1e3), 1),
+            "mlp_infer_inputs_GBps": round(n_total * (2 * pdc.MLP_INPUT_WORDS + 2 * 4) / (ms_inf16 / 1e3) / 1e9, 1),
+            "mlp_infer_inputs_same_positions": same_inputs,
             "centroid_eta_hits_per_s": round(n_te / (ms_ce / 1e3), 1),
             "train_hits_per_s": round(steps * bs / (ms_train / 1e3), 1),
             "data": "synthetic charge-sharing patches (uniform impact points, cloud sigma U(0.1, 0.4) px, "

@@ -384,6 +384,16 @@ int32_t pdc_graph_items(const pdc_graph *graph);
 pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev, uint64_t capacity,
                                uint64_t *n_out);
 
+/* The learned estimator's inputs of the same hits, 64 bytes per hit instead
+ * of 100: inputs_dev uint16 [capacity][PDC_MLP_INPUT_WORDS], word j < 25 of a
+ * hit the bfloat16 (round to nearest even) of fl(v_j * fl(1 / photon_adu)) for
+ * patch value v_j, words 25..31 zero.  These are the values pdc_mlp_infer
+ * forms from a float32 patch, so pdc_mlp_infer_inputs on them gives the same
+ * positions.  photon_adu in [2^-24, 2^24]; otherwise as pdc_capture_patches. */
+#define PDC_MLP_INPUT_WORDS 32
+pdc_status pdc_capture_inputs(pdc_ctx *ctx, uint64_t batch, float photon_adu, uint16_t *inputs_dev,
+                              uint64_t capacity, uint64_t *n_out);
+
 /* Masked 3x3 centroid of each patch: s = (v > t_nb ? v : 0) over the central
  * 3x3 pixels; dy = sum(s*dr) / sum(s), dx = sum(s*dc) / sum(s), the sums in
  * row-major order from +0.0f, IEEE binary32, (0, 0) when sum(s) == 0.
@@ -428,6 +438,18 @@ pdc_status pdc_mlp_get_params(pdc_mlp *net, float *theta_host);
 /* Positions of n hits: out_dev float32 [n][2].  photon_adu in [2^-24, 2^24]. */
 pdc_status pdc_mlp_infer(pdc_mlp *net, const float *patches_dev, uint64_t n, float photon_adu,
                          float *out_dev, void *hip_stream);
+
+/* Network inputs (layout of pdc_capture_inputs) of n float32 patches:
+ * inputs_dev uint16 [n][PDC_MLP_INPUT_WORDS].  photon_adu in [2^-24, 2^24]. */
+pdc_status pdc_mlp_make_inputs(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float photon_adu,
+                               uint16_t *inputs_dev, void *hip_stream);
+
+/* Positions of n hits from their network inputs (inputs_dev uint16
+ * [n][PDC_MLP_INPUT_WORDS]; the padding words are ignored): the same values as
+ * pdc_mlp_infer on the patches the inputs were made from, with 36 % fewer
+ * bytes read. */
+pdc_status pdc_mlp_infer_inputs(pdc_mlp *net, const uint16_t *inputs_dev, uint64_t n, float *out_dev,
+                                void *hip_stream);
 
 /* Gradient of L = sum((y - target)^2) / (2 n) over n >= 1 hits (target_dev
  * float32 [n][2]) into grad_host float32 [PDC_MLP_PARAMS] and L into

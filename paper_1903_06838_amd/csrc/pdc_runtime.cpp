@@ -1587,14 +1587,23 @@ pdc_status pdc_graph_destroy(pdc_graph *g)
 // subpixel stage
 // ---------------------------------------------------------------------------
 
-pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev, uint64_t capacity, uint64_t *n_out)
+}  // extern "C"
+
+namespace {
+
+// The network's input scale 1/photon_adu, rounded once to binary32.
+float inv_adu_of(float photon_adu) { return (float)(1.0 / (double)photon_adu); }
+
+// Patches (float32, patches != NULL) or network inputs (bf16 words) of the
+// batch's first min(total, capacity) hits.
+pdc_status capture(pdc_ctx *ctx, uint64_t batch, float *patches, uint16_t *inputs, float inv_adu, uint64_t capacity,
+                   uint64_t *n_out)
 {
-    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
     Batch *bt = find_batch(ctx, batch);
     if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
     if (!bt->keep && !bt->meds)
         return fail(ctx, PDC_ESTATE, "batch was processed with neither PDC_KEEP_CORRECTED nor PDC_KEEP_MEDIANS");
-    if (capacity > 0 && !patches_dev) return fail(ctx, PDC_EINVAL, "patches_dev is NULL with capacity > 0");
+    if (capacity > 0 && !patches && !inputs) return fail(ctx, PDC_EINVAL, "output pointer is NULL with capacity > 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     pdc_status rc = finish_batch(ctx, *bt);
     if (rc != PDC_OK) return rc;
@@ -1605,7 +1614,7 @@ pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev,
     const uint64_t n = std::min<uint64_t>(b->host_state->total, capacity);
     if (bt->keep) {
         HIP_TRY(ctx, launch_capture_patches(b->corrected, b->hits, b->frame_offset, bt->n_frames, n, d.g.n_tiles,
-                                            d.g.rows, d.g.cols, patches_dev, cs));
+                                            d.g.rows, d.g.cols, patches, inputs, inv_adu, cs));
     } else {
         PatchSrc ps{};
         ps.frames = bt->frames;
@@ -1621,10 +1630,44 @@ pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev,
         ps.cm = d.p.cm_mode ? b->cm : nullptr;
         ps.cm_regions = d.cm_regions;
         ps.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
-        HIP_TRY(ctx, launch_patches_from_frames(ps, b->hits, b->frame_offset, bt->n_frames, n, patches_dev, cs));
+        HIP_TRY(ctx, launch_patches_from_frames(ps, b->hits, b->frame_offset, bt->n_frames, n, patches, inputs,
+                                                inv_adu, cs));
     }
     HIP_TRY(ctx, hipStreamSynchronize(cs));
     if (n_out) *n_out = n;
+    return PDC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev, uint64_t capacity, uint64_t *n_out)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (capacity > 0 && !patches_dev) return fail(ctx, PDC_EINVAL, "patches_dev is NULL with capacity > 0");
+    return capture(ctx, batch, patches_dev, nullptr, 0.0f, capacity, n_out);
+}
+
+pdc_status pdc_capture_inputs(pdc_ctx *ctx, uint64_t batch, float photon_adu, uint16_t *inputs_dev, uint64_t capacity,
+                              uint64_t *n_out)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (capacity > 0 && !inputs_dev) return fail(ctx, PDC_EINVAL, "inputs_dev is NULL with capacity > 0");
+    if (!finite_in(photon_adu, 0x1p-24f, 0x1p24f)) return fail(ctx, PDC_EINVAL, "photon_adu must be in [2^-24, 2^24]");
+    return capture(ctx, batch, nullptr, inputs_dev, inv_adu_of(photon_adu), capacity, n_out);
+}
+
+pdc_status pdc_mlp_make_inputs(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float photon_adu,
+                               uint16_t *inputs_dev, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (n > 0 && (!patches_dev || !inputs_dev)) return fail(ctx, PDC_EINVAL, "device pointers must be non-NULL");
+    if (!finite_in(photon_adu, 0x1p-24f, 0x1p24f)) return fail(ctx, PDC_EINVAL, "photon_adu must be in [2^-24, 2^24]");
+    if (n > ((uint64_t)1 << 36)) return fail(ctx, PDC_EINVAL, "n too large");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_make_inputs(patches_dev, n, inv_adu_of(photon_adu), inputs_dev, s));
     return PDC_OK;
 }
 
@@ -1702,8 +1745,6 @@ pdc_status mlp_check_run(pdc_mlp *net, const float *patches_dev, const float *ta
     if (n > ((uint64_t)1 << 36)) return fail(ctx, PDC_EINVAL, "n too large");
     return PDC_OK;
 }
-
-float inv_adu_of(float photon_adu) { return (float)(1.0 / (double)photon_adu); }
 
 }  // namespace
 
@@ -1790,6 +1831,20 @@ pdc_status pdc_mlp_infer(pdc_mlp *net, const float *patches_dev, uint64_t n, flo
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
     HIP_TRY(ctx, launch_mlp_infer(patches_dev, n, inv_adu_of(photon_adu), net->theta, net->packed, out_dev,
                                   8u * (uint32_t)ctx->n_cu, s));
+    HIP_TRY(ctx, hipEventRecord(net->done, s));
+    return PDC_OK;
+}
+
+pdc_status pdc_mlp_infer_inputs(pdc_mlp *net, const uint16_t *inputs_dev, uint64_t n, float *out_dev,
+                                void *hip_stream)
+{
+    if (!net) return fail(nullptr, PDC_EINVAL, "net is NULL");
+    pdc_ctx *ctx = net->ctx;
+    if (n > 0 && (!inputs_dev || !out_dev)) return fail(ctx, PDC_EINVAL, "device pointers must be non-NULL");
+    if (n > ((uint64_t)1 << 36)) return fail(ctx, PDC_EINVAL, "n too large");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+    HIP_TRY(ctx, launch_mlp_infer_inputs(inputs_dev, n, net->theta, net->packed, out_dev, 8u * (uint32_t)ctx->n_cu, s));
     HIP_TRY(ctx, hipEventRecord(net->done, s));
     return PDC_OK;
 }

@@ -32,11 +32,17 @@ struct InFlight {
     hipEvent_t done = nullptr;
 };
 
+// Device bytes a hit's subpixel input takes: network inputs or a patch.
+uint64_t subpixel_bytes(int32_t subpixel)
+{
+    return subpixel == PDC_SERVE_SUBPIXEL_MLP ? PDC_MLP_INPUT_WORDS * sizeof(uint16_t) : 25 * sizeof(float);
+}
+
 struct StreamState {
     pdc_serve_stream *d = nullptr;
     hipStream_t hs = nullptr;
     hipStream_t ss = nullptr;    // subpixel work of completed batches
-    float *patches = nullptr;    // device [cap][25]
+    void *patches = nullptr;     // device [cap][25] float32 patches, or [cap][32] bf16 network inputs
     float *pos = nullptr;        // device [cap][2]
     uint64_t cap = 0;
     uint64_t next_arrival = 0;   // next frame index not yet arrived
@@ -130,22 +136,27 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
         for (uint64_t j = 0; j < kept; ++j) dst[j].frame += (uint32_t)b.first;  // stream frame index
         if (st.d->subpixel && total > 0) {
             // positions of all the batch's hits; those of the kept hits are copied out
+            // the learned stage takes the network's inputs (64 bytes a hit),
+            // the centroid the float32 patches (100 bytes)
+            const bool mlp = st.d->subpixel == PDC_SERVE_SUBPIXEL_MLP;
             if (total > st.cap) {
                 hipFree(st.patches);
                 hipFree(st.pos);
-                st.patches = st.pos = nullptr;
+                st.patches = nullptr;
+                st.pos = nullptr;
                 st.cap = 0;
-                if (hipMalloc((void **)&st.patches, total * 25 * sizeof(float)) != hipSuccess ||
+                if (hipMalloc(&st.patches, total * subpixel_bytes(st.d->subpixel)) != hipSuccess ||
                     hipMalloc((void **)&st.pos, total * 2 * sizeof(float)) != hipSuccess)
                     return PDC_ENOMEM;
                 st.cap = total;
             }
             uint64_t np = 0;
-            r = pdc_capture_patches(ctx, b.batch, st.patches, total, &np);
+            r = mlp ? pdc_capture_inputs(ctx, b.batch, st.d->photon_adu, static_cast<uint16_t *>(st.patches), total, &np)
+                    : pdc_capture_patches(ctx, b.batch, static_cast<float *>(st.patches), total, &np);
             if (r < 0) return r;
-            r = st.d->subpixel == PDC_SERVE_SUBPIXEL_MLP
-                    ? pdc_mlp_infer(cfg->net, st.patches, np, st.d->photon_adu, st.pos, st.ss)
-                    : pdc_centroid(ctx, st.patches, np, st.d->t_nb, cfg->eta_dev, cfg->eta_bins, st.pos, st.ss);
+            r = mlp ? pdc_mlp_infer_inputs(cfg->net, static_cast<const uint16_t *>(st.patches), np, st.pos, st.ss)
+                    : pdc_centroid(ctx, static_cast<const float *>(st.patches), np, st.d->t_nb, cfg->eta_dev,
+                                   cfg->eta_bins, st.pos, st.ss);
             if (r < 0) return r;
             if (st.d->positions && kept > 0 &&
                 hipMemcpyAsync(st.d->positions + 2 * st.hits_written, st.pos, kept * 2 * sizeof(float),
@@ -204,7 +215,7 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
                 uint64_t bytes = 0;
                 rc = pdc_batch_bytes(ctx, d.det, n, hit_cap, &bytes);
                 if (rc != PDC_OK) break;
-                if (d.subpixel) bytes += hit_cap * 27 * sizeof(float);  // patches and positions
+                if (d.subpixel) bytes += hit_cap * (subpixel_bytes(d.subpixel) + 2 * sizeof(float));  // and positions
                 if (cfg->hbm_budget && held_bytes + bytes > cfg->hbm_budget && !st.inflight.empty()) break;
                 InFlight b;
                 b.first = first;

@@ -10,6 +10,8 @@ namespace pdc {
 constexpr int kMlpIn = 25, kMlpHidden = 64, kMlpOut = 2;
 constexpr int kMlpParams = 25 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2;  // 5954
 constexpr int kOffW1 = 0, kOffB1 = 1600, kOffW2 = 1664, kOffB2 = 5760, kOffW3 = 5824, kOffB3 = 5952;
+// A hit's network input: 25 bf16 words, then 7 zeros (64 bytes).
+constexpr int kMlpInWords = 32;
 
 // bfloat16 copies of the weights in the layouts the MFMA operand loads want
 // (each row holds the contraction index contiguously):
@@ -29,6 +31,9 @@ hipError_t launch_eta_table(const float *patches, uint64_t n, float t_nb, int nb
 hipError_t launch_mlp_pack(const float *theta, uint16_t *packed, hipStream_t s);
 hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, const float *theta,
                             const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s);
+// The same on the network's inputs (uint16 [n][kMlpInWords]).
+hipError_t launch_mlp_infer_inputs(const uint16_t *inputs, uint64_t n, const float *theta, const uint16_t *packed,
+                                   float *out, uint32_t max_grid, hipStream_t s);
 // Gradient of sum((y - t)^2) / (2 n) over n hits: out[0..kMlpParams) gets the
 // gradient, out[kMlpParams] gets sum((y - t)^2).  Each wave writes its partial
 // sums to a slot of kMlpSlotStride floats; slots must hold
@@ -39,9 +44,11 @@ hipError_t launch_mlp_grad(const float *patches, const float *target, uint64_t n
                            const float *theta, const uint16_t *packed, float *out, float *slots, uint32_t max_grid,
                            hipStream_t s);
 hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, float lr, int64_t step, hipStream_t s);
+// patches float32 [n][25], or, when inputs is not NULL, the network's inputs
+// uint16 [n][kMlpInWords] (bf16 of each value times inv_adu, zero padding)
 hipError_t launch_capture_patches(const float *corrected, const uint2 *hits,
                                   const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, int T,
-                                  int H, int W, float *patches, hipStream_t s);
+                                  int H, int W, float *patches, uint16_t *inputs, float inv_adu, hipStream_t s);
 // Patches rebuilt from the frames: Frames2 of each window pixel from its raw
 // word, the calibration and the frame's kept common-mode values (meds: bank
 // medians [n_frames][T*H*nb]; or, with meds null, the thresholded mean's
@@ -56,7 +63,10 @@ struct PatchSrc {
     int32_t cm_tile;
 };
 hipError_t launch_patches_from_frames(const PatchSrc &a, const uint2 *hits, const unsigned long long *frame_offset,
-                                      uint64_t n_frames, uint64_t n, float *patches, hipStream_t s);
+                                      uint64_t n_frames, uint64_t n, float *patches, uint16_t *inputs, float inv_adu,
+                                      hipStream_t s);
+// The network's inputs of n float32 patches.
+hipError_t launch_make_inputs(const float *patches, uint64_t n, float inv_adu, uint16_t *inputs, hipStream_t s);
 hipError_t launch_mfma_probe(const uint16_t *A, const uint16_t *B, float *D, hipStream_t s);
 
 }  // namespace pdc

@@ -359,25 +359,31 @@ __device__ __forceinline__ void tile_forward(const float *patches, uint64_t n, u
 constexpr int kInferWaves = 4;
 
 // The 32-hit tile's 800 patch words as 200 16-byte groups, lane l taking
-// groups l + 64 k, through a buffer resource that covers the tile's own hits
-// only, so that groups past the tile read as 0.  A partial last tile is read
-// word by word, each word range-checked on its own.
+// groups l + 64 k, through a buffer resource that covers the tile only if
+// all its hits exist (else nothing: every group reads as 0).  The same four
+// loads whatever the tile, so that the wait counts of the loop below are
+// the same on every path.
 constexpr int kXWords = kTile * 25, kXGroups = kXWords / 4;
-__device__ __forceinline__ void load_x_tile(const float *patches, uint64_t n, uint64_t h0, int lane, u32x4 (&xv)[4])
+__device__ __forceinline__ void load_x_full(const float *patches, uint64_t n, uint64_t h0, int lane, u32x4 (&xv)[4])
 {
-    const uint64_t nv = n - h0 < (uint64_t)kTile ? n - h0 : (uint64_t)kTile;
+    const int bytes = h0 + kTile <= n ? kXWords * 4 : 0;
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(patches + h0 * 25), 0, (int)(nv * 100), 0x00020000);
-    if (nv == (uint64_t)kTile) {
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(patches + h0 * 25), 0, bytes, 0x00020000);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            xv[k] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (lane + 64 * k), 0, 0));
-    } else {
+    for (int k = 0; k < 4; ++k)
+        xv[k] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, 16 * (lane + 64 * k), 0, 0));
+}
+
+// A partial last tile (h0 < n < h0 + 32), word by word, each word range-
+// checked on its own, so that words past the last hit read as 0.
+__device__ __forceinline__ void load_x_part(const float *patches, uint64_t n, uint64_t h0, int lane, u32x4 (&xv)[4])
+{
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float *>(patches + h0 * 25), 0, (int)((n - h0) * 100), 0x00020000);
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
+    for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) xv[k][i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 16 * (lane + 64 * k) + 4 * i, 0, 0);
-    }
+        for (int i = 0; i < 4; ++i) xv[k][i] = __builtin_amdgcn_raw_buffer_load_b32(rs, 16 * (lane + 64 * k) + 4 * i, 0, 0);
 }
 
 // ReLU and bf16 of the result fragments d[2c], d[2c + 1] (bias included):
@@ -391,9 +397,29 @@ __device__ __forceinline__ bf16x8 relu_chunk(const f32x4 &d0, const f32x4 &d1)
     return __builtin_bit_cast(bf16x8, v);
 }
 
-__global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float *patches, uint64_t n, float inv_adu,
-                                                                     const float *theta, const uint16_t *packed,
-                                                                     float *out)
+// The first layer's B operand of a 32-hit tile of network inputs (IN16):
+// lane (n, g) loads words 8 g .. 8 g + 7 of hits n and 16 + n, one 16-byte
+// load each, through a resource that covers the tile's own hits.  Two loads
+// whatever the tile, as for the patches.
+__device__ __forceinline__ void load_in_tile(const uint16_t *inputs, uint64_t n, uint64_t h0, int lane, u32x4 (&xq)[2])
+{
+    // hits past n (a whole tile past the end too) read as 0: each lane's
+    // 16 bytes lie wholly inside or outside the resource
+    const uint64_t nv = h0 >= n ? 0 : (n - h0 < (uint64_t)kTile ? n - h0 : (uint64_t)kTile);
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+        const_cast<uint16_t *>(inputs + h0 * kMlpInWords), 0, (int)(nv * 2 * kMlpInWords), 0x00020000);
+    const int lo = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt)
+        xq[rt] = __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                               rs, (16 * rt + lo) * 2 * kMlpInWords + 16 * g, 0, 0));
+}
+
+// IN16: src holds the network's inputs (uint16 [n][kMlpInWords], inv_adu
+// unused), else float32 patches [n][25].
+template <bool IN16>
+__device__ __forceinline__ void mlp_infer_body(const void *src, uint64_t n, float inv_adu, const float *theta,
+                                               const uint16_t *packed, float *out)
 {
     const int lane = threadIdx.x & 63;
     const int r = lane & 15, g = lane >> 4;
@@ -401,7 +427,10 @@ __global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float
     // 16 m + r of w1t (columns 8 g .. 8 g + 7) and of w2t, and row r of w3t,
     // the latter two at the permuted columns (two runs of 4)
     bf16x8 w1[4], w2[4][2], w3[2];
-    f32x4 b1[4], b2[4];  // accumulator start: the bias of units 16 m + 4 g + i
+    // biases in LDS (registers are kept for the weights): lane group g reads
+    // the 4 of units 16 m + 4 g .. + 3 as an accumulator start
+    __shared__ __align__(16) float s_b[128];
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) s_b[i] = theta[i < 64 ? kOffB1 + i : kOffB2 + i - 64];
     float b3[2];
     typedef __attribute__((ext_vector_type(2))) unsigned int u32x2v;
     auto runs = [&](const uint16_t *row, int c) {
@@ -414,11 +443,6 @@ __global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float
         w1[m] = frag<32, 1>(packed + kPackW1t, 16 * m + r, 8 * g);
 #pragma unroll
         for (int c = 0; c < 2; ++c) w2[m][c] = runs(packed + kPackW2t + (16 * m + r) * 64, c);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            b1[m][i] = theta[kOffB1 + 16 * m + 4 * g + i];
-            b2[m][i] = theta[kOffB2 + 16 * m + 4 * g + i];
-        }
     }
 #pragma unroll
     for (int c = 0; c < 2; ++c) w3[c] = runs(packed + kPackW3t + r * 64, c);
@@ -427,51 +451,73 @@ __global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float
     // wait for these loads here: a first use inside the loop below would wait
     // for every load in flight there, the next tile's included (vmcnt 0)
     __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();  // the biases in LDS
 
-    // inputs 25..31 (lane group 3, slots 1..7) are zero
+    // inputs 25..31 (lane group 3, slots 1..7) are zero (also for network
+    // inputs, whose padding words a caller may have left unset)
     const u32x4 xmask = g < 3 ? u32x4{~0u, ~0u, ~0u, ~0u} : u32x4{0xFFFFu, 0u, 0u, 0u};
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const uint64_t tiles = (n + kTile - 1) / kTile;
     const uint64_t stride = (uint64_t)gridDim.x * kInferWaves;
     uint64_t t = (uint64_t)blockIdx.x * kInferWaves + wv;
-    // the wave's tile, staged in LDS so that the loads above stay coalesced;
-    // lane (n, g) then reads inputs 8 g .. 8 g + 7 of hits n and 16 + n (lane
-    // group 3 also reads the words after input 24, which the mask clears)
-    __shared__ float s_x[kInferWaves][kXWords + 32];
-    float *xs = s_x[wv];
-    u32x4 xv[4];
-    if (t < tiles) load_x_tile(patches, n, t * kTile, lane, xv);
-    for (; t < tiles; t += stride) {
+    // float32 patches: the wave's tile, staged in LDS so that the loads stay
+    // coalesced; lane (n, g) then reads inputs 8 g .. 8 g + 7 of hits n and
+    // 16 + n (lane group 3 also reads the words after input 24, which the mask
+    // clears)
+    __shared__ float s_x[IN16 ? 1 : kInferWaves][kXWords + 32];
+    float *xs = s_x[IN16 ? 0 : wv];
+    const float *patches = static_cast<const float *>(src);
+    const uint16_t *inputs = static_cast<const uint16_t *>(src);
+    // tiles are loaded kDepth ahead of their use (kDepth register buffers,
+    // the loop unrolled over them; the patches' larger buffers leave room for
+    // one).  Loads are issued for tiles past the end too (they read
+    // nothing), so that every path waits for the same counts.  Float32 patches:
+    // the loop takes the whole tiles, a partial last tile comes after it.
+    constexpr int kDepth = IN16 ? 3 : 1;
+    const uint64_t full = IN16 ? tiles : n / kTile;
+    u32x4 xv[kDepth][IN16 ? 2 : 4];
+    auto load = [&](uint64_t tile, u32x4 (&buf)[IN16 ? 2 : 4]) {
+        if constexpr (IN16)
+            load_in_tile(inputs, n, tile * kTile, lane, buf);
+        else
+            load_x_full(patches, n, tile * kTile, lane, buf);
+    };
+    // float32 patches of the tile in buf, staged in LDS, as B operands
+    auto stage = [&](const u32x4 (&buf)[4], bf16x8 (&x)[2]) {
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-            if (lane + 64 * k < kXGroups) *reinterpret_cast<u32x4 *>(xs + 4 * (lane + 64 * k)) = xv[k];
+        for (int q = 0; q < 4; ++q)
+            if (lane + 64 * q < kXGroups) *reinterpret_cast<u32x4 *>(xs + 4 * (lane + 64 * q)) = buf[q];
         wave_lds_wait();
-        if (t + stride < tiles) load_x_tile(patches, n, (t + stride) * kTile, lane, xv);
-        bf16x8 x[2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
-            const float *src = xs + (16 * rt + r) * 25 + 8 * g;
+            const float *sp = xs + (16 * rt + r) * 25 + 8 * g;
             u32x4 xw;
 #pragma unroll
-            for (int j = 0; j < 4; ++j) xw[j] = pk_bf16(src[2 * j] * inv_adu, src[2 * j + 1] * inv_adu);
-            xw &= xmask;
-            x[rt] = __builtin_bit_cast(bf16x8, xw);
+            for (int j = 0; j < 4; ++j) xw[j] = pk_bf16(sp[2 * j] * inv_adu, sp[2 * j + 1] * inv_adu);
+            x[rt] = __builtin_bit_cast(bf16x8, xw & xmask);
         }
         wave_lds_wait();
+    };
+    auto forward = [&](uint64_t tk, const bf16x8 (&x)[2]) {
+        // the bias reads stay in the loop (an opaque offset each tile): kept
+        // in registers they would cost the waves per SIMD they save
+        int go = g;
+        asm volatile("" : "+v"(go));
+        const f32x4 *b1 = reinterpret_cast<const f32x4 *>(s_b) + go, *b2 = b1 + 16;
         f32x4 y[2];
 #pragma unroll
         for (int rt = 0; rt < 2; ++rt) {
             f32x4 d[4];
 #pragma unroll
-            for (int m = 0; m < 4; ++m) d[m] = mfma(w1[m], x[rt], b1[m]);
+            for (int m = 0; m < 4; ++m) d[m] = mfma(w1[m], x[rt], b1[4 * m]);
             const bf16x8 h1a = relu_chunk(d[0], d[1]), h1b = relu_chunk(d[2], d[3]);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) d[m] = mfma(w2[m][1], h1b, mfma(w2[m][0], h1a, b2[m]));
+            for (int m = 0; m < 4; ++m) d[m] = mfma(w2[m][1], h1b, mfma(w2[m][0], h1a, b2[4 * m]));
             const bf16x8 h2a = relu_chunk(d[0], d[1]), h2b = relu_chunk(d[2], d[3]);
             y[rt] = mfma(w3[1], h2b, mfma(w3[0], h2a, zero4()));
         }
         if (g == 0) {
-            const uint64_t h0 = t * kTile;
+            const uint64_t h0 = tk * kTile;
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
                 const uint64_t h = h0 + 16 * rt + r;
@@ -479,15 +525,55 @@ __global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const float
                     *reinterpret_cast<float2 *>(out + 2 * h) = make_float2(y[rt][0] + b3[0], y[rt][1] + b3[1]);
             }
         }
+    };
+#pragma unroll
+    for (int k = 0; k < kDepth; ++k) load(t + k * stride, xv[k]);
+    for (; t < full; t += kDepth * stride)
+#pragma unroll
+        for (int k = 0; k < kDepth; ++k) {
+            const uint64_t tk = t + k * stride;
+            if (tk >= full) break;
+            bf16x8 x[2];
+            if constexpr (IN16) {
+#pragma unroll
+                for (int rt = 0; rt < 2; ++rt) x[rt] = __builtin_bit_cast(bf16x8, xv[k][rt] & xmask);
+                load(tk + kDepth * stride, xv[k]);
+            } else {
+                stage(xv[k], x);
+                load(tk + kDepth * stride, xv[k]);
+            }
+            forward(tk, x);
+        }
+    if (!IN16 && full < tiles && (uint64_t)blockIdx.x * kInferWaves + wv == full % stride) {
+        u32x4 buf[4];
+        load_x_part(patches, n, full * kTile, lane, buf);
+        bf16x8 x[2];
+        stage(buf, x);
+        forward(full, x);
     }
 }
 
-hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, const float *theta,
-                            const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s)
+__global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_kernel(const void *src, uint64_t n, float inv_adu,
+                                                                     const float *theta, const uint16_t *packed,
+                                                                     float *out)
 {
+    mlp_infer_body<false>(src, n, inv_adu, theta, packed, out);
+}
+
+__global__ void __launch_bounds__(64 * kInferWaves) mlp_infer_inputs_kernel(const void *src, uint64_t n, float inv_adu, const float *theta, const uint16_t *packed,
+                        float *out)
+{
+    mlp_infer_body<true>(src, n, inv_adu, theta, packed, out);
+}
+
+// At most the workgroups that are resident at once: every wave loads the
+// weights once and then takes tiles until none are left.
+template <bool IN16>
+static hipError_t launch_infer(const void *src, uint64_t n, float inv_adu, const float *theta,
+                               const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s)
+{
+    const auto kernel = IN16 ? mlp_infer_inputs_kernel : mlp_infer_kernel;
     if (n == 0) return hipSuccess;
-    // at most the workgroups that are resident at once: every wave loads the
-    // weights once and then takes tiles until none are left
     static std::atomic<int> resident[64];
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -495,7 +581,7 @@ hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, con
     int res = dev < 64 ? resident[dev].load(std::memory_order_relaxed) : 0;
     if (res <= 0) {
         int per_cu = 0, n_cu = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(mlp_infer_kernel),
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(kernel),
                                                          64 * kInferWaves, 0);
         if (e != hipSuccess) return e;
         e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
@@ -507,9 +593,21 @@ hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, con
     uint64_t grid = (tiles + kInferWaves - 1) / kInferWaves;
     if (grid > max_grid) grid = max_grid;
     if (grid > (uint64_t)res) grid = (uint64_t)res;
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3((uint32_t)grid), dim3(64 * kInferWaves), 0, s, patches, n, inv_adu,
-                       theta, packed, out);
+    hipLaunchKernelGGL(kernel, dim3((uint32_t)grid), dim3(64 * kInferWaves), 0, s, src, n, inv_adu, theta, packed,
+                       out);
     return hipGetLastError();
+}
+
+hipError_t launch_mlp_infer(const float *patches, uint64_t n, float inv_adu, const float *theta,
+                            const uint16_t *packed, float *out, uint32_t max_grid, hipStream_t s)
+{
+    return launch_infer<false>(patches, n, inv_adu, theta, packed, out, max_grid, s);
+}
+
+hipError_t launch_mlp_infer_inputs(const uint16_t *inputs, uint64_t n, const float *theta, const uint16_t *packed,
+                                   float *out, uint32_t max_grid, hipStream_t s)
+{
+    return launch_infer<true>(inputs, n, 0.0f, theta, packed, out, max_grid, s);
 }
 
 // Sum over the 4 lane groups that share l % 16 (the rows of a C tile).
@@ -731,39 +829,72 @@ hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, floa
 // 5x5 neighbourhood of each hit in the corrected frames (zero outside the
 // tile).  hits[i] = {pixel, charge bits} of the raster-order list; its frame
 // is the largest f with frame_offset[f] <= i.
-__global__ void capture_patches_kernel(const float *corrected, const uint2 *hits,
-                                       const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, int T,
-                                       int H, int W, float *patches)
+// A captured patch goes out as 25 float32 values (patches[i][25]) or as the
+// network's input (inputs != nullptr): bf16(fl(v * inv_adu)) of each value,
+// then 7 zero words, 64 bytes per hit (inputs[i][32]).
+__device__ __forceinline__ void store_patch(const float (&v)[25], uint64_t i, float *patches, uint16_t *inputs,
+                                            float inv_adu)
 {
-    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (inputs) {
+        u32x4 *dst = reinterpret_cast<u32x4 *>(inputs + i * kMlpInWords);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            u32x4 w;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int e = 8 * q + 2 * j;
+                w[j] = pk_bf16(e < 25 ? v[e] * inv_adu : 0.0f, e + 1 < 25 ? v[e + 1] * inv_adu : 0.0f);
+            }
+            dst[q] = w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 25; ++e) patches[i * 25 + e] = v[e];
+    }
+}
+
+// Frame of hit i: the last frame whose first hit is at most i.
+__device__ __forceinline__ uint64_t hit_frame(const unsigned long long *frame_offset, uint64_t n_frames, uint64_t i)
+{
     uint64_t lo = 0, hi = n_frames;
     while (hi - lo > 1) {
         const uint64_t mid = (lo + hi) / 2;
         if (frame_offset[mid] <= i) lo = mid;
         else hi = mid;
     }
+    return lo;
+}
+
+__global__ void capture_patches_kernel(const float *corrected, const uint2 *hits,
+                                       const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, int T,
+                                       int H, int W, float *patches, uint16_t *inputs, float inv_adu)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t lo = hit_frame(frame_offset, n_frames, i);
     const uint32_t p = hits[i].x;
     const int c = (int)(p % (uint32_t)W);
     const int rt = (int)(p / (uint32_t)W);
     const int t = rt / H, r = rt - t * H;
     const float *fr = corrected + (lo * (uint64_t)T + (uint64_t)t) * (uint64_t)H * W;
-    float *dst = patches + i * 25;
+    float v[25];
 #pragma unroll
     for (int dr = -2; dr <= 2; ++dr)
 #pragma unroll
         for (int dc = -2; dc <= 2; ++dc) {
             const int rr = r + dr, cc = c + dc;
-            dst[(dr + 2) * 5 + dc + 2] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? fr[(uint64_t)rr * W + cc] : 0.0f;
+            v[(dr + 2) * 5 + dc + 2] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? fr[(uint64_t)rr * W + cc] : 0.0f;
         }
+    store_patch(v, i, patches, inputs, inv_adu);
 }
 
 hipError_t launch_capture_patches(const float *corrected, const uint2 *hits, const unsigned long long *frame_offset,
-                                  uint64_t n_frames, uint64_t n, int T, int H, int W, float *patches, hipStream_t s)
+                                  uint64_t n_frames, uint64_t n, int T, int H, int W, float *patches,
+                                  uint16_t *inputs, float inv_adu, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(capture_patches_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, corrected, hits,
-                       frame_offset, n_frames, n, T, H, W, patches);
+                       frame_offset, n_frames, n, T, H, W, patches, inputs, inv_adu);
     return hipGetLastError();
 }
 
@@ -771,16 +902,12 @@ hipError_t launch_capture_patches(const float *corrected, const uint2 *hits, con
 // again from its raw word, the calibration and the kept common-mode values,
 // by the frame kernels' operations (invalid gain codes give +0).
 __global__ void patches_from_frames_kernel(PatchSrc a, const uint2 *hits, const unsigned long long *frame_offset,
-                                           uint64_t n_frames, uint64_t n, float *patches)
+                                           uint64_t n_frames, uint64_t n, float *patches, uint16_t *inputs,
+                                           float inv_adu)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    uint64_t lo = 0, hi = n_frames;
-    while (hi - lo > 1) {
-        const uint64_t mid = (lo + hi) / 2;
-        if (frame_offset[mid] <= i) lo = mid;
-        else hi = mid;
-    }
+    const uint64_t lo = hit_frame(frame_offset, n_frames, i);
     const int H = a.H, W = a.W;
     const uint64_t HW = (uint64_t)H * W, npix = (uint64_t)a.T * HW;
     const uint32_t p = hits[i].x;
@@ -788,7 +915,7 @@ __global__ void patches_from_frames_kernel(PatchSrc a, const uint2 *hits, const 
     const int rt = (int)(p / (uint32_t)W);
     const int t = rt / H, r = rt - t * H;
     const uint16_t *fr = a.frames + lo * npix;
-    float *dst = patches + i * 25;
+    float out[25];
 #pragma unroll
     for (int dr = -2; dr <= 2; ++dr)
 #pragma unroll
@@ -811,16 +938,44 @@ __global__ void patches_from_frames_kernel(PatchSrc a, const uint2 *hits, const 
                     v = bad ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, cv[0]), cv[1]), cv[2]);
                 }
             }
-            dst[(dr + 2) * 5 + dc + 2] = v;
+            out[(dr + 2) * 5 + dc + 2] = v;
         }
+    store_patch(out, i, patches, inputs, inv_adu);
 }
 
 hipError_t launch_patches_from_frames(const PatchSrc &a, const uint2 *hits, const unsigned long long *frame_offset,
-                                      uint64_t n_frames, uint64_t n, float *patches, hipStream_t s)
+                                      uint64_t n_frames, uint64_t n, float *patches, uint16_t *inputs, float inv_adu,
+                                      hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(patches_from_frames_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, a, hits,
-                       frame_offset, n_frames, n, patches);
+                       frame_offset, n_frames, n, patches, inputs, inv_adu);
+    return hipGetLastError();
+}
+
+// Network inputs of n float32 patches: thread 4 h + q writes words 8 q .. 8 q
+// + 7 of hit h (16 bytes; consecutive threads write consecutive groups).
+__global__ void make_inputs_kernel(const float *patches, uint64_t n, float inv_adu, uint16_t *inputs)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * n) return;
+    const uint64_t h = t >> 2;
+    const int q = (int)(t & 3);
+    const float *src = patches + h * 25 + 8 * q;
+    u32x4 w;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int e = 8 * q + 2 * j;
+        w[j] = pk_bf16(e < 25 ? src[2 * j] * inv_adu : 0.0f, e + 1 < 25 ? src[2 * j + 1] * inv_adu : 0.0f);
+    }
+    reinterpret_cast<u32x4 *>(inputs + h * kMlpInWords)[q] = w;
+}
+
+hipError_t launch_make_inputs(const float *patches, uint64_t n, float inv_adu, uint16_t *inputs, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(make_inputs_kernel, dim3((uint32_t)((4 * n + 255) / 256)), dim3(256), 0, s, patches, n,
+                       inv_adu, inputs);
     return hipGetLastError();
 }
 

@@ -78,6 +78,10 @@ _sig = {
     "pdc_batch_timing": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_float),
                                ctypes.POINTER(ctypes.c_float)]),
     "pdc_capture_patches": (_st, [_P, ctypes.c_uint64, _P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)]),
+    "pdc_capture_inputs": (_st, [_P, ctypes.c_uint64, ctypes.c_float, _P, ctypes.c_uint64,
+                                 ctypes.POINTER(ctypes.c_uint64)]),
+    "pdc_mlp_make_inputs": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, _P, _P]),
+    "pdc_mlp_infer_inputs": (_st, [_P, _P, ctypes.c_uint64, _P, _P]),
     "pdc_centroid": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, _P, ctypes.c_int32, _P, _P]),
     "pdc_eta_table": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.c_int32, _P, _P, _P]),
     "pdc_mlp_create": (_st, [_P, _P, ctypes.POINTER(_P)]),
@@ -370,6 +374,20 @@ def capture_patches(ctx, batch: int, patches_dev, capacity: int) -> int:
     return n.value
 
 
+MLP_INPUT_WORDS = 32
+
+
+def capture_inputs(ctx, batch: int, photon_adu: float, inputs_dev, capacity: int) -> int:
+    """The network inputs (uint16 [capacity][MLP_INPUT_WORDS]) of the batch's first hits; returns the count."""
+    n = ctypes.c_uint64(0)
+    _check(_lib.pdc_capture_inputs(ctx, batch, photon_adu, _ptr(inputs_dev), capacity, ctypes.byref(n)), ctx)
+    return n.value
+
+
+def mlp_make_inputs(ctx, patches_dev, n: int, photon_adu: float, inputs_dev, stream=None) -> None:
+    _check(_lib.pdc_mlp_make_inputs(ctx, _ptr(patches_dev), n, photon_adu, _ptr(inputs_dev), _stream(stream)), ctx)
+
+
 def centroid(ctx, patches_dev, n: int, t_nb: float, out_dev, eta_dev=None, nbins: int = 0, stream=None) -> None:
     _check(_lib.pdc_centroid(ctx, _ptr(patches_dev), n, t_nb, _ptr(eta_dev), nbins, _ptr(out_dev),
                              _stream(stream)), ctx)
@@ -408,6 +426,10 @@ def mlp_get_params(net) -> np.ndarray:
 
 def mlp_infer(net, patches_dev, n: int, photon_adu: float, out_dev, stream=None) -> None:
     _check(_lib.pdc_mlp_infer(net, _ptr(patches_dev), n, photon_adu, _ptr(out_dev), _stream(stream)))
+
+
+def mlp_infer_inputs(net, inputs_dev, n: int, out_dev, stream=None) -> None:
+    _check(_lib.pdc_mlp_infer_inputs(net, _ptr(inputs_dev), n, _ptr(out_dev), _stream(stream)))
 
 
 def mlp_gradient(net, patches_dev, target_dev, n: int, photon_adu: float, stream=None):

@@ -39,6 +39,15 @@ def _bits(a):
     return np.ascontiguousarray(a, dtype=F32).view(np.uint32)
 
 
+def _input_words(P, adu):
+    """The learned estimator's inputs of float32 patches as the oracle's
+    forward pass forms them: bf16 of fl(v * fl(1 / adu)) as 16-bit words,
+    then 7 zero words per hit."""
+    x = np.asarray(P, F32).reshape(len(P), 25) * F32(1.0 / adu)
+    w = (S.bf16(x).view(np.uint32) >> 16).astype(np.uint16)
+    return np.concatenate([w, np.zeros((len(P), 7), np.uint16)], axis=1)
+
+
 def _edge_patches():
     """Patches that probe the mask: all zero, all at the threshold, negative
     values, one pixel above it, signal outside the 3x3 only."""
@@ -152,6 +161,60 @@ def test_mlp_forward_matches_oracle(ctx):
     assert d.max() <= 2e-2, d.max()
     ref64, _ = S.mlp_forward(th.astype(np.float64), P, ADU, bf16_ops=False)
     assert np.sqrt(np.mean((got - ref64) ** 2)) <= 0.02
+
+
+def test_make_inputs_bit_exact(ctx):
+    """Network inputs of float32 patches: bf16 words of fl(v * fl(1/adu))
+    bit for bit, padding words zero (ties and small values included)."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    P, _ = synth.make_patches(4133, seed=17)
+    P[:6] = _edge_patches()
+    P[6, 0, :] = np.float32(150.0 * (1 + 2 ** -8))  # x = 1 + 2^-8: a tie, rounds to even
+    P[7, 0, :] = np.float32(1e-30)
+    x = torch.full((len(P), pdc.MLP_INPUT_WORDS), -1, dtype=torch.int16, device="cuda")
+    torch.cuda.synchronize()
+    pdc.mlp_make_inputs(ctx, _dev(P), len(P), ADU, x)
+    torch.cuda.synchronize()
+    assert np.array_equal(x.cpu().numpy().view(np.uint16), _input_words(P, ADU))
+    with pytest.raises(pdc.PdcError):
+        pdc.mlp_make_inputs(ctx, _dev(P), len(P), 0.0, x)
+
+
+@pytest.mark.parametrize("n", [1, 37, 4133, 150001])
+def test_mlp_infer_inputs_equals_infer(ctx, n):
+    """Positions from the network inputs equal those from the float32
+    patches bit for bit (the same bf16 operands), whatever the padding words
+    hold; both within the forward tolerance of the oracle."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    th = _theta(9)
+    P, _ = synth.make_patches(n, seed=19)
+    net = pdc.mlp_create(ctx, th)
+    try:
+        dP = _dev(P)
+        x = torch.zeros((n, pdc.MLP_INPUT_WORDS), dtype=torch.int16, device="cuda")
+        y0 = torch.full((n, 2), -7.0, dtype=torch.float32, device="cuda")
+        y1 = torch.full((n, 2), -7.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        pdc.mlp_make_inputs(ctx, dP, n, ADU, x)
+        torch.cuda.synchronize()
+        x[:, 25:] = 0x7FC0  # NaN padding: ignored
+        torch.cuda.synchronize()
+        pdc.mlp_infer(net, dP, n, ADU, y0)
+        pdc.mlp_infer_inputs(net, x, n, y1)
+        torch.cuda.synchronize()
+        a, b = y0.cpu().numpy(), y1.cpu().numpy()
+    finally:
+        pdc.mlp_destroy(net)
+    assert np.array_equal(_bits(a), _bits(b))
+    want, _ = S.mlp_forward(th, P, ADU, bf16_ops=True)
+    d = np.abs(b - want)
+    assert np.quantile(d, 0.99) <= 1e-5 and d.max() <= 2e-2
 
 
 def test_mlp_forward_after_frame_kernel(ctx):
@@ -373,22 +436,29 @@ def test_capture_patches_from_kept_medians(ctx, geom, gm, cm, stages, occ, n, ge
                 b = pdc.process_frames(c, det, frames, n, 200000)
                 hits, total, _, _, _ = pdc.get_hits(c, b, n)
                 pt = torch.full((total + 3, 25), -1.0, dtype=torch.float32, device="cuda")
+                xi = torch.full((total + 3, pdc.MLP_INPUT_WORDS), -1, dtype=torch.int16, device="cuda")
                 torch.cuda.synchronize()
                 m = pdc.capture_patches(c, b, pt, total + 3)
+                mi = pdc.capture_inputs(c, b, ADU, xi, total + 3)
                 path = pdc.debug_batch_path(c, b)
                 pdc.release_batch(c, b)
             finally:
                 pdc.release_detector(c, det)
-            out[flag] = (hits, m, pt.cpu().numpy(), path)
+            assert mi == m
+            out[flag] = (hits, m, pt.cpu().numpy(), path, xi.cpu().numpy().view(np.uint16))
     finally:
         if general:
             pdc.destroy(c)
-    (h1, n1, p1, path1), (h2, n2, p2, path2) = out[pdc.KEEP_CORRECTED], out[pdc.KEEP_MEDIANS]
+    (h1, n1, p1, path1, x1), (h2, n2, p2, path2, x2) = out[pdc.KEEP_CORRECTED], out[pdc.KEEP_MEDIANS]
     assert n1 == n2 == len(h1) > 20
     assert path1 == path2 == (1 if general else 2)
     assert np.array_equal(h1.view(np.uint32), h2.view(np.uint32))
     assert np.array_equal(_bits(p1), _bits(p2))
     assert np.all(p2[n2:] == -1.0)
+    # the network inputs of both batches are those the oracle forms from the patches
+    want = _input_words(p1[:n1], ADU)
+    assert np.array_equal(x1[:n1], want) and np.array_equal(x2[:n2], want)
+    assert np.all(x2[n2:] == 0xFFFF)
 
 
 def test_capture_patches_needs_a_kept_buffer(ctx):
