@@ -432,9 +432,11 @@ def mixed(torch, pdc, ctx, frames_each=4000, steps=3):
     ePix10k-like 352x384 (three gain ranges, 96-pixel banks) and
     Jungfrau-like 512x1024 (three gain ranges, 256-pixel banks), 4,000 frames
     each at occupancies spread over 0.001..0.02, enqueued together with
-    pdc_process_mixed (launches on forked streams, each on the whole chip, and
-    again each sized to its share of the chip), captured once into one graph
-    and replayed, and the three processed one after another."""
+    pdc_process_mixed (one launch of the persistent kernel over all three,
+    frame groups sized for the whole chip per detector and again for each
+    detector's share of it; and a launch per detector on forked streams),
+    captured once into one graph and replayed, and the three processed one
+    after another."""
     import numpy as np
 
     from paper_1903_06838_amd import synth
@@ -524,10 +526,22 @@ def mixed(torch, pdc, ctx, frames_each=4000, steps=3):
     for d in dets2:
         pdc.release_detector(c2, d)
     pdc.destroy(c2)
+    # a launch per detector on forked streams
+    os.environ["PDC_MIX_FORKED"] = "1"
+    try:
+        c3 = pdc.create(0)
+    finally:
+        del os.environ["PDC_MIX_FORKED"]
+    dets3, items3 = setup(c3)
+    ms_forked = time_mixed(c3, items3)
+    for d in dets3:
+        pdc.release_detector(c3, d)
+    pdc.destroy(c3)
     del frames
     return {"frames_per_detector": frames_each, "pixels": px, "ms_mixed": round(ms_mixed, 3),
             "Mpixel_s_mixed": round(px / (ms_mixed / 1e3) / 1e6, 1),
-            "ms_mixed_graph": round(ms_graph, 3), "ms_mixed_shared_chip": round(ms_share, 3), "ms_alone": alone,
+            "ms_mixed_graph": round(ms_graph, 3), "ms_mixed_shared_chip": round(ms_share, 3),
+            "ms_mixed_forked_launches": round(ms_forked, 3), "ms_alone": alone,
             "ms_alone_sum": round(sum(alone.values()), 3),
             "Mpixel_s_one_after_another": round(px / (sum(alone.values()) / 1e3) / 1e6, 1),
             "occupancies": list(occs), "gain_ranges": "95/3/1 % of pixels, 1 % invalid codes"}

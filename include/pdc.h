@@ -237,8 +237,16 @@ pdc_status pdc_process_frames_static(pdc_ctx *ctx, int32_t det, const uint16_t *
  * exactly as pdc_process_frames would make it, on one of up to 8 internal
  * streams forked from hip_stream (NULL: the context's stream) and joined back
  * into it, so the detectors' kernels may overlap and work enqueued later on
- * hip_stream waits for all of them.  Each persistent launch takes the whole
- * chip (PDC_MIX_SHARE=1 in the environment at pdc_create sizes each for the
+ * hip_stream waits for all of them.  When there are 2 to 8 items and every
+ * one takes the persistent kernel with the median common mode, keeping
+ * neither Frames2 nor common-mode values, their frame kernels are one launch
+ * over the (detector, strip, frame group) work items of all of them, each
+ * workgroup running the body compiled for its detector's lane layout and gain
+ * mode (the Dark and Gain section's several darks and gains in one pass);
+ * the work before and after it stays on the batches' streams.  Otherwise, or
+ * with PDC_MIX_FORKED=1 in the environment at pdc_create, each batch has
+ * launches of its own.  Each batch's share of the launch is the whole chip's
+ * worth of frame groups (PDC_MIX_SHARE=1 at pdc_create sizes each for the
  * share of the chip its pixels are of the whole instead).  1 <= n_items <= 64.
  * On an error no batch is left outstanding. */
 typedef struct {
@@ -621,7 +629,8 @@ pdc_status pdc_debug_mfma_probe(pdc_ctx *ctx, const uint16_t *A, const uint16_t 
 /* Test hook: the kernel that produced a batch's results, 1 for the general
  * kernel, 2 for the persistent one, 3 for the persistent one with the units
  * whose seed lists overflowed redone by the general kernel (after any
- * recomputation).  Waits for the batch. */
+ * recomputation); 4 and 5 for 2 and 3 when the persistent kernel ran in the
+ * one launch of a mixed call.  Waits for the batch. */
 pdc_status pdc_debug_batch_path(pdc_ctx *ctx, uint64_t batch, int32_t *path);
 
 #ifdef __cplusplus

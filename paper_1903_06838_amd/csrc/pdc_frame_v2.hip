@@ -430,8 +430,10 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // at most 256 / 128 pixels, i.e. 16384 pixels).
 constexpr int kFlatChunks = 4;
 
+// One workgroup's work: work item `item` of the launch over A's strips and
+// frame groups (strip item % n_strips, frame group item / n_strips).
 template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG>
-__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(4, 4))) frame_kernel_v2(V2Args A)
+__device__ __forceinline__ void frame_body(const V2Args &A, const int item)
 {
     // Single-gain kernels correct the strip as one flat block of pixels
     // (FLAT); auto-ranging kernels keep a wave per bank-row, whose lanes
@@ -449,7 +451,6 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
     uint32_t *s_p2next = &s_p2ctr;  // next phase-2 seed chunk
     uint32_t *s_p4next = &s_p4ctr;  // next phase-4 hit chunk
 
-    constexpr int NV = 2 * NQ;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -467,7 +468,6 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
     uint32_t *s_pref = reinterpret_cast<uint32_t *>(lds + Ly.pref);
     float *s_gs = lds + Ly.gs;  // one slot per thread: median finish scratch
 
-    const int item = block_item((int)blockIdx.x, (int)gridDim.x);
     const int strip = item % A.n_strips;
     const int fg = item / A.n_strips;
     const V2Strip S = A.strips[strip];
@@ -1121,6 +1121,52 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
 #undef PDC_PHASE
 }
 
+template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG>
+__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(4, 4))) frame_kernel_v2(V2Args A)
+{
+    frame_body<NQ, GMAX, L, V, KEEP, CMM, MG>(A, block_item((int)blockIdx.x, (int)gridDim.x));
+}
+
+// Several detectors' batches in one launch: the work items of detector d are
+// [first[d], first[d + 1]) of the launch (finer frame groups than a launch
+// of its own, so that items of unequal cost even out as they are handed
+// out), and each workgroup runs the body
+// compiled for its detector's lane layout and gain mode (median common mode,
+// Frames2 not kept: the variants v2_mix_variant lists).
+__global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu(4, 4))) frame_kernel_v2_mix(V2Mix M)
+{
+    // work items in launch order: consecutive workgroups go to different
+    // chiplets, so each chiplet takes a share of every detector's items
+    const int item = (int)blockIdx.x;
+    int d = 0;
+    while (d + 1 < M.n && item >= M.first[d + 1]) ++d;
+    // the detector's arguments as opaque scalars: read through a dynamic
+    // index, the compiler would reload fields from the argument memory
+    // inside the frame loop rather than keep them
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&M.a[d]);
+    uint32_t w[sizeof(V2Args) / 4];
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(V2Args) / 4); ++i) {
+        w[i] = src[i];
+        asm volatile("" : "+s"(w[i]));
+    }
+    V2Args A;
+    __builtin_memcpy(&A, w, sizeof(V2Args));
+    const int it = item - M.first[d];
+    switch (M.variant[d]) {
+    case 0: frame_body<2, 4, 16, 13, false, false, false>(A, it); break;
+    case 1: frame_body<2, 4, 16, 16, false, false, false>(A, it); break;
+    case 2: frame_body<1, 8, 8, 8, false, false, false>(A, it); break;
+    case 3: frame_body<1, 8, 8, 12, false, false, false>(A, it); break;
+    case 4: frame_body<1, 8, 8, 16, false, false, false>(A, it); break;
+    case 5: frame_body<2, 4, 16, 13, false, false, true>(A, it); break;
+    case 6: frame_body<2, 4, 16, 16, false, false, true>(A, it); break;
+    case 7: frame_body<1, 8, 8, 12, false, false, true>(A, it); break;
+    case 8: frame_body<1, 8, 8, 16, false, false, true>(A, it); break;
+    default: break;
+    }
+}
+
 template <int NQ, int GMAX, int L, int V, bool KEEP, bool CMM, bool MG = false>
 static hipError_t launch_v2_k(const V2Args &a, uint32_t grid, size_t lds, hipStream_t s)
 {
@@ -1188,6 +1234,39 @@ hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t gr
         return launch_v2_t<1, 8, 8, 16>(a, grid, lds, keep, s);
     }
     return hipErrorInvalidValue;
+}
+
+int v2_mix_variant(const V2Args &a, int nq, int gmax, bool keep)
+{
+    if (keep || a.cm_mode || a.meds || a.B < 1 || a.rmax * a.nb > 16 * gmax) return -1;
+    const int mg = a.gain_mode ? 5 : 0;
+    if (nq == 2 && gmax == 4 && a.B <= 256) return a.B <= 16 * 13 ? mg : mg + 1;
+    if (nq == 1 && gmax == 8 && a.B <= 128) {
+        if (a.B <= 8 * 8 && !a.gain_mode) return 2;
+        return a.B <= 8 * 12 ? (a.gain_mode ? 7 : 3) : (a.gain_mode ? 8 : 4);
+    }
+    return -1;
+}
+
+size_t frame_kernel_v2_mix_static_lds()
+{
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void *)frame_kernel_v2_mix) != hipSuccess) return SIZE_MAX;
+    return fa.sharedSizeBytes;
+}
+
+hipError_t launch_frame_kernel_v2_mix(const V2Mix &m, size_t lds, hipStream_t s)
+{
+    if (m.n < 1 || m.n > kMixMax) return hipErrorInvalidValue;
+    for (int d = 0; d < m.n; ++d)
+        if (m.variant[d] < 0 || m.first[d + 1] < m.first[d]) return hipErrorInvalidValue;
+    const uint32_t grid = (uint32_t)m.first[m.n];
+    if (grid == 0) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void *)frame_kernel_v2_mix, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(frame_kernel_v2_mix, dim3(grid), dim3(kV2Threads), lds, s, m);
+    return hipGetLastError();
 }
 
 }  // namespace pdc

@@ -111,6 +111,24 @@ struct V2Args {
 };
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);
+// Several detectors' batches in one launch of the persistent kernel: the
+// work items (strip, frame group) of detector d are [first[d], first[d + 1]).
+constexpr int kMixMax = 8;
+struct V2Mix {
+    V2Args a[kMixMax];
+    int32_t variant[kMixMax];     // from v2_mix_variant
+    int32_t first[kMixMax + 1];
+    int32_t n;
+};
+static_assert(sizeof(V2Mix) <= 4096, "V2Mix is passed as a kernel argument");
+// The compiled body of the one launch for a batch, or -1 when it has none
+// (Frames2 or common-mode values kept, thresholded mean): such batches take
+// launches of their own.
+int v2_mix_variant(const V2Args &a, int nq, int gmax, bool keep);
+// Dynamic LDS lds: at least the largest v2 LDS of the detectors.
+hipError_t launch_frame_kernel_v2_mix(const V2Mix &m, size_t lds, hipStream_t s);
+// Static LDS of that kernel (every body's own variables), SIZE_MAX if unknown.
+size_t frame_kernel_v2_mix_static_lds();
 // a.cm_mode != 0 selects the thresholded-mean variant (no median search)
 hipError_t launch_frame_kernel_v2(const V2Args &a, int nq, int gmax, uint32_t grid, size_t lds, bool keep,
                                   hipStream_t s);

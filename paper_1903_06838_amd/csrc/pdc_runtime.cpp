@@ -120,6 +120,8 @@ struct Batch {
     bool checked = false;  // overflow handled, totals final
     int fb = 0;            // 1: overflowing units recomputed by the general kernel, 2: whole batch
     bool capture = false;  // being captured into a graph: kernels only, no events or copies
+    bool mix_one = false;  // its frame kernel ran in one launch with the other batches of a mixed call
+    int fg_more = 1;       // frame groups x this beyond the detector's choice (one-launch mixed calls)
     pdc_graph *graph = nullptr;  // launched from this graph, whose buffers it holds
     int gitem = 0;               // its item in that graph
     Buffers *buf = nullptr;
@@ -165,6 +167,7 @@ struct pdc_ctx {
     hipStream_t copy_stream = nullptr;  // result copies: they wait for their batch only
     std::vector<hipStream_t> mix_streams;  // concurrent batches of pdc_process_mixed
     bool mix_share = false;                // PDC_MIX_SHARE=1: size each mixed launch to its share of the chip
+    bool mix_one = true;                   // mixed batches in one launch (PDC_MIX_FORKED=1: a launch each)
     std::vector<hipEvent_t> mix_events;
     std::vector<Detector> dets;
     std::map<uint64_t, Batch> batches;
@@ -412,12 +415,13 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     d.v2_max_unit_hits = (uint32_t)((own_rows_max + 3) / 2) * (uint32_t)((g.cols + 1) / 2);
     // seed lists: as large as the workgroup's LDS allows (the kernel's
     // registers admit one workgroup per compute unit anyway), at least 1024
-    // entries; 256 bytes stay free for the kernel's static LDS
+    // entries; 512 bytes stay free for the kernel's static LDS (the one-launch
+    // mixed kernel holds every body's own variables)
     const size_t lds_wg = (size_t)ctx->max_lds / kV2GroupsPerCu;
 #ifdef PDC_PHASE_TIMERS
     const size_t static_lds = 2048;  // the tracing build's per-wave counters
 #else
-    const size_t static_lds = 256;
+    const size_t static_lds = 512;
 #endif
     const size_t lds_cap = lds_wg > static_lds ? lds_wg - static_lds : 0;
     size_t base = frame_kernel_v2_lds_bytes(rmax, g.cols, nb, 0);
@@ -625,7 +629,16 @@ pdc_status enqueue_tail(pdc_ctx *ctx, Batch &bt)
     return record_end(ctx, b, s);
 }
 
-pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
+// The persistent kernel computes a bank's thresholded mean itself unless the
+// stage values are kept for patches.
+bool cm_inline_of(const Detector &d, const Batch &bt)
+{
+    return d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2 && !bt.meds;
+}
+
+// A batch's work before its frame kernel: state, timing events, invalid
+// counts and the common-mode pass.
+pdc_status enqueue_pre(pdc_ctx *ctx, Batch &bt)
 {
     Detector &d = ctx->dets[bt.det];
     Buffers *b = bt.buf;
@@ -633,60 +646,170 @@ pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
     HIP_TRY(ctx, launch_init_state(b->state, s));
     if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_start, s));
     if (d.g.gain_mode) HIP_TRY(ctx, launch_fill_u32(b->invalid, bt.n_frames, s));
-    // the persistent kernel computes a bank's thresholded mean itself
-    // the persistent kernel computes a bank's thresholded mean itself unless
-    // the stage values are kept for patches
-    const bool cm_inline = d.p.cm_mode == PDC_CM_BANK_MEAN && bt.path == 2 && !bt.meds;
-    if (d.p.cm_mode && !cm_inline) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));
+    if (d.p.cm_mode && !cm_inline_of(d, bt)) HIP_TRY(ctx, launch_cm_pass(ctx, d, bt));
     if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_cm, s));
+    return PDC_OK;
+}
+
+// Arguments of the persistent kernel for a batch.
+void fill_v2_args(const Detector &d, const Batch &bt, V2Args &a)
+{
+    const Buffers *b = bt.buf;
+    const bool cm_inline = cm_inline_of(d, bt);
+    a = V2Args{};
+    a.frames = bt.frames;
+    a.ped = d.d_ped;
+    a.k = d.d_k;
+    a.n_frames = bt.n_frames;
+    a.T = d.g.n_tiles;
+    a.H = d.g.rows;
+    a.W = d.g.cols;
+    a.B = d.g.bank_cols;
+    a.nb = d.g.cols / d.g.bank_cols;
+    a.n_strips = d.n_strips;
+    a.n_fgroups = bt.n_fg;
+    a.rmax = d.rmax;
+    a.seed_cap = d.seed_cap;
+    a.strips = d.d_strips;
+    a.t_seed = d.t_seed;
+    a.t_nb = d.t_nb;
+    a.photon_adu = d.p.photon_adu;
+    a.rank_width = d.rank_width;
+    a.pool = b->pool;
+    a.pool_cap = bt.pool_cap;
+    a.unit_count = b->unit_count;
+    a.unit_photons = b->unit_photons;
+    a.unit_base = b->unit_base;
+    a.state = b->state;
+    a.corrected = bt.keep ? b->corrected : nullptr;
+    a.fb_units = d.fb_ok ? b->fb_units : nullptr;
+    a.cm = cm_inline ? nullptr : b->cm;
+    a.cm_regions = d.cm_regions;
+    a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+    a.cm_mode = d.p.cm_mode == PDC_CM_MEDIAN ? 0 : (cm_inline ? 1 : 2);
+    a.cm_stages = d.p.cm_stages;
+    a.t_cm = d.t_cm;
+    a.cm_guard = d.cm_guard;
+    a.sum_lo = d.sum_lo;
+    a.sum_hi = d.sum_hi;
+    a.gain_mode = d.g.gain_mode;
+    a.invalid = b->invalid;
+    a.meds = bt.meds && !d.p.cm_mode ? b->meds : nullptr;
+}
+
+// After the frame kernel: its timing event, then the scans and scatter.
+pdc_status enqueue_post(pdc_ctx *ctx, Batch &bt)
+{
+    if (!bt.capture) HIP_TRY(ctx, hipEventRecord(bt.buf->ev_main, bt.stream));
+    return enqueue_tail(ctx, bt);
+}
+
+pdc_status enqueue(pdc_ctx *ctx, Batch &bt)
+{
+    pdc_status rc = enqueue_pre(ctx, bt);
+    if (rc != PDC_OK) return rc;
+    Detector &d = ctx->dets[bt.det];
+    hipStream_t s = bt.stream;
     if (bt.n_units > 0 && bt.path == 2) {
-        V2Args a{};
-        a.frames = bt.frames;
-        a.ped = d.d_ped;
-        a.k = d.d_k;
-        a.n_frames = bt.n_frames;
-        a.T = d.g.n_tiles;
-        a.H = d.g.rows;
-        a.W = d.g.cols;
-        a.B = d.g.bank_cols;
-        a.nb = d.g.cols / d.g.bank_cols;
-        a.n_strips = d.n_strips;
-        a.n_fgroups = bt.n_fg;
-        a.rmax = d.rmax;
-        a.seed_cap = d.seed_cap;
-        a.strips = d.d_strips;
-        a.t_seed = d.t_seed;
-        a.t_nb = d.t_nb;
-        a.photon_adu = d.p.photon_adu;
-        a.rank_width = d.rank_width;
-        a.pool = b->pool;
-        a.pool_cap = bt.pool_cap;
-        a.unit_count = b->unit_count;
-        a.unit_photons = b->unit_photons;
-        a.unit_base = b->unit_base;
-        a.state = b->state;
-        a.corrected = bt.keep ? b->corrected : nullptr;
-        a.fb_units = d.fb_ok ? b->fb_units : nullptr;
-        a.cm = cm_inline ? nullptr : b->cm;
-        a.cm_regions = d.cm_regions;
-        a.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
-        a.cm_mode = d.p.cm_mode == PDC_CM_MEDIAN ? 0 : (cm_inline ? 1 : 2);
-        a.cm_stages = d.p.cm_stages;
-        a.t_cm = d.t_cm;
-        a.cm_guard = d.cm_guard;
-        a.sum_lo = d.sum_lo;
-        a.sum_hi = d.sum_hi;
-        a.gain_mode = d.g.gain_mode;
-        a.invalid = b->invalid;
-        a.meds = bt.meds && !d.p.cm_mode ? b->meds : nullptr;
+        V2Args a;
+        fill_v2_args(d, bt, a);
         HIP_TRY(ctx, launch_frame_kernel_v2(a, d.nq, d.gmax, batch_grid(d, bt), d.v2_lds, bt.keep, s));
     } else if (bt.n_units > 0) {
         FrameKernelArgs a{};
         fill_v1_args(d, bt, a);
         HIP_TRY(ctx, launch_frame_kernel_v1(a, batch_grid(d, bt), d.lds_bytes, bt.keep, s));
     }
-    if (!bt.capture) HIP_TRY(ctx, hipEventRecord(b->ev_main, s));
-    return enqueue_tail(ctx, bt);
+    return enqueue_post(ctx, bt);
+}
+
+// The one-launch form of a mixed call: 2 to kMixMax batches whose detectors
+// all take the persistent kernel through a compiled body of the mixed kernel
+// (v2_mix_variant: median common mode, nothing kept), with the largest LDS
+// beside the kernel's own static variables.  Otherwise the batches launch on
+// their own.
+bool mix_one_launch(pdc_ctx *ctx, const std::vector<int32_t> &dets)
+{
+    if (!ctx->mix_one || dets.size() < 2 || dets.size() > (size_t)kMixMax) return false;
+    static const size_t static_lds = frame_kernel_v2_mix_static_lds();
+    size_t lds = 0;
+    for (int32_t det : dets) {
+        const Detector &d = ctx->dets[det];
+        if (!d.v2_ok) return false;
+        V2Args a{};
+        a.B = d.g.bank_cols;
+        a.nb = d.g.cols / d.g.bank_cols;
+        a.rmax = d.rmax;
+        a.gain_mode = d.g.gain_mode;
+        a.cm_mode = d.p.cm_mode == PDC_CM_MEDIAN ? 0 : 1;
+        if ((d.p.flags & PDC_KEEP_MEDIANS) || v2_mix_variant(a, d.nq, d.gmax, (d.p.flags & PDC_KEEP_CORRECTED) != 0) < 0)
+            return false;
+        lds = std::max(lds, d.v2_lds);
+    }
+    return static_lds != SIZE_MAX && lds + static_lds <= (size_t)ctx->max_lds / kV2GroupsPerCu;
+}
+
+// Frame groups of a batch in the one launch, beyond its detector's choice:
+// finer work items, so that workgroups of detectors of unequal cost per pixel
+// even out across the chip as they are handed out.
+constexpr int kMixFgMore = 2;
+
+// Enqueue the batches of a mixed call, each on its own stream (streams[i]),
+// forked from and joined back into the stream s (events: at least
+// streams.size() + 1).  With one launch, the batches' work before and after
+// the frame kernel stays on their streams and the kernel runs on s.
+pdc_status enqueue_mixed(pdc_ctx *ctx, std::vector<Batch *> &bts, hipStream_t s, const std::vector<hipStream_t> &streams,
+                         const std::vector<hipEvent_t> &events)
+{
+    const int n_str = (int)streams.size();
+    auto fork = [&]() -> pdc_status {
+        HIP_TRY(ctx, hipEventRecord(events[0], s));
+        for (int j = 0; j < n_str; ++j) HIP_TRY(ctx, hipStreamWaitEvent(streams[j], events[0], 0));
+        return PDC_OK;
+    };
+    auto join = [&]() -> pdc_status {
+        for (int j = 0; j < n_str; ++j) {
+            HIP_TRY(ctx, hipEventRecord(events[1 + j], streams[j]));
+            HIP_TRY(ctx, hipStreamWaitEvent(s, events[1 + j], 0));
+        }
+        return PDC_OK;
+    };
+    pdc_status rc = fork();
+    if (rc != PDC_OK) return rc;
+    std::vector<int32_t> dets;
+    for (const Batch *bt : bts) dets.push_back(bt->det);
+    bool one = mix_one_launch(ctx, dets);
+    for (const Batch *bt : bts) one = one && bt->path == 2 && bt->n_units > 0;
+    if (!one) {
+        for (Batch *bt : bts)
+            if ((rc = enqueue(ctx, *bt)) != PDC_OK) break;
+        pdc_status rj = join();
+        return rc != PDC_OK ? rc : rj;
+    }
+    for (Batch *bt : bts)
+        if ((rc = enqueue_pre(ctx, *bt)) != PDC_OK) break;
+    pdc_status rj = join();
+    if (rc != PDC_OK || rj != PDC_OK) return rc != PDC_OK ? rc : rj;
+    V2Mix m{};
+    size_t lds = 0;
+    int first = 0;
+    for (size_t i = 0; i < bts.size(); ++i) {
+        bts[i]->mix_one = true;
+        const Batch &bt = *bts[i];
+        const Detector &d = ctx->dets[bt.det];
+        fill_v2_args(d, bt, m.a[i]);
+        m.variant[i] = v2_mix_variant(m.a[i], d.nq, d.gmax, bt.keep);
+        m.first[i] = first;
+        first += (int)batch_grid(d, bt);
+        lds = std::max(lds, d.v2_lds);
+    }
+    m.first[bts.size()] = first;
+    m.n = (int32_t)bts.size();
+    HIP_TRY(ctx, launch_frame_kernel_v2_mix(m, lds, s));
+    if ((rc = fork()) != PDC_OK) return rc;
+    for (Batch *bt : bts)
+        if ((rc = enqueue_post(ctx, *bt)) != PDC_OK) break;
+    rj = join();
+    return rc != PDC_OK ? rc : rj;
 }
 
 // Redo the units the persistent kernel listed as overflowing with the general
@@ -741,7 +864,7 @@ void set_path(const Detector &d, Batch &bt, int path)
 {
     bt.path = path;
     if (path == 2) {
-        const int fgb = frame_groups(d.n_cu * kV2GroupsPerCu, d.n_strips, bt.n_frames, d.fg_mult);
+        const int fgb = frame_groups(d.n_cu * kV2GroupsPerCu, d.n_strips, bt.n_frames, d.fg_mult * bt.fg_more);
         const uint64_t fg = (uint64_t)std::max(1.0, std::floor((double)fgb * bt.share));
         bt.n_fg = (int)std::max<uint64_t>(1, std::min<uint64_t>(fg, bt.n_frames));
         bt.upf = d.n_strips;
@@ -867,6 +990,47 @@ void maybe_free_detector(pdc_ctx *ctx, int32_t det)
     }
 }
 
+// A batch's plan and buffers, not yet enqueued (on failure nothing is held).
+pdc_status setup_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                       uint64_t hit_capacity, hipStream_t stream, double share, Batch &bt, int fg_more = 1)
+{
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    if (n_frames > 0 && !frames_dev) return fail(ctx, PDC_EINVAL, "frames_dev is NULL");
+    if (n_frames > ((uint64_t)1 << 31)) return fail(ctx, PDC_EINVAL, "n_frames must be <= 2^31");
+    Detector &d = ctx->dets[det];
+    bt = Batch{};
+    bt.det = det;
+    bt.frames = frames_dev;
+    bt.n_frames = n_frames;
+    bt.share = share;
+    bt.fg_more = fg_more;
+    set_path(d, bt, d.v2_ok ? 2 : 1);
+    bt.stream = stream;
+    bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
+    bt.meds = (d.p.flags & PDC_KEEP_MEDIANS) != 0;
+    bt.pool_cap = ctx->tight_pool ? hit_capacity : pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
+    Buffers *b = take_buffers(ctx);
+    if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
+    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt),
+                                   meds_floats(d, bt));
+    if (rc != PDC_OK) {
+        ctx->spare.push_back(b);
+        return rc;
+    }
+    bt.buf = b;
+    return PDC_OK;
+}
+
+// An enqueued batch becomes outstanding under the next id.
+uint64_t register_batch(pdc_ctx *ctx, Batch &bt)
+{
+    bt.id = ctx->next_batch++;
+    ctx->dets[bt.det].pending += 1;
+    ctx->batches[bt.id] = bt;
+    return bt.id;
+}
+
 }  // namespace
 
 extern "C" {
@@ -910,6 +1074,8 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
         ctx->force_v1 = fv && fv[0] == '1';
         const char *ms = std::getenv("PDC_MIX_SHARE");
         ctx->mix_share = ms && ms[0] == '1';
+        const char *mf = std::getenv("PDC_MIX_FORKED");
+        ctx->mix_one = !(mf && mf[0] == '1');
         const char *tp = std::getenv("PDC_DEBUG_TIGHT_POOL");
         ctx->tight_pool = tp && tp[0] == '1';
     }
@@ -1196,23 +1362,33 @@ pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t 
         work += (double)items[i].n_frames * g.n_tiles * g.rows * g.cols;
     }
     hipStream_t hs = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    HIP_TRY(ctx, hipEventRecord(ctx->mix_events[0], hs));  // fork
-    for (int j = 0; j < n_str; ++j) HIP_TRY(ctx, hipStreamWaitEvent(ctx->mix_streams[j], ctx->mix_events[0], 0));
+    std::vector<Batch> bts(n_items);
+    std::vector<Batch *> ptrs(n_items);
+    std::vector<int32_t> mix_dets;
+    for (int i = 0; i < n_items; ++i) mix_dets.push_back(items[i].det);
+    const int fg_more = mix_one_launch(ctx, mix_dets) ? kMixFgMore : 1;
+    auto drop = [&](int upto) {
+        for (int j = 0; j < upto; ++j) ctx->spare.push_back(bts[j].buf);
+    };
     for (int i = 0; i < n_items; ++i) {
         const pdc_geometry &g = ctx->dets[items[i].det].g;
         const double px = (double)items[i].n_frames * g.n_tiles * g.rows * g.cols;
         const double share = ctx->mix_share && work > 0.0 ? std::min(1.0, px / work) : 1.0;
-        pdc_status rc = process_batch(ctx, items[i].det, items[i].frames_dev, items[i].n_frames,
-                                      items[i].hit_capacity, ctx->mix_streams[i % n_str], share, &batch_out[i]);
+        pdc_status rc = setup_batch(ctx, items[i].det, items[i].frames_dev, items[i].n_frames, items[i].hit_capacity,
+                                    ctx->mix_streams[i % n_str], share, bts[i], fg_more);
         if (rc != PDC_OK) {
-            for (int j = 0; j < i; ++j) pdc_release_batch(ctx, batch_out[j]);
+            drop(i);
             return rc;
         }
+        ptrs[i] = &bts[i];
     }
-    for (int j = 0; j < n_str; ++j) {  // join
-        HIP_TRY(ctx, hipEventRecord(ctx->mix_events[1 + j], ctx->mix_streams[j]));
-        HIP_TRY(ctx, hipStreamWaitEvent(hs, ctx->mix_events[1 + j], 0));
+    const std::vector<hipStream_t> streams(ctx->mix_streams.begin(), ctx->mix_streams.begin() + n_str);
+    pdc_status rc = enqueue_mixed(ctx, ptrs, hs, streams, ctx->mix_events);
+    if (rc != PDC_OK) {
+        drop(n_items);
+        return rc;
     }
+    for (int i = 0; i < n_items; ++i) batch_out[i] = register_batch(ctx, bts[i]);
     return PDC_OK;
 }
 
@@ -1220,43 +1396,19 @@ pdc_status process_batch(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, 
                          uint64_t hit_capacity, void *hip_stream, double share, uint64_t *batch_out)
 {
     if (!ctx || !batch_out) return fail(ctx, PDC_EINVAL, "ctx and batch_out must be non-NULL");
-    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
-        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
-    if (n_frames > 0 && !frames_dev) return fail(ctx, PDC_EINVAL, "frames_dev is NULL");
-    if (n_frames > ((uint64_t)1 << 31)) return fail(ctx, PDC_EINVAL, "n_frames must be <= 2^31");
     if ((int)ctx->batches.size() >= kMaxOutstandingBatches)
         return fail(ctx, PDC_ESTATE, "too many outstanding batches (release some)");
-    Detector &d = ctx->dets[det];
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     Batch bt;
-    bt.id = ctx->next_batch;
-    bt.det = det;
-    bt.frames = frames_dev;
-    bt.n_frames = n_frames;
-    bt.share = share;
-    set_path(d, bt, d.v2_ok ? 2 : 1);
-    bt.stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    bt.keep = (d.p.flags & PDC_KEEP_CORRECTED) != 0;
-    bt.meds = (d.p.flags & PDC_KEEP_MEDIANS) != 0;
-    bt.pool_cap = ctx->tight_pool ? hit_capacity : pool_capacity(d, bt.path, hit_capacity, batch_grid(d, bt));
-    Buffers *b = take_buffers(ctx);
-    if (!b) return fail(ctx, PDC_ENOMEM, "host allocation failed");
-    pdc_status rc = ensure_buffers(ctx, b, bt.n_units, n_frames, bt.pool_cap, corr_floats(d, bt), cm_floats(d, bt),
-                                   meds_floats(d, bt));
-    if (rc != PDC_OK) {
-        ctx->spare.push_back(b);
-        return rc;
-    }
-    bt.buf = b;
+    pdc_status rc = setup_batch(ctx, det, frames_dev, n_frames, hit_capacity,
+                                hip_stream ? (hipStream_t)hip_stream : ctx->stream, share, bt);
+    if (rc != PDC_OK) return rc;
     rc = enqueue(ctx, bt);
     if (rc != PDC_OK) {
-        ctx->spare.push_back(b);
+        ctx->spare.push_back(bt.buf);
         return rc;
     }
-    ++ctx->next_batch;
-    d.pending += 1;
-    ctx->batches[bt.id] = bt;
-    *batch_out = bt.id;
+    *batch_out = register_batch(ctx, bt);
     return PDC_OK;
 }
 
@@ -1434,11 +1586,15 @@ static pdc_status graph_capture(pdc_ctx *ctx, const pdc_mixed_item *items, int32
         const pdc_geometry &gg = ctx->dets[items[i].det].g;
         work += (double)items[i].n_frames * gg.n_tiles * gg.rows * gg.cols;
     }
+    std::vector<int32_t> mix_dets;
+    for (int i = 0; i < n_items; ++i) mix_dets.push_back(items[i].det);
+    const int fg_more = mix_one_launch(ctx, mix_dets) ? kMixFgMore : 1;
     for (int i = 0; i < n_items; ++i) {
         const Detector &d = ctx->dets[items[i].det];
         Batch &bt = g->proto[i];
         bt.det = items[i].det;
         bt.gitem = i;
+        bt.fg_more = fg_more;
         bt.frames = items[i].frames_dev;
         bt.n_frames = items[i].n_frames;
         const double px = (double)items[i].n_frames * d.g.n_tiles * d.g.rows * d.g.cols;
@@ -1472,20 +1628,15 @@ static pdc_status graph_capture(pdc_ctx *ctx, const pdc_mixed_item *items, int32
     }
     pdc_status rc = PDC_OK;
     // the forked streams join the capture by waiting for an event recorded in
-    // it, and are joined back (also after a failed enqueue, so that no stream
-    // is left capturing)
-    int forked = 0;
+    // it, and are joined back (enqueue_mixed joins them also after a failed
+    // enqueue, so that no stream is left capturing)
     if (n_str) {
-        e = hipEventRecord(ctx->mix_events[0], cs);
-        for (; e == hipSuccess && forked < n_str; ++forked)
-            e = hipStreamWaitEvent(ctx->mix_streams[forked], ctx->mix_events[0], 0);
-        if (e != hipSuccess) rc = fail(ctx, PDC_EDEVICE, "graph fork: %s", hipGetErrorString(e));
-    }
-    for (int i = 0; rc == PDC_OK && i < n_items; ++i) rc = enqueue(ctx, g->proto[i]);
-    for (int j = 0; j < forked; ++j) {
-        e = hipEventRecord(ctx->mix_events[1 + j], ctx->mix_streams[j]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->mix_events[1 + j], 0);
-        if (e != hipSuccess && rc == PDC_OK) rc = fail(ctx, PDC_EDEVICE, "graph join: %s", hipGetErrorString(e));
+        std::vector<Batch *> ptrs;
+        for (Batch &bt : g->proto) ptrs.push_back(&bt);
+        const std::vector<hipStream_t> streams(ctx->mix_streams.begin(), ctx->mix_streams.begin() + n_str);
+        rc = enqueue_mixed(ctx, ptrs, cs, streams, ctx->mix_events);
+    } else {
+        for (int i = 0; rc == PDC_OK && i < n_items; ++i) rc = enqueue(ctx, g->proto[i]);
     }
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
@@ -2105,6 +2256,7 @@ pdc_status pdc_debug_batch_path(pdc_ctx *ctx, uint64_t batch, int32_t *path)
     pdc_status rc = finish_batch(ctx, *bt);
     if (rc != PDC_OK) return rc;
     *path = bt->path == 2 && bt->fb == 1 ? 3 : bt->path;
+    if (bt->path == 2 && bt->mix_one) *path += 2;
     return PDC_OK;
 }
 

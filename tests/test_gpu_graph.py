@@ -296,6 +296,58 @@ def test_mixed_graph_replays_equal_oracle(ctx):
             pdc.release_detector(ctx, d)
 
 
+def test_mixed_graph_one_launch_replays_equal_oracle(ctx):
+    """A graph of three detectors whose frame kernels are one launch
+    (median, nothing kept: ePix100-like rows, CSPAD-like, Jungfrau-like with
+    three gain ranges): each of three replays with new frames equals the
+    oracles, and each batch reports the one-launch path."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    n = 3
+    specs = []
+    g = synth.Geometry(1, 64, 768, 96)
+    ped, gain = synth.make_calibration(g, 91)
+    sets = [synth.make_frames(g, ped, gain, n, 0.01, sd) for sd in (91, 92)]
+    specs.append((g, 0, ped, gain, sets, [oracle_threads(r, ped, gain, 96) for r in sets]))
+    g = synth.Geometry(2, 40, 388, 194)
+    ped, gain = synth.make_calibration(g, 93)
+    sets = [synth.make_frames(g, ped, gain, n, 0.02, sd) for sd in (93, 94)]
+    specs.append((g, 0, ped, gain, sets, [oracle_threads(r, ped, gain, 194) for r in sets]))
+    g = synth.Geometry(1, 48, 1024, 256)
+    ped, gain = synth.make_calibration_multigain(g, 95)
+    sets = [synth.make_frames_multigain(g, ped, gain, n, 0.01, sd, 2, **FEW_LOW_GAIN) for sd in (95, 96)]
+    specs.append((g, 2, ped, gain, sets, [G.process(r, ped, gain, 256, 2) for r in sets]))
+
+    dets, graph = [], None
+    try:
+        for g, gm, ped, gain, _, _ in specs:
+            dets.append(pdc.calibrate(ctx, pdc.geometry(*g.shape, g.bank_cols, gm), ped, gain, pdc.params()))
+        devs = [[torch.from_numpy(r).cuda() for r in sp[4]] for sp in specs]
+        bufs = [torch.empty_like(dv[0]) for dv in devs]
+        torch.cuda.synchronize()
+        graph = pdc.graph_create_mixed(ctx, [(d, b, n, 1 << 18) for d, b in zip(dets, bufs)])
+        s = torch.cuda.Stream()
+        for k in (0, 1, 0):
+            with torch.cuda.stream(s):
+                for b, dv in zip(bufs, devs):
+                    b.copy_(dv[k])
+            batches = pdc.graph_launch(ctx, graph, s)
+            for b, sp in zip(batches, specs):
+                got = _results(ctx, b, n, keep=False, invalid=bool(sp[1]))
+                pdc.release_batch(ctx, b)
+                assert got["path"] in (4, 5), got["path"]
+                _same(got, sp[5][k], keep=False)
+            (devs[0][1].float() + 1).sum().item()
+            torch.cuda.synchronize()
+    finally:
+        if graph is not None:
+            pdc.graph_destroy(ctx, graph)
+        for d in dets:
+            pdc.release_detector(ctx, d)
+
+
 def test_mixed_graph_items_move_off_graph_on_overflow():
     """No staging slack and capacity 0: every item of a two-detector graph
     overflows and is recomputed on buffers of its own, each item freeing its

@@ -1,7 +1,8 @@
 """Mixed batches (pdc_process_mixed): several detectors with different
 geometries, gain modes and common-mode settings enqueued at once, running
-concurrently; every batch equals its oracle bit for bit and work enqueued
-afterwards on the caller's stream sees all of them finished."""
+concurrently or in one launch of the persistent kernel; every batch equals
+its oracle bit for bit and work enqueued afterwards on the caller's stream
+sees all of them finished."""
 import numpy as np
 import pytest
 
@@ -85,6 +86,83 @@ def test_mixed_batch_equals_oracle(ctx):
     finally:
         for d in dets:
             pdc.release_detector(ctx, d)
+
+
+def _one_launch_detectors():
+    """Median common mode, nothing kept: four lane layouts and gain modes of
+    the one-launch kernel, with different frame counts."""
+    out = []
+    g = synth.Geometry(1, 64, 768, 96)                 # ePix100-like rows, 8 lanes per bank
+    ped, gain = synth.make_calibration(g, 51)
+    raw = synth.make_frames(g, ped, gain, 5, 0.01, 51)
+    out.append((g, 0, raw, ped, gain, oracle_threads(raw, ped, gain, 96)))
+    g = synth.Geometry(2, 40, 388, 194)                # CSPAD-like, 16 lanes per bank
+    ped, gain = synth.make_calibration(g, 52)
+    raw = synth.make_frames(g, ped, gain, 6, 0.02, 52)
+    out.append((g, 0, raw, ped, gain, oracle_threads(raw, ped, gain, 194)))
+    g = synth.Geometry(1, 64, 384, 96)                 # ePix10k-like, three gain ranges
+    ped, gain = synth.make_calibration_multigain(g, 53)
+    raw = synth.make_frames_multigain(g, ped, gain, 7, 0.02, 53, 1, **FEW_LOW_GAIN)
+    out.append((g, 1, raw, ped, gain, G.process(raw, ped, gain, 96, 1)))
+    g = synth.Geometry(1, 48, 1024, 256)               # Jungfrau-like, three gain ranges
+    ped, gain = synth.make_calibration_multigain(g, 54)
+    raw = synth.make_frames_multigain(g, ped, gain, 3, 0.01, 54, 2, **FEW_LOW_GAIN)
+    out.append((g, 2, raw, ped, gain, G.process(raw, ped, gain, 256, 2)))
+    return out
+
+
+def test_mixed_one_launch_equals_oracle(ctx):
+    """The four batches run as one launch (path 4, or 5 with overflowing
+    units redone) and equal their oracles; a context with PDC_MIX_FORKED=1
+    runs them as launches of their own (path 2 or 3) with the same results."""
+    import os
+
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    cases = _one_launch_detectors()
+    os.environ["PDC_MIX_FORKED"] = "1"
+    try:
+        forked = pdc.create(0)
+    finally:
+        del os.environ["PDC_MIX_FORKED"]
+    try:
+        got = {}
+        for c, name in ((ctx, "one"), (forked, "forked")):
+            dets, items, devs = [], [], []
+            try:
+                for g, gm, raw, ped, gain, _ in cases:
+                    d = pdc.calibrate(c, pdc.geometry(*g.shape, g.bank_cols, gm), ped, gain, pdc.params())
+                    dets.append(d)
+                    dev = torch.from_numpy(raw).cuda()
+                    devs.append(dev)
+                    items.append((d, dev, raw.shape[0], 1 << 16))
+                torch.cuda.synchronize()
+                stream = torch.cuda.Stream()
+                batches = pdc.process_mixed(c, items, stream)
+                stream.synchronize()
+                res = []
+                for b, (g, gm, raw, ped, gain, want) in zip(batches, cases):
+                    hits, total, fh, fp, _ = pdc.get_hits(c, b, raw.shape[0])
+                    out = dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp,
+                               path=pdc.debug_batch_path(c, b))
+                    if gm:
+                        out["invalid"] = pdc.get_invalid_counts(c, b, raw.shape[0])
+                    pdc.release_batch(c, b)
+                    res.append(out)
+                got[name] = res
+            finally:
+                for d in dets:
+                    pdc.release_detector(c, d)
+    finally:
+        pdc.destroy(forked)
+    for one, fk, (g, gm, raw, ped, gain, want) in zip(got["one"], got["forked"], cases):
+        assert one["path"] in (4, 5) and fk["path"] in (2, 3), (g, one["path"], fk["path"])
+        for r in (one, fk):
+            assert_same(r, want)
+            if gm:
+                assert np.array_equal(r["invalid"], want["invalid"])
 
 
 def test_mixed_rejects_bad_items(ctx):
