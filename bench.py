@@ -717,9 +717,11 @@ def main():
 
     pool, frames = make_batch(torch, synth, geom, ped, gain, 1, args.pool, N, dev)
     est = int(0.01 * 1.2 * npix * N) + 4096
-    # tile shape: the frame-group count of the persistent launch, tuned on this batch
-    tune_mult, tune_ms = pdc.autotune(ctx, det, frames, N, est, torch.cuda.current_stream())
-    log("autotune: frame groups x%d (frame kernel ms x1/x2/x4: %s)" % (tune_mult, [round(float(x), 3) for x in tune_ms]))
+    # tile shape: strip height and frame-group count of the persistent launch,
+    # tuned on this batch
+    tune_rows, tune_mult, tune_ms = pdc.autotune_strips(ctx, det, frames, N, est, torch.cuda.current_stream())
+    log("autotune: %d own rows per strip, frame groups x%d (frame kernel ms, rows by strip height, x1/x2/x4: %s)"
+        % (tune_rows, tune_mult, [[round(float(x), 3) for x in row] for row in tune_ms]))
     phase_fn = None
     if args.phase_timers:
         import ctypes
@@ -774,8 +776,9 @@ def main():
                                   "batch (64 distinct, replicated in HBM), occupancy 0.01" % N,
                       "frames": N, "tiles": 32, "rows": 185, "cols": 388, "bank_cols": 194,
                       "occupancy": 0.01, "thresholds": "5 sigma seed, 3 sigma neighbours, sigma 3 ADU",
-                      "frame_groups_autotuned": {"multiplier": tune_mult,
-                                                 "frame_kernel_ms_x1_x2_x4": [round(float(x), 3) for x in tune_ms]}},
+                      "tile_shape_autotuned": {"strip_rows": tune_rows, "frame_group_multiplier": tune_mult,
+                                               "frame_kernel_ms_by_strip_rows_x1_x2_x4":
+                                                   [[round(float(x), 3) for x in row] for row in tune_ms]}},
            "roofline": roofline(N, npix, hits, mains),
            "hits_per_step": hits,
            "all_kernels_ms": round(sum(totals) / len(totals), 4),

@@ -269,6 +269,20 @@ pdc_status pdc_process_mixed(pdc_ctx *ctx, const pdc_mixed_item *items, int32_t 
 pdc_status pdc_autotune(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
                         uint64_t hit_capacity, void *hip_stream, int32_t *mult_out, float *ms_out);
 
+/* Strip-height autotuner: the persistent kernel with at most R own rows per
+ * strip, R the most its lane layout holds and 4 and 8 fewer (those of at
+ * least 4 rows), each timed with pdc_autotune's three frame-group counts on
+ * the caller's frames; the detector keeps the fastest (strip rows, frame
+ * groups) for its later batches (results do not depend on them).  *rows_out
+ * and *mult_out (may be NULL) receive the choice, ms_out (host float[9], may
+ * be NULL) the frame-kernel times, row r of 3 for the r-th strip height,
+ * *n_tried (may be NULL) the strip heights timed.  ESTATE while the detector
+ * has outstanding batches or graphs (they hold its strip plan) or does not
+ * take the persistent kernel.  Synchronous; runs 9 batches per height. */
+pdc_status pdc_autotune_strips(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                               uint64_t hit_capacity, void *hip_stream, int32_t *rows_out, int32_t *mult_out,
+                               float *ms_out, int32_t *n_tried);
+
 /* Wait for the batch and copy its results (Summarization section: lists of
  * sparse photons, each with its position, energy and photon count; per-frame
  * photon-counting totals), hits in (frame, pixel) order.

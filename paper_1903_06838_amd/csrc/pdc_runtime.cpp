@@ -61,6 +61,7 @@ struct Detector {
     int nq = 0, gmax = 0, n_strips = 0, rmax = 0, seed_cap = 0;
     int n_cu = 0;                         // compute units of the device (frame-group choice)
     int fg_mult = 1;                      // frame groups x this (pdc_autotune)
+    int strip_cap = 0;                    // own rows per strip at most this (0: as many as fit; pdc_autotune_strips)
     uint32_t v2_max_unit_hits = 0;
     size_t v2_lds = 0;
     float rank_width = 0;
@@ -177,6 +178,7 @@ struct pdc_ctx {
     HitRecord *fmt_buf = nullptr;  // staging for host-destination get_hits
     uint64_t fmt_cap = 0;
     bool force_v1 = false;         // PDC_FORCE_GENERAL=1 in the environment
+    int strip_rows = 0;            // PDC_STRIP_ROWS=n: own rows per strip at most n for new detectors
     bool tight_pool = false;       // PDC_DEBUG_TIGHT_POOL=1: first staging holds hit_capacity only
     hipStream_t capture_stream = nullptr;  // private stream for graph capture
     std::set<pdc_graph *> graphs;
@@ -375,7 +377,7 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     const int max_bank_rows = kV2Waves * d.gmax;  // a bank-row group per wave and slot
     const int rmax_lim = max_bank_rows / nb;
     if (rmax_lim < 3) return false;
-    const int own_max = rmax_lim - 2;
+    const int own_max = d.strip_cap > 0 ? std::min(rmax_lim - 2, d.strip_cap) : rmax_lim - 2;
     // Strips of at most own_max own rows over the frame's rows counted across
     // tiles (global row t * H + r): a strip may cross a tile edge, which
     // evens out strips when H is not a multiple of own_max (CSPAD: 198 strips
@@ -445,6 +447,10 @@ bool plan_v2(pdc_ctx *ctx, Detector &d)
     }
     d.rank_width = d.p.sigma / (0.4f * (float)g.bank_cols);
     d.n_cu = ctx->n_cu;
+    if (d.d_strips) {  // a new plan of the same detector (no batch holds the old one)
+        hipFree(d.d_strips);
+        d.d_strips = nullptr;
+    }
     if (hipMalloc((void **)&d.d_strips, strips.size() * sizeof(V2Strip)) != hipSuccess) return false;
     if (hipMemcpy(d.d_strips, strips.data(), strips.size() * sizeof(V2Strip), hipMemcpyHostToDevice) != hipSuccess)
         return false;
@@ -1072,6 +1078,8 @@ pdc_status pdc_create(int32_t device, pdc_ctx **out)
     {
         const char *fv = std::getenv("PDC_FORCE_GENERAL");
         ctx->force_v1 = fv && fv[0] == '1';
+        const char *sr = std::getenv("PDC_STRIP_ROWS");
+        ctx->strip_rows = sr ? std::max(0, std::atoi(sr)) : 0;
         const char *ms = std::getenv("PDC_MIX_SHARE");
         ctx->mix_share = ms && ms[0] == '1';
         const char *mf = std::getenv("PDC_MIX_FORKED");
@@ -1179,6 +1187,7 @@ pdc_status pdc_calibrate(pdc_ctx *ctx, const pdc_geometry *geom, const float *pe
     HIP_TRY(ctx, hipMalloc((void **)&d.d_k, n * sizeof(float)));
     HIP_TRY(ctx, hipMemcpy(d.d_ped, pedestal, n * sizeof(float), hipMemcpyHostToDevice));
     HIP_TRY(ctx, hipMemcpy(d.d_k, k.data(), n * sizeof(float), hipMemcpyHostToDevice));
+    d.strip_cap = ctx->strip_rows;
     if (!ctx->force_v1) plan_v2(ctx, d);
     d.live = true;
     for (size_t i = 0; i < ctx->dets.size(); ++i)
@@ -2300,6 +2309,61 @@ pdc_status pdc_autotune(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, u
     }
     ctx->dets[det].fg_mult = best;
     if (mult_out) *mult_out = best;
+    return PDC_OK;
+}
+
+pdc_status pdc_autotune_strips(pdc_ctx *ctx, int32_t det, const uint16_t *frames_dev, uint64_t n_frames,
+                               uint64_t hit_capacity, void *hip_stream, int32_t *rows_out, int32_t *mult_out,
+                               float *ms_out, int32_t *n_tried)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (det < 0 || det >= (int32_t)ctx->dets.size() || !ctx->dets[det].live || ctx->dets[det].release_requested)
+        return fail(ctx, PDC_ESTATE, "unknown detector %d", det);
+    if (n_frames < 1 || !frames_dev) return fail(ctx, PDC_EINVAL, "need frames_dev and n_frames >= 1");
+    Detector &d = ctx->dets[det];
+    if (!d.v2_ok) return fail(ctx, PDC_ESTATE, "the detector does not take the persistent kernel");
+    if (d.pending) return fail(ctx, PDC_ESTATE, "the detector has outstanding batches or graphs");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    // own rows per strip: the most the lane layout holds, then 4 and 8 fewer
+    d.strip_cap = 0;
+    if (!plan_v2(ctx, d)) return fail(ctx, PDC_EDEVICE, "re-plan failed");
+    const int full = kV2Waves * d.gmax / (d.g.cols / d.g.bank_cols) - 2;  // as plan_v2 allows
+    int caps[3] = {full, full - 4, full - 8};
+    int n_caps = 1;
+    while (n_caps < 3 && caps[n_caps] >= 4) ++n_caps;
+    float best_ms = 0.0f;
+    int best_cap = full, best_mult = 1, tried = 0;
+    for (int c = 0; c < n_caps; ++c) {
+        d.strip_cap = caps[c];
+        if (!plan_v2(ctx, d)) {
+            d.strip_cap = 0;
+            plan_v2(ctx, d);
+            return fail(ctx, PDC_EDEVICE, "re-plan failed");
+        }
+        int mult = 1;
+        float ms3[3] = {0.0f, 0.0f, 0.0f};
+        const pdc_status rc = pdc_autotune(ctx, det, frames_dev, n_frames, hit_capacity, hip_stream, &mult, ms3);
+        if (rc != PDC_OK) {
+            d.strip_cap = 0;
+            plan_v2(ctx, d);
+            return rc;
+        }
+        const float ms = std::min(ms3[0], std::min(ms3[1], ms3[2]));
+        for (int j = 0; j < 3; ++j)
+            if (ms_out) ms_out[3 * c + j] = ms3[j];
+        ++tried;
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            best_cap = caps[c];
+            best_mult = mult;
+        }
+    }
+    d.strip_cap = best_cap == full ? 0 : best_cap;
+    if (!plan_v2(ctx, d)) return fail(ctx, PDC_EDEVICE, "re-plan failed");
+    d.fg_mult = best_mult;
+    if (rows_out) *rows_out = best_cap;
+    if (mult_out) *mult_out = best_mult;
+    if (n_tried) *n_tried = tried;
     return PDC_OK;
 }
 

@@ -102,6 +102,9 @@ _sig = {
     "pdc_process_mixed": (_st, [_P, _P, ctypes.c_int32, _P, _P]),
     "pdc_autotune": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64, _P,
                            ctypes.POINTER(ctypes.c_int32), _P]),
+    "pdc_autotune_strips": (_st, [_P, ctypes.c_int32, _P, ctypes.c_uint64, ctypes.c_uint64, _P,
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32), _P,
+                                  ctypes.POINTER(ctypes.c_int32)]),
     "pdc_debug_batch_path": (_st, [_P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]),
     "pdc_dark_stats": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, _P, _P]),
     "pdc_calibrate_darks": (_st, [_P, ctypes.POINTER(Geometry), _P, ctypes.c_uint64, _P, ctypes.POINTER(Params), _P,
@@ -232,6 +235,15 @@ def autotune(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int, stream
     _check(_lib.pdc_autotune(ctx, det, _ptr(frames_dev), n_frames, hit_capacity, _stream(stream), ctypes.byref(m),
                              ms.ctypes.data), ctx)
     return m.value, ms
+
+
+def autotune_strips(ctx, det: int, frames_dev, n_frames: int, hit_capacity: int, stream=None):
+    """Returns (chosen own rows per strip, frame-group multiplier, frame-kernel ms [heights tried][3])."""
+    rows, m, n = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    ms = np.zeros(9, np.float32)
+    _check(_lib.pdc_autotune_strips(ctx, det, _ptr(frames_dev), n_frames, hit_capacity, _stream(stream),
+                                    ctypes.byref(rows), ctypes.byref(m), ms.ctypes.data, ctypes.byref(n)), ctx)
+    return rows.value, m.value, ms.reshape(3, 3)[:n.value]
 
 
 def get_hits(ctx, batch: int, n_frames: int, capacity: int | None = None, dst_dev=None):

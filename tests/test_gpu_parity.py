@@ -404,3 +404,52 @@ def test_autotune_keeps_results(ctx):
     finally:
         pdc.release_detector(ctx, det)
     assert_same(dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp), want)
+
+
+def test_strip_heights_keep_results(ctx):
+    """The strip-height autotuner times three strip heights and keeps one;
+    batches with each height (forced at pdc_create) and after the tuner equal
+    the oracle bit for bit; the tuner refuses while a batch is outstanding."""
+    import os
+
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(2, 40, 388, 194)
+    raw, ped, gain = _case(geom, 0.02, 24, 53)
+    want = oracle_threads(raw, ped, gain, geom.bank_cols)
+    dev = torch.from_numpy(raw).cuda()
+    torch.cuda.synchronize()
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, 194), ped, gain, pdc.params())
+    try:
+        b = pdc.process_frames(ctx, det, dev, raw.shape[0], 1 << 16)
+        with pytest.raises(pdc.PdcError) as e:
+            pdc.autotune_strips(ctx, det, dev, raw.shape[0], 1 << 16)
+        assert e.value.status == pdc.ESTATE
+        pdc.release_batch(ctx, b)
+        rows, mult, ms = pdc.autotune_strips(ctx, det, dev, raw.shape[0], 1 << 16)
+        assert rows in (30, 26, 22) and mult in (1, 2, 4) and ms.shape == (3, 3) and np.all(ms > 0)
+        b = pdc.process_frames(ctx, det, dev, raw.shape[0], 1 << 16)
+        hits, total, fh, fp, _ = pdc.get_hits(ctx, b, raw.shape[0])
+        assert pdc.debug_batch_path(ctx, b) in (2, 3)
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
+    assert_same(dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp), want)
+    for r in (26, 22, 5):
+        os.environ["PDC_STRIP_ROWS"] = str(r)
+        try:
+            c = pdc.create(0)
+        finally:
+            del os.environ["PDC_STRIP_ROWS"]
+        try:
+            d = pdc.calibrate(c, pdc.geometry(*geom.shape, 194), ped, gain, pdc.params())
+            b = pdc.process_frames(c, d, dev, raw.shape[0], 1 << 16)
+            hits, total, fh, fp, _ = pdc.get_hits(c, b, raw.shape[0])
+            assert pdc.debug_batch_path(c, b) in (2, 3), r
+            pdc.release_batch(c, b)
+            pdc.release_detector(c, d)
+        finally:
+            pdc.destroy(c)
+        assert_same(dict(hits=hits, total=total, frame_hits=fh, frame_photons=fp), want)
