@@ -217,6 +217,51 @@ def test_mlp_infer_inputs_equals_infer(ctx, n):
     assert np.quantile(d, 0.99) <= 1e-5 and d.max() <= 2e-2
 
 
+def test_inputs_edge_cases(ctx):
+    """Empty calls succeed; capture of inputs needs a kept buffer and a valid
+    photon_adu; a capacity below the hit count takes the first hits."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    th = _theta(10)
+    net = pdc.mlp_create(ctx, th)
+    try:
+        pdc.mlp_make_inputs(ctx, None, 0, ADU, None)
+        pdc.mlp_infer_inputs(net, None, 0, None)
+        with pytest.raises(pdc.PdcError):
+            pdc.mlp_infer_inputs(net, None, 5, None)
+    finally:
+        pdc.mlp_destroy(net)
+    geom = synth.Geometry(1, 32, 96, 48)
+    ped, gain = synth.make_calibration(geom, 35)
+    raw = synth.make_frames(geom, ped, gain, 2, 0.03, 35)
+    for flags in (0, pdc.KEEP_MEDIANS):
+        det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params(flags=flags))
+        try:
+            frames = _dev(raw)  # held: kept-median patches are formed from the frames
+            b = pdc.process_frames(ctx, det, frames, 2, 10000)
+            x = torch.full((4, pdc.MLP_INPUT_WORDS), -1, dtype=torch.int16, device="cuda")
+            torch.cuda.synchronize()
+            if not flags:
+                with pytest.raises(pdc.PdcError) as e:
+                    pdc.capture_inputs(ctx, b, ADU, x, 4)
+                assert e.value.status == pdc.ESTATE
+            else:
+                with pytest.raises(pdc.PdcError) as e:
+                    pdc.capture_inputs(ctx, b, float("nan"), x, 4)
+                assert e.value.status == pdc.EINVAL
+                assert pdc.capture_inputs(ctx, b, ADU, x, 0) == 0
+                assert pdc.capture_inputs(ctx, b, ADU, x, 4) == 4
+                p = torch.zeros((4, 25), dtype=torch.float32, device="cuda")
+                torch.cuda.synchronize()
+                assert pdc.capture_patches(ctx, b, p, 4) == 4
+                assert np.array_equal(x.cpu().numpy().view(np.uint16), _input_words(p.cpu().numpy(), ADU))
+            pdc.release_batch(ctx, b)
+        finally:
+            pdc.release_detector(ctx, det)
+
+
 def test_mlp_forward_after_frame_kernel(ctx):
     """Regression: the frame kernel leaves +inf padding in LDS; the network's
     tiles must not read stale LDS (inf * 0 = NaN, which ReLU would turn into
