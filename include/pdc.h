@@ -416,6 +416,19 @@ pdc_status pdc_capture_patches(pdc_ctx *ctx, uint64_t batch, float *patches_dev,
 pdc_status pdc_capture_inputs(pdc_ctx *ctx, uint64_t batch, float photon_adu, uint16_t *inputs_dev,
                               uint64_t capacity, uint64_t *n_out);
 
+/* Classical positions of the same hits without patches: the masked 3x3
+ * centroid below (eta-corrected when eta_dev is not NULL) of each of the first
+ * min(total, capacity) hits, computed from the hit's Frames2 values as
+ * pdc_capture_patches forms them, into positions_dev float32 [capacity][2]; the
+ * same values as pdc_centroid on the captured patches.  only_implausible != 0:
+ * positions_dev already holds positions of these hits (the learned
+ * estimator's) and only those that are not finite or outside [-1, 1] in a
+ * coordinate are replaced by the classical ones: the runtime fallback.
+ * t_nb finite; 1 <= nbins <= 65536 when eta_dev is used.  Synchronous;
+ * ESTATE as for pdc_capture_patches. */
+pdc_status pdc_capture_centroids(pdc_ctx *ctx, uint64_t batch, float t_nb, const float *eta_dev, int32_t nbins,
+                                 float *positions_dev, uint64_t capacity, int32_t only_implausible, uint64_t *n_out);
+
 /* Masked 3x3 centroid of each patch: s = (v > t_nb ? v : 0) over the central
  * 3x3 pixels; dy = sum(s*dr) / sum(s), dx = sum(s*dc) / sum(s), the sums in
  * row-major order from +0.0f, IEEE binary32, (0, 0) when sum(s) == 0.
@@ -518,8 +531,12 @@ typedef struct {
  * positions of every hit, from the batch's patches (the detector must keep
  * PDC_KEEP_CORRECTED or PDC_KEEP_MEDIANS). */
 #define PDC_SERVE_SUBPIXEL_NONE 0
-#define PDC_SERVE_SUBPIXEL_MLP 1       /* pdc_mlp_infer with the config's network */
-#define PDC_SERVE_SUBPIXEL_CENTROID 2  /* pdc_centroid, eta-corrected when the config has a table */
+#define PDC_SERVE_SUBPIXEL_MLP 1       /* the config's network on each hit's inputs (pdc_capture_inputs,
+                                          pdc_mlp_infer_inputs) */
+#define PDC_SERVE_SUBPIXEL_CENTROID 2  /* pdc_capture_centroids, eta-corrected when the config has a table */
+#define PDC_SERVE_SUBPIXEL_MLP_FALLBACK 3  /* the network, then the centroid (eta-corrected when the config
+                                              has a table) in place of every position that is not finite
+                                              or outside [-1, 1] (pdc_capture_centroids' fallback) */
 
 typedef struct {
     int32_t det;                 /* detector id from pdc_calibrate */
@@ -549,9 +566,10 @@ typedef struct {
     uint64_t hbm_budget;         /* bytes of in-flight batches over all streams (0: none), each
                                     charged pdc_batch_bytes plus its patches and positions;
                                     a stream with nothing in flight may always launch */
-    pdc_mlp *net;                /* network of PDC_SERVE_SUBPIXEL_MLP streams, or NULL */
-    const float *eta_dev;        /* eta table of PDC_SERVE_SUBPIXEL_CENTROID streams (float32
-                                    [2][eta_bins + 1] from pdc_eta_table), or NULL: plain centroid */
+    pdc_mlp *net;                /* network of PDC_SERVE_SUBPIXEL_MLP(_FALLBACK) streams, or NULL */
+    const float *eta_dev;        /* eta table of the centroid of PDC_SERVE_SUBPIXEL_CENTROID and
+                                    _MLP_FALLBACK streams (float32 [2][eta_bins + 1] from
+                                    pdc_eta_table), or NULL: plain centroid */
     int32_t eta_bins;
 } pdc_serve_config;
 

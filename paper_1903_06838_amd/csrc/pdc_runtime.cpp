@@ -1754,6 +1754,27 @@ namespace {
 // The network's input scale 1/photon_adu, rounded once to binary32.
 float inv_adu_of(float photon_adu) { return (float)(1.0 / (double)photon_adu); }
 
+// Where a batch's Frames2 values are formed again from (kept medians or
+// thresholded-mean stage values).
+PatchSrc patch_src(const Detector &d, const Batch &bt)
+{
+    PatchSrc ps{};
+    ps.frames = bt.frames;
+    ps.ped = d.d_ped;
+    ps.k = d.d_k;
+    ps.T = d.g.n_tiles;
+    ps.H = d.g.rows;
+    ps.W = d.g.cols;
+    ps.B = d.g.bank_cols;
+    ps.nb = d.g.cols / d.g.bank_cols;
+    ps.gain_mode = d.g.gain_mode;
+    ps.meds = d.p.cm_mode ? nullptr : bt.buf->meds;
+    ps.cm = d.p.cm_mode ? bt.buf->cm : nullptr;
+    ps.cm_regions = d.cm_regions;
+    ps.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
+    return ps;
+}
+
 // Patches (float32, patches != NULL) or network inputs (bf16 words) of the
 // batch's first min(total, capacity) hits.
 pdc_status capture(pdc_ctx *ctx, uint64_t batch, float *patches, uint16_t *inputs, float inv_adu, uint64_t capacity,
@@ -1776,22 +1797,8 @@ pdc_status capture(pdc_ctx *ctx, uint64_t batch, float *patches, uint16_t *input
         HIP_TRY(ctx, launch_capture_patches(b->corrected, b->hits, b->frame_offset, bt->n_frames, n, d.g.n_tiles,
                                             d.g.rows, d.g.cols, patches, inputs, inv_adu, cs));
     } else {
-        PatchSrc ps{};
-        ps.frames = bt->frames;
-        ps.ped = d.d_ped;
-        ps.k = d.d_k;
-        ps.T = d.g.n_tiles;
-        ps.H = d.g.rows;
-        ps.W = d.g.cols;
-        ps.B = d.g.bank_cols;
-        ps.nb = d.g.cols / d.g.bank_cols;
-        ps.gain_mode = d.g.gain_mode;
-        ps.meds = d.p.cm_mode ? nullptr : b->meds;
-        ps.cm = d.p.cm_mode ? b->cm : nullptr;
-        ps.cm_regions = d.cm_regions;
-        ps.cm_tile = d.p.cm_mode == PDC_CM_TILE_MEAN;
-        HIP_TRY(ctx, launch_patches_from_frames(ps, b->hits, b->frame_offset, bt->n_frames, n, patches, inputs,
-                                                inv_adu, cs));
+        HIP_TRY(ctx, launch_patches_from_frames(patch_src(d, *bt), b->hits, b->frame_offset, bt->n_frames, n, patches,
+                                                inputs, inv_adu, cs));
     }
     HIP_TRY(ctx, hipStreamSynchronize(cs));
     if (n_out) *n_out = n;
@@ -1816,6 +1823,32 @@ pdc_status pdc_capture_inputs(pdc_ctx *ctx, uint64_t batch, float photon_adu, ui
     if (capacity > 0 && !inputs_dev) return fail(ctx, PDC_EINVAL, "inputs_dev is NULL with capacity > 0");
     if (!finite_in(photon_adu, 0x1p-24f, 0x1p24f)) return fail(ctx, PDC_EINVAL, "photon_adu must be in [2^-24, 2^24]");
     return capture(ctx, batch, nullptr, inputs_dev, inv_adu_of(photon_adu), capacity, n_out);
+}
+
+pdc_status pdc_capture_centroids(pdc_ctx *ctx, uint64_t batch, float t_nb, const float *eta_dev, int32_t nbins,
+                                 float *positions_dev, uint64_t capacity, int32_t only_implausible, uint64_t *n_out)
+{
+    if (!ctx) return fail(nullptr, PDC_EINVAL, "ctx is NULL");
+    if (capacity > 0 && !positions_dev) return fail(ctx, PDC_EINVAL, "positions_dev is NULL with capacity > 0");
+    if (!std::isfinite(t_nb)) return fail(ctx, PDC_EINVAL, "t_nb must be finite");
+    if (eta_dev && (nbins < 1 || nbins > 65536)) return fail(ctx, PDC_EINVAL, "nbins must be in [1, 65536]");
+    Batch *bt = find_batch(ctx, batch);
+    if (!bt) return fail(ctx, PDC_ESTATE, "unknown batch %llu", (unsigned long long)batch);
+    if (!bt->keep && !bt->meds)
+        return fail(ctx, PDC_ESTATE, "batch was processed with neither PDC_KEEP_CORRECTED nor PDC_KEEP_MEDIANS");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    pdc_status rc = finish_batch(ctx, *bt);
+    if (rc != PDC_OK) return rc;
+    const Detector &d = ctx->dets[bt->det];
+    Buffers *b = bt->buf;
+    hipStream_t cs = ctx->copy_stream;
+    HIP_TRY(ctx, hipStreamWaitEvent(cs, b->ev_end, 0));
+    const uint64_t n = std::min<uint64_t>(b->host_state->total, capacity);
+    HIP_TRY(ctx, launch_centroids(patch_src(d, *bt), bt->keep ? b->corrected : nullptr, b->hits, b->frame_offset,
+                                  bt->n_frames, n, t_nb, eta_dev, nbins, only_implausible ? 1 : 0, positions_dev, cs));
+    HIP_TRY(ctx, hipStreamSynchronize(cs));
+    if (n_out) *n_out = n;
+    return PDC_OK;
 }
 
 pdc_status pdc_mlp_make_inputs(pdc_ctx *ctx, const float *patches_dev, uint64_t n, float photon_adu,

@@ -32,10 +32,11 @@ struct InFlight {
     hipEvent_t done = nullptr;
 };
 
-// Device bytes a hit's subpixel input takes: network inputs or a patch.
+// Device bytes a hit's subpixel input takes: network inputs, or none for the
+// centroid (computed from the batch directly).
 uint64_t subpixel_bytes(int32_t subpixel)
 {
-    return subpixel == PDC_SERVE_SUBPIXEL_MLP ? PDC_MLP_INPUT_WORDS * sizeof(uint16_t) : 25 * sizeof(float);
+    return subpixel == PDC_SERVE_SUBPIXEL_CENTROID ? 0 : PDC_MLP_INPUT_WORDS * sizeof(uint16_t);
 }
 
 struct StreamState {
@@ -96,8 +97,9 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
         pdc_serve_stream &d = streams[s];
         if (d.n_frames > 0 && (!d.pool_dev || d.pool_frames == 0 || !d.arrival_ns || !d.results)) return PDC_EINVAL;
         if (d.pixels_per_frame == 0) return PDC_EINVAL;
-        if (d.subpixel < PDC_SERVE_SUBPIXEL_NONE || d.subpixel > PDC_SERVE_SUBPIXEL_CENTROID) return PDC_EINVAL;
-        if (d.subpixel == PDC_SERVE_SUBPIXEL_MLP && !cfg->net) return PDC_EINVAL;
+        if (d.subpixel < PDC_SERVE_SUBPIXEL_NONE || d.subpixel > PDC_SERVE_SUBPIXEL_MLP_FALLBACK) return PDC_EINVAL;
+        if ((d.subpixel == PDC_SERVE_SUBPIXEL_MLP || d.subpixel == PDC_SERVE_SUBPIXEL_MLP_FALLBACK) && !cfg->net)
+            return PDC_EINVAL;
         for (uint64_t i = 1; i < d.n_frames; ++i)
             if (d.arrival_ns[i] < d.arrival_ns[i - 1]) return PDC_EINVAL;
         S[s].d = &d;
@@ -135,29 +137,39 @@ pdc_status pdc_serve_run(pdc_ctx *ctx, pdc_serve_stream *streams, int32_t n_stre
         const uint64_t kept = std::min(total, cap);
         for (uint64_t j = 0; j < kept; ++j) dst[j].frame += (uint32_t)b.first;  // stream frame index
         if (st.d->subpixel && total > 0) {
-            // positions of all the batch's hits; those of the kept hits are copied out
-            // the learned stage takes the network's inputs (64 bytes a hit),
-            // the centroid the float32 patches (100 bytes)
-            const bool mlp = st.d->subpixel == PDC_SERVE_SUBPIXEL_MLP;
+            // positions of all the batch's hits; those of the kept hits are copied out.
+            // The learned stage takes the network's inputs (64 bytes a hit); the
+            // centroid is computed from the batch directly, and with the fallback
+            // it replaces the network's implausible positions.
+            const int32_t mode = st.d->subpixel;
             if (total > st.cap) {
                 hipFree(st.patches);
                 hipFree(st.pos);
                 st.patches = nullptr;
                 st.pos = nullptr;
                 st.cap = 0;
-                if (hipMalloc(&st.patches, total * subpixel_bytes(st.d->subpixel)) != hipSuccess ||
+                const uint64_t in_bytes = total * subpixel_bytes(mode);
+                if ((in_bytes && hipMalloc(&st.patches, in_bytes) != hipSuccess) ||
                     hipMalloc((void **)&st.pos, total * 2 * sizeof(float)) != hipSuccess)
                     return PDC_ENOMEM;
                 st.cap = total;
             }
             uint64_t np = 0;
-            r = mlp ? pdc_capture_inputs(ctx, b.batch, st.d->photon_adu, static_cast<uint16_t *>(st.patches), total, &np)
-                    : pdc_capture_patches(ctx, b.batch, static_cast<float *>(st.patches), total, &np);
-            if (r < 0) return r;
-            r = mlp ? pdc_mlp_infer_inputs(cfg->net, static_cast<const uint16_t *>(st.patches), np, st.pos, st.ss)
-                    : pdc_centroid(ctx, static_cast<const float *>(st.patches), np, st.d->t_nb, cfg->eta_dev,
-                                   cfg->eta_bins, st.pos, st.ss);
-            if (r < 0) return r;
+            if (mode == PDC_SERVE_SUBPIXEL_CENTROID) {
+                r = pdc_capture_centroids(ctx, b.batch, st.d->t_nb, cfg->eta_dev, cfg->eta_bins, st.pos, total, 0, &np);
+                if (r < 0) return r;
+            } else {
+                r = pdc_capture_inputs(ctx, b.batch, st.d->photon_adu, static_cast<uint16_t *>(st.patches), total, &np);
+                if (r < 0) return r;
+                r = pdc_mlp_infer_inputs(cfg->net, static_cast<const uint16_t *>(st.patches), np, st.pos, st.ss);
+                if (r < 0) return r;
+                if (mode == PDC_SERVE_SUBPIXEL_MLP_FALLBACK) {
+                    if (hipStreamSynchronize(st.ss) != hipSuccess) return PDC_EDEVICE;
+                    r = pdc_capture_centroids(ctx, b.batch, st.d->t_nb, cfg->eta_dev, cfg->eta_bins, st.pos, np, 1,
+                                              nullptr);
+                    if (r < 0) return r;
+                }
+            }
             if (st.d->positions && kept > 0 &&
                 hipMemcpyAsync(st.d->positions + 2 * st.hits_written, st.pos, kept * 2 * sizeof(float),
                                hipMemcpyDeviceToHost, st.ss) != hipSuccess)

@@ -65,6 +65,12 @@ struct PatchSrc {
 hipError_t launch_patches_from_frames(const PatchSrc &a, const uint2 *hits, const unsigned long long *frame_offset,
                                       uint64_t n_frames, uint64_t n, float *patches, uint16_t *inputs, float inv_adu,
                                       hipStream_t s);
+// Centroid (+ eta) positions of the first n hits of a batch, from Frames2
+// (corrected != NULL) or formed again from the frames (a); only_bad: replace
+// only the positions in pos that are not finite or outside [-1, 1].
+hipError_t launch_centroids(const PatchSrc &a, const float *corrected, const uint2 *hits,
+                            const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, float t_nb,
+                            const float *eta, int nbins, int only_bad, float *pos, hipStream_t s);
 // The network's inputs of n float32 patches.
 hipError_t launch_make_inputs(const float *patches, uint64_t n, float inv_adu, uint16_t *inputs, hipStream_t s);
 hipError_t launch_mfma_probe(const uint16_t *A, const uint16_t *B, float *D, hipStream_t s);

@@ -898,9 +898,30 @@ hipError_t launch_capture_patches(const float *corrected, const uint2 *hits, con
     return hipGetLastError();
 }
 
+// Frames2 of pixel (rr, cc) of tile t of frame lo, formed again from its raw
+// word, the calibration and the kept common-mode values by the frame
+// kernels' operations (an invalid gain code gives +0).
+__device__ __forceinline__ float frames2_at(const PatchSrc &a, uint64_t lo, int t, int rr, int cc)
+{
+    const int H = a.H, W = a.W;
+    const uint64_t HW = (uint64_t)H * W, npix = (uint64_t)a.T * HW;
+    const uint64_t q = (uint64_t)t * HW + (uint64_t)rr * W + cc;
+    const uint32_t w = a.frames[lo * npix + q];
+    bool bad = false;
+    const float u = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, a.ped[q], a.k[q], a.ped, a.k, npix, q, bad)
+                                : dark_gain(w, a.ped[q], a.k[q]);
+    const uint32_t grow = (uint32_t)(t * H + rr);
+    if (a.meds) {
+        const float m = a.meds[lo * (uint64_t)a.T * H * a.nb + (uint64_t)grow * a.nb + cc / a.B];
+        return bad ? 0.0f : __fsub_rn(u, m);  // invalid: fl(m - m) = +0
+    }
+    const uint32_t reg = a.cm_tile ? (uint32_t)t : grow * (uint32_t)a.nb + (uint32_t)(cc / a.B);
+    const float *cv = a.cm + (lo * a.cm_regions + reg) * 3;
+    return bad ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, cv[0]), cv[1]), cv[2]);
+}
+
 // The same patches without Frames2: each window pixel's Frames2 value formed
-// again from its raw word, the calibration and the kept common-mode values,
-// by the frame kernels' operations (invalid gain codes give +0).
+// again (frames2_at).
 __global__ void patches_from_frames_kernel(PatchSrc a, const uint2 *hits, const unsigned long long *frame_offset,
                                            uint64_t n_frames, uint64_t n, float *patches, uint16_t *inputs,
                                            float inv_adu)
@@ -909,38 +930,70 @@ __global__ void patches_from_frames_kernel(PatchSrc a, const uint2 *hits, const 
     if (i >= n) return;
     const uint64_t lo = hit_frame(frame_offset, n_frames, i);
     const int H = a.H, W = a.W;
-    const uint64_t HW = (uint64_t)H * W, npix = (uint64_t)a.T * HW;
     const uint32_t p = hits[i].x;
     const int c = (int)(p % (uint32_t)W);
     const int rt = (int)(p / (uint32_t)W);
     const int t = rt / H, r = rt - t * H;
-    const uint16_t *fr = a.frames + lo * npix;
     float out[25];
 #pragma unroll
     for (int dr = -2; dr <= 2; ++dr)
 #pragma unroll
         for (int dc = -2; dc <= 2; ++dc) {
             const int rr = r + dr, cc = c + dc;
-            float v = 0.0f;
-            if (rr >= 0 && rr < H && cc >= 0 && cc < W) {
-                const uint64_t q = (uint64_t)t * HW + (uint64_t)rr * W + cc;
-                const uint32_t w = fr[q];
-                bool bad = false;
-                const float u = a.gain_mode ? dark_gain_ranged(w, a.gain_mode, a.ped[q], a.k[q], a.ped, a.k, npix, q, bad)
-                                            : dark_gain(w, a.ped[q], a.k[q]);
-                const uint32_t grow = (uint32_t)(t * H + rr);
-                if (a.meds) {
-                    const float m = a.meds[lo * (uint64_t)a.T * H * a.nb + (uint64_t)grow * a.nb + cc / a.B];
-                    v = bad ? 0.0f : __fsub_rn(u, m);  // invalid: fl(m - m) = +0
-                } else {
-                    const uint32_t reg = a.cm_tile ? (uint32_t)t : grow * (uint32_t)a.nb + (uint32_t)(cc / a.B);
-                    const float *cv = a.cm + (lo * a.cm_regions + reg) * 3;
-                    v = bad ? 0.0f : __fsub_rn(__fsub_rn(__fsub_rn(u, cv[0]), cv[1]), cv[2]);
-                }
-            }
-            out[(dr + 2) * 5 + dc + 2] = v;
+            out[(dr + 2) * 5 + dc + 2] = (rr >= 0 && rr < H && cc >= 0 && cc < W) ? frames2_at(a, lo, t, rr, cc) : 0.0f;
         }
     store_patch(out, i, patches, inputs, inv_adu);
+}
+
+// Classical positions straight from a batch: the masked 3x3 centroid of each
+// hit (eta-corrected when eta is not NULL) from its Frames2 values, read from
+// corrected when Frames2 was kept, else formed again (frames2_at); the same
+// arithmetic as centroid_eta_kernel on the hit's patch.  only_bad: pos holds
+// positions already (the learned estimator's) and only those that are not
+// finite or outside [-1, 1] in a coordinate are replaced.
+__global__ void centroids_kernel(PatchSrc a, const float *corrected, const uint2 *hits,
+                                 const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, float t_nb,
+                                 const float *eta, int nbins, int only_bad, float *pos)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (only_bad && fabsf(pos[2 * i]) <= 1.0f && fabsf(pos[2 * i + 1]) <= 1.0f) return;  // NaN is replaced
+    const uint64_t lo = hit_frame(frame_offset, n_frames, i);
+    const int H = a.H, W = a.W;
+    const uint32_t p = hits[i].x;
+    const int c = (int)(p % (uint32_t)W);
+    const int rt = (int)(p / (uint32_t)W);
+    const int t = rt / H, r = rt - t * H;
+    float v[25];
+#pragma unroll
+    for (int e = 0; e < 25; ++e) v[e] = 0.0f;
+#pragma unroll
+    for (int dr = -1; dr <= 1; ++dr)
+#pragma unroll
+        for (int dc = -1; dc <= 1; ++dc) {
+            const int rr = r + dr, cc = c + dc;
+            if (rr >= 0 && rr < H && cc >= 0 && cc < W)
+                v[(dr + 2) * 5 + dc + 2] = corrected ? corrected[((lo * a.T + t) * H + rr) * (uint64_t)W + cc]
+                                                     : frames2_at(a, lo, t, rr, cc);
+        }
+    float cy, cx;
+    centroid3(v, t_nb, cy, cx);
+    if (eta) {
+        cy = eta_map(eta, nbins, cy);
+        cx = eta_map(eta + nbins + 1, nbins, cx);
+    }
+    pos[2 * i] = cy;
+    pos[2 * i + 1] = cx;
+}
+
+hipError_t launch_centroids(const PatchSrc &a, const float *corrected, const uint2 *hits,
+                            const unsigned long long *frame_offset, uint64_t n_frames, uint64_t n, float t_nb,
+                            const float *eta, int nbins, int only_bad, float *pos, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(centroids_kernel, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, s, a, corrected, hits,
+                       frame_offset, n_frames, n, t_nb, eta, nbins, only_bad, pos);
+    return hipGetLastError();
 }
 
 hipError_t launch_patches_from_frames(const PatchSrc &a, const uint2 *hits, const unsigned long long *frame_offset,

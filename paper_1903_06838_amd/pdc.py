@@ -81,6 +81,8 @@ _sig = {
     "pdc_capture_inputs": (_st, [_P, ctypes.c_uint64, ctypes.c_float, _P, ctypes.c_uint64,
                                  ctypes.POINTER(ctypes.c_uint64)]),
     "pdc_mlp_make_inputs": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, _P, _P]),
+    "pdc_capture_centroids": (_st, [_P, ctypes.c_uint64, ctypes.c_float, _P, ctypes.c_int32, _P, ctypes.c_uint64,
+                                    ctypes.c_int32, ctypes.POINTER(ctypes.c_uint64)]),
     "pdc_mlp_infer_inputs": (_st, [_P, _P, ctypes.c_uint64, _P, _P]),
     "pdc_centroid": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, _P, ctypes.c_int32, _P, _P]),
     "pdc_eta_table": (_st, [_P, _P, ctypes.c_uint64, ctypes.c_float, ctypes.c_int32, _P, _P, _P]),
@@ -396,6 +398,15 @@ def capture_inputs(ctx, batch: int, photon_adu: float, inputs_dev, capacity: int
     return n.value
 
 
+def capture_centroids(ctx, batch: int, t_nb: float, positions_dev, capacity: int, eta_dev=None, nbins: int = 0,
+                      only_implausible: bool = False) -> int:
+    """Centroid (+ eta) positions of the batch's first hits, or the fallback for implausible ones; returns the count."""
+    n = ctypes.c_uint64(0)
+    _check(_lib.pdc_capture_centroids(ctx, batch, t_nb, _ptr(eta_dev), nbins, _ptr(positions_dev), capacity,
+                                      1 if only_implausible else 0, ctypes.byref(n)), ctx)
+    return n.value
+
+
 def mlp_make_inputs(ctx, patches_dev, n: int, photon_adu: float, inputs_dev, stream=None) -> None:
     _check(_lib.pdc_mlp_make_inputs(ctx, _ptr(patches_dev), n, photon_adu, _ptr(inputs_dev), _stream(stream)), ctx)
 
@@ -499,7 +510,7 @@ class ServeSummary(ctypes.Structure):
                 ("peak_bytes", ctypes.c_uint64), ("wall_ns", ctypes.c_uint64)]
 
 
-SERVE_SUBPIXEL_NONE, SERVE_SUBPIXEL_MLP, SERVE_SUBPIXEL_CENTROID = 0, 1, 2
+SERVE_SUBPIXEL_NONE, SERVE_SUBPIXEL_MLP, SERVE_SUBPIXEL_CENTROID, SERVE_SUBPIXEL_MLP_FALLBACK = 0, 1, 2, 3
 
 
 def serve_run(ctx, streams, max_batch=64, max_inflight=2, max_queue=0, hbm_budget=0, net=None, eta_dev=None,

@@ -153,19 +153,25 @@ def test_batch_bytes_counts_the_kept_buffers(ctx, detectors):
         pdc.batch_bytes(ctx, 9999, 1, 10)
 
 
-@pytest.mark.parametrize("stage", ["centroid", "mlp"])
+@pytest.mark.parametrize("stage", ["centroid", "mlp", "mlp_fallback"])
 def test_subpixel_stage(ctx, detectors, stage):
     """Every kept hit of every served frame gets its position: the masked
     centroid equals the oracle's on the oracle's patches bit for bit; the
     learned estimator equals pdc_mlp_infer on the oracle's patches bit for
-    bit (the same patches, hence the same bfloat16 products)."""
+    bit (the same patches, hence the same bfloat16 products); with the
+    fallback, positions outside [-1, 1] (output biases push some there) are
+    the oracle's centroids and the others the network's."""
     import torch
 
     from paper_1903_06838_amd import pdc
 
     theta = S.init_params(5)
-    net = pdc.mlp_create(ctx, theta) if stage == "mlp" else None
-    sp = pdc.SERVE_SUBPIXEL_MLP if stage == "mlp" else pdc.SERVE_SUBPIXEL_CENTROID
+    if stage == "mlp_fallback":
+        theta = theta.copy()
+        theta[-2:] = (0.9, -0.9)  # b3
+    net = pdc.mlp_create(ctx, theta) if stage != "centroid" else None
+    sp = {"centroid": pdc.SERVE_SUBPIXEL_CENTROID, "mlp": pdc.SERVE_SUBPIXEL_MLP,
+          "mlp_fallback": pdc.SERVE_SUBPIXEL_MLP_FALLBACK}[stage]
     try:
         ns = (25, 20, 15, 12)
         streams = [dict(det=d["det"], pool=d["pool"], arrival_ns=_arrivals(n, 10000.0, 11 + j), hit_fraction=0.05,
@@ -181,6 +187,16 @@ def test_subpixel_stage(ctx, detectors, stage):
             assert len(want_p) == len(h) == len(p) > 0
             if stage == "centroid":
                 want = S.centroid(want_p.reshape(-1, 5, 5), T_NB)
+            elif stage == "mlp_fallback":
+                out = torch.empty((len(want_p), 2), dtype=torch.float32, device="cuda")
+                pd = torch.from_numpy(want_p).cuda()
+                torch.cuda.synchronize()
+                pdc.mlp_infer(net, pd, len(want_p), ADU, out)
+                torch.cuda.synchronize()
+                y = out.cpu().numpy()
+                ok = np.all(np.abs(y) <= 1.0, axis=1)
+                assert 0 < ok.sum() < len(ok)
+                want = np.where(ok[:, None], y, np.asarray(S.centroid(want_p.reshape(-1, 5, 5), T_NB), np.float32))
             else:
                 out = torch.empty((len(want_p), 2), dtype=torch.float32, device="cuda")
                 pd = torch.from_numpy(want_p).cuda()

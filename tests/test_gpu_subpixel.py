@@ -506,6 +506,63 @@ def test_capture_patches_from_kept_medians(ctx, geom, gm, cm, stages, occ, n, ge
     assert np.all(x2[n2:] == 0xFFFF)
 
 
+@pytest.mark.parametrize("flag", ["corrected", "medians"])
+def test_capture_centroids_and_fallback(ctx, flag):
+    """Centroids straight from a batch equal pdc_centroid on the batch's
+    captured patches bit for bit, plain and eta-corrected; with
+    only_implausible, positions that are finite and inside [-1, 1] stay and the
+    others become the classical ones."""
+    import torch
+
+    from paper_1903_06838_amd import pdc
+
+    geom = synth.Geometry(2, 40, 388, 194)
+    ped, gain = synth.make_calibration(geom, 37)
+    raw = synth.make_frames(geom, ped, gain, 3, 0.02, 37)
+    fl = pdc.KEEP_CORRECTED if flag == "corrected" else pdc.KEEP_MEDIANS
+    det = pdc.calibrate(ctx, pdc.geometry(*geom.shape, geom.bank_cols), ped, gain, pdc.params(flags=fl))
+    nb = 64
+    try:
+        frames = _dev(raw)
+        b = pdc.process_frames(ctx, det, frames, raw.shape[0], 200000)
+        _, total, _, _, _ = pdc.get_hits(ctx, b, raw.shape[0], capacity=0)
+        P = torch.zeros((total, 25), dtype=torch.float32, device="cuda")
+        table = torch.zeros((2, nb + 1), dtype=torch.float32, device="cuda")
+        ws = torch.zeros(2 * nb, dtype=torch.int32, device="cuda")
+        c0 = torch.zeros((total, 2), dtype=torch.float32, device="cuda")
+        c1 = torch.zeros((total, 2), dtype=torch.float32, device="cuda")
+        g0 = torch.full((total, 2), -9.0, dtype=torch.float32, device="cuda")
+        g1 = torch.full((total, 2), -9.0, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        assert pdc.capture_patches(ctx, b, P, total) == total > 100
+        pdc.eta_table(ctx, P, total, T_NB, nb, ws, table)
+        pdc.centroid(ctx, P, total, T_NB, c0)
+        pdc.centroid(ctx, P, total, T_NB, c1, eta_dev=table, nbins=nb)
+        torch.cuda.synchronize()
+        assert pdc.capture_centroids(ctx, b, T_NB, g0, total) == total
+        assert pdc.capture_centroids(ctx, b, T_NB, g1, total, eta_dev=table, nbins=nb) == total
+        # fallback: a pattern of plausible and implausible positions
+        rng = np.random.default_rng(3)
+        pos = rng.uniform(-1.0, 1.0, size=(total, 2)).astype(F32)
+        bad = rng.random(total) < 0.3
+        pos[bad, rng.integers(0, 2, size=bad.sum())] = rng.choice(
+            np.array([np.nan, np.inf, -np.inf, 1.0001, -3.0], F32), size=bad.sum())
+        pos[0] = (1.0, -1.0)  # on the bounds: kept
+        g2 = _dev(pos)
+        torch.cuda.synchronize()
+        assert pdc.capture_centroids(ctx, b, T_NB, g2, total, eta_dev=table, nbins=nb, only_implausible=True) == total
+        torch.cuda.synchronize()
+        pdc.release_batch(ctx, b)
+    finally:
+        pdc.release_detector(ctx, det)
+    assert np.array_equal(_bits(g0.cpu().numpy()), _bits(c0.cpu().numpy()))
+    assert np.array_equal(_bits(g1.cpu().numpy()), _bits(c1.cpu().numpy()))
+    keep = np.all(np.abs(pos) <= 1.0, axis=1)
+    want = np.where(keep[:, None], pos, c1.cpu().numpy())
+    assert 0 < keep.sum() < total and keep[0]
+    assert np.array_equal(_bits(g2.cpu().numpy()), _bits(want))
+
+
 def test_capture_patches_needs_a_kept_buffer(ctx):
     from paper_1903_06838_amd import pdc
 
