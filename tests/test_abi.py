@@ -135,6 +135,7 @@ def test_null_context_paths(pdc):
     assert lib.pdc_graph_items(None) == 0
     assert lib.pdc_stream_read(None, None, 16, None, None) == pdc.EINVAL
     assert lib.pdc_capture_inputs(None, 1, 150.0, None, 0, None) == pdc.EINVAL
+    assert lib.pdc_capture_centroids(None, 1, 9.0, None, 0, None, 0, 0, None) == pdc.EINVAL
     assert lib.pdc_mlp_make_inputs(None, None, 0, 150.0, None, None) == pdc.EINVAL
     assert lib.pdc_mlp_infer_inputs(None, None, 0, None, None) == pdc.EINVAL
     assert lib.pdc_autotune_strips(None, 0, None, 1, 0, None, None, None, None, None) == pdc.EINVAL
