@@ -2074,10 +2074,8 @@ pdc_status pdc_mlp_train_step(pdc_mlp *net, const float *patches_dev, const floa
     if (!(std::isfinite(lr) && lr >= 0.0f)) return fail(ctx, PDC_EINVAL, "lr must be finite and >= 0");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
-    HIP_TRY(ctx, launch_mlp_grad(patches_dev, target_dev, n, inv_adu_of(photon_adu), net->theta, net->packed,
-                                 net->grad, net->slots, net->max_grid, s));
-    HIP_TRY(ctx, launch_adam(net->theta, net->m, net->v, net->grad, lr, net->step + 1, s));
-    HIP_TRY(ctx, launch_mlp_pack(net->theta, net->packed, s));
+    HIP_TRY(ctx, launch_mlp_train(patches_dev, target_dev, n, inv_adu_of(photon_adu), net->theta, net->m, net->v,
+                                  net->packed, net->grad, net->slots, net->max_grid, lr, net->step + 1, s));
     HIP_TRY(ctx, hipEventRecord(net->done, s));
     net->step += 1;
     net->last_n = n;

@@ -43,7 +43,12 @@ uint32_t mlp_grad_grid(uint64_t n, uint32_t max_grid);
 hipError_t launch_mlp_grad(const float *patches, const float *target, uint64_t n, float inv_adu,
                            const float *theta, const uint16_t *packed, float *out, float *slots, uint32_t max_grid,
                            hipStream_t s);
-hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, float lr, int64_t step, hipStream_t s);
+// One training step: the gradient of n >= 1 hits into the slots, then one
+// kernel that sums them (grad[0..kMlpParams]), takes the Adam step (step >= 1)
+// and refreshes the packed bf16 weights.
+hipError_t launch_mlp_train(const float *patches, const float *target, uint64_t n, float inv_adu, float *theta,
+                            float *m, float *v, uint16_t *packed, float *grad, float *slots, uint32_t max_grid,
+                            float lr, int64_t step, hipStream_t s);
 // patches float32 [n][25], or, when inputs is not NULL, the network's inputs
 // uint16 [n][kMlpInWords] (bf16 of each value times inv_adu, zero padding)
 hipError_t launch_capture_patches(const float *corrected, const uint2 *hits,

@@ -803,26 +803,66 @@ hipError_t launch_mlp_grad(const float *patches, const float *target, uint64_t n
 //   theta -= (lr (m / c1)) / (sqrt(v / c2) + eps),  c1 = 1 - b1^t, c2 = 1 - b2^t.
 // sqrtf is correctly rounded under -fhip-fp32-correctly-rounded-divide-sqrt;
 // __fsqrt_rn is not used: it maps to the native approximation.
-__global__ void adam_kernel(float *theta, float *m, float *v, const float *grad, int n, float lr, float b1,
-                            float omb1, float b2, float omb2, float eps, float c1, float c2)
+// One training step's update after mlp_grad_kernel, in one kernel: each
+// parameter's gradient summed over the slots in index order (the additions
+// of slot_reduce_kernel, with the loads issued eight ahead), then Adam as
+// above, then the bf16 copies of the new value in every packed layout
+// (the packing's zero padding is never written).  grad also receives the
+// sums (the loss term at kMlpParams).
+__global__ void mlp_update_kernel(const float *slots, uint32_t n_slots, float *grad, float *theta, float *m, float *v,
+                                  float lr, float b1, float omb1, float b2, float omb2, float eps, float c1, float c2,
+                                  uint16_t *pk)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float g = grad[i];
-    const float mi = __fadd_rn(__fmul_rn(b1, m[i]), __fmul_rn(omb1, g));
-    const float vi = __fadd_rn(__fmul_rn(b2, v[i]), __fmul_rn(__fmul_rn(omb2, g), g));
-    m[i] = mi;
-    v[i] = vi;
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p > kMlpParams) return;
+    float s = 0.0f;
+    uint32_t i = 0;
+    for (; i + 8 <= n_slots; i += 8) {
+        float t[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t[j] = slots[(uint64_t)(i + j) * kMlpSlotStride + p];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s += t[j];
+    }
+    for (; i < n_slots; ++i) s += slots[(uint64_t)i * kMlpSlotStride + p];
+    grad[p] = s;
+    if (p == kMlpParams) return;
+    const float g = s;
+    const float mi = __fadd_rn(__fmul_rn(b1, m[p]), __fmul_rn(omb1, g));
+    const float vi = __fadd_rn(__fmul_rn(b2, v[p]), __fmul_rn(__fmul_rn(omb2, g), g));
+    m[p] = mi;
+    v[p] = vi;
     const float step = __fdiv_rn(__fmul_rn(lr, __fdiv_rn(mi, c1)), __fadd_rn(sqrtf(__fdiv_rn(vi, c2)), eps));
-    theta[i] = __fsub_rn(theta[i], step);
+    const float th = __fsub_rn(theta[p], step);
+    theta[p] = th;
+    const uint16_t b = f2bf(th);
+    if (p < kOffB1) {  // W1[k][c]
+        const int k = p / 64, c = p % 64;
+        pk[kPackW1t + c * 32 + k] = b;
+    } else if (p >= kOffW2 && p < kOffB2) {  // W2[k][c]
+        const int q = p - kOffW2, k = q / 64, c = q % 64;
+        pk[kPackW2t + c * 64 + k] = b;
+        pk[kPackW2 + q] = b;
+    } else if (p >= kOffW3 && p < kOffB3) {  // W3[k][c]
+        const int q = p - kOffW3, k = q / 2, c = q % 2;
+        pk[kPackW3t + c * 64 + k] = b;
+        pk[kPackW3p + k * 32 + c] = b;
+    }
 }
 
-hipError_t launch_adam(float *theta, float *m, float *v, const float *grad, float lr, int64_t step, hipStream_t s)
+hipError_t launch_mlp_train(const float *patches, const float *target, uint64_t n, float inv_adu, float *theta,
+                            float *m, float *v, uint16_t *packed, float *grad, float *slots, uint32_t max_grid,
+                            float lr, int64_t step, hipStream_t s)
 {
+    if (n == 0) return hipErrorInvalidValue;
+    const uint32_t grid = mlp_grad_grid(n, max_grid);
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(grid), dim3(64 * kWaves), 0, s, patches, target, n, inv_adu,
+                       (float)(1.0 / (double)n), theta, packed, slots);
     const double b1 = 0.9, b2 = 0.999;
     const float c1 = (float)(1.0 - pow(b1, (double)step)), c2 = (float)(1.0 - pow(b2, (double)step));
-    hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, theta, m, v, grad, kMlpParams,
-                       lr, (float)b1, (float)(1.0 - b1), (float)b2, (float)(1.0 - b2), 1e-8f, c1, c2);
+    hipLaunchKernelGGL(mlp_update_kernel, dim3((kMlpParams + 256) / 256), dim3(256), 0, s, slots,
+                       grid * (uint32_t)kWaves, grad, theta, m, v, lr, (float)b1, (float)(1.0 - b1), (float)b2,
+                       (float)(1.0 - b2), 1e-8f, c1, c2, packed);
     return hipGetLastError();
 }
 

@@ -345,6 +345,13 @@ def test_adam_step_bit_exact(ctx):
             cur, m, v = S.adam(cur, m, v, g, step, F32(lr))
             got = pdc.mlp_get_params(net)
             assert np.array_equal(got.view(np.uint32), cur.view(np.uint32)), step
+        # the bf16 weights the steps refreshed are those of the new parameters
+        out = torch.zeros((len(P), 2), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        pdc.mlp_infer(net, dP, len(P), ADU, out)
+        torch.cuda.synchronize()
+        want, _ = S.mlp_forward(cur, P, ADU, bf16_ops=True)
+        assert np.quantile(np.abs(out.cpu().numpy() - want), 0.99) <= 1e-5
     finally:
         pdc.mlp_destroy(net)
 
