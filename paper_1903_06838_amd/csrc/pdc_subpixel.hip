@@ -473,10 +473,10 @@ __device__ __forceinline__ void mlp_infer_body(const void *src, uint64_t n, floa
     // one).  Loads are issued for tiles past the end too (they read
     // nothing), so that every path waits for the same counts.  Float32 patches:
     // the loop takes the whole tiles, a partial last tile comes after it.
-    constexpr int kDepth = IN16 ? 3 : 1;
+    constexpr int kDepth = 1;
     const uint64_t full = IN16 ? tiles : n / kTile;
-    u32x4 xv[kDepth][IN16 ? 2 : 4];
-    auto load = [&](uint64_t tile, u32x4 (&buf)[IN16 ? 2 : 4]) {
+    u32x4 xv[kDepth][4];
+    auto load = [&](uint64_t tile, auto &buf) {
         if constexpr (IN16)
             load_in_tile(inputs, n, tile * kTile, lane, buf);
         else
@@ -526,24 +526,52 @@ __device__ __forceinline__ void mlp_infer_body(const void *src, uint64_t n, floa
             }
         }
     };
+    if constexpr (IN16) {
+        // two sets of kSet tiles, each loaded while the other is computed: the
+        // set in use was issued before the other on every path, so the waits
+        // for it leave the other's loads in flight
+        constexpr int kSet = 2;
+        u32x4 sa[kSet][2], sb[kSet][2];
 #pragma unroll
-    for (int k = 0; k < kDepth; ++k) load(t + k * stride, xv[k]);
-    for (; t < full; t += kDepth * stride)
+        for (int k = 0; k < kSet; ++k) load(t + k * stride, sa[k]);
+        for (; t < full; t += 2 * kSet * stride) {
 #pragma unroll
-        for (int k = 0; k < kDepth; ++k) {
-            const uint64_t tk = t + k * stride;
-            if (tk >= full) break;
-            bf16x8 x[2];
-            if constexpr (IN16) {
+            for (int k = 0; k < kSet; ++k) load(t + (kSet + k) * stride, sb[k]);
 #pragma unroll
-                for (int rt = 0; rt < 2; ++rt) x[rt] = __builtin_bit_cast(bf16x8, xv[k][rt] & xmask);
-                load(tk + kDepth * stride, xv[k]);
-            } else {
+            for (int k = 0; k < kSet; ++k) {
+                const uint64_t tk = t + k * stride;
+                if (tk < full) {
+                    const bf16x8 x[2] = {__builtin_bit_cast(bf16x8, sa[k][0] & xmask),
+                                         __builtin_bit_cast(bf16x8, sa[k][1] & xmask)};
+                    forward(tk, x);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < kSet; ++k) load(t + (2 * kSet + k) * stride, sa[k]);
+#pragma unroll
+            for (int k = 0; k < kSet; ++k) {
+                const uint64_t tk = t + (kSet + k) * stride;
+                if (tk < full) {
+                    const bf16x8 x[2] = {__builtin_bit_cast(bf16x8, sb[k][0] & xmask),
+                                         __builtin_bit_cast(bf16x8, sb[k][1] & xmask)};
+                    forward(tk, x);
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < kDepth; ++k) load(t + k * stride, xv[k]);
+        for (; t < full; t += kDepth * stride)
+#pragma unroll
+            for (int k = 0; k < kDepth; ++k) {
+                const uint64_t tk = t + k * stride;
+                if (tk >= full) break;
+                bf16x8 x[2];
                 stage(xv[k], x);
                 load(tk + kDepth * stride, xv[k]);
+                forward(tk, x);
             }
-            forward(tk, x);
-        }
+    }
     if (!IN16 && full < tiles && (uint64_t)blockIdx.x * kInferWaves + wv == full % stride) {
         u32x4 buf[4];
         load_x_part(patches, n, full * kTile, lane, buf);
