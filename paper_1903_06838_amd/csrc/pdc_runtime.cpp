@@ -767,20 +767,29 @@ pdc_status enqueue_mixed(pdc_ctx *ctx, std::vector<Batch *> &bts, hipStream_t s,
                          const std::vector<hipEvent_t> &events)
 {
     const int n_str = (int)streams.size();
+    // the streams forked so far are joined back also after a failure, so that
+    // none is left waiting on (or, under capture, capturing from) s
+    int forked = 0;
     auto fork = [&]() -> pdc_status {
         HIP_TRY(ctx, hipEventRecord(events[0], s));
-        for (int j = 0; j < n_str; ++j) HIP_TRY(ctx, hipStreamWaitEvent(streams[j], events[0], 0));
+        for (; forked < n_str; ++forked) HIP_TRY(ctx, hipStreamWaitEvent(streams[forked], events[0], 0));
         return PDC_OK;
     };
     auto join = [&]() -> pdc_status {
-        for (int j = 0; j < n_str; ++j) {
-            HIP_TRY(ctx, hipEventRecord(events[1 + j], streams[j]));
-            HIP_TRY(ctx, hipStreamWaitEvent(s, events[1 + j], 0));
+        pdc_status r = PDC_OK;
+        for (int j = 0; j < forked; ++j) {
+            hipError_t e = hipEventRecord(events[1 + j], streams[j]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, events[1 + j], 0);
+            if (e != hipSuccess && r == PDC_OK) r = fail(ctx, PDC_EDEVICE, "join: %s", hipGetErrorString(e));
         }
-        return PDC_OK;
+        forked = 0;
+        return r;
     };
     pdc_status rc = fork();
-    if (rc != PDC_OK) return rc;
+    if (rc != PDC_OK) {
+        join();
+        return rc;
+    }
     std::vector<int32_t> dets;
     for (const Batch *bt : bts) dets.push_back(bt->det);
     bool one = mix_one_launch(ctx, dets);
@@ -811,9 +820,9 @@ pdc_status enqueue_mixed(pdc_ctx *ctx, std::vector<Batch *> &bts, hipStream_t s,
     m.first[bts.size()] = first;
     m.n = (int32_t)bts.size();
     HIP_TRY(ctx, launch_frame_kernel_v2_mix(m, lds, s));
-    if ((rc = fork()) != PDC_OK) return rc;
+    rc = fork();
     for (Batch *bt : bts)
-        if ((rc = enqueue_post(ctx, *bt)) != PDC_OK) break;
+        if (rc == PDC_OK) rc = enqueue_post(ctx, *bt);
     rj = join();
     return rc != PDC_OK ? rc : rj;
 }
