@@ -1140,18 +1140,9 @@ __global__ void __launch_bounds__(kV2Threads) __attribute__((amdgpu_waves_per_eu
     const int item = (int)blockIdx.x;
     int d = 0;
     while (d + 1 < M.n && item >= M.first[d + 1]) ++d;
-    // the detector's arguments as opaque scalars: read through a dynamic
-    // index, the compiler would reload fields from the argument memory
-    // inside the frame loop rather than keep them
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(&M.a[d]);
-    uint32_t w[sizeof(V2Args) / 4];
-#pragma unroll
-    for (int i = 0; i < (int)(sizeof(V2Args) / 4); ++i) {
-        w[i] = src[i];
-        asm volatile("" : "+s"(w[i]));
-    }
-    V2Args A;
-    __builtin_memcpy(&A, w, sizeof(V2Args));
+    // fields are read from the argument memory where they are used (scalar
+    // loads, cached): copied into registers up front they would be spilled
+    const V2Args &A = M.a[d];
     const int it = item - M.first[d];
     switch (M.variant[d]) {
     case 0: frame_body<2, 4, 16, 13, false, false, false>(A, it); break;
