@@ -135,9 +135,9 @@ __device__ __forceinline__ float group_estimate(const float (&x)[V], int B)
     static_assert(V >= 3, "the start estimate takes triples of values per lane");
     constexpr int NT = V / 3 < 8 ? V / 3 : 8;
     if (!SPARSE && B >= 3 * L * NT) {  // uniform: every lane's NT triples lie inside the bank
-        float s3 = 0.0f;
+        float s3 = __builtin_amdgcn_fmed3f(x[0], x[1], x[2]);
 #pragma unroll
-        for (int t = 0; t < NT; ++t) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
+        for (int t = 1; t < NT; ++t) s3 += __builtin_amdgcn_fmed3f(x[3 * t], x[3 * t + 1], x[3 * t + 2]);
         return gsum_f<L>(s3) * (1.0f / (float)(NT * L));
     }
     float s3 = 0.0f;
@@ -210,8 +210,9 @@ __device__ __forceinline__ float group_sort_pick(float y, int r)
 // held by an L-lane group (V values per lane, absent values +inf, lane value
 // v also at src[L v] in LDS); every group of the wave searches its own bank
 // at once.  Bracketing search on counts, count(x < lo) <= k < count(x < hi)
-// throughout, with the lane masks of both bounds kept: the first step tests
-// est -/+ 5 rank widths rw together (widening until they bracket), later steps
+// throughout, with the lane masks of both bounds kept: the first bracket is
+// the estimate and a bound placed from its count (widening until they
+// bracket), later steps
 // interpolate the pivot from the bracket counts and bisect in key space when
 // the interpolated pivot is not strictly inside or the bracket stopped
 // halving.  Once at most L values remain in [lo, hi) (the lane's are the bits
@@ -225,14 +226,27 @@ __device__ float group_median(const float (&x)[V], const float *src, int nval, i
 {
     const float est = group_estimate<V, L, SPARSE>(x, B);
 
-    const float w0 = 5.0f * rw;
-    float lo = est - w0, hi = est + w0;
-    uint32_t mlo = lane_mask<V>(x, lo), mhi = lane_mask<V>(x, hi);
+    // First bracket in two counts: the count below the estimate gives its
+    // rank error e, and the second bound goes e + 4 rank widths beyond it on
+    // the side of rank k (the estimate misses by about 5 ranks on these
+    // banks; two bounds placed around it at once missed twice as often)
+    float lo, hi;
+    uint32_t mlo, mhi;
     int clo, chi;
     {
-        const int pk = gsum_i<L>(__popc(mlo) | (__popc(mhi) << 16));
-        clo = pk & 0xFFFF;
-        chi = pk >> 16;
+        const uint32_t m1 = lane_mask<V>(x, est);
+        const int c1 = gsum_i<L>(__popc(m1));
+        const bool up = c1 <= k;  // rank k lies at or above the estimate
+        const float d = (float)((up ? k + 1 - c1 : c1 - k) + 4) * rw;
+        const float p2 = up ? est + d : est - d;
+        const uint32_t m2 = lane_mask<V>(x, p2);
+        const int c2 = gsum_i<L>(__popc(m2));
+        lo = up ? est : p2;
+        hi = up ? p2 : est;
+        mlo = up ? m1 : m2;
+        mhi = up ? m2 : m1;
+        clo = up ? c1 : c2;
+        chi = up ? c2 : c1;
     }
     bool ok = !act || (clo <= k && k < chi);
     // widening: a start bracket that misses by m ranks moves its violated
