@@ -157,6 +157,27 @@ __device__ __forceinline__ float group_estimate(const float (&x)[V], int B)
     return nl > 0 ? ssum * __builtin_amdgcn_rcpf((float)nl) : 0.0f;
 }
 
+// The sides of the compare-exchanges below: e[j] is -inf for a lane whose
+// bit j of its place in the group is clear (it keeps the smaller value of a
+// pair) and +inf otherwise.  Made once per kernel and kept in registers (an
+// opaque copy, so that the compiler does not recompute them per use).
+struct SortSides {
+    float e[4];
+};
+
+template <int L>
+__device__ __forceinline__ SortSides sort_sides()
+{
+    const int gl = __lane_id() & (L - 1);
+    SortSides sd;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        sd.e[j] = (gl >> j) & 1 ? INFINITY : -INFINITY;
+        asm volatile("" : "+v"(sd.e[j]));
+    }
+    return sd;
+}
+
 // Ascending bitonic sort of one value per lane over an aligned L-lane group,
 // then the value of lane r broadcast to the group.  Merges of size 2b start
 // with the mirror partner inside the block, then halve with xor partners; a
@@ -165,13 +186,10 @@ __device__ __forceinline__ float group_estimate(const float (&x)[V], int B)
 // +inf) the larger (no NaN is present).  The pick is an OR over the group of
 // the chosen lane's bits and zeros elsewhere.  All lanes must be active.
 template <int L>
-__device__ __forceinline__ float group_sort_pick(float y, int r)
+__device__ __forceinline__ float group_sort_pick(float y, int r, const SortSides &sd)
 {
     const int gl = __lane_id() & (L - 1);
-    const float e1 = (gl & 1) ? INFINITY : -INFINITY;
-    const float e2 = (gl & 2) ? INFINITY : -INFINITY;
-    const float e4 = (gl & 4) ? INFINITY : -INFINITY;
-    const float e8 = (gl & 8) ? INFINITY : -INFINITY;
+    const float e1 = sd.e[0], e2 = sd.e[1], e4 = sd.e[2], e8 = sd.e[3];
 #define PDC_CX(partner, e) y = __builtin_amdgcn_fmed3f(y, (partner), (e));
 #define PDC_DPP(ctrl) __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), ctrl, 0xF, 0xF, false))
     PDC_CX(PDC_DPP(0xB1), e1)                      // merge 2: mirror (xor 1)
@@ -187,9 +205,9 @@ __device__ __forceinline__ float group_sort_pick(float y, int r)
     if (L >= 16) {
         PDC_CX(PDC_DPP(0x140), e8)                 // merge 16: row_mirror
         {
-            const float dn = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x104, 0xF, 0xF, true));  // row_shl:4
-            const float up = __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(y), 0x114, 0xF, 0xF, true));  // row_shr:4
-            PDC_CX((gl & 4) ? up : dn, e4)         // xor 4
+            // xor 4 = xor 3 (quad mirror) then xor 7 (half-row mirror)
+            const int t = __builtin_amdgcn_mov_dpp(__float_as_int(y), 0x1B, 0xF, 0xF, false);
+            PDC_CX(__int_as_float(__builtin_amdgcn_mov_dpp(t, 0x141, 0xF, 0xF, false)), e4)
         }
         PDC_CX(PDC_DPP(0x4E), e2)
         PDC_CX(PDC_DPP(0xB1), e1)
@@ -222,7 +240,7 @@ __device__ __forceinline__ float group_sort_pick(float y, int r)
 // an unspecified value.
 template <int V, int L, bool SPARSE>
 __device__ float group_median(const float (&x)[V], const float *src, int nval, int k, float rw, bool act,
-                              float *gsc, int B)
+                              float *gsc, int B, const SortSides &sd)
 {
     const float est = group_estimate<V, L, SPARSE>(x, B);
 
@@ -322,10 +340,12 @@ __device__ float group_median(const float (&x)[V], const float *src, int nval, i
     uint32_t cm = gather ? mhi & ~mlo : 0u;
     const int c = __popc(cm);
     int incl = c;
+    // (a shift from outside the 16-lane row reads 0, so with L = 16 the
+    // group edge needs no test)
 #define PDC_SCAN(ctrl, sh)                                                                       \
     {                                                                                            \
         const int o = __builtin_amdgcn_update_dpp(0, incl, ctrl, 0xF, 0xF, true);                 \
-        incl += gl >= sh ? o : 0;                                                                \
+        incl += (L == 16 || gl >= sh) ? o : 0;                                                   \
     }
     PDC_SCAN(0x111, 1)
     if (L >= 4) PDC_SCAN(0x112, 2)
@@ -349,29 +369,26 @@ __device__ float group_median(const float (&x)[V], const float *src, int nval, i
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     // exactly one lane of the group (k - clo < n <= L) holds the answer
-    const float pick = group_sort_pick<L>(y, k - clo);
+    const float pick = group_sort_pick<L>(y, k - clo, sd);
     return gather ? pick : lo;
 }
 
 // The L-lane group's values of a bank-row: lane gl takes src[L v] (src
-// points at its first column) for L v < lim = B - gl, else pad.  When
-// tail_only (wave-uniform: B > L (V - 1)) only the last slot can lie past
-// the bank, and the others are read without a test.
+// points at its first column) for L v < lim = B - gl, else pad.  Every slot
+// is read into its own register first; when tail_only (wave-uniform:
+// B > L (V - 1)) only the last slot can lie past the bank and the others
+// are kept without a test.  (Reads under the two cases in separate branches
+// put the values in different registers, and the join then copies them.)
 template <int V, int L>
 __device__ __forceinline__ void read_group(float (&x)[V], const float *src, int lim, bool tail_only, float pad)
 {
-    if (tail_only) {
 #pragma unroll
-        for (int v = 0; v < V - 1; ++v) x[v] = src[L * v];
-        const float t = src[L * (V - 1)];
-        x[V - 1] = L * (V - 1) < lim ? t : pad;
-    } else {
+    for (int v = 0; v < V; ++v) x[v] = src[L * v];
+    if (!tail_only) {
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-            const float t = src[L * v];
-            x[v] = L * v < lim ? t : pad;
-        }
+        for (int v = 0; v < V - 1; ++v) x[v] = L * v < lim ? x[v] : pad;
     }
+    x[V - 1] = L * (V - 1) < lim ? x[V - 1] : pad;
 }
 
 struct V2Layout {
@@ -502,6 +519,7 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) lane_ok[q] = 128 * q + 2 * lane < B;
     const uint32_t lane_off = 2u * lane;
+    const SortSides sides = sort_sides<L>();  // the bank-median finish's sort
     // this wave's bank-rows g < ng: bank-row index i = wave + 16g, its local
     // row and its first pixel (offset from row_base), all wave-uniform
     const int ng = BR > wave ? min(GMAX, (BR - wave + kV2Waves - 1) / kV2Waves) : 0;
@@ -578,17 +596,19 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
     u32x2 rawq[kFlatChunks];
 #pragma unroll
     for (int c = 0; c < kFlatChunks; ++c) rawq[c] = u32x2{0u, 0u};
-    auto load_raw_flat = [&](uint64_t f) {
+    // (t: the thread index, an opaque copy made each frame, so that the
+    // chunk tests are recomputed rather than kept in scalar registers)
+    auto load_raw_flat = [&](uint64_t f, int t) {
         const u32x2 *fr = reinterpret_cast<const u32x2 *>(A.frames + f * npix + row_base);
 #pragma unroll
         for (int c = 0; c < kFlatChunks; ++c) {
-            const int j = tid + kV2Threads * c;
+            const int j = t + kV2Threads * c;
             if (j < nchunk) rawq[c] = __builtin_nontemporal_load(fr + j);
         }
     };
     if (f_begin < f_end) {
         if constexpr (FLAT)
-            load_raw_flat(f_begin);
+            load_raw_flat(f_begin, tid);
         else
             load_raw(f_begin, lane_ok);
     }
@@ -675,12 +695,15 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
 #else
 #define PDC_PHASE(ph)
 #endif
-    for (uint64_t f = f_begin; f < f_end + 2; ++f) {
+    // f mod 3, advanced with f (a 64-bit remainder per frame costs scalar
+    // instructions and registers)
+    int f3 = (int)(f_begin % 3);
+    for (uint64_t f = f_begin; f < f_end + 2; ++f, f3 = f3 == 2 ? 0 : f3 + 1) {
         const bool cur_ok = f < f_end;
         const bool p1_ok = f >= f_begin + 1 && f - 1 < f_end;
         const bool p2_ok = f >= f_begin + 2;
         const int par = (int)(f & 1), pp = par ^ 1;
-        const int sc0 = (int)(f % 3), sc1 = (int)((f + 2) % 3), sc2 = (int)((f + 1) % 3);  // seed counts of f, f-1, f-2
+        const int sc0 = f3, sc1 = f3 == 0 ? 2 : f3 - 1, sc2 = f3 == 2 ? 0 : f3 + 1;  // seed counts of f, f-1, f-2
         const uint32_t nseed_1 = p1_ok ? s_nseed[sc1] : 0u;  // frame f-1
         const uint32_t nseed_2 = p2_ok ? s_nseed[sc2] : 0u;  // frame f-2
         const uint32_t nhit_2 = p2_ok ? s_hcnt[par] : 0u;    // frame f-2's listed hits
@@ -701,13 +724,15 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
 #pragma unroll
             for (int q = 0; q < NQ; ++q) lok[q] = 128u * q + lo < (uint32_t)B;
         }
+        int tid_f = tid;  // the same for the flat chunk tests
+        asm volatile("" : "+v"(tid_f));
 
         // ================= A: 1a(f) | Frames2(f-1) | 3(f-2) =======================
         if (FLAT && cur_ok) {
             // frame f's words were loaded at the end of the previous A
 #pragma unroll
             for (int c = 0; c < kFlatChunks; ++c) {
-                const int j = tid + kV2Threads * c;
+                const int j = tid_f + kV2Threads * c;
                 if (j < nchunk) {
                     const uint32_t w0 = rawq[c].x & 0x3FFF3FFFu, w1 = rawq[c].y & 0x3FFF3FFFu;
                     float4 o;
@@ -850,7 +875,7 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
         // the loads of frame f + 1 go out last in A, into the registers frame
         // f's words were in: they overlap phase B and the barriers, and no
         // wait in A (the staging claim's atomics) waits for them
-        if (FLAT && f + 1 < f_end) load_raw_flat(f + 1);
+        if (FLAT && f + 1 < f_end) load_raw_flat(f + 1, tid_f);
         PDC_PHASE(0);
         lds_barrier();  // A -> B
         PDC_PHASE(1);
@@ -963,7 +988,7 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
             const bool tail_only = B > L * (V - 1);
             float x[V];
             read_group<V, L>(x, src, lim, tail_only, INFINITY);
-            const float m = group_median<V, L, false>(x, src, B, kmed, A.rank_width, act, s_gs + tid, B);
+            const float m = group_median<V, L, false>(x, src, B, kmed, A.rank_width, act, s_gs + tid, B, sides);
             if (act && gl == 0) {
                 med_c[i] = m;
                 // kept for patches: the own rows' medians (each row has one owner)
@@ -1014,7 +1039,7 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
                 kq = nv > 0 ? (nv - 1) / 2 : 0;
                 actv = act && nv > 0;
             }
-            float m = group_median<V, L, MG>(x, src + gl, nv, kq, A.rank_width, actv, s_gs + tid, B);
+            float m = group_median<V, L, MG>(x, src + gl, nv, kq, A.rank_width, actv, s_gs + tid, B, sides);
             if constexpr (MG) {
                 if (!actv) m = 0.0f;
                 // invalid pixels take the median: v = fl(m - m) = +0
