@@ -520,6 +520,26 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
     for (int q = 0; q < NQ; ++q) lane_ok[q] = 128 * q + 2 * lane < B;
     const uint32_t lane_off = 2u * lane;
     const SortSides sides = sort_sides<L>();  // the bank-median finish's sort
+    // Lane constants of the single-gain median groups (bank-row mi = wave
+    // 64 / L + lane / L): LDS offset of the lane's first value, its row, its
+    // first seed key and the mask of its value slots inside the bank.  Made
+    // once and kept (opaque copies): recomputed per frame they cost three
+    // quarter-rate multiplies and a 64-bit shift.
+    int mi = 0, mrow = 0, moff = 0;
+    uint32_t mkey0 = 0, mvmask = 0;
+    if constexpr (!CMM && FLAT) {
+        const int grp = lane / L, gl = lane - grp * L;
+        mi = wave * (64 / L) + grp;
+        const bool act = mi < BR;
+        mrow = act ? mi / nb : 0;
+        const int bank = act ? mi - mrow * nb : 0;
+        moff = mrow * W + bank * B + gl;
+        mkey0 = seed_key(mrow, bank, bank * B + gl);
+        const int lim = B - gl;
+        mvmask = B > L * (V - 1) ? ((L * (V - 1) < lim) ? (1u << V) - 1u : (1u << (V - 1)) - 1u)
+                                 : (uint32_t)((1ull << min(V, max(0, (lim + L - 1) / L))) - 1ull);
+        asm volatile("" : "+v"(mi), "+v"(mrow), "+v"(moff), "+v"(mkey0), "+v"(mvmask));
+    }
     // this wave's bank-rows g < ng: bank-row index i = wave + 16g, its local
     // row and its first pixel (offset from row_base), all wave-uniform
     const int ng = BR > wave ? min(GMAX, (BR - wave + kV2Waves - 1) / kV2Waves) : 0;
@@ -651,8 +671,8 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
     // seed when fl(x - m) > t, that is when fl(t - fl(x - m)) < 0 (exact
     // difference of two finite values: its sign is the test, equality gives
     // +0), one sign bit per value shifted in from the last value down.
-    auto append_seeds_dense = [&](const float(&xs)[V], float m, float t, bool own, uint32_t vmask, int row, int bank,
-                                  int gl, int sbuf, int slot) {
+    auto append_seeds_dense = [&](const float(&xs)[V], float m, float t, bool own, uint32_t vmask, uint32_t key0,
+                                  int sbuf, int slot) {
         uint32_t sb = 0;
 #pragma unroll
         for (int v = V - 1; v >= 0; --v)
@@ -665,7 +685,6 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
             uint32_t base = 0;
             if (lane == 0) base = atomicAdd(&s_nseed[slot], wtot);
             uint32_t pos = (uint32_t)__builtin_amdgcn_readfirstlane((int)base) + incl - ns;
-            const uint32_t key0 = seed_key(row, bank, bank * B + gl);
             while (sb) {
                 const int v = __ffs(sb) - 1;
                 sb &= sb - 1;
@@ -972,13 +991,9 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
             append_seeds(x, 0.0f, A.t_seed, act && row >= own_lo && row < own_hi, row, bank, gl, par, sc0);
         }
         if (!CMM && FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
-            constexpr int G = 64 / L;
-            const int grp = lane / L, gl = lane - grp * L;
-            const int i = wave * G + grp;
-            const bool act = i < BR;
-            const int row = act ? i / nb : 0;
-            const int bank = act ? i - row * nb : 0;
-            const float *src = u_c + row * W + bank * B + gl;
+            const int gl = lane & (L - 1);
+            const bool act = mi < BR;
+            const float *src = u_c + moff;
             // every lane reads (inside the u buffers or the LDS that follows
             // them; an inactive group reads row 0) and columns past the bank
             // become +inf; lim is opaque so that the compares stay at the
@@ -990,23 +1005,21 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
             read_group<V, L>(x, src, lim, tail_only, INFINITY);
             const float m = group_median<V, L, false>(x, src, B, kmed, A.rank_width, act, s_gs + tid, B, sides);
             if (act && gl == 0) {
-                med_c[i] = m;
+                med_c[mi] = m;
                 // kept for patches: the own rows' medians (each row has one owner)
-                if (A.meds && row >= own_lo && row < own_hi)
-                    A.meds[f * ((uint64_t)A.T * A.H * nb) + (uint64_t)(lr0 + row) * nb + bank] = m;
+                if (A.meds && mrow >= own_lo && mrow < own_hi)
+                    A.meds[f * ((uint64_t)A.T * A.H * nb) + (uint64_t)lr0 * nb + (uint32_t)mi] = m;
             }
-            const bool own = act && row >= own_lo && row < own_hi;
+            const bool own = act && mrow >= own_lo && mrow < own_hi;
             if (KEEP && own) {
-                float *f2 = A.corrected + f * npix + row_base + row * W + bank * B + gl;
+                float *f2 = A.corrected + f * npix + row_base + moff;
 #pragma unroll
                 for (int v = 0; v < V; ++v)
                     if (L * v < lim) f2[L * v] = __fsub_rn(x[v], m);
             }
-            // slots past the bank (+inf) are no seeds
-            const uint32_t vmask = tail_only ? ((L * (V - 1) < lim) ? (1u << V) - 1u : (1u << (V - 1)) - 1u)
-                                             : (uint32_t)((1ull << min(V, max(0, (lim + L - 1) / L))) - 1ull);
             PDC_PHASE(2);
-            append_seeds_dense(x, m, A.t_seed, own, vmask, row, bank, gl, par, sc0);
+            // slots past the bank (+inf) are no seeds
+            append_seeds_dense(x, m, A.t_seed, own, mvmask, mkey0, par, sc0);
         }
         if (!CMM && !FLAT && cur_ok && wave * (64 / L) < BR) {  // waves without a bank-row skip the search
             constexpr int G = 64 / L;
