@@ -520,16 +520,30 @@ __device__ __forceinline__ void frame_body(const V2Args &A, const int item)
     for (int q = 0; q < NQ; ++q) lane_ok[q] = 128 * q + 2 * lane < B;
     const uint32_t lane_off = 2u * lane;
     const SortSides sides = sort_sides<L>();  // the bank-median finish's sort
-    // Lane constants of the single-gain median groups (bank-row mi = wave
-    // 64 / L + lane / L): LDS offset of the lane's first value, its row, its
-    // first seed key and the mask of its value slots inside the bank.  Made
-    // once and kept (opaque copies): recomputed per frame they cost three
-    // quarter-rate multiplies and a 64-bit shift.
+    // Lane constants of the single-gain median groups: the bank-row mi of
+    // the lane's group, the LDS offset of its first value, its row, its first
+    // seed key and the mask of its value slots inside the bank.  Made once and
+    // kept (opaque copies): recomputed per frame they cost three quarter-rate
+    // multiplies and a 64-bit shift.  Group slot s = wave 64 / L + lane / L
+    // takes bank-row s, except that with the row step d = 4 (16-lane groups)
+    // the loaded rows go in blocks of 4 d, and the four groups of a wave take
+    // one bank of rows j, j + d, j + 2 d, j + 3 d of a block, so that their
+    // LDS reads fall in different banks; rows past the last whole block keep
+    // bank-row s.  Either way slot s is active exactly when s < BR.
     int mi = 0, mrow = 0, moff = 0;
     uint32_t mkey0 = 0, mvmask = 0;
     if constexpr (!CMM && FLAT) {
         const int grp = lane / L, gl = lane - grp * L;
         mi = wave * (64 / L) + grp;
+        if (L == 16 && A.med_row_step == 4) {
+            constexpr int d = 4;
+            const int per = 4 * d * nb;                  // bank-rows of a block
+            if (mi < (R / (4 * d)) * per) {
+                const int blk = mi / per, t = mi - blk * per;
+                const int wi = t >> 2, g = t & 3;        // wave of the block, group
+                mi = (blk * 4 * d + wi % d + d * g) * nb + wi / d;
+            }
+        }
         const bool act = mi < BR;
         mrow = act ? mi / nb : 0;
         const int bank = act ? mi - mrow * nb : 0;

@@ -108,6 +108,8 @@ struct V2Args {
     int32_t gain_mode;
     uint32_t *invalid;
     float *meds;                  // as in FrameKernelArgs (median mode)
+    int32_t med_row_step;         // single-gain median kernels with 16-lane groups: 4 when one
+                                  // wave's four groups take every fourth row, else 0
 };
 
 size_t frame_kernel_v2_lds_bytes(int rmax, int W, int nb, int seed_cap);

@@ -657,6 +657,34 @@ pdc_status enqueue_pre(pdc_ctx *ctx, Batch &bt)
     return PDC_OK;
 }
 
+// Rows between the bank-rows that one wave's four 16-lane median groups read:
+// 4 or 0 (consecutive bank-rows).  Each group reads 16 consecutive LDS words
+// per value slot from its bank-row's start; every fourth row is taken when it
+// spreads the four windows more evenly over the 64 LDS banks (W = 388: starts
+// 16 banks apart, no conflict, against four-way conflicts for consecutive
+// bank-rows).
+static int median_row_step(int W, int B, int nb)
+{
+    auto worst = [](const int(&off)[4]) {
+        int cnt[64] = {}, mx = 0;
+        for (int g = 0; g < 4; ++g)
+            for (int k = 0; k < 16; ++k) mx = std::max(mx, ++cnt[(off[g] + k) & 63]);
+        return mx;
+    };
+    int off[4];
+    for (int g = 0; g < 4; ++g) off[g] = (g / nb) * W + (g % nb) * B;
+    int best = 0, best_w = worst(off);
+    for (int step : {4}) {
+        for (int g = 0; g < 4; ++g) off[g] = g * step * W;
+        const int w = worst(off);
+        if (w < best_w) {
+            best = step;
+            best_w = w;
+        }
+    }
+    return best;
+}
+
 // Arguments of the persistent kernel for a batch.
 void fill_v2_args(const Detector &d, const Batch &bt, V2Args &a)
 {
@@ -698,6 +726,7 @@ void fill_v2_args(const Detector &d, const Batch &bt, V2Args &a)
     a.cm_guard = d.cm_guard;
     a.sum_lo = d.sum_lo;
     a.sum_hi = d.sum_hi;
+    a.med_row_step = d.nq == 2 ? median_row_step(a.W, a.B, a.nb) : 0;
     a.gain_mode = d.g.gain_mode;
     a.invalid = b->invalid;
     a.meds = bt.meds && !d.p.cm_mode ? b->meds : nullptr;
