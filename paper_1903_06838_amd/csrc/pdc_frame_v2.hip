@@ -22,7 +22,9 @@
 // by one wave as NQ pair-slots; lane l of pair-slot q holds columns 128q + 2l
 // and 128q + 2l + 1 of the bank (value-slots 2q and 2q+1); absent pixels hold
 // +inf.  Phase 1b: bank-row i belongs to lane group i % (64 / L) of wave
-// i / (64 / L); lane j of the group holds columns L v + j, v < V.
+// i / (64 / L) (single-gain kernels with a row step: a wave's four groups
+// take every fourth row, see the median groups' lane constants); lane j of
+// the group holds columns L v + j, v < V.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
