@@ -397,22 +397,63 @@ hipError_t launch_frame_scan(const uint32_t *frame_hits, uint64_t n_frames,
     return hipGetLastError();
 }
 
-// One wave per unit copies its staged run into the raster-order list.
+// Each wave copies the staged runs of kScatterUnits consecutive units into
+// the raster-order list.  A unit's run is short (about a hundred hits at
+// occupancy 0.01), so one unit per wave left each wave two dependent memory
+// round trips for little data; here lanes 0..kScatterUnits-1 read the units'
+// counts, bases and destinations at once, and the first two 64-hit rows of
+// every run are loaded before any is stored, so up to 2 kScatterUnits loads
+// per lane are in flight.  Longer runs finish row by row.  Units whose run
+// was not staged (kNoBase) or would end past hits_cap (only after a staging
+// overflow; the batch is then recomputed) copy nothing.
+constexpr int kScatterUnits = 4;
+
 __global__ void __launch_bounds__(256)
 scatter_kernel(const uint32_t *unit_count, const uint64_t *unit_base, const uint32_t *unit_local,
                const unsigned long long *frame_offset, const uint2 *pool, uint64_t n_units,
                int32_t upf, uint2 *hits, uint64_t hits_cap)
 {
-    const uint64_t unit = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    constexpr int U = kScatterUnits;
+    const uint64_t u0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * U;
     const int lane = threadIdx.x & 63;
-    if (unit >= n_units) return;
-    const uint32_t c = unit_count[unit];
-    const uint64_t b = unit_base[unit];
-    if (c == 0 || b == kNoBase) return;
-    const uint64_t f = unit / (uint64_t)upf;
-    const uint64_t dst = frame_offset[f] + unit_local[unit];
-    if (dst + c > hits_cap) return;  // only after a staging overflow; the batch is recomputed
-    for (uint32_t i = lane; i < c; i += 64) hits[dst + i] = pool[b + i];
+    if (u0 >= n_units) return;
+    uint32_t c = 0;
+    uint64_t b = 0, dst = 0;
+    if (lane < U && u0 + lane < n_units) {
+        const uint64_t unit = u0 + lane;
+        c = unit_count[unit];
+        b = unit_base[unit];
+        dst = frame_offset[unit / (uint64_t)upf] + unit_local[unit];
+        if (b == kNoBase || dst + c > hits_cap) c = 0;
+    }
+    uint32_t cu[U];
+    uint64_t bu[U], du[U];
+#pragma unroll
+    for (int k = 0; k < U; ++k) {
+        cu[k] = (uint32_t)__builtin_amdgcn_readlane((int)c, k);
+        bu[k] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(b >> 32), k) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, k);
+        du[k] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(dst >> 32), k) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)dst, k);
+    }
+    uint2 v[U][2];
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const uint32_t i = (uint32_t)lane + 64u * r;
+            if (i < cu[k]) v[k][r] = pool[bu[k] + i];
+        }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+            const uint32_t i = (uint32_t)lane + 64u * r;
+            if (i < cu[k]) hits[du[k] + i] = v[k][r];
+        }
+#pragma unroll
+    for (int k = 0; k < U; ++k)
+        for (uint32_t i = (uint32_t)lane + 128u; i < cu[k]; i += 64) hits[du[k] + i] = pool[bu[k] + i];
 }
 
 hipError_t launch_scatter(const uint32_t *unit_count, const uint64_t *unit_base,
@@ -421,7 +462,8 @@ hipError_t launch_scatter(const uint32_t *unit_count, const uint64_t *unit_base,
                           uint2 *hits, uint64_t hits_cap, hipStream_t s)
 {
     if (n_units == 0) return hipSuccess;
-    uint64_t blocks = (n_units + 3) / 4;
+    const uint64_t per_block = 4 * (uint64_t)kScatterUnits;  // 4 waves
+    const uint64_t blocks = (n_units + per_block - 1) / per_block;
     hipLaunchKernelGGL(scatter_kernel, dim3((uint32_t)blocks), dim3(256), 0, s, unit_count,
                        unit_base, unit_local, frame_offset, pool, n_units, units_per_frame, hits,
                        hits_cap);
